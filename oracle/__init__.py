@@ -1,0 +1,258 @@
+"""ctypes binding of the CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark; never by the product path (the GPU package
+does not import this module, and this module does not import the GPU binding).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+MAX_MESH = 8
+STRICT, WEAK = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (plain -O2, no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-Wall", "-o", LIB_PATH + ".tmp", os.path.join(HERE, "oracle.c"),
+               "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+Mat = (C.c_double * MAX_MESH) * MAX_MESH
+
+
+class OrParams(C.Structure):
+    _fields_ = [
+        ("n_cells", C.c_int32),
+        ("d", C.c_double), ("area", C.c_double), ("eps0", C.c_double), ("dt", C.c_double),
+        ("Z", C.c_int32 * 2),
+        ("mass", C.c_double * 2),
+        ("q_unit", C.c_double), ("weight", C.c_double),
+        ("ev", C.c_double),
+        ("n_mesh", C.c_int32), ("gap_mesh", C.c_int32),
+        ("L", Mat), ("R", Mat), ("S", Mat),
+        ("src", C.c_double * MAX_MESH),
+        ("src_dc", C.c_double), ("src_amp", C.c_double), ("src_freq", C.c_double),
+        ("src_phase", C.c_double),
+        ("c_par", C.c_double),
+        ("q0", C.c_double * MAX_MESH),
+        ("see_amp", C.c_double), ("see_E0_eV", C.c_double),
+        ("see_law", C.c_int32), ("see_max", C.c_int32),
+        ("see_E_eV", C.c_double),
+        ("beam_per_step", C.c_int64),
+        ("beam_Emin_eV", C.c_double), ("beam_Emax_eV", C.c_double),
+        ("seed", C.c_uint64),
+        ("fp32", C.c_int32),
+    ]
+
+
+class OrDiag(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("t", C.c_double), ("phi0", C.c_double), ("sigma", C.c_double),
+        ("qcirc", C.c_double), ("qcirc_star", C.c_double), ("qconv", C.c_double),
+        ("e_ground", C.c_double),
+        ("q", C.c_double * MAX_MESH), ("I", C.c_double * MAX_MESH),
+        ("n_live", C.c_int64 * 2),
+        ("abs_step", (C.c_int64 * 2) * 2), ("emit_step", C.c_int64 * 2), ("inj_step", C.c_int64),
+        ("abs_cum", (C.c_int64 * 2) * 2), ("emit_cum", C.c_int64 * 2), ("inj_cum", C.c_int64),
+        ("pushed_cum", C.c_int64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        P, D = C.POINTER(C.c_double), C.POINTER(C.c_uint64)
+        L.or_philox4x64.argtypes = [D, D, D]
+        L.or_poisson_draw.argtypes = [C.c_double, C.c_double, C.c_int32]
+        L.or_poisson_draw.restype = C.c_int32
+        L.or_create.argtypes = [C.POINTER(OrParams)]
+        L.or_create.restype = C.c_void_p
+        L.or_destroy.argtypes = [C.c_void_p]
+        L.or_inject.argtypes = [C.c_void_p, C.c_int32, C.c_int64, P, P]
+        L.or_inject.restype = C.c_int32
+        L.or_step.argtypes = [C.c_void_p, C.c_int32]
+        L.or_step.restype = C.c_int32
+        L.or_get_diag.argtypes = [C.c_void_p, C.POINTER(OrDiag)]
+        L.or_get_fields.argtypes = [C.c_void_p, P, P, P]
+        L.or_count.argtypes = [C.c_void_p, C.c_int32]
+        L.or_count.restype = C.c_int64
+        L.or_get_particles.argtypes = [C.c_void_p, C.c_int32, P, P, C.POINTER(C.c_uint32)]
+        L.or_get_particles.restype = C.c_int64
+        L.or_get_particles_f32.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_float),
+                                           C.POINTER(C.c_float), C.POINTER(C.c_uint32)]
+        L.or_get_particles_f32.restype = C.c_int64
+        L.or_poisson_gauss.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, P, P]
+        L.or_gather64.argtypes = [C.c_int32, C.c_double, P, C.c_double, C.c_double, C.c_double]
+        L.or_gather64.restype = C.c_double
+        L.or_gather32.argtypes = [C.c_int32, C.POINTER(C.c_float), C.c_float]
+        L.or_gather32.restype = C.c_float
+        L.or_circuit_run.argtypes = [C.POINTER(OrParams), C.c_int64, P, P]
+        L.or_circuit_run.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def params_from(cfg, fp32: bool = False) -> OrParams:
+    p = OrParams()
+    p.n_cells = cfg.n_cells
+    p.d, p.area, p.eps0, p.dt = cfg.d, cfg.area, cfg.eps0, cfg.dt
+    p.Z[0], p.Z[1] = int(cfg.Z[0]), int(cfg.Z[1])
+    p.mass[0], p.mass[1] = float(cfg.mass[0]), float(cfg.mass[1])
+    p.q_unit, p.weight, p.ev = cfg.q_unit, cfg.weight, cfg.ev
+    p.n_mesh, p.gap_mesh = cfg.n_mesh, cfg.gap_mesh
+    for i in range(cfg.n_mesh):
+        for j in range(cfg.n_mesh):
+            p.L[i][j] = float(cfg.L[i, j])
+            p.R[i][j] = float(cfg.R[i, j])
+            p.S[i][j] = float(cfg.S[i, j])
+        p.src[i] = float(cfg.src[i])
+        p.q0[i] = float(cfg.q0[i])
+    p.src_dc, p.src_amp, p.src_freq, p.src_phase = cfg.src_dc, cfg.src_amp, cfg.src_freq, cfg.src_phase
+    p.c_par = cfg.c_par
+    p.see_amp, p.see_E0_eV, p.see_law, p.see_max = cfg.see_amp, cfg.see_E0_eV, cfg.see_law, cfg.see_max
+    p.see_E_eV = cfg.see_E_eV
+    p.beam_per_step = cfg.beam_per_step
+    p.beam_Emin_eV, p.beam_Emax_eV = cfg.beam_Emin_eV, cfg.beam_Emax_eV
+    p.seed = cfg.seed
+    p.fp32 = 1 if fp32 else 0
+    return p
+
+
+def philox4x64(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint64)
+    k = np.asarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    D = C.POINTER(C.c_uint64)
+    lib().or_philox4x64(c.ctypes.data_as(D), k.ctypes.data_as(D), out.ctypes.data_as(D))
+    return out
+
+
+def poisson_draw(lam: float, u: float, kmax: int = 32) -> int:
+    return int(lib().or_poisson_draw(lam, u, kmax))
+
+
+def poisson_gauss(rho: np.ndarray, dx: float, eps0: float, sigma: float) -> np.ndarray:
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    n_cells = rho.size - 1
+    phi = np.zeros(n_cells + 1)
+    lib().or_poisson_gauss(n_cells, dx, eps0, sigma, _dp(rho), _dp(phi))
+    return phi
+
+
+def gather64(E_half, dx, e0_surf, e_ground, x) -> np.ndarray:
+    E_half = np.ascontiguousarray(E_half, dtype=np.float64)
+    N = E_half.size
+    return np.array([lib().or_gather64(N, dx, _dp(E_half), e0_surf, e_ground, float(v)) for v in x])
+
+
+def gather32(ehat, xi) -> np.ndarray:
+    ehat = np.ascontiguousarray(ehat, dtype=np.float32)
+    N = ehat.size - 2
+    F = C.POINTER(C.c_float)
+    return np.array([lib().or_gather32(N, ehat.ctypes.data_as(F), float(v)) for v in xi],
+                    dtype=np.float32)
+
+
+def circuit_run(cfg, nsteps: int):
+    p = params_from(cfg)
+    q = np.zeros(nsteps * cfg.n_mesh)
+    v = np.zeros(nsteps)
+    rc = lib().or_circuit_run(C.byref(p), nsteps, _dp(q), _dp(v))
+    if rc:
+        raise RuntimeError(f"or_circuit_run failed: {rc}")
+    return q.reshape(nsteps, cfg.n_mesh), v
+
+
+class OracleSim:
+    """One gap advanced by the oracle."""
+
+    def __init__(self, cfg, fp32: bool = False):
+        self.cfg = cfg
+        self.fp32 = fp32
+        self._p = params_from(cfg, fp32)
+        self._h = lib().or_create(C.byref(self._p))
+        if not self._h:
+            raise ValueError("oracle rejected the parameters")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().or_destroy(h)
+            self._h = None
+
+    def inject(self, species: int, x, v):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        rc = lib().or_inject(self._h, species, x.size, _dp(x), _dp(v))
+        if rc:
+            raise ValueError(f"or_inject failed: {rc}")
+
+    def step(self, mode: int = STRICT, n: int = 1):
+        for _ in range(n):
+            rc = lib().or_step(self._h, mode)
+            if rc:
+                raise RuntimeError(f"or_step failed: {rc}")
+
+    def diag(self) -> dict:
+        D = OrDiag()
+        lib().or_get_diag(self._h, C.byref(D))
+        M = self.cfg.n_mesh
+        return dict(step=D.step, t=D.t, phi0=D.phi0, sigma=D.sigma, qcirc=D.qcirc,
+                    qcirc_star=D.qcirc_star, qconv=D.qconv,
+                    e_ground=D.e_ground, q=np.array(D.q[:M]), I=np.array(D.I[:M]),
+                    n_live=np.array(D.n_live[:]),
+                    abs_step=np.array([[D.abs_step[a][b] for b in range(2)] for a in range(2)]),
+                    emit_step=np.array(D.emit_step[:]), inj_step=D.inj_step,
+                    abs_cum=np.array([[D.abs_cum[a][b] for b in range(2)] for a in range(2)]),
+                    emit_cum=np.array(D.emit_cum[:]), inj_cum=D.inj_cum,
+                    pushed_cum=D.pushed_cum)
+
+    def fields(self):
+        N = self.cfg.n_cells
+        phi, E, rho = np.zeros(N + 1), np.zeros(N), np.zeros(N + 1)
+        lib().or_get_fields(self._h, _dp(phi), _dp(E), _dp(rho))
+        return phi, E, rho
+
+    def count(self, species: int) -> int:
+        return int(lib().or_count(self._h, species))
+
+    def particles(self, species: int):
+        n = self.count(species)
+        x, v = np.zeros(n), np.zeros(n)
+        ids = np.zeros(n, dtype=np.uint32)
+        lib().or_get_particles(self._h, species, _dp(x), _dp(v),
+                               ids.ctypes.data_as(C.POINTER(C.c_uint32)))
+        return x, v, ids
+
+    def particles_f32(self, species: int):
+        n = self.count(species)
+        xi, u = np.zeros(n, dtype=np.float32), np.zeros(n, dtype=np.float32)
+        ids = np.zeros(n, dtype=np.uint32)
+        F = C.POINTER(C.c_float)
+        rc = lib().or_get_particles_f32(self._h, species, xi.ctypes.data_as(F), u.ctypes.data_as(F),
+                                        ids.ctypes.data_as(C.POINTER(C.c_uint32)))
+        if rc < 0:
+            raise RuntimeError("not an fp32 oracle")
+        return xi, u, ids
