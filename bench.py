@@ -1,0 +1,169 @@
+"""Throughput of the circuit-coupled ES-PIC step on one MI355X.
+
+Default workload: the weak-coupling beam gap (4096 cells, 2e7 H+ macroparticles in
+binary32, 2e4 beam ions per step, coupled-LC circuit, SEE with exponential 3 eV
+electrons), inputs resident in HBM before the timed region.  One step = circuit +
+field solve, gather/push/walls/SEE/beam/deposit, and the periodic slot
+compaction, for every particle.
+
+Prints one JSON line: particle-steps/s, the push kernel against the HBM
+roofline (HIP events on the library's stream over the timed region), and the
+CPU oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+BYTES_PER_PUSH_F32 = 16  # read x, v and write x, v (binary32)
+
+WORKLOADS = {
+    # name: (config builder kwargs, initial H+ count, coupling)
+    "beam_gap_4096c_2e7p_weak": dict(n_cells=4096, n0=20_000_000, beam=20_000, mode=1,
+                                     load="uniform"),
+    "beam_gap_16384c_2e8p_strict": dict(n_cells=16384, n0=200_000_000, beam=20_000, mode=0,
+                                        load="gauss"),
+    "beam_gap_16384c_2e8p_weak": dict(n_cells=16384, n0=200_000_000, beam=20_000, mode=1,
+                                      load="gauss"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_sim(name, spec, capacity_pad=1.6):
+    from paper_2603_24010_amd import gapsim, workloads as W
+    cfg = W.config2(n_cells=spec["n_cells"], beam_per_step=spec["beam"])
+    if spec["load"] == "uniform":
+        loads = W.load_config2(n=spec["n0"], seed=2, d=cfg.d)
+    else:
+        loads = W.load_config3(n=spec["n0"], seed=3, d=cfg.d)
+    n_ion = spec["n0"]
+    cap = (max(1 << 22, n_ion // 4), int(n_ion * capacity_pad) + 4 * (1 << 20))
+    sim = gapsim.GapSim(cfg, particle_fp=32, capacity=cap)
+    for sp, (x, v) in loads.items():
+        sim.inject(0, sp, x, v)
+    return sim, cfg, loads
+
+
+def cpu_baseline(spec, steps: int):
+    """The oracle (binary32 mode, one thread) on the workload's initial state."""
+    import oracle
+    from paper_2603_24010_amd import workloads as W
+    cfg = W.config2(n_cells=spec["n_cells"], beam_per_step=spec["beam"])
+    n = min(spec["n0"], 20_000_000)
+    if spec["load"] == "uniform":
+        loads = W.load_config2(n=n, seed=2, d=cfg.d)
+    else:
+        loads = W.load_config3(n=n, seed=3, d=cfg.d)
+    s = oracle.OracleSim(cfg, fp32=True)
+    for sp, (x, v) in loads.items():
+        s.inject(sp, x, v)
+    t0 = time.perf_counter()
+    s.step(spec["mode"], steps)
+    el = time.perf_counter() - t0
+    d = s.diag()
+    return {"value": d["pushed_cum"] / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} initial H+ of the same workload, {steps} steps, binary32 oracle mode, "
+                      f"{d['pushed_cum']} particle-steps in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="beam_gap_4096c_2e7p_weak", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compact-every", type=int, default=16)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this method has no multi-GPU path in this build "
+              "(independent gaps would shard across GPUs with no exchange)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_24010_amd import gapsim
+    torch.cuda.set_device(0)
+    spec = WORKLOADS[args.workload]
+    log(f"[bench] building workload {args.workload}")
+    sim, cfg, _ = make_sim(args.workload, spec)
+    sim.set_option(gapsim.OPT_COMPACT_EVERY, args.compact_every)
+    if args.block:
+        sim.set_option(gapsim.OPT_BLOCK, args.block)
+    if args.tile:
+        sim.set_option(gapsim.OPT_TILE, args.tile)
+    if args.grid:
+        sim.set_option(gapsim.OPT_GRID, args.grid)
+    mode = spec["mode"]
+    log(f"[bench] warmup {args.warmup} steps")
+    sim.step(mode, args.warmup)
+    d0 = sim.diag(0)
+    sim.set_option(gapsim.OPT_TIMING, 1)
+    sim.timing(reset=True)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    chunk = 250
+    done = 0
+    while done < args.steps:
+        k = min(chunk, args.steps - done)
+        sim.step(mode, k)
+        done += k
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    d1 = sim.diag(0)
+    tm = sim.timing(reset=True)
+    pushed = d1["pushed_cum"] - d0["pushed_cum"]
+    value = pushed / el
+    push_s = tm["push_ms"] * 1e-3
+    achieved = BYTES_PER_PUSH_F32 * pushed / push_s / 1e9
+    out = {
+        "metric": "particle-steps/s",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "cells": cfg.n_cells, "initial_particles": spec["n0"],
+                   "beam_per_step": cfg.beam_per_step, "coupling": "weak" if mode else "strict",
+                   "particles": "binary32", "field_circuit": "binary64",
+                   "live_particles_end": int(d1["n_live"].sum())},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_push", "bytes_per_particle_step": BYTES_PER_PUSH_F32,
+                     "avg_launch_ms": tm["push_ms"] / max(1, tm["push_launches"]),
+                     "launches": tm["push_launches"]},
+        "kernel_ms_per_step": {"push": tm["push_ms"] / args.steps, "field": tm["field_ms"] / args.steps,
+                               "compact": tm["compact_ms"] / args.steps},
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * gapsim: circuit-coupled 1D electrostatic particle-in-cell step on AMD MI355X
+ * (gfx950), after Kim, Yun, Lee, Na, "Self-Consistent Numerical Framework for
+ * Multiscale Circuit-Plasma Coupling with Secondary Electron Emission"
+ * (arXiv 2603.24010).
+ *
+ * One time step of one or many independent vacuum gaps.  Node 0 (x = 0) is the
+ * electrode wired to the external circuit, node N (x = d) is grounded.  Per
+ * step and gap:
+ *   1. circuit + field at level n: BDF2 loop-charge circuit (Sec. 2.1, App. A),
+ *      node-centred Poisson with phi_N = 0 (Sec. 2.2.1, App. B) whose first row
+ *      couples to the circuit, strict (Sec. 2.4.2, eq. Poisson_BC2) or weak
+ *      (Sec. 2.4.3, eq. Poisson_BC3); surface charge eq. top_plate_charge;
+ *   2. gather from the half-grid field and leapfrog push (Sec. 2.2.2, App. C);
+ *   3. absorption at either electrode, convection charge (Sec. 2.4.1) and
+ *      ion-induced secondary emission (Sec. 2.3, Alg. 2);
+ *   4. optional ion beam entering at the circuit electrode;
+ *   5. charge deposit with the same linear weights, electrode nodes doubled
+ *      (App. C, App. E).
+ *
+ * Conventions of every entry point:
+ *   - Return a gs_status; nothing throws or aborts across this boundary.
+ *   - Work is queued on the HIP stream given to gs_init and is asynchronous,
+ *     except gs_read_diagnostics / gs_read_particles / gs_get_timing, which
+ *     synchronise that stream.
+ *   - The library owns all device state; caller buffers are read or written
+ *     during the call only and never retained.
+ *   - A device-side error (particle capacity exceeded) is sticky: the next call
+ *     returns GS_ECAPACITY and gs_last_error says which gap.
+ *   - Calls on one context are not thread-safe.
+ *   - Units are SI unless a name says otherwise.
+ */
+#ifndef GAPSIM_H
+#define GAPSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_MAX_MESH 8
+
+typedef enum {
+  GS_OK = 0,
+  GS_EINVAL = -1,     /* bad argument or parameter; nothing changed */
+  GS_ENOMEM = -2,     /* an allocation failed; the context is unusable */
+  GS_ECAPACITY = -3,  /* a gap ran out of particle slots; new particles were dropped */
+  GS_EDEVICE = -4,    /* a HIP call failed; the context is unusable */
+  GS_ENOCONV = -5,    /* a Newton solve missed its tolerance within its iteration cap */
+  GS_ESTATE = -6      /* call out of order (e.g. no context) */
+} gs_status;
+
+enum { GS_SEE_FIXED = 0, GS_SEE_EXP = 1 };
+enum { GS_GUESS_DIRECT = 0, GS_GUESS_EXTRAP = 1, GS_GUESS_MLP = 2 };
+
+/* Device memory hook.  alloc(bytes, user) returns device memory or NULL;
+ * release(ptr, user) frees it.  A NULL allocator means hipMalloc/hipFree. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *user);
+  void (*release)(void *ptr, void *user);
+  void *user;
+} gs_allocator;
+
+/* Parameters of one gap.
+ *   Species 0 are electrons, species 1 ions.  A macroparticle of species s
+ *   carries the areal sheet charge weight * q_unit * Z[s] [C/m^2] (the
+ *   superparticle ratio times the particle charge, as in tab:validation_parameters).
+ *   The circuit is written in loop (mesh) charges q (Sec. 2.1):
+ *     L q'' + R q' + S q + e_gap V_gap = src * Vs(t),
+ *     Vs(t) = src_dc + src_amp sin(2 pi src_freq t + src_phase),
+ *   the gap element (the gap itself, eps0 area / d, in parallel with c_par) lying
+ *   in mesh gap_mesh.  q0 holds the loop charges before t = 0 (switch closes at
+ *   t = 0).  Matrices are row-major, only the leading n_mesh x n_mesh used.
+ *   SEE: an ion hitting either electrode frees Poisson(gamma) electrons, at most
+ *   see_max, gamma(E) = see_amp (E/see_E0_eV) / (1 + E/see_E0_eV), E the ion's
+ *   normal kinetic energy; each leaves the surface normally with energy see_E_eV
+ *   (GS_SEE_FIXED) or an exponential draw of mean see_E_eV (GS_SEE_EXP).
+ *   Beam: beam_per_step ions per step enter at the circuit electrode with
+ *   energies uniform in [beam_Emin_eV, beam_Emax_eV].
+ *   particle_fp: 32 (binary32 particles, 2^-24 fixed-point deposit weights) or
+ *   64 (binary64 particles, 2^-44 weights); the same for every gap of a context.
+ *   capacity[s]: particle slots of species s (live plus not-yet-reclaimed). */
+typedef struct {
+  int32_t n_cells;
+  double d, area, eps0, dt;
+  int32_t Z[2];
+  double mass[2];
+  double q_unit, weight, ev;
+  int32_t n_mesh, gap_mesh;
+  double L[GS_MAX_MESH][GS_MAX_MESH];
+  double R[GS_MAX_MESH][GS_MAX_MESH];
+  double S[GS_MAX_MESH][GS_MAX_MESH];
+  double src[GS_MAX_MESH];
+  double src_dc, src_amp, src_freq, src_phase;
+  double c_par;
+  double q0[GS_MAX_MESH];
+  double see_amp, see_E0_eV;
+  int32_t see_law, see_max;
+  double see_E_eV;
+  int64_t beam_per_step;
+  double beam_Emin_eV, beam_Emax_eV;
+  uint64_t seed;
+  int32_t particle_fp;
+  int64_t capacity[2];
+  double v_ref; /* voltage scale of the Newton residual norm (> 0) */
+} gs_gap_params;
+
+/* State of one gap after the last completed step (level n = step). */
+typedef struct {
+  int64_t step;           /* level of the last field solve (-1 before the first step) */
+  double t;               /* step * dt */
+  double phi0;            /* electrode potential = gap voltage */
+  double sigma;           /* surface charge sigma_+ of the circuit electrode [C/m^2] */
+  double qcirc;           /* circuit charge Q_circ (weak: re-imposed C_gap phi0) */
+  double qcirc_star;      /* weak: the circuit's own gap charge; strict: = qcirc */
+  double qconv;           /* convection charge that entered this level [C] */
+  double e_ground;        /* field at the grounded electrode [V/m] */
+  double q[GS_MAX_MESH];  /* loop charges */
+  double I[GS_MAX_MESH];  /* loop currents (BDF2) */
+  int64_t n_live[2];      /* live particles per species */
+  int64_t n_slots[2];     /* slots in use per species (live + absorbed, not reclaimed) */
+  int64_t abs_step[2][2]; /* absorbed in the last push [species][0 circuit, 1 ground] */
+  int64_t emit_step[2];   /* electrons emitted in the last push at [electrode] */
+  int64_t inj_step;       /* beam ions injected in the last step */
+  int64_t abs_cum[2][2];
+  int64_t emit_cum[2];
+  int64_t inj_cum;
+  int64_t pushed_cum;     /* particle pushes so far (particle-steps) */
+  int32_t newton_last;    /* Newton updates at the last strict step (-1: direct solve) */
+  int32_t newton_fallback_last; /* 1 if the last step fell back from the MLP guess */
+  int64_t newton_total;   /* Newton updates summed over strict steps */
+  int64_t newton_fallbacks;
+  double newton_resid0;   /* infinity norm of the scaled residual at the initial guess */
+  double newton_resid;    /* ... after the last update */
+} gs_diag;
+
+/* Accumulated device time of the library's kernels, measured with HIP events
+ * on the context's stream while timing is switched on (GS_OPT_TIMING). */
+typedef struct {
+  double push_ms, field_ms, compact_ms;
+  int64_t push_launches, field_launches, compact_launches;
+} gs_timing;
+
+/* Options for gs_set_option. */
+enum {
+  GS_OPT_BLOCK = 1,        /* push threads per block: 256, 512 or 1024 */
+  GS_OPT_TILE = 2,         /* particles per work tile (multiple of the block size) */
+  GS_OPT_GRID = 3,         /* push blocks; 0 = from occupancy */
+  GS_OPT_COMPACT_EVERY = 4,/* steps between reclaiming absorbed slots (>= 1) */
+  GS_OPT_GRAPH = 5,        /* 1: replay steps through a captured hipGraph */
+  GS_OPT_TIMING = 6,       /* 1: time each kernel launch with HIP events */
+  GS_OPT_NEWTON_TOL = 7,   /* value * 1e-12 = scaled residual tolerance (default 1e-10) */
+  GS_OPT_NEWTON_MAXIT = 8
+};
+
+typedef struct gs_ctx gs_ctx;
+
+/* Create a context for n_gaps gaps (Sec. 2.4: each gap is one load capacitor
+ * with its own circuit).  params: n_gaps host structs, copied.  Each gap starts
+ * with no particles, its circuit at q0 and the electrode holding the gap's share
+ * of the gap-mesh charge; the first step solves level 0.  alloc may be NULL.
+ * hip_stream is a hipStream_t (NULL = the default stream).  Errors: GS_EINVAL
+ * (message from gs_last_error(NULL)), GS_ENOMEM, GS_EDEVICE; *out is NULL then. */
+gs_status gs_init(gs_ctx **out, int32_t n_gaps, const gs_gap_params *params,
+                  const gs_allocator *alloc, void *hip_stream);
+
+/* Destroy a context and free its device memory (NULL is ignored). */
+void gs_destroy(gs_ctx *ctx);
+
+/* Add n particles of one species to one gap at the current level: x in [0, d]
+ * [m], v = v_x [m/s], each an array of n doubles, in host memory
+ * (ptr_is_device = 0) or device memory (1).  Ids are assigned in order from the
+ * gap's counter (ions' ids key their secondary-emission draws).  Their charge is
+ * added to the density the next step solves with (App. E: a particle appearing
+ * at a level counts at that level).  Copied; the caller keeps ownership.
+ * Errors: GS_EINVAL (bad gap/species/position), GS_ECAPACITY. */
+gs_status gs_inject(gs_ctx *ctx, int32_t gap, int32_t species, int64_t n, const double *x,
+                    const double *v, int32_t ptr_is_device);
+
+/* Advance every gap n_steps steps with strict coupling (Sec. 2.4.2): the circuit
+ * charge is an affine function of the electrode potential, eq. Q4_phi_relation,
+ * folded into the first Poisson row (eq. Poisson_BC2) and solved in one pass.
+ * guess = GS_GUESS_DIRECT solves that closed system directly; GS_GUESS_EXTRAP or
+ * GS_GUESS_MLP instead runs Newton on u = (gap voltage, loop currents) from a
+ * quadratic extrapolation or from the network set by gs_mlp_set_weights (the
+ * Newton iteration decides convergence; a non-finite or worse MLP guess falls
+ * back to the extrapolation).  Asynchronous.  Errors: GS_EINVAL, GS_ECAPACITY
+ * (sticky), GS_EDEVICE. */
+gs_status gs_step_strict(gs_ctx *ctx, int32_t n_steps, int32_t guess);
+
+/* Advance every gap n_steps steps with weak coupling (Sec. 2.4.3): the circuit
+ * is stepped first with the gap as a capacitor, its gap charge enters the
+ * surface-charge update (eq. Poisson_BC3), and after the field solve the gap
+ * charge is re-imposed as C_gap phi0 (the circuit's increment history kept).
+ * Asynchronous.  Errors as gs_step_strict. */
+gs_status gs_step_weak(gs_ctx *ctx, int32_t n_steps);
+
+/* Read one gap's state (synchronises the stream).  phi (n_cells + 1 values),
+ * E (n_cells half-grid values E_{k+1/2}) and rho (n_cells + 1 nodal densities,
+ * electrode nodes already doubled) of the last solved level are written to the
+ * caller's host arrays when not NULL.  Errors: GS_EINVAL, GS_EDEVICE. */
+gs_status gs_read_diagnostics(gs_ctx *ctx, int32_t gap, gs_diag *out, double *phi, double *E,
+                              double *rho);
+
+/* Copy one gap's live particles of one species to host arrays in grid units:
+ * xi = x / dx, u = v_x dt / dx, as binary32 (particle_fp 32) or binary64 (64);
+ * id: their ids (0xFFFFFFFF for emitted electrons).  Order is unspecified.
+ * At most max_n are written; *n_out receives the live count.  Synchronises. */
+gs_status gs_read_particles(gs_ctx *ctx, int32_t gap, int32_t species, void *xi, void *u,
+                            uint32_t *id, int64_t max_n, int64_t *n_out);
+
+/* Tune or switch parts of the launch configuration (see GS_OPT_*). */
+gs_status gs_set_option(gs_ctx *ctx, int32_t option, int64_t value);
+
+/* Accumulated kernel timings since the last reset (synchronises); reset != 0
+ * clears them afterwards. */
+gs_status gs_get_timing(gs_ctx *ctx, gs_timing *out, int32_t reset);
+
+/* Check one gap's parameters on the host without touching a device.  On
+ * GS_EINVAL a message is written to msg (cap bytes, NUL-terminated). */
+gs_status gs_validate_params(const gs_gap_params *p, char *msg, size_t cap);
+
+/* Message of the last failed call on ctx ("" if none); with ctx NULL the last
+ * failed gs_init. */
+const char *gs_last_error(const gs_ctx *ctx);
+
+/* Library version string. */
+const char *gs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

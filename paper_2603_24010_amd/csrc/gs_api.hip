@@ -1,0 +1,765 @@
+// Host side of the C ABI (include/gapsim.h): parameter checks, the constant
+// circuit matrices of each gap, device memory, launch orchestration, readback.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gs_internal.h"
+
+using namespace gs;
+
+static thread_local std::string g_init_error;
+
+struct gs_ctx {
+  int G = 0;
+  int fp64 = 0;
+  int nmax = 0;
+  std::vector<gs_gap_params> params;
+  std::vector<GapConst> hc;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream graphs are captured on
+  gs_allocator alloc{nullptr, nullptr, nullptr};
+  std::vector<void *> blocks;
+  DevPtrs dp{};
+  LaunchCfg lc{};
+  int compact_every = 16;
+  int since_compact = 0;
+  int use_graph = 0;
+  int timing = 0;
+  double newton_tol = 1e-10;
+  int newton_maxit = 8;
+  int64_t steps_done = 0;
+  int64_t epoch = 0;
+  std::vector<int64_t> next_id;
+  std::string err;
+  int sticky = 0;  // gs_status of a device error already seen
+  // timing
+  struct Pend {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pend> pend;
+  std::vector<hipEvent_t> pool;
+  gs_timing tm{};
+  // graph cache: one captured chunk of `compact_every` steps per (mode, guess)
+  hipGraphExec_t gexec[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  int gexec_len[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  double *mlp_u = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+static gs_status fail(gs_ctx *c, gs_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c)
+    c->err = buf;
+  else
+    g_init_error = buf;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                                     \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(ctx, GS_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));            \
+  } while (0)
+
+static void *dev_alloc(gs_ctx *c, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  void *p = nullptr;
+  if (c->alloc.alloc) {
+    p = c->alloc.alloc(bytes, c->alloc.user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) c->blocks.push_back(p);
+  return p;
+}
+
+static void dev_free_all(gs_ctx *c) {
+  for (void *p : c->blocks) {
+    if (c->alloc.release)
+      c->alloc.release(p, c->alloc.user);
+    else if (!c->alloc.alloc)
+      (void)hipFree(p);
+  }
+  c->blocks.clear();
+}
+
+// Gauss-Jordan inverse in extended precision; returns false if singular
+static bool invert(int n, const long double *A, long double *Ainv) {
+  long double a[(MAXM + 1) * 2 * (MAXM + 1)];
+  const int w = 2 * n;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < w; ++j) a[i * w + j] = j < n ? A[i * n + j] : (j - n == i ? 1.0L : 0.0L);
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabsl(a[r * w + col]) > fabsl(a[piv * w + col])) piv = r;
+    if (a[piv * w + col] == 0.0L || !std::isfinite((double)a[piv * w + col])) return false;
+    if (piv != col)
+      for (int j = 0; j < w; ++j) std::swap(a[col * w + j], a[piv * w + j]);
+    long double d = a[col * w + col];
+    for (int j = 0; j < w; ++j) a[col * w + j] /= d;
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      long double f = a[r * w + col];
+      if (f == 0.0L) continue;
+      for (int j = 0; j < w; ++j) a[r * w + j] -= f * a[col * w + j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Ainv[i * n + j] = a[i * w + n + j];
+  return true;
+}
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+extern "C" gs_status gs_validate_params(const gs_gap_params *p, char *msg, size_t cap) {
+  auto bad = [&](const char *m) {
+    if (msg && cap) snprintf(msg, cap, "%s", m);
+    return GS_EINVAL;
+  };
+  if (!p) return bad("params is NULL");
+  if (p->particle_fp != 32 && p->particle_fp != 64) return bad("particle_fp must be 32 or 64");
+  const int nlim = p->particle_fp == 32 ? 16384 : 8192;
+  if (p->n_cells < 2 || p->n_cells > nlim) return bad("n_cells out of range (2..16384 fp32, 2..8192 fp64)");
+  if (!finite_pos(p->d) || !finite_pos(p->area) || !finite_pos(p->eps0) || !finite_pos(p->dt))
+    return bad("d, area, eps0 and dt must be finite and positive");
+  for (int s = 0; s < 2; ++s) {
+    if (p->Z[s] == 0 || p->Z[s] < -64 || p->Z[s] > 64) return bad("Z must be a nonzero integer in [-64, 64]");
+    if (!finite_pos(p->mass[s])) return bad("masses must be finite and positive");
+    if (p->capacity[s] < 0 || p->capacity[s] > (int64_t)0x7FFFFFFF) return bad("capacity out of range");
+  }
+  if (!finite_pos(p->q_unit) || !finite_pos(p->ev)) return bad("q_unit and ev must be positive");
+  if (!std::isfinite(p->weight) || p->weight < 0) return bad("weight must be finite and >= 0");
+  if (p->n_mesh < 1 || p->n_mesh > GS_MAX_MESH) return bad("n_mesh must be in 1..8");
+  if (p->gap_mesh < 0 || p->gap_mesh >= p->n_mesh) return bad("gap_mesh out of range");
+  if (!std::isfinite(p->c_par) || p->c_par < 0) return bad("c_par must be >= 0");
+  for (int i = 0; i < p->n_mesh; ++i) {
+    for (int j = 0; j < p->n_mesh; ++j)
+      if (!std::isfinite(p->L[i][j]) || !std::isfinite(p->R[i][j]) || !std::isfinite(p->S[i][j]))
+        return bad("circuit matrices must be finite");
+    if (!std::isfinite(p->src[i]) || !std::isfinite(p->q0[i])) return bad("src and q0 must be finite");
+  }
+  if (!std::isfinite(p->src_dc) || !std::isfinite(p->src_amp) || !std::isfinite(p->src_freq) ||
+      !std::isfinite(p->src_phase))
+    return bad("source parameters must be finite");
+  if (!std::isfinite(p->see_amp) || p->see_amp < 0) return bad("see_amp must be >= 0");
+  if (!finite_pos(p->see_E0_eV)) return bad("see_E0_eV must be positive");
+  if (p->see_law != GS_SEE_FIXED && p->see_law != GS_SEE_EXP) return bad("see_law must be FIXED or EXP");
+  if (p->see_max < 0 || p->see_max > 1024) return bad("see_max must be in 0..1024");
+  if (!std::isfinite(p->see_E_eV) || p->see_E_eV < 0) return bad("see_E_eV must be >= 0");
+  if (p->beam_per_step < 0 || p->beam_per_step > (int64_t)1 << 30) return bad("beam_per_step out of range");
+  if (p->beam_per_step > 0 &&
+      (!finite_pos(p->beam_Emin_eV) || !std::isfinite(p->beam_Emax_eV) || p->beam_Emax_eV < p->beam_Emin_eV))
+    return bad("beam energies must satisfy 0 < Emin <= Emax");
+  if (!finite_pos(p->v_ref)) return bad("v_ref must be positive");
+  if (p->particle_fp == 64 && p->capacity[0] + p->capacity[1] > ((int64_t)1 << 19))
+    return bad("particle_fp 64 holds at most 2^19 particles per gap (2^-44 weights in int64)");
+  return GS_OK;
+}
+
+// constant per-gap data: grid, species, and the circuit matrices (extended precision)
+static gs_status build_const(gs_ctx *ctx, int g, const gs_gap_params &p, GapConst &c) {
+  memset(&c, 0, sizeof c);
+  const int M = p.n_mesh;
+  c.N = p.n_cells;
+  c.M = M;
+  c.g = p.gap_mesh;
+  c.see_law = p.see_law;
+  c.see_max = p.see_max;
+  c.Z[0] = p.Z[0];
+  c.Z[1] = p.Z[1];
+  c.beam_n = p.beam_per_step;
+  c.cap[0] = p.capacity[0];
+  c.cap[1] = p.capacity[1];
+  c.seed = p.seed;
+  c.d = p.d;
+  c.dx = p.d / (double)p.n_cells;
+  c.A = p.area;
+  c.eps0 = p.eps0;
+  c.dt = p.dt;
+  c.cgap = p.eps0 * p.area / p.d;
+  c.c_par = p.c_par;
+  c.s0 = p.weight * p.q_unit;
+  for (int s = 0; s < 2; ++s) {
+    // velocity change (cells per step) per V/m: Z q dt^2 / (m dx)
+    c.alpha[s] = ((double)p.Z[s] * p.q_unit) * p.dt * p.dt / (p.mass[s] * c.dx);
+    c.mass[s] = p.mass[s];
+  }
+  c.ev = p.ev;
+  c.see_amp = p.see_amp;
+  c.see_E0 = p.see_E0_eV;
+  c.see_E = p.see_E_eV;
+  c.beam_Emin = p.beam_Emin_eV;
+  c.beam_Emax = p.beam_Emax_eV;
+  c.v_ref = p.v_ref;
+  c.src_dc = p.src_dc;
+  c.src_amp = p.src_amp;
+  c.src_w = 2.0 * M_PI * p.src_freq;
+  c.src_phase = p.src_phase;
+
+  // T' = 9 L / (4 dt^2) + 3 R / (2 dt) + S (gap row without the gap capacitor),
+  // Tw = T' + e_g e_g^T / (C_gap + c_par) (gap as a capacitor, weak mode)
+  const long double dt = p.dt;
+  const long double cg = (long double)c.cgap + (long double)p.c_par;
+  long double Tp[MAXM * MAXM], Tw[MAXM * MAXM], Ti[MAXM * MAXM], Twi[MAXM * MAXM];
+  for (int i = 0; i < M; ++i)
+    for (int j = 0; j < M; ++j) {
+      Tp[i * M + j] = 9.0L * p.L[i][j] / (4.0L * dt * dt) + 3.0L * p.R[i][j] / (2.0L * dt) + p.S[i][j];
+      Tw[i * M + j] = Tp[i * M + j] + ((i == c.g && j == c.g) ? 1.0L / cg : 0.0L);
+    }
+  if (!invert(M, Tp, Ti)) return fail(ctx, GS_EINVAL, "gap %d: strict circuit matrix is singular", g);
+  if (!invert(M, Tw, Twi)) return fail(ctx, GS_EINVAL, "gap %d: circuit matrix is singular", g);
+  for (int i = 0; i < M; ++i) {
+    long double sb = 0, sz = 0, wb = 0;
+    for (int j = 0; j < M; ++j) {
+      long double aL = 0, aR = 0, aS = 0, bL = 0, bR = 0, bS = 0;
+      for (int k = 0; k < M; ++k) {
+        aL += Ti[i * M + k] * p.L[k][j];
+        aR += Ti[i * M + k] * p.R[k][j];
+        aS += Ti[i * M + k] * p.S[k][j];
+        bL += Twi[i * M + k] * p.L[k][j];
+        bR += Twi[i * M + k] * p.R[k][j];
+        long double sw = p.S[k][j] + ((k == c.g && j == c.g) ? 1.0L / cg : 0.0L);
+        bS += Twi[i * M + k] * sw;
+      }
+      c.sL[i * MAXM + j] = (double)(aL / (4.0L * dt * dt));
+      c.sR[i * MAXM + j] = (double)(aR / (2.0L * dt));
+      c.sS[i * MAXM + j] = (double)aS;
+      c.wL[i * MAXM + j] = (double)(bL / (4.0L * dt * dt));
+      c.wR[i * MAXM + j] = (double)(bR / (2.0L * dt));
+      c.wS[i * MAXM + j] = (double)bS;
+      c.Tp[i * MAXM + j] = (double)Tp[i * M + j];
+      sb += Ti[i * M + j] * p.src[j];
+      wb += Twi[i * M + j] * p.src[j];
+    }
+    sz = Ti[i * M + c.g];
+    c.sb[i] = (double)sb;
+    c.sz[i] = (double)sz;
+    c.wb[i] = (double)wb;
+  }
+  // Newton Jacobian of r(u), u = (V, I_0..I_{M-1}) (see k_field)
+  const int nu = M + 1;
+  long double J[(MAXM + 1) * (MAXM + 1)], Ji[(MAXM + 1) * (MAXM + 1)];
+  const long double vr = p.v_ref;
+  const long double dfac = (long double)p.d / ((long double)p.eps0 * (long double)p.area);
+  for (int i = 0; i < nu * nu; ++i) J[i] = 0;
+  J[0] = (1.0L + dfac * p.c_par) / vr;
+  J[0 * nu + 1 + c.g] = -dfac * (2.0L * dt / 3.0L) / vr;
+  for (int i = 0; i < M; ++i) {
+    J[(1 + i) * nu + 0] = (i == c.g ? 1.0L : 0.0L) / vr;
+    for (int j = 0; j < M; ++j) J[(1 + i) * nu + 1 + j] = Tp[i * M + j] * (2.0L * dt / 3.0L) / vr;
+  }
+  if (!invert(nu, J, Ji)) return fail(ctx, GS_EINVAL, "gap %d: Newton Jacobian is singular", g);
+  for (int i = 0; i < nu; ++i)
+    for (int j = 0; j < nu; ++j) c.Jinv[i * (MAXM + 1) + j] = (double)Ji[i * nu + j];
+  return GS_OK;
+}
+
+static void init_state(const gs_gap_params &p, const GapConst &c, GapState &s) {
+  memset(&s, 0, sizeof s);
+  s.level = -1;
+  for (int j = 0; j < p.n_mesh; ++j) s.qprev[j] = p.q0[j];
+  // the gap's share of the gap-mesh charge sits on the electrode
+  const double qgap0 = p.q0[p.gap_mesh] * c.cgap / (c.cgap + p.c_par);
+  s.qcirc_prev = qgap0;
+  s.sigma_prev = qgap0 / p.area;
+  const double v0 = p.q0[p.gap_mesh] / (c.cgap + p.c_par);
+  for (int k = 0; k < 3; ++k) s.uh[k][0] = v0;
+  s.newton_last = -1;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" const char *gs_version(void) { return "gapsim 0.1 (gfx950)"; }
+
+extern "C" const char *gs_last_error(const gs_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+static gs_status setup(gs_ctx *ctx) {
+  const int G = ctx->G;
+  ctx->hc.resize(G);
+  size_t slots = 0, nodes = 0, etab = 0;
+  ctx->nmax = 0;
+  for (int g = 0; g < G; ++g) {
+    gs_status st = build_const(ctx, g, ctx->params[g], ctx->hc[g]);
+    if (st != GS_OK) return st;
+    GapConst &c = ctx->hc[g];
+    c.pbase[0] = (int64_t)slots;
+    slots += (size_t)c.cap[0];
+    c.pbase[1] = (int64_t)slots;
+    slots += (size_t)c.cap[1];
+    c.nbase = (int64_t)nodes;
+    nodes += (size_t)c.N + 1;
+    c.ebase = (int64_t)etab;
+    etab += (size_t)c.N + 2;
+    ctx->nmax = std::max(ctx->nmax, c.N);
+  }
+  const size_t ps = ctx->fp64 ? 8 : 4;
+  DevPtrs &d = ctx->dp;
+#define ALLOC(dst, type, count)                                                     \
+  do {                                                                              \
+    dst = (type)dev_alloc(ctx, (size_t)(count));                                    \
+    if (!dst) return fail(ctx, GS_ENOMEM, "device allocation of %zu bytes failed", \
+                          (size_t)(count));                                         \
+  } while (0)
+  for (int b = 0; b < 2; ++b) {
+    ALLOC(d.X[b], void *, slots * ps);
+    ALLOC(d.U[b], void *, slots * ps);
+    ALLOC(d.ID[b], uint32_t *, slots * 4);
+  }
+  ALLOC(d.next_count, unsigned long long *, (size_t)G * 2 * 8);
+  ALLOC(d.cursor, unsigned long long *, (size_t)G * 2 * 8);
+  ALLOC(d.tally, unsigned long long *, (size_t)G * T_N * 8);
+  ALLOC(d.acc, unsigned long long *, nodes * 8);
+  ALLOC(d.rho64, double *, nodes * 8);
+  ALLOC(d.E64, double *, nodes * 8);
+  ALLOC(d.phi64, double *, nodes * 8);
+  ALLOC(d.ehat, void *, etab * ps);
+  ALLOC(d.epoch, int64_t *, 8);
+  ALLOC(d.err, unsigned int *, 8);
+  ALLOC(d.gc, const GapConst *, sizeof(GapConst) * (size_t)G);
+  ALLOC(d.gs, GapState *, sizeof(GapState) * (size_t)G);
+  ALLOC(ctx->mlp_u, double *, sizeof(double) * (size_t)G * (MAXM + 1));
+#undef ALLOC
+  d.tile_prefix = nullptr;
+  d.done_counter = nullptr;
+  d.mlp_u = nullptr;
+  hipStream_t s = ctx->stream;
+  std::vector<GapState> hs(G);
+  for (int g = 0; g < G; ++g) init_state(ctx->params[g], ctx->hc[g], hs[g]);
+  HIPCHK(ctx, hipMemcpyAsync((void *)d.gc, ctx->hc.data(), sizeof(GapConst) * G, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemcpyAsync(d.gs, hs.data(), sizeof(GapState) * G, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemsetAsync(d.next_count, 0, (size_t)G * 2 * 8, s));
+  HIPCHK(ctx, hipMemsetAsync(d.cursor, 0, (size_t)G * 2 * 8, s));
+  HIPCHK(ctx, hipMemsetAsync(d.tally, 0, (size_t)G * T_N * 8, s));
+  HIPCHK(ctx, hipMemsetAsync(d.acc, 0, nodes * 8, s));
+  HIPCHK(ctx, hipMemsetAsync(d.rho64, 0, nodes * 8, s));
+  HIPCHK(ctx, hipMemsetAsync(d.E64, 0, nodes * 8, s));
+  HIPCHK(ctx, hipMemsetAsync(d.phi64, 0, nodes * 8, s));
+  HIPCHK(ctx, hipMemsetAsync(d.epoch, 0, 8, s));
+  const unsigned int err0[2] = {0u, 0xFFFFFFFFu};
+  HIPCHK(ctx, hipMemcpyAsync(d.err, err0, 8, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  ctx->next_id.assign(G, 0);
+  // launch shape: one persistent wave of workgroups sized by LDS occupancy
+  int dev = 0, ncu = 0;
+  HIPCHK(ctx, hipGetDevice(&dev));
+  HIPCHK(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  ctx->lc.fp64 = ctx->fp64;
+  ctx->lc.nmax = ctx->nmax;
+  const size_t lds = push_lds_bytes(ctx->nmax, ctx->fp64, G);
+  ctx->lc.block = lds > 65536 ? 1024 : 256;
+  const int per_cu_lds = (int)std::max<size_t>(1, 163840 / lds);
+  const int per_cu_thr = 2048 / ctx->lc.block;
+  ctx->lc.grid = std::max(1, ncu * std::min(per_cu_lds, per_cu_thr));
+  ctx->lc.tile = ctx->lc.block * (ctx->fp64 ? 2 : 4) * 2;
+  return GS_OK;
+}
+
+extern "C" gs_status gs_init(gs_ctx **out, int32_t n_gaps, const gs_gap_params *params,
+                             const gs_allocator *alloc, void *hip_stream) {
+  if (!out) return fail(nullptr, GS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_gaps < 1 || n_gaps > 16384 || !params) return fail(nullptr, GS_EINVAL, "n_gaps must be in 1..16384");
+  char msg[256];
+  for (int g = 0; g < n_gaps; ++g) {
+    if (gs_validate_params(&params[g], msg, sizeof msg) != GS_OK)
+      return fail(nullptr, GS_EINVAL, "gap %d: %s", g, msg);
+    if (params[g].particle_fp != params[0].particle_fp)
+      return fail(nullptr, GS_EINVAL, "all gaps of a context share particle_fp");
+  }
+  if (alloc && (!alloc->alloc || !alloc->release))
+    return fail(nullptr, GS_EINVAL, "allocator needs both alloc and release");
+  gs_ctx *ctx = new (std::nothrow) gs_ctx();
+  if (!ctx) return fail(nullptr, GS_ENOMEM, "out of host memory");
+  ctx->G = n_gaps;
+  ctx->fp64 = params[0].particle_fp == 64;
+  ctx->params.assign(params, params + n_gaps);
+  ctx->stream = (hipStream_t)hip_stream;
+  if (alloc) ctx->alloc = *alloc;
+  size_t lds = push_lds_bytes(0, ctx->fp64, n_gaps);
+  int nm = 0;
+  for (int g = 0; g < n_gaps; ++g) nm = std::max(nm, params[g].n_cells);
+  lds = push_lds_bytes(nm, ctx->fp64, n_gaps);
+  if (lds > 163840) {
+    delete ctx;
+    return fail(nullptr, GS_EINVAL, "grid of %d cells with %d gaps exceeds the 160 KiB LDS budget", nm, n_gaps);
+  }
+  gs_status st = setup(ctx);
+  if (st != GS_OK) {
+    g_init_error = ctx->err;
+    dev_free_all(ctx);
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return GS_OK;
+}
+
+extern "C" void gs_destroy(gs_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto &pe : ctx->pend) {
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+  for (int m = 0; m < 2; ++m)
+    for (int k = 0; k < 3; ++k)
+      if (ctx->gexec[m][k]) (void)hipGraphExecDestroy(ctx->gexec[m][k]);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  dev_free_all(ctx);
+  delete ctx;
+}
+
+static gs_status check_sticky(gs_ctx *ctx, bool sync) {
+  if (ctx->sticky) return (gs_status)ctx->sticky;
+  if (!sync) return GS_OK;
+  unsigned int e[2];
+  HIPCHK(ctx, hipMemcpyAsync(e, ctx->dp.err, 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (e[0] & ERR_CAPACITY) {
+    ctx->sticky = GS_ECAPACITY;
+    return fail(ctx, GS_ECAPACITY, "gap %u ran out of particle slots", e[1]);
+  }
+  if (e[0] & ERR_BADINJECT) {
+    ctx->sticky = GS_EINVAL;
+    return fail(ctx, GS_EINVAL, "an injected position was outside [0, d]");
+  }
+  return GS_OK;
+}
+
+extern "C" gs_status gs_inject(gs_ctx *ctx, int32_t gap, int32_t species, int64_t n, const double *x,
+                               const double *v, int32_t ptr_is_device) {
+  if (!ctx) return GS_ESTATE;
+  if (gap < 0 || gap >= ctx->G || species < 0 || species > 1 || n < 0)
+    return fail(ctx, GS_EINVAL, "bad gap, species or count");
+  if (n == 0) return GS_OK;
+  if (!x || !v) return fail(ctx, GS_EINVAL, "x and v must not be NULL");
+  gs_status st = check_sticky(ctx, false);
+  if (st != GS_OK) return st;
+  const double d = ctx->params[gap].d;
+  const double *xd = x, *vd = v;
+  void *tmp = nullptr;
+  if (!ptr_is_device) {
+    for (int64_t i = 0; i < n; ++i)
+      if (!(x[i] >= 0.0 && x[i] <= d) || !std::isfinite(v[i]))
+        return fail(ctx, GS_EINVAL, "particle %lld: x outside [0, d] or v not finite", (long long)i);
+    HIPCHK(ctx, hipMalloc(&tmp, (size_t)n * 16));
+    HIPCHK(ctx, hipMemcpyAsync(tmp, x, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync((char *)tmp + (size_t)n * 8, v, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream));
+    xd = (const double *)tmp;
+    vd = (const double *)((char *)tmp + (size_t)n * 8);
+  }
+  hipError_t e = launch_inject(ctx->dp, gap, species, n, xd, vd, ctx->next_id[gap], ctx->fp64, ctx->stream);
+  ctx->next_id[gap] += n;
+  if (tmp) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(tmp);
+  }
+  if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "inject launch: %s", hipGetErrorString(e));
+  return check_sticky(ctx, true);
+}
+
+static hipEvent_t ev_get(gs_ctx *ctx) {
+  if (!ctx->pool.empty()) {
+    hipEvent_t e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+template <class F>
+static hipError_t timed(gs_ctx *ctx, int kind, F &&launch) {
+  if (!ctx->timing) return launch();
+  hipEvent_t a = ev_get(ctx), b = ev_get(ctx);
+  (void)hipEventRecord(a, ctx->stream);
+  hipError_t e = launch();
+  (void)hipEventRecord(b, ctx->stream);
+  ctx->pend.push_back({kind, a, b});
+  return e;
+}
+
+static gs_status one_step(gs_ctx *ctx, int mode, int guess) {
+  hipError_t e = timed(ctx, 1, [&] {
+    return launch_field(ctx->dp, ctx->G, mode, guess, ctx->newton_tol, ctx->newton_maxit, ctx->fp64,
+                        ctx->stream);
+  });
+  if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "field launch: %s", hipGetErrorString(e));
+  e = timed(ctx, 0, [&] { return launch_push(ctx->dp, ctx->G, ctx->lc, ctx->stream); });
+  if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "push launch: %s", hipGetErrorString(e));
+  ctx->since_compact += 1;
+  if (ctx->since_compact >= ctx->compact_every) {
+    e = timed(ctx, 2, [&] { return launch_compact(ctx->dp, ctx->G, ctx->lc, ctx->stream); });
+    if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "compact launch: %s", hipGetErrorString(e));
+    ctx->since_compact = 0;
+    ctx->epoch += 1;
+  }
+  ctx->steps_done += 1;
+  for (int g = 0; g < ctx->G; ++g) ctx->next_id[g] += ctx->params[g].beam_per_step;
+  return GS_OK;
+}
+
+static gs_status run_steps(gs_ctx *ctx, int n_steps, int mode, int guess) {
+  if (!ctx) return GS_ESTATE;
+  if (n_steps < 0) return fail(ctx, GS_EINVAL, "n_steps < 0");
+  gs_status st = check_sticky(ctx, false);
+  if (st != GS_OK) return st;
+  if (guess == GS_GUESS_MLP) ctx->dp.mlp_u = ctx->mlp_u;
+  int left = n_steps;
+  // graph replay: whole chunks that start right after a compaction
+  if (ctx->use_graph && !ctx->timing) {
+    while (left > 0 && ctx->since_compact != 0) {
+      if ((st = one_step(ctx, mode, guess)) != GS_OK) return st;
+      --left;
+    }
+    const int L = ctx->compact_every;
+    while (left >= L) {
+      hipGraphExec_t &ge = ctx->gexec[mode][guess];
+      if (!ge || ctx->gexec_len[mode][guess] != L) {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        ge = nullptr;
+        // capture on a private stream (the caller's may be the legacy default
+        // stream, which cannot be captured); replay on the caller's stream
+        if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        hipStream_t cs = ctx->cap_stream;
+        hipGraph_t graph = nullptr;
+        HIPCHK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        hipError_t e1 = hipSuccess, e2 = hipSuccess, e3 = hipSuccess;
+        for (int k = 0; k < L && e1 == hipSuccess && e2 == hipSuccess; ++k) {
+          e1 = launch_field(ctx->dp, ctx->G, mode, guess, ctx->newton_tol, ctx->newton_maxit, ctx->fp64, cs);
+          if (e1 == hipSuccess) e2 = launch_push(ctx->dp, ctx->G, ctx->lc, cs);
+        }
+        if (e1 == hipSuccess && e2 == hipSuccess) e3 = launch_compact(ctx->dp, ctx->G, ctx->lc, cs);
+        hipError_t ec = hipStreamEndCapture(cs, &graph);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || ec != hipSuccess || !graph) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return fail(ctx, GS_EDEVICE, "graph capture failed (%s)",
+                      hipGetErrorString(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3 != hipSuccess ? e3 : ec));
+        }
+        hipError_t ei = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(ctx, GS_EDEVICE, "graph instantiate: %s", hipGetErrorString(ei));
+        ctx->gexec_len[mode][guess] = L;
+      }
+      HIPCHK(ctx, hipGraphLaunch(ge, ctx->stream));
+      left -= L;
+      ctx->steps_done += L;
+      ctx->epoch += 1;
+      for (int g = 0; g < ctx->G; ++g) ctx->next_id[g] += (int64_t)L * ctx->params[g].beam_per_step;
+    }
+  }
+  while (left > 0) {
+    if ((st = one_step(ctx, mode, guess)) != GS_OK) return st;
+    --left;
+  }
+  return GS_OK;
+}
+
+extern "C" gs_status gs_step_strict(gs_ctx *ctx, int32_t n_steps, int32_t guess) {
+  if (!ctx) return GS_ESTATE;
+  if (guess < GS_GUESS_DIRECT || guess > GS_GUESS_MLP) return fail(ctx, GS_EINVAL, "bad guess mode");
+  return run_steps(ctx, n_steps, 0, guess);
+}
+
+extern "C" gs_status gs_step_weak(gs_ctx *ctx, int32_t n_steps) {
+  if (!ctx) return GS_ESTATE;
+  return run_steps(ctx, n_steps, 1, GS_GUESS_DIRECT);
+}
+
+extern "C" gs_status gs_read_diagnostics(gs_ctx *ctx, int32_t gap, gs_diag *out, double *phi, double *E,
+                                         double *rho) {
+  if (!ctx) return GS_ESTATE;
+  if (gap < 0 || gap >= ctx->G || !out) return fail(ctx, GS_EINVAL, "bad gap or out is NULL");
+  const GapConst &c = ctx->hc[gap];
+  GapState s;
+  unsigned long long tl[T_N], nc[2];
+  hipStream_t st = ctx->stream;
+  if (phi) {
+    hipError_t e = launch_phi(ctx->dp, gap, st);
+    if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "phi launch: %s", hipGetErrorString(e));
+  }
+  HIPCHK(ctx, hipMemcpyAsync(&s, ctx->dp.gs + gap, sizeof s, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(tl, ctx->dp.tally + (size_t)gap * T_N, sizeof tl, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(nc, ctx->dp.next_count + gap * 2, sizeof nc, hipMemcpyDeviceToHost, st));
+  const size_t nn = (size_t)c.N + 1;
+  if (phi) HIPCHK(ctx, hipMemcpyAsync(phi, ctx->dp.phi64 + c.nbase, nn * 8, hipMemcpyDeviceToHost, st));
+  if (E) HIPCHK(ctx, hipMemcpyAsync(E, ctx->dp.E64 + c.nbase, (nn - 1) * 8, hipMemcpyDeviceToHost, st));
+  if (rho) HIPCHK(ctx, hipMemcpyAsync(rho, ctx->dp.rho64 + c.nbase, nn * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  memset(out, 0, sizeof *out);
+  out->step = s.level;
+  out->t = s.t;
+  out->phi0 = s.phi0;
+  out->sigma = s.sigma;
+  out->qcirc = s.qcirc;
+  out->qcirc_star = s.qcirc_star;
+  out->qconv = s.qconv;
+  out->e_ground = s.e_ground;
+  for (int j = 0; j < c.M; ++j) {
+    out->q[j] = s.q[j];
+    out->I[j] = s.I[j];
+  }
+  // the last push's tallies are folded into the state by the next field solve;
+  // combine them here
+  const long long ab[4] = {(long long)tl[T_ABS], (long long)tl[T_ABS + 1], (long long)tl[T_ABS + 2],
+                           (long long)tl[T_ABS + 3]};
+  const long long em[2] = {(long long)tl[T_EMIT], (long long)tl[T_EMIT + 1]};
+  for (int sp = 0; sp < 2; ++sp)
+    for (int w = 0; w < 2; ++w) {
+      out->abs_step[sp][w] = ab[sp * 2 + w];
+      out->abs_cum[sp][w] = s.abs_cum[sp * 2 + w] + ab[sp * 2 + w];
+    }
+  for (int w = 0; w < 2; ++w) {
+    out->emit_step[w] = em[w];
+    out->emit_cum[w] = s.emit_cum[w] + em[w];
+  }
+  out->inj_step = (long long)tl[T_INJ];
+  out->inj_cum = s.inj_cum + (long long)tl[T_INJ];
+  out->pushed_cum = s.pushed_cum + (long long)tl[T_PUSHED];
+  out->n_live[0] = s.live[0] + em[0] + em[1] - ab[0] - ab[1];
+  out->n_live[1] = s.live[1] + (long long)tl[T_INJ] - ab[2] - ab[3];
+  out->n_slots[0] = (long long)nc[0];
+  out->n_slots[1] = (long long)nc[1];
+  out->newton_last = s.newton_last;
+  out->newton_fallback_last = s.newton_fb_last;
+  out->newton_total = s.newton_total;
+  out->newton_fallbacks = s.newton_fallbacks;
+  out->newton_resid0 = s.newton_r0;
+  out->newton_resid = s.newton_r;
+  return check_sticky(ctx, true);
+}
+
+extern "C" gs_status gs_read_particles(gs_ctx *ctx, int32_t gap, int32_t species, void *xi, void *u,
+                                       uint32_t *id, int64_t max_n, int64_t *n_out) {
+  if (!ctx) return GS_ESTATE;
+  if (gap < 0 || gap >= ctx->G || species < 0 || species > 1 || max_n < 0)
+    return fail(ctx, GS_EINVAL, "bad gap, species or max_n");
+  const GapConst &c = ctx->hc[gap];
+  unsigned long long nc = 0;
+  int64_t ep = 0;
+  HIPCHK(ctx, hipMemcpyAsync(&nc, ctx->dp.next_count + gap * 2 + species, 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(&ep, ctx->dp.epoch, 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  const int sel = (int)(ep & 1);
+  const size_t n = std::min<size_t>((size_t)nc, (size_t)c.cap[species]);
+  const size_t ps = ctx->fp64 ? 8 : 4;
+  std::vector<unsigned char> hx(n * ps), hu(n * ps);
+  std::vector<uint32_t> hid(n);
+  const size_t off = (size_t)c.pbase[species];
+  if (n) {
+    HIPCHK(ctx, hipMemcpy(hx.data(), (char *)ctx->dp.X[sel] + off * ps, n * ps, hipMemcpyDeviceToHost));
+    HIPCHK(ctx, hipMemcpy(hu.data(), (char *)ctx->dp.U[sel] + off * ps, n * ps, hipMemcpyDeviceToHost));
+    HIPCHK(ctx, hipMemcpy(hid.data(), ctx->dp.ID[sel] + off, n * 4, hipMemcpyDeviceToHost));
+  }
+  int64_t live = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const bool alive = ctx->fp64 ? ((double *)hx.data())[i] >= 0.0 : ((float *)hx.data())[i] >= 0.0f;
+    if (!alive) continue;
+    if (live < max_n) {
+      if (xi) memcpy((char *)xi + live * ps, hx.data() + i * ps, ps);
+      if (u) memcpy((char *)u + live * ps, hu.data() + i * ps, ps);
+      if (id) id[live] = hid[i];
+    }
+    ++live;
+  }
+  if (n_out) *n_out = live;
+  return check_sticky(ctx, true);
+}
+
+extern "C" gs_status gs_set_option(gs_ctx *ctx, int32_t option, int64_t value) {
+  if (!ctx) return GS_ESTATE;
+  switch (option) {
+    case GS_OPT_BLOCK:
+      if (value != 256 && value != 512 && value != 1024) return fail(ctx, GS_EINVAL, "block must be 256, 512 or 1024");
+      if (push_lds_bytes(ctx->nmax, ctx->fp64, ctx->G) > 65536 && value < 1024) {
+        // a block that needs more than 64 KiB of LDS runs alone on its CU
+      }
+      ctx->lc.block = (int)value;
+      if (ctx->lc.tile % ctx->lc.block) ctx->lc.tile = ctx->lc.block * (ctx->fp64 ? 2 : 4);
+      break;
+    case GS_OPT_TILE:
+      if (value < ctx->lc.block || value % ctx->lc.block || value > (1 << 24))
+        return fail(ctx, GS_EINVAL, "tile must be a positive multiple of the block size");
+      ctx->lc.tile = (int)value;
+      break;
+    case GS_OPT_GRID: {
+      if (value < 0 || value > 1 << 20) return fail(ctx, GS_EINVAL, "grid out of range");
+      if (value == 0) {
+        int dev = 0, ncu = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        const size_t lds = push_lds_bytes(ctx->nmax, ctx->fp64, ctx->G);
+        const int per_cu = std::min((int)std::max<size_t>(1, 163840 / lds), 2048 / ctx->lc.block);
+        value = (int64_t)ncu * per_cu;
+      }
+      ctx->lc.grid = (int)value;
+      break;
+    }
+    case GS_OPT_COMPACT_EVERY:
+      if (value < 1 || value > 1 << 20) return fail(ctx, GS_EINVAL, "compact_every must be >= 1");
+      ctx->compact_every = (int)value;
+      break;
+    case GS_OPT_GRAPH:
+      ctx->use_graph = value ? 1 : 0;
+      break;
+    case GS_OPT_TIMING:
+      ctx->timing = value ? 1 : 0;
+      break;
+    case GS_OPT_NEWTON_TOL:
+      if (value <= 0) return fail(ctx, GS_EINVAL, "tolerance must be positive");
+      ctx->newton_tol = (double)value * 1e-12;
+      break;
+    case GS_OPT_NEWTON_MAXIT:
+      if (value < 0 || value > 64) return fail(ctx, GS_EINVAL, "maxit must be in 0..64");
+      ctx->newton_maxit = (int)value;
+      break;
+    default:
+      return fail(ctx, GS_EINVAL, "unknown option %d", option);
+  }
+  return GS_OK;
+}
+
+extern "C" gs_status gs_get_timing(gs_ctx *ctx, gs_timing *out, int32_t reset) {
+  if (!ctx || !out) return GS_ESTATE;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto &pe : ctx->pend) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, pe.a, pe.b);
+    if (pe.kind == 0) {
+      ctx->tm.push_ms += ms;
+      ctx->tm.push_launches += 1;
+    } else if (pe.kind == 1) {
+      ctx->tm.field_ms += ms;
+      ctx->tm.field_launches += 1;
+    } else {
+      ctx->tm.compact_ms += ms;
+      ctx->tm.compact_launches += 1;
+    }
+    ctx->pool.push_back(pe.a);
+    ctx->pool.push_back(pe.b);
+  }
+  ctx->pend.clear();
+  *out = ctx->tm;
+  if (reset) memset(&ctx->tm, 0, sizeof ctx->tm);
+  return GS_OK;
+}

@@ -1,0 +1,120 @@
+// Private definitions shared by the library's host and device sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gapsim.h"
+
+namespace gs {
+
+constexpr int MAXM = GS_MAX_MESH;
+constexpr uint32_t NO_ID = 0xFFFFFFFFu;
+// fixed-point charge weights: a macroparticle is 2^F units
+constexpr int F32_BITS = 24;
+constexpr int F64_BITS = 44;
+// tallies per gap, filled by the push and folded into the state by the field solve
+enum {
+  T_ABS = 0,      // [s*2 + wall], 4 entries
+  T_EMIT = 4,     // [wall], 2 entries
+  T_INJ = 6,
+  T_PUSHED = 7,   // live particles pushed
+  T_N = 8
+};
+
+// Per-gap constants (read-only on the device).
+struct GapConst {
+  int32_t N;          // cells
+  int32_t M, g;       // meshes, gap mesh
+  int32_t see_law, see_max;
+  int32_t Z[2];
+  int32_t pad0;
+  int64_t beam_n;
+  int64_t cap[2];
+  int64_t pbase[2];   // first particle slot of species s
+  int64_t nbase;      // offset of the node arrays (N + 1 entries)
+  int64_t ebase;      // offset of the binary32/64 field table (N + 2 entries)
+  uint64_t seed;
+  double d, dx, A, eps0, dt, cgap, c_par;
+  double s0;           // sheet charge per unit of Z: weight * q_unit [C/m^2]
+  double alpha[2];     // Z q dt^2 / (m dx): velocity change in cells/step per V/m
+  double mass[2], ev;
+  double see_amp, see_E0, see_E;
+  double beam_Emin, beam_Emax;
+  double v_ref;
+  double src_dc, src_amp, src_w, src_phase;
+  // strict: D = sL h + sR D1 - sS q1 + sb Vs - sz phi0     (h = 15 D1 - 7 D2 + D3)
+  double sL[MAXM * MAXM], sR[MAXM * MAXM], sS[MAXM * MAXM], sb[MAXM], sz[MAXM];
+  // weak: D* = wL h + wR D1 - wS q1 + wb Vs
+  double wL[MAXM * MAXM], wR[MAXM * MAXM], wS[MAXM * MAXM], wb[MAXM];
+  // T' itself (loop equations in volts for the Newton residual)
+  double Tp[MAXM * MAXM];
+  // Newton on u = (V, I_0..I_{M-1}): the residual is affine in u, so its
+  // Jacobian J is constant; Jinv row-major (M+1)^2
+  double Jinv[(MAXM + 1) * (MAXM + 1)];
+};
+
+// Per-gap mutable state (device).
+struct GapState {
+  int64_t level;        // last solved level (-1 before the first step)
+  int64_t seen_epoch;   // compaction epoch already applied to this gap
+  int64_t count[2];     // slots the current push sweeps, per species
+  int64_t live[2];      // live particles after the last push, per species
+  int64_t next_id;      // next particle id
+  int64_t beam_id0;     // id of beam particle 0 of the current push
+  double qprev[MAXM];   // loop charges q^{n-1}
+  double dq[3][MAXM];   // increments D^{n-1}, D^{n-2}, D^{n-3}
+  double sigma_prev, qcirc_prev;
+  // u = (V, I) history for the Newton guess
+  double uh[3][MAXM + 1];
+  // diagnostics of the last solved level
+  double t, phi0, sigma, qcirc, qcirc_star, qconv, e_ground;
+  double q[MAXM], I[MAXM];
+  int64_t abs_last[4], emit_last[2], inj_last, pushed_last;
+  int64_t abs_cum[4], emit_cum[2], inj_cum, pushed_cum;
+  int32_t newton_last, newton_fb_last;
+  int64_t newton_total, newton_fallbacks;
+  double newton_r0, newton_r;
+};
+
+// Context-wide device pointers handed to kernels.
+struct DevPtrs {
+  const GapConst *gc;
+  GapState *gs;
+  // particle slots, two buffers selected by compaction epoch parity
+  void *X[2], *U[2];
+  uint32_t *ID[2];
+  unsigned long long *next_count;  // [G][2] append cursor
+  unsigned long long *cursor;      // [G][2] compaction destination cursor
+  unsigned long long *tally;       // [G][T_N]
+  unsigned long long *acc;         // node charge accumulators, int64 two's complement
+  double *rho64, *E64, *phi64;     // node / half-grid / node arrays (nbase offsets; E uses nbase too)
+  void *ehat;                      // field table for the push, binary32 or binary64
+  int64_t *epoch;                  // compaction epoch (device)
+  int32_t *tile_prefix;            // [G + 1] push work tiles per gap, prefix
+  unsigned int *done_counter;      // for the last-block pattern of the field kernel
+  unsigned int *err;               // [0] flags, [1] gap of first error
+  const double *mlp_u;             // [G][MAXM+1] MLP guesses (or null)
+};
+
+enum { ERR_CAPACITY = 1u, ERR_BADINJECT = 2u, ERR_NOCONV = 4u };
+
+struct LaunchCfg {
+  int block;      // push block size
+  int tile;       // particles per tile
+  int grid;       // push blocks
+  int nmax;       // largest n_cells of the context
+  int fp64;       // particle precision
+};
+
+// launchers (gs_kernels.hip)
+hipError_t launch_field(const DevPtrs &p, int G, int mode, int guess, double newton_tol,
+                        int newton_maxit, int fp64, hipStream_t s);
+hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s);
+hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s);
+hipError_t launch_inject(const DevPtrs &p, int gap, int species, long long n, const double *x_dev,
+                         const double *v_dev, long long id0, int fp64, hipStream_t s);
+hipError_t launch_phi(const DevPtrs &p, int gap, hipStream_t s);
+size_t push_lds_bytes(int nmax, int fp64, int G);
+
+}  // namespace gs

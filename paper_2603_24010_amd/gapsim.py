@@ -1,0 +1,306 @@
+"""Thin ctypes binding of libgapsim.so (the C ABI in include/gapsim.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch supplies device memory (its caching allocator, through the
+library's allocator hook) and the stream.  There is no CPU fallback: if the
+library is missing or no GPU is present, construction fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, List, Optional, Sequence, Union
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgapsim.so")
+MAX_MESH = 8
+
+GS_OK, GS_EINVAL, GS_ENOMEM, GS_ECAPACITY, GS_EDEVICE, GS_ENOCONV, GS_ESTATE = 0, -1, -2, -3, -4, -5, -6
+GUESS_DIRECT, GUESS_EXTRAP, GUESS_MLP = 0, 1, 2
+OPT_BLOCK, OPT_TILE, OPT_GRID, OPT_COMPACT_EVERY, OPT_GRAPH, OPT_TIMING = 1, 2, 3, 4, 5, 6
+OPT_NEWTON_TOL, OPT_NEWTON_MAXIT = 7, 8
+
+EXPORTED = [
+    "gs_init", "gs_destroy", "gs_inject", "gs_step_strict", "gs_step_weak", "gs_read_diagnostics",
+    "gs_read_particles", "gs_set_option", "gs_get_timing", "gs_validate_params", "gs_last_error",
+    "gs_version",
+]
+
+Mat = (C.c_double * MAX_MESH) * MAX_MESH
+
+
+class GsGapParams(C.Structure):
+    _fields_ = [
+        ("n_cells", C.c_int32),
+        ("d", C.c_double), ("area", C.c_double), ("eps0", C.c_double), ("dt", C.c_double),
+        ("Z", C.c_int32 * 2),
+        ("mass", C.c_double * 2),
+        ("q_unit", C.c_double), ("weight", C.c_double), ("ev", C.c_double),
+        ("n_mesh", C.c_int32), ("gap_mesh", C.c_int32),
+        ("L", Mat), ("R", Mat), ("S", Mat),
+        ("src", C.c_double * MAX_MESH),
+        ("src_dc", C.c_double), ("src_amp", C.c_double), ("src_freq", C.c_double),
+        ("src_phase", C.c_double),
+        ("c_par", C.c_double),
+        ("q0", C.c_double * MAX_MESH),
+        ("see_amp", C.c_double), ("see_E0_eV", C.c_double),
+        ("see_law", C.c_int32), ("see_max", C.c_int32),
+        ("see_E_eV", C.c_double),
+        ("beam_per_step", C.c_int64),
+        ("beam_Emin_eV", C.c_double), ("beam_Emax_eV", C.c_double),
+        ("seed", C.c_uint64),
+        ("particle_fp", C.c_int32),
+        ("capacity", C.c_int64 * 2),
+        ("v_ref", C.c_double),
+    ]
+
+
+class GsDiag(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("t", C.c_double), ("phi0", C.c_double), ("sigma", C.c_double),
+        ("qcirc", C.c_double), ("qcirc_star", C.c_double), ("qconv", C.c_double),
+        ("e_ground", C.c_double),
+        ("q", C.c_double * MAX_MESH), ("I", C.c_double * MAX_MESH),
+        ("n_live", C.c_int64 * 2), ("n_slots", C.c_int64 * 2),
+        ("abs_step", (C.c_int64 * 2) * 2), ("emit_step", C.c_int64 * 2), ("inj_step", C.c_int64),
+        ("abs_cum", (C.c_int64 * 2) * 2), ("emit_cum", C.c_int64 * 2), ("inj_cum", C.c_int64),
+        ("pushed_cum", C.c_int64),
+        ("newton_last", C.c_int32), ("newton_fallback_last", C.c_int32),
+        ("newton_total", C.c_int64), ("newton_fallbacks", C.c_int64),
+        ("newton_resid0", C.c_double), ("newton_resid", C.c_double),
+    ]
+
+
+class GsTiming(C.Structure):
+    _fields_ = [
+        ("push_ms", C.c_double), ("field_ms", C.c_double), ("compact_ms", C.c_double),
+        ("push_launches", C.c_int64), ("field_launches", C.c_int64), ("compact_launches", C.c_int64),
+    ]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class GsAllocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("user", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libgapsim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2603_24010_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, P = C.c_void_p, C.POINTER(C.c_double)
+        L.gs_init.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(GsGapParams), C.POINTER(GsAllocator), vp]
+        L.gs_init.restype = C.c_int
+        L.gs_destroy.argtypes = [vp]
+        L.gs_inject.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, vp, vp, C.c_int32]
+        L.gs_inject.restype = C.c_int
+        L.gs_step_strict.argtypes = [vp, C.c_int32, C.c_int32]
+        L.gs_step_strict.restype = C.c_int
+        L.gs_step_weak.argtypes = [vp, C.c_int32]
+        L.gs_step_weak.restype = C.c_int
+        L.gs_read_diagnostics.argtypes = [vp, C.c_int32, C.POINTER(GsDiag), P, P, P]
+        L.gs_read_diagnostics.restype = C.c_int
+        L.gs_read_particles.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, C.POINTER(C.c_uint32),
+                                        C.c_int64, C.POINTER(C.c_int64)]
+        L.gs_read_particles.restype = C.c_int
+        L.gs_set_option.argtypes = [vp, C.c_int32, C.c_int64]
+        L.gs_set_option.restype = C.c_int
+        L.gs_get_timing.argtypes = [vp, C.POINTER(GsTiming), C.c_int32]
+        L.gs_get_timing.restype = C.c_int
+        L.gs_validate_params.argtypes = [C.POINTER(GsGapParams), C.c_char_p, C.c_size_t]
+        L.gs_validate_params.restype = C.c_int
+        L.gs_last_error.argtypes = [vp]
+        L.gs_last_error.restype = C.c_char_p
+        L.gs_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+class GapsimError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gapsim status {status}: {msg}")
+        self.status = status
+
+
+def params_from(cfg, particle_fp: int = 32, capacity=(1 << 20, 1 << 20)) -> GsGapParams:
+    p = GsGapParams()
+    p.n_cells = cfg.n_cells
+    p.d, p.area, p.eps0, p.dt = cfg.d, cfg.area, cfg.eps0, cfg.dt
+    p.Z[0], p.Z[1] = int(cfg.Z[0]), int(cfg.Z[1])
+    p.mass[0], p.mass[1] = float(cfg.mass[0]), float(cfg.mass[1])
+    p.q_unit, p.weight, p.ev = cfg.q_unit, cfg.weight, cfg.ev
+    p.n_mesh, p.gap_mesh = cfg.n_mesh, cfg.gap_mesh
+    for i in range(cfg.n_mesh):
+        for j in range(cfg.n_mesh):
+            p.L[i][j] = float(cfg.L[i, j])
+            p.R[i][j] = float(cfg.R[i, j])
+            p.S[i][j] = float(cfg.S[i, j])
+        p.src[i] = float(cfg.src[i])
+        p.q0[i] = float(cfg.q0[i])
+    p.src_dc, p.src_amp, p.src_freq, p.src_phase = cfg.src_dc, cfg.src_amp, cfg.src_freq, cfg.src_phase
+    p.c_par = cfg.c_par
+    p.see_amp, p.see_E0_eV, p.see_law, p.see_max = cfg.see_amp, cfg.see_E0_eV, cfg.see_law, cfg.see_max
+    p.see_E_eV = cfg.see_E_eV
+    p.beam_per_step = cfg.beam_per_step
+    p.beam_Emin_eV, p.beam_Emax_eV = cfg.beam_Emin_eV, cfg.beam_Emax_eV
+    p.seed = cfg.seed
+    p.particle_fp = particle_fp
+    p.capacity[0], p.capacity[1] = int(capacity[0]), int(capacity[1])
+    p.v_ref = cfg.v_ref
+    return p
+
+
+def validate(cfg, particle_fp: int = 32, capacity=(1 << 20, 1 << 20)) -> Optional[str]:
+    """Host-only parameter check; returns None if valid, else the message."""
+    p = params_from(cfg, particle_fp, capacity)
+    buf = C.create_string_buffer(256)
+    rc = lib().gs_validate_params(C.byref(p), buf, 256)
+    return None if rc == GS_OK else buf.value.decode()
+
+
+class GapSim:
+    """Gaps advanced together on one GPU stream."""
+
+    def __init__(self, cfgs, particle_fp: int = 32, capacity=(1 << 20, 1 << 20),
+                 stream=None, torch_alloc: bool = True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("gapsim needs a ROCm GPU; none is visible")
+        if not isinstance(cfgs, (list, tuple)):
+            cfgs = [cfgs]
+        self.cfgs = list(cfgs)
+        self.G = len(cfgs)
+        self.fp64 = particle_fp == 64
+        caps = capacity if (isinstance(capacity, (list, tuple)) and len(capacity) == self.G
+                            and isinstance(capacity[0], (list, tuple))) else [capacity] * self.G
+        arr = (GsGapParams * self.G)()
+        for g, cfg in enumerate(cfgs):
+            arr[g] = params_from(cfg, particle_fp, caps[g])
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._alloc = None
+        alloc_p = None
+        if torch_alloc:
+            dev_index = self.device.index
+            stream_handle = self.stream
+
+            def _a(nbytes, user):
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev_index, stream_handle)
+
+            def _r(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc = GsAllocator(ALLOC_FN(_a), RELEASE_FN(_r), None)
+            alloc_p = C.byref(self._alloc)
+        h = C.c_void_p()
+        rc = lib().gs_init(C.byref(h), self.G, arr, alloc_p, C.c_void_p(self.stream.cuda_stream))
+        if rc != GS_OK:
+            raise GapsimError(rc, lib().gs_last_error(None).decode())
+        self._h = h
+
+    # -- helpers ----------------------------------------------------------
+    def _chk(self, rc: int):
+        if rc != GS_OK:
+            raise GapsimError(rc, lib().gs_last_error(self._h).decode())
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().gs_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the C ABI ----------------------------------------------------------
+    def inject(self, gap: int, species: int, x, v):
+        try:
+            import torch
+            is_dev = isinstance(x, torch.Tensor) and x.is_cuda
+        except ImportError:  # pragma: no cover
+            is_dev = False
+        if is_dev:
+            x = x.contiguous().to(dtype=torch.float64)
+            v = v.contiguous().to(dtype=torch.float64)
+            self._chk(lib().gs_inject(self._h, gap, species, x.numel(), C.c_void_p(x.data_ptr()),
+                                      C.c_void_p(v.data_ptr()), 1))
+        else:
+            x = np.ascontiguousarray(x, dtype=np.float64)
+            v = np.ascontiguousarray(v, dtype=np.float64)
+            self._chk(lib().gs_inject(self._h, gap, species, x.size, x.ctypes.data_as(C.c_void_p),
+                                      v.ctypes.data_as(C.c_void_p), 0))
+
+    def step_strict(self, n: int = 1, guess: int = GUESS_DIRECT):
+        self._chk(lib().gs_step_strict(self._h, n, guess))
+
+    def step_weak(self, n: int = 1):
+        self._chk(lib().gs_step_weak(self._h, n))
+
+    def step(self, mode: int, n: int = 1, guess: int = GUESS_DIRECT):
+        """mode 0 = strict, 1 = weak (the oracle's numbering)."""
+        if mode == 0:
+            self.step_strict(n, guess)
+        else:
+            self.step_weak(n)
+
+    def set_option(self, option: int, value: int):
+        self._chk(lib().gs_set_option(self._h, option, int(value)))
+
+    def diag(self, gap: int = 0) -> dict:
+        D = GsDiag()
+        self._chk(lib().gs_read_diagnostics(self._h, gap, C.byref(D), None, None, None))
+        M = self.cfgs[gap].n_mesh
+        return dict(step=D.step, t=D.t, phi0=D.phi0, sigma=D.sigma, qcirc=D.qcirc,
+                    qcirc_star=D.qcirc_star, qconv=D.qconv, e_ground=D.e_ground,
+                    q=np.array(D.q[:M]), I=np.array(D.I[:M]),
+                    n_live=np.array(D.n_live[:]), n_slots=np.array(D.n_slots[:]),
+                    abs_step=np.array([[D.abs_step[a][b] for b in range(2)] for a in range(2)]),
+                    emit_step=np.array(D.emit_step[:]), inj_step=D.inj_step,
+                    abs_cum=np.array([[D.abs_cum[a][b] for b in range(2)] for a in range(2)]),
+                    emit_cum=np.array(D.emit_cum[:]), inj_cum=D.inj_cum, pushed_cum=D.pushed_cum,
+                    newton_last=D.newton_last, newton_fallback_last=D.newton_fallback_last,
+                    newton_total=D.newton_total, newton_fallbacks=D.newton_fallbacks,
+                    newton_resid0=D.newton_resid0, newton_resid=D.newton_resid)
+
+    def fields(self, gap: int = 0):
+        N = self.cfgs[gap].n_cells
+        phi, E, rho = np.zeros(N + 1), np.zeros(N), np.zeros(N + 1)
+        D = GsDiag()
+        P = C.POINTER(C.c_double)
+        self._chk(lib().gs_read_diagnostics(self._h, gap, C.byref(D), phi.ctypes.data_as(P),
+                                            E.ctypes.data_as(P), rho.ctypes.data_as(P)))
+        return phi, E, rho
+
+    def particles(self, gap: int, species: int):
+        """Live particles in grid units (xi = x/dx, u = v dt/dx) and ids."""
+        n = C.c_int64(0)
+        self._chk(lib().gs_read_particles(self._h, gap, species, None, None, None, 0, C.byref(n)))
+        dt = np.float64 if self.fp64 else np.float32
+        xi, u = np.zeros(n.value, dtype=dt), np.zeros(n.value, dtype=dt)
+        ids = np.zeros(n.value, dtype=np.uint32)
+        m = C.c_int64(0)
+        self._chk(lib().gs_read_particles(self._h, gap, species, xi.ctypes.data_as(C.c_void_p),
+                                          u.ctypes.data_as(C.c_void_p),
+                                          ids.ctypes.data_as(C.POINTER(C.c_uint32)), n.value,
+                                          C.byref(m)))
+        return xi[:m.value], u[:m.value], ids[:m.value]
+
+    def timing(self, reset: bool = False) -> dict:
+        T = GsTiming()
+        self._chk(lib().gs_get_timing(self._h, C.byref(T), 1 if reset else 0))
+        return dict(push_ms=T.push_ms, field_ms=T.field_ms, compact_ms=T.compact_ms,
+                    push_launches=T.push_launches, field_launches=T.field_launches,
+                    compact_launches=T.compact_launches)
