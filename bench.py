@@ -87,10 +87,16 @@ def main():
     ap.add_argument("--workload", default="beam_gap_4096c_2e7p_weak", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--compact-every", type=int, default=16)
+    ap.add_argument("--compact-every", type=int, default=32)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--deposit", type=int, default=0, help="0 auto, 1 64-bit LDS cells, 2 32-bit")
+    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--ppt", type=int, default=0, help="16-byte particle vectors per thread (1, 2)")
+    ap.add_argument("--copy-reference-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (5 times): the "
+                         "reference that scales rocprof's FETCH_SIZE / WRITE_SIZE to bytes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this method has no multi-GPU path in this build "
@@ -100,6 +106,15 @@ def main():
     import torch
     from paper_2603_24010_amd import gapsim
     torch.cuda.set_device(0)
+    if args.copy_reference_mb:
+        n = args.copy_reference_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes_per_launch": 4 * n, "launches": 5}), flush=True)
+        return
     spec = WORKLOADS[args.workload]
     log(f"[bench] building workload {args.workload}")
     sim, cfg, _ = make_sim(args.workload, spec)
@@ -110,6 +125,10 @@ def main():
         sim.set_option(gapsim.OPT_TILE, args.tile)
     if args.grid:
         sim.set_option(gapsim.OPT_GRID, args.grid)
+    if args.deposit:
+        sim.set_option(gapsim.OPT_DEPOSIT, args.deposit)
+    if args.ppt:
+        sim.set_option(gapsim.OPT_PPT, args.ppt)
     mode = spec["mode"]
     log(f"[bench] warmup {args.warmup} steps")
     sim.step(mode, args.warmup)
@@ -156,6 +175,7 @@ def main():
                      "avg_launch_ms": tm["push_ms"] / max(1, tm["push_launches"]),
                      "launches": tm["push_launches"]},
         "kernel_ms_per_step": {"push": tm["push_ms"] / args.steps, "field": tm["field_ms"] / args.steps,
+                               "source": tm["source_ms"] / args.steps,
                                "compact": tm["compact_ms"] / args.steps},
     }
     sim.close()

@@ -139,20 +139,23 @@ typedef struct {
 /* Accumulated device time of the library's kernels, measured with HIP events
  * on the context's stream while timing is switched on (GS_OPT_TIMING). */
 typedef struct {
-  double push_ms, field_ms, compact_ms;
-  int64_t push_launches, field_launches, compact_launches;
+  double push_ms, field_ms, compact_ms, source_ms;
+  int64_t push_launches, field_launches, compact_launches, source_launches;
 } gs_timing;
 
 /* Options for gs_set_option. */
 enum {
   GS_OPT_BLOCK = 1,        /* push threads per block: 256, 512 or 1024 */
-  GS_OPT_TILE = 2,         /* particles per work tile (multiple of the block size) */
+  GS_OPT_TILE = 2,         /* particles per work tile (multiple of 8 x the block size) */
   GS_OPT_GRID = 3,         /* push blocks; 0 = from occupancy */
   GS_OPT_COMPACT_EVERY = 4,/* steps between reclaiming absorbed slots (>= 1) */
   GS_OPT_GRAPH = 5,        /* 1: replay steps through a captured hipGraph */
   GS_OPT_TIMING = 6,       /* 1: time each kernel launch with HIP events */
   GS_OPT_NEWTON_TOL = 7,   /* value * 1e-12 = scaled residual tolerance (default 1e-10) */
-  GS_OPT_NEWTON_MAXIT = 8
+  GS_OPT_NEWTON_MAXIT = 8,
+  GS_OPT_DEPOSIT = 9,      /* binary32 deposit cells: 0 auto, 1 64-bit, 2 32-bit with carries */
+  GS_OPT_COMPACT_GRID = 10,/* workgroups of the compaction kernel (>= 1) */
+  GS_OPT_PPT = 11          /* 16-byte particle vectors per thread per chunk: 1 or 2 */
 };
 
 typedef struct gs_ctx gs_ctx;

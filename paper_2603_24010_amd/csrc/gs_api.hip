@@ -27,12 +27,15 @@ struct gs_ctx {
   std::vector<void *> blocks;
   DevPtrs dp{};
   LaunchCfg lc{};
-  int compact_every = 16;
+  int compact_every = 32;
   int since_compact = 0;
   int use_graph = 0;
   int timing = 0;
   double newton_tol = 1e-10;
   int newton_maxit = 8;
+  int device = 0, ncu = 0;
+  int deposit_opt = 0;  // 0 auto, 1 wide, 2 carry
+  int grid_opt = 0;     // grid fixed by the caller
   int64_t steps_done = 0;
   int64_t epoch = 0;
   std::vector<int64_t> next_id;
@@ -291,21 +294,30 @@ extern "C" const char *gs_last_error(const gs_ctx *ctx) {
   return ctx ? ctx->err.c_str() : g_init_error.c_str();
 }
 
+static void choose_launch(gs_ctx *ctx);
+
 static gs_status setup(gs_ctx *ctx) {
   const int G = ctx->G;
   ctx->hc.resize(G);
-  size_t slots = 0, nodes = 0, etab = 0;
+  size_t slots = 0, nodes = 0, etab = 0, events = 0;
   ctx->nmax = 0;
   for (int g = 0; g < G; ++g) {
     gs_status st = build_const(ctx, g, ctx->params[g], ctx->hc[g]);
     if (st != GS_OK) return st;
     GapConst &c = ctx->hc[g];
+    // regions start on 64-slot boundaries: the push moves particles with
+    // 16-byte vector loads and stores
+    auto pad = [](size_t v) { return (v + 63) / 64 * 64; };
     c.pbase[0] = (int64_t)slots;
-    slots += (size_t)c.cap[0];
+    slots += pad((size_t)c.cap[0]);
     c.pbase[1] = (int64_t)slots;
-    slots += (size_t)c.cap[1];
+    slots += pad((size_t)c.cap[1]);
     c.nbase = (int64_t)nodes;
     nodes += (size_t)c.N + 1;
+    // absorbed-ion events of one push: up to an eighth of the ion slots
+    c.evbase = (int64_t)events;
+    c.evcap = (ctx->params[g].see_amp > 0.0) ? (int64_t)(c.cap[1] / 8 + 4096) : 0;
+    events += (size_t)c.evcap;
     c.ebase = (int64_t)etab;
     etab += (size_t)c.N + 2;
     ctx->nmax = std::max(ctx->nmax, c.N);
@@ -331,6 +343,8 @@ static gs_status setup(gs_ctx *ctx) {
   ALLOC(d.E64, double *, nodes * 8);
   ALLOC(d.phi64, double *, nodes * 8);
   ALLOC(d.ehat, void *, etab * ps);
+  ALLOC(d.ev, Event *, events * sizeof(Event));
+  ALLOC(d.ev_count, unsigned long long *, (size_t)G * 8);
   ALLOC(d.epoch, int64_t *, 8);
   ALLOC(d.err, unsigned int *, 8);
   ALLOC(d.gc, const GapConst *, sizeof(GapConst) * (size_t)G);
@@ -348,6 +362,7 @@ static gs_status setup(gs_ctx *ctx) {
   HIPCHK(ctx, hipMemsetAsync(d.next_count, 0, (size_t)G * 2 * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.cursor, 0, (size_t)G * 2 * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.tally, 0, (size_t)G * T_N * 8, s));
+  HIPCHK(ctx, hipMemsetAsync(d.ev_count, 0, (size_t)G * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.acc, 0, nodes * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.rho64, 0, nodes * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.E64, 0, nodes * 8, s));
@@ -357,19 +372,43 @@ static gs_status setup(gs_ctx *ctx) {
   HIPCHK(ctx, hipMemcpyAsync(d.err, err0, 8, hipMemcpyHostToDevice, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
   ctx->next_id.assign(G, 0);
-  // launch shape: one persistent wave of workgroups sized by LDS occupancy
-  int dev = 0, ncu = 0;
-  HIPCHK(ctx, hipGetDevice(&dev));
-  HIPCHK(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(ctx, hipGetDevice(&ctx->device));
+  HIPCHK(ctx, hipDeviceGetAttribute(&ctx->ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
   ctx->lc.fp64 = ctx->fp64;
   ctx->lc.nmax = ctx->nmax;
-  const size_t lds = push_lds_bytes(ctx->nmax, ctx->fp64, G);
-  ctx->lc.block = lds > 65536 ? 1024 : 256;
-  const int per_cu_lds = (int)std::max<size_t>(1, 163840 / lds);
-  const int per_cu_thr = 2048 / ctx->lc.block;
-  ctx->lc.grid = std::max(1, ncu * std::min(per_cu_lds, per_cu_thr));
-  ctx->lc.tile = ctx->lc.block * (ctx->fp64 ? 2 : 4) * 2;
+  ctx->lc.block = 512;
+  ctx->lc.tile = ctx->lc.block * 16;
+  ctx->lc.wide = 1;
+  ctx->lc.compact_grid = 4 * ctx->ncu;
+  ctx->lc.source_grid = ctx->ncu;
+  ctx->lc.ppt = ctx->fp64 ? 2 : 4;
+  choose_launch(ctx);
   return GS_OK;
+}
+
+// LDS of one push workgroup (dynamic part plus the static prefix-scan buffer)
+static size_t push_lds_total(const gs_ctx *ctx, int wide, int block) {
+  return push_lds_bytes(ctx->nmax, ctx->fp64, ctx->G, wide) + (size_t)block * 4;
+}
+
+// the deposit-cell width (auto: 64-bit cells whenever the grid fits) and a
+// persistent grid sized by LDS and thread occupancy
+static void choose_launch(gs_ctx *ctx) {
+  const size_t lds_cap = 163840;
+  int wide = 1;
+  if (!ctx->fp64) {
+    if (ctx->deposit_opt == 2 || (ctx->deposit_opt == 0 && push_lds_total(ctx, 1, ctx->lc.block) > lds_cap))
+      wide = 0;
+  }
+  ctx->lc.wide = wide;
+  const size_t lds = push_lds_total(ctx, wide, ctx->lc.block);
+  const int per_cu_lds = (int)std::max<size_t>(1, lds_cap / lds);
+  const int per_cu_thr = std::max(1, 2048 / ctx->lc.block);
+  if (!ctx->grid_opt) ctx->lc.grid = std::max(1, ctx->ncu * std::min(per_cu_lds, per_cu_thr));
+}
+
+static bool launch_fits(const gs_ctx *ctx) {
+  return push_lds_total(ctx, ctx->lc.wide, ctx->lc.block) <= 163840;
 }
 
 extern "C" gs_status gs_init(gs_ctx **out, int32_t n_gaps, const gs_gap_params *params,
@@ -393,10 +432,9 @@ extern "C" gs_status gs_init(gs_ctx **out, int32_t n_gaps, const gs_gap_params *
   ctx->params.assign(params, params + n_gaps);
   ctx->stream = (hipStream_t)hip_stream;
   if (alloc) ctx->alloc = *alloc;
-  size_t lds = push_lds_bytes(0, ctx->fp64, n_gaps);
   int nm = 0;
   for (int g = 0; g < n_gaps; ++g) nm = std::max(nm, params[g].n_cells);
-  lds = push_lds_bytes(nm, ctx->fp64, n_gaps);
+  const size_t lds = push_lds_bytes(nm, ctx->fp64, n_gaps, ctx->fp64) + 256 * 4;
   if (lds > 163840) {
     delete ctx;
     return fail(nullptr, GS_EINVAL, "grid of %d cells with %d gaps exceeds the 160 KiB LDS budget", nm, n_gaps);
@@ -502,11 +540,13 @@ static hipError_t timed(gs_ctx *ctx, int kind, F &&launch) {
 static gs_status one_step(gs_ctx *ctx, int mode, int guess) {
   hipError_t e = timed(ctx, 1, [&] {
     return launch_field(ctx->dp, ctx->G, mode, guess, ctx->newton_tol, ctx->newton_maxit, ctx->fp64,
-                        ctx->stream);
+                        ctx->nmax, ctx->stream);
   });
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "field launch: %s", hipGetErrorString(e));
   e = timed(ctx, 0, [&] { return launch_push(ctx->dp, ctx->G, ctx->lc, ctx->stream); });
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "push launch: %s", hipGetErrorString(e));
+  e = timed(ctx, 3, [&] { return launch_source(ctx->dp, ctx->G, ctx->lc, ctx->stream); });
+  if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "source launch: %s", hipGetErrorString(e));
   ctx->since_compact += 1;
   if (ctx->since_compact >= ctx->compact_every) {
     e = timed(ctx, 2, [&] { return launch_compact(ctx->dp, ctx->G, ctx->lc, ctx->stream); });
@@ -546,8 +586,10 @@ static gs_status run_steps(gs_ctx *ctx, int n_steps, int mode, int guess) {
         HIPCHK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         hipError_t e1 = hipSuccess, e2 = hipSuccess, e3 = hipSuccess;
         for (int k = 0; k < L && e1 == hipSuccess && e2 == hipSuccess; ++k) {
-          e1 = launch_field(ctx->dp, ctx->G, mode, guess, ctx->newton_tol, ctx->newton_maxit, ctx->fp64, cs);
+          e1 = launch_field(ctx->dp, ctx->G, mode, guess, ctx->newton_tol, ctx->newton_maxit, ctx->fp64,
+                            ctx->nmax, cs);
           if (e1 == hipSuccess) e2 = launch_push(ctx->dp, ctx->G, ctx->lc, cs);
+          if (e2 == hipSuccess) e2 = launch_source(ctx->dp, ctx->G, ctx->lc, cs);
         }
         if (e1 == hipSuccess && e2 == hipSuccess) e3 = launch_compact(ctx->dp, ctx->G, ctx->lc, cs);
         hipError_t ec = hipStreamEndCapture(cs, &graph);
@@ -688,54 +730,72 @@ extern "C" gs_status gs_read_particles(gs_ctx *ctx, int32_t gap, int32_t species
 
 extern "C" gs_status gs_set_option(gs_ctx *ctx, int32_t option, int64_t value) {
   if (!ctx) return GS_ESTATE;
+  const LaunchCfg keep = ctx->lc;
+  const int keep_dep = ctx->deposit_opt, keep_grid = ctx->grid_opt;
   switch (option) {
     case GS_OPT_BLOCK:
       if (value != 256 && value != 512 && value != 1024) return fail(ctx, GS_EINVAL, "block must be 256, 512 or 1024");
-      if (push_lds_bytes(ctx->nmax, ctx->fp64, ctx->G) > 65536 && value < 1024) {
-        // a block that needs more than 64 KiB of LDS runs alone on its CU
-      }
       ctx->lc.block = (int)value;
-      if (ctx->lc.tile % ctx->lc.block) ctx->lc.tile = ctx->lc.block * (ctx->fp64 ? 2 : 4);
+      if (ctx->lc.tile % (8 * ctx->lc.block)) ctx->lc.tile = ctx->lc.block * 16;
       break;
     case GS_OPT_TILE:
-      if (value < ctx->lc.block || value % ctx->lc.block || value > (1 << 24))
-        return fail(ctx, GS_EINVAL, "tile must be a positive multiple of the block size");
+      if (value < 8 * ctx->lc.block || value % (8 * ctx->lc.block) || value > (1 << 24))
+        return fail(ctx, GS_EINVAL, "tile must be a positive multiple of 8 x the block size");
       ctx->lc.tile = (int)value;
       break;
-    case GS_OPT_GRID: {
+    case GS_OPT_GRID:
       if (value < 0 || value > 1 << 20) return fail(ctx, GS_EINVAL, "grid out of range");
-      if (value == 0) {
-        int dev = 0, ncu = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        const size_t lds = push_lds_bytes(ctx->nmax, ctx->fp64, ctx->G);
-        const int per_cu = std::min((int)std::max<size_t>(1, 163840 / lds), 2048 / ctx->lc.block);
-        value = (int64_t)ncu * per_cu;
-      }
-      ctx->lc.grid = (int)value;
+      ctx->grid_opt = value > 0;
+      if (value > 0) ctx->lc.grid = (int)value;
       break;
-    }
+    case GS_OPT_DEPOSIT:
+      if (value < 0 || value > 2) return fail(ctx, GS_EINVAL, "deposit must be 0, 1 or 2");
+      ctx->deposit_opt = (int)value;
+      break;
+    case GS_OPT_PPT:
+      if (value != 1 && value != 2) return fail(ctx, GS_EINVAL, "vectors per thread must be 1 or 2");
+      ctx->lc.ppt = (int)value * (ctx->fp64 ? 2 : 4);
+      if (ctx->lc.tile % (ctx->lc.block * ctx->lc.ppt)) ctx->lc.tile = ctx->lc.block * ctx->lc.ppt * 4;
+      break;
+    case GS_OPT_COMPACT_GRID:
+      if (value < 1 || value > 1 << 20) return fail(ctx, GS_EINVAL, "compact grid out of range");
+      ctx->lc.compact_grid = (int)value;
+      break;
     case GS_OPT_COMPACT_EVERY:
       if (value < 1 || value > 1 << 20) return fail(ctx, GS_EINVAL, "compact_every must be >= 1");
       ctx->compact_every = (int)value;
-      break;
+      return GS_OK;
     case GS_OPT_GRAPH:
       ctx->use_graph = value ? 1 : 0;
-      break;
+      return GS_OK;
     case GS_OPT_TIMING:
       ctx->timing = value ? 1 : 0;
-      break;
+      return GS_OK;
     case GS_OPT_NEWTON_TOL:
       if (value <= 0) return fail(ctx, GS_EINVAL, "tolerance must be positive");
       ctx->newton_tol = (double)value * 1e-12;
-      break;
+      return GS_OK;
     case GS_OPT_NEWTON_MAXIT:
       if (value < 0 || value > 64) return fail(ctx, GS_EINVAL, "maxit must be in 0..64");
       ctx->newton_maxit = (int)value;
-      break;
+      return GS_OK;
     default:
       return fail(ctx, GS_EINVAL, "unknown option %d", option);
   }
+  choose_launch(ctx);
+  if (!launch_fits(ctx)) {
+    ctx->lc = keep;
+    ctx->deposit_opt = keep_dep;
+    ctx->grid_opt = keep_grid;
+    return fail(ctx, GS_EINVAL, "that launch shape needs more than 160 KiB of LDS per workgroup");
+  }
+  // a new shape invalidates captured graphs
+  for (int m = 0; m < 2; ++m)
+    for (int k = 0; k < 3; ++k)
+      if (ctx->gexec[m][k]) {
+        (void)hipGraphExecDestroy(ctx->gexec[m][k]);
+        ctx->gexec[m][k] = nullptr;
+      }
   return GS_OK;
 }
 
@@ -751,6 +811,9 @@ extern "C" gs_status gs_get_timing(gs_ctx *ctx, gs_timing *out, int32_t reset) {
     } else if (pe.kind == 1) {
       ctx->tm.field_ms += ms;
       ctx->tm.field_launches += 1;
+    } else if (pe.kind == 3) {
+      ctx->tm.source_ms += ms;
+      ctx->tm.source_launches += 1;
     } else {
       ctx->tm.compact_ms += ms;
       ctx->tm.compact_launches += 1;

@@ -33,6 +33,8 @@ struct GapConst {
   int64_t cap[2];
   int64_t pbase[2];   // first particle slot of species s
   int64_t nbase;      // offset of the node arrays (N + 1 entries)
+  int64_t evbase;     // first slot of the gap's absorbed-ion event list
+  int64_t evcap;      // its capacity
   int64_t ebase;      // offset of the binary32/64 field table (N + 2 entries)
   uint64_t seed;
   double d, dx, A, eps0, dt, cgap, c_par;
@@ -77,6 +79,13 @@ struct GapState {
   double newton_r0, newton_r;
 };
 
+// An ion absorbed by an electrode, waiting for its secondary emission.
+struct Event {
+  double u;     // impact velocity in cells per step
+  uint32_t id;  // the ion's id (keys its random draws)
+  uint32_t wall;
+};
+
 // Context-wide device pointers handed to kernels.
 struct DevPtrs {
   const GapConst *gc;
@@ -95,26 +104,33 @@ struct DevPtrs {
   unsigned int *done_counter;      // for the last-block pattern of the field kernel
   unsigned int *err;               // [0] flags, [1] gap of first error
   const double *mlp_u;             // [G][MAXM+1] MLP guesses (or null)
+  Event *ev;                       // absorbed-ion events, per-gap lists
+  unsigned long long *ev_count;    // [G]
 };
 
 enum { ERR_CAPACITY = 1u, ERR_BADINJECT = 2u, ERR_NOCONV = 4u };
 
 struct LaunchCfg {
-  int block;      // push block size
-  int tile;       // particles per tile
-  int grid;       // push blocks
-  int nmax;       // largest n_cells of the context
-  int fp64;       // particle precision
+  int block;         // push block size
+  int tile;          // particles per tile
+  int grid;          // push blocks
+  int nmax;          // largest n_cells of the context
+  int fp64;          // particle precision
+  int wide;          // binary32: 64-bit LDS deposit cells (else 32-bit cells with carries)
+  int compact_grid;  // compaction blocks
+  int source_grid;   // emission / injection blocks
+  int ppt;           // particles per thread per chunk (one or two 16-byte vectors)
 };
 
 // launchers (gs_kernels.hip)
 hipError_t launch_field(const DevPtrs &p, int G, int mode, int guess, double newton_tol,
-                        int newton_maxit, int fp64, hipStream_t s);
+                        int newton_maxit, int fp64, int nmax, hipStream_t s);
 hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s);
+hipError_t launch_source(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s);
 hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s);
 hipError_t launch_inject(const DevPtrs &p, int gap, int species, long long n, const double *x_dev,
                          const double *v_dev, long long id0, int fp64, hipStream_t s);
 hipError_t launch_phi(const DevPtrs &p, int gap, hipStream_t s);
-size_t push_lds_bytes(int nmax, int fp64, int G);
+size_t push_lds_bytes(int nmax, int fp64, int G, int wide);
 
 }  // namespace gs

@@ -1,17 +1,20 @@
 // Device side of the circuit-coupled 1D ES-PIC step for gfx950.
 //
-// Per step two kernels run on the context's stream:
-//   k_field  one workgroup per gap: charge accumulator -> rho, prefix scans for
-//            the half-grid field, the circuit/surface-charge update (strict or
-//            weak), the binary32/64 field table the push gathers from.
-//   k_push   persistent workgroups over tiles of every gap's particles: gather,
-//            leapfrog, wall test, secondary emission, beam injection and the
-//            charge deposit, privatised in LDS per workgroup.
+// Per step three kernels run on the context's stream:
+//   k_field   one workgroup per gap: charge accumulator -> rho, prefix scans for
+//             the half-grid field, the circuit/surface-charge update (strict or
+//             weak), the binary32/64 field table the push gathers from.
+//   k_push    persistent workgroups over tiles of every gap's particles: gather,
+//             leapfrog, wall test and the charge deposit, privatised in LDS per
+//             workgroup; absorbed ions are queued for emission.
+//   k_source  secondary emission of the queued ions and the ion beam.
 // Every few steps k_compact reclaims the slots of absorbed particles.
 //
 // Compiled with -ffp-contract=off: the binary32 particle arithmetic is a fixed
 // sequence of IEEE operations (no fused multiply-adds).
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "gs_internal.h"
 
@@ -65,37 +68,20 @@ __device__ inline int poisson_inverse(double lam, double u, int kmax) {
 }
 
 // ---------------------------------------------------------------------------
-// helpers
+// workgroup helpers
 // ---------------------------------------------------------------------------
-// block-wide exclusive scan of one double per thread (blockDim.x <= 1024)
-__device__ inline double block_exclusive_scan(double v, double *sh, double *total) {
+template <class T>
+__device__ inline T block_exclusive_scan(T v, T *sh, T *total) {
   const int tid = threadIdx.x, nt = blockDim.x;
   sh[tid] = v;
   __syncthreads();
   for (int off = 1; off < nt; off <<= 1) {
-    double a = (tid >= off) ? sh[tid - off] : 0.0;
+    T a = (tid >= off) ? sh[tid - off] : (T)0;
     __syncthreads();
     sh[tid] += a;
     __syncthreads();
   }
-  double incl = sh[tid];
-  *total = sh[nt - 1];
-  __syncthreads();
-  return incl - v;
-}
-
-// block-wide exclusive scan of one int per thread
-__device__ inline int block_exclusive_scan_int(int v, int *sh, int *total) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int off = 1; off < nt; off <<= 1) {
-    int a = (tid >= off) ? sh[tid - off] : 0;
-    __syncthreads();
-    sh[tid] += a;
-    __syncthreads();
-  }
-  int incl = sh[tid];
+  T incl = sh[tid];
   *total = sh[nt - 1];
   __syncthreads();
   return incl - v;
@@ -114,315 +100,421 @@ __device__ inline double block_sum(double v, double *sh) {
   return r;
 }
 
-__device__ inline double node_rho(const GapConst &c, const unsigned long long *acc, int j, int fp64) {
-  const double scale = fp64 ? 5.684341886080801486968994140625e-14 /* 2^-44 */
-                            : 5.9604644775390625e-08 /* 2^-24 */;
-  double r = c.s0 * ((double)(long long)acc[j] * scale) / c.dx;
-  if (j == 0 || j == c.N) r *= 2.0;
-  return r;
+// block-wide exclusive scan of doubles built from wave scans: two barriers
+// (wsum: one slot per wave)
+__device__ inline double wave_incl_scan_d(double v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    double t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ inline double block_exclusive_scan_w(double v, double *wsum, double *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const double incl = wave_incl_scan_d(v);
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  double before = 0.0, all = 0.0;
+  for (int q = 0; q < nw; ++q) {
+    const double a = wsum[q];
+    if (q < w) before += a;
+    all += a;
+  }
+  *total = all;
+  __syncthreads();
+  return before + incl - v;
+}
+
+__device__ inline double block_sum_w(double v, double *wsum) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane == 0) wsum[w] = v;
+  __syncthreads();
+  double all = 0.0;
+  for (int q = 0; q < nw; ++q) all += wsum[q];
+  __syncthreads();
+  return all;
+}
+
+// wave-wide inclusive prefix sum (64 lanes)
+__device__ inline int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ inline unsigned int wave_sum(unsigned int a) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  return a;
 }
 
 // ---------------------------------------------------------------------------
 // k_field: level n of one gap per workgroup
 // ---------------------------------------------------------------------------
-constexpr int FBS = 256;
+constexpr int FBS = 1024;
+constexpr int FCH = 16;  // nodes per thread: n_cells <= FBS * FCH = 16384
+
+__device__ inline double node_rho(double s0, double dx, unsigned long long a, int j, int N, int fp64) {
+  const double scale = fp64 ? 5.684341886080801486968994140625e-14 /* 2^-44 */
+                            : 5.9604644775390625e-08 /* 2^-24 */;
+  double r = s0 * ((double)(long long)a * scale) / dx;
+  if (j == 0 || j == N) r *= 2.0;
+  return r;
+}
+
+// Circuit, surface charge and electrode potential of level n (thread 0, on LDS
+// copies of the gap's constants and state).  P = (dx/eps0) sum_k S_k is the
+// potential the space charge alone gives the electrode.
+__device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState &st, double P,
+                            int mode, int guess, double tol, int maxit, double *sigma_out,
+                            double *wk, const unsigned long long *tl) {
+  const int M = c.M, gm = c.g;
+  const double A = c.A, eps0 = c.eps0;
+  const long long n = st.level + 1;
+  const double t = (double)n * c.dt;
+  // convection charge of the push that led to this level (Sec. 2.4.1); tl is
+  // the gap's tally, already staged in LDS
+  long long ab[4], em[2], inj, pushed;
+  for (int i = 0; i < 4; ++i) ab[i] = (long long)tl[T_ABS + i];
+  em[0] = (long long)tl[T_EMIT];
+  em[1] = (long long)tl[T_EMIT + 1];
+  inj = (long long)tl[T_INJ];
+  pushed = (long long)tl[T_PUSHED];
+  const double qsh_i = A * (c.s0 * (double)c.Z[1]);
+  const double qsh_e = A * (c.s0 * (double)c.Z[0]);
+  double qconv = 0.0;
+  qconv += qsh_i * (double)ab[1 * 2 + 0];
+  qconv += qsh_e * (double)ab[0 * 2 + 0];
+  qconv -= qsh_e * (double)em[0];
+  for (int i = 0; i < 4; ++i) {
+    st.abs_last[i] = ab[i];
+    st.abs_cum[i] += ab[i];
+  }
+  for (int i = 0; i < 2; ++i) {
+    st.emit_last[i] = em[i];
+    st.emit_cum[i] += em[i];
+  }
+  st.inj_last = inj;
+  st.inj_cum += inj;
+  st.pushed_last = pushed;
+  st.pushed_cum += pushed;
+  st.live[0] += em[0] + em[1] - ab[0] - ab[1];
+  st.live[1] += inj - ab[2] - ab[3];
+
+  const double Vs = c.src_dc + c.src_amp * sin(c.src_w * t + c.src_phase);
+  // small work vectors live in LDS: indexed by the run-time mesh count they would
+  // otherwise go to scratch memory
+  double *h = wk, *q = wk + MAXM, *Dn = wk + 2 * MAXM, *y = wk + 3 * MAXM;
+  double *u = wk + 4 * MAXM, *r = u + (MAXM + 1), *ue = r + (MAXM + 1), *rc = ue + (MAXM + 1);
+  for (int j = 0; j < M; ++j) h[j] = 15.0 * st.dq[0][j] - 7.0 * st.dq[1][j] + st.dq[2][j];
+  double sigma, qcirc, qstar, phi0;
+  if (mode == 0) {
+    // strict: D = y - z phi0, Q_gap = K - G phi0 (eq. Q4_phi_relation, eq. K_def)
+    for (int i = 0; i < M; ++i) {
+      double a = c.sb[i] * Vs;
+      for (int j = 0; j < M; ++j)
+        a += c.sL[i * MAXM + j] * h[j] + c.sR[i * MAXM + j] * st.dq[0][j] -
+             c.sS[i * MAXM + j] * st.qprev[j];
+      y[i] = a;
+    }
+    const double K = st.qprev[gm] + y[gm];
+    const double G = c.sz[gm] + c.c_par;
+    // eq. Poisson_BC2 closed over the interior rows:
+    // phi0 = (d/eps0) sigma + P with sigma = sigma* - G phi0 / A
+    const double sig_star = st.sigma_prev + (qconv + K - st.qcirc_prev) / A;
+    phi0 = ((c.d / eps0) * sig_star + P) / (1.0 + G * c.d / (eps0 * A));
+    int iters = -1, fb = 0;
+    double r0n = 0.0, rn = 0.0;
+    if (guess != GS_GUESS_DIRECT) {
+      // Newton on u = (V, I_0..I_{M-1}); the residual is affine in u
+      const int nu = M + 1;
+      auto residual = [&](const double *uu, double *rr) {
+        // BDF2 increments from the currents: I = (3 D - D1) / (2 dt)
+        for (int j = 0; j < M; ++j) rc[j] = (2.0 * c.dt * uu[1 + j] + st.dq[0][j]) / 3.0 - y[j];
+        // loop equations in volts: T' D - C' + g V = T' (D - y) + g V
+        for (int i = 0; i < M; ++i) {
+          double a = (i == gm) ? uu[0] : 0.0;
+          for (int j = 0; j < M; ++j) a += c.Tp[i * MAXM + j] * rc[j];
+          rr[1 + i] = a / c.v_ref;
+        }
+        // closure: V equals the electrode potential the field gives
+        const double qgap = st.qprev[gm] + (rc[gm] + y[gm]) - c.c_par * uu[0];
+        const double sg = st.sigma_prev + (qconv + qgap - st.qcirc_prev) / A;
+        rr[0] = (uu[0] - ((c.d / eps0) * sg + P)) / c.v_ref;
+      };
+      auto norm = [&](const double *rr) {
+        double m = 0.0;
+        for (int i = 0; i < nu; ++i) m = fmax(m, fabs(rr[i]));
+        return m;
+      };
+      // plain guess: quadratic extrapolation of the last three levels
+      for (int i = 0; i < nu; ++i) ue[i] = 3.0 * st.uh[0][i] - 3.0 * st.uh[1][i] + st.uh[2][i];
+      residual(ue, r);
+      const double rext = norm(r);
+      bool use_mlp = false;
+      if (guess == GS_GUESS_MLP && p.mlp_u) {
+        for (int i = 0; i < nu; ++i) u[i] = p.mlp_u[(size_t)g * (MAXM + 1) + i];
+        residual(u, r);
+        const double rm = norm(r);
+        use_mlp = (rm == rm) && (rm <= rext);
+        if (!use_mlp) fb = 1;
+      }
+      if (!use_mlp) {
+        for (int i = 0; i < nu; ++i) u[i] = ue[i];
+        residual(u, r);
+      }
+      r0n = norm(r);
+      rn = r0n;
+      iters = 0;
+      while (!(rn <= tol) && iters < maxit) {
+        for (int i = 0; i < nu; ++i) {
+          double a = 0.0;
+          for (int j = 0; j < nu; ++j) a += c.Jinv[i * (MAXM + 1) + j] * r[j];
+          ue[i] = u[i] - a;
+        }
+        for (int i = 0; i < nu; ++i) u[i] = ue[i];
+        residual(u, r);
+        rn = norm(r);
+        iters += 1;
+      }
+      if (!(rn <= tol)) atomicOr(p.err, ERR_NOCONV);
+      phi0 = u[0];
+    }
+    qcirc = K - G * phi0;
+    qstar = qcirc;
+    sigma = st.sigma_prev + (qconv + qcirc - st.qcirc_prev) / A;  // eq. sigma_update
+    for (int j = 0; j < M; ++j) {
+      Dn[j] = y[j] - c.sz[j] * phi0;
+      q[j] = st.qprev[j] + Dn[j];
+    }
+    st.newton_last = iters;
+    st.newton_fb_last = fb;
+    if (iters >= 0) {
+      st.newton_total += iters;
+      st.newton_fallbacks += fb;
+    }
+    st.newton_r0 = r0n;
+    st.newton_r = rn;
+  } else {
+    // weak: the circuit alone with the gap as a capacitor, then the field
+    for (int i = 0; i < M; ++i) {
+      double a = c.wb[i] * Vs;
+      for (int j = 0; j < M; ++j)
+        a += c.wL[i * MAXM + j] * h[j] + c.wR[i * MAXM + j] * st.dq[0][j] -
+             c.wS[i * MAXM + j] * st.qprev[j];
+      y[i] = a;
+    }
+    for (int j = 0; j < M; ++j) {
+      q[j] = st.qprev[j] + y[j];
+      Dn[j] = y[j];
+    }
+    const double vstar = q[gm] / (c.cgap + c.c_par);
+    qstar = c.cgap * vstar;
+    sigma = st.sigma_prev + (qconv + qstar - st.qcirc_prev) / A;
+    phi0 = (c.d / eps0) * sigma + P;
+    // re-impose the gap charge the field implies; the increment history stays
+    q[gm] = (c.cgap + c.c_par) * phi0;
+    qcirc = c.cgap * phi0;
+    st.newton_last = -1;
+    st.newton_fb_last = 0;
+  }
+  for (int j = 0; j < M; ++j) {
+    st.I[j] = (3.0 * Dn[j] - st.dq[0][j]) / (2.0 * c.dt);
+    st.q[j] = q[j];
+    st.dq[2][j] = st.dq[1][j];
+    st.dq[1][j] = st.dq[0][j];
+    st.dq[0][j] = Dn[j];
+    st.qprev[j] = q[j];
+  }
+  for (int i = 0; i <= M; ++i) {
+    st.uh[2][i] = st.uh[1][i];
+    st.uh[1][i] = st.uh[0][i];
+  }
+  st.uh[0][0] = phi0;
+  for (int j = 0; j < M; ++j) st.uh[0][1 + j] = st.I[j];
+  st.sigma_prev = sigma;
+  st.qcirc_prev = qcirc;
+  st.level = n;
+  st.t = t;
+  st.phi0 = phi0;
+  st.sigma = sigma;
+  st.qcirc = qcirc;
+  st.qcirc_star = qstar;
+  st.qconv = qconv;
+  // particles the coming push sweeps; the step's beam gets the slots right after
+  // them (its ids and slots are fixed before the push)
+  // (append counters can run past the capacity after an overflow, which was
+  // flagged when it happened; never sweep past the region)
+  for (int s = 0; s < 2; ++s) st.count[s] = min((long long)p.next_count[g * 2 + s], c.cap[s]);
+  p.next_count[g * 2 + 1] = (unsigned long long)(st.count[1] + c.beam_n);
+  p.ev_count[g] = 0ull;
+  st.beam_id0 = st.next_id;
+  st.next_id += c.beam_n;
+  *sigma_out = sigma;
+}
 
 __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, double tol,
                                                int maxit, int fp64) {
   const int g = blockIdx.x, tid = threadIdx.x;
-  const GapConst &c = p.gc[g];
-  GapState &st = p.gs[g];
-  const int N = c.N;
-  const int M = c.M;
-  const double dx = c.dx, eps0 = c.eps0, A = c.A;
-  unsigned long long *acc = p.acc + c.nbase;
-  double *rho = p.rho64 + c.nbase;
-  double *E = p.E64 + c.nbase;
+  extern __shared__ __align__(16) double Sk[];  // S_k, one per cell
+  __shared__ GapConst sc;
+  __shared__ GapState ss;
+  __shared__ double wsum[FBS / 64];
+  __shared__ double s_sigma, s_rhoN;
+  __shared__ double s_work[8 * MAXM + 8];
+  __shared__ unsigned long long s_tally[T_N];
+  // stage the gap's constants, state and last push's tallies in LDS
+  if (tid < T_N) {
+    unsigned long long *tl = p.tally + (size_t)g * T_N;
+    s_tally[tid] = tl[tid];
+    tl[tid] = 0ull;
+  }
+  {
+    const unsigned long long *a = (const unsigned long long *)&p.gc[g];
+    unsigned long long *b = (unsigned long long *)&sc;
+    for (int i = tid; i < (int)(sizeof(GapConst) / 8); i += FBS) b[i] = a[i];
+    a = (const unsigned long long *)&p.gs[g];
+    b = (unsigned long long *)&ss;
+    for (int i = tid; i < (int)(sizeof(GapState) / 8); i += FBS) b[i] = a[i];
+  }
+  __syncthreads();
+  const int N = sc.N;
+  const double dx = sc.dx, eps0 = sc.eps0, s0 = sc.s0;
+  unsigned long long *acc = p.acc + sc.nbase;
+  double *rho = p.rho64 + sc.nbase;
+  double *E = p.E64 + sc.nbase;
 
-  __shared__ double sh[FBS];
-  __shared__ double s_sigma, s_P, s_rhoN;
-
-  // 1. nodal density of level n and prefix sums S_k = dx rho_0/2 + dx sum_{1..k} rho_j
-  const int chunk = (N + FBS - 1) / FBS;
-  const int k0 = tid * chunk;
-  const int k1 = min(k0 + chunk, N);
+  // 1. nodal density of level n; prefix sums S_k = dx rho_0/2 + dx sum_{1..k} rho_j
+  const int ch = (N + FBS - 1) / FBS;
+  const int k0 = tid * ch;
+  double rv[FCH];
   double loc = 0.0;
-  for (int k = k0; k < k1; ++k) {
-    double r = node_rho(c, acc, k, fp64);
-    rho[k] = r;
-    acc[k] = 0ull;
-    loc += (k == 0) ? dx * r / 2.0 : dx * r;
+#pragma unroll
+  for (int i = 0; i < FCH; ++i) {
+    rv[i] = 0.0;
+    const int k = k0 + i;
+    if (i < ch && k < N) rv[i] = node_rho(s0, dx, acc[k], k, N, fp64);
+  }
+#pragma unroll
+  for (int i = 0; i < FCH; ++i) {
+    const int k = k0 + i;
+    if (i < ch && k < N) {
+      rho[k] = rv[i];
+      acc[k] = 0ull;
+      loc += (k == 0) ? dx * rv[i] / 2.0 : dx * rv[i];
+    }
   }
   if (tid == FBS - 1) {
-    double r = node_rho(c, acc, N, fp64);
+    const double r = node_rho(s0, dx, acc[N], N, N, fp64);
     rho[N] = r;
     acc[N] = 0ull;
     s_rhoN = r;
   }
   double tot;
-  double run = block_exclusive_scan(loc, sh, &tot);
+  double run = block_exclusive_scan_w(loc, wsum, &tot);
   double sumS = 0.0;
-  for (int k = k0; k < k1; ++k) {
-    double r = rho[k];
-    run += (k == 0) ? dx * r / 2.0 : dx * r;
-    E[k] = run;  // S_k for now
-    sumS += run;
+#pragma unroll
+  for (int i = 0; i < FCH; ++i) {
+    const int k = k0 + i;
+    if (i < ch && k < N) {
+      run += (k == 0) ? dx * rv[i] / 2.0 : dx * rv[i];
+      Sk[k] = run;
+      sumS += run;
+    }
   }
-  double P = block_sum(sumS, sh) * dx / eps0;
+  const double P = block_sum_w(sumS, wsum) * dx / eps0;
 
-  // 2. circuit, surface charge and electrode potential (scalar work)
+  // 2. circuit and surface charge
   if (tid == 0) {
-    const long long n = st.level + 1;
-    const double t = (double)n * c.dt;
-    unsigned long long *tl = p.tally + (size_t)g * T_N;
-    // convection charge of the push that led to this level (Sec. 2.4.1)
-    long long ab[4], em[2], inj, pushed;
-    for (int i = 0; i < 4; ++i) ab[i] = (long long)tl[T_ABS + i];
-    em[0] = (long long)tl[T_EMIT];
-    em[1] = (long long)tl[T_EMIT + 1];
-    inj = (long long)tl[T_INJ];
-    pushed = (long long)tl[T_PUSHED];
-    for (int i = 0; i < T_N; ++i) tl[i] = 0ull;
-    const double qsh_i = A * (c.s0 * (double)c.Z[1]);
-    const double qsh_e = A * (c.s0 * (double)c.Z[0]);
-    double qconv = 0.0;
-    qconv += qsh_i * (double)ab[1 * 2 + 0];
-    qconv += qsh_e * (double)ab[0 * 2 + 0];
-    qconv -= qsh_e * (double)em[0];
-    for (int i = 0; i < 4; ++i) {
-      st.abs_last[i] = ab[i];
-      st.abs_cum[i] += ab[i];
-    }
-    for (int i = 0; i < 2; ++i) {
-      st.emit_last[i] = em[i];
-      st.emit_cum[i] += em[i];
-    }
-    st.inj_last = inj;
-    st.inj_cum += inj;
-    st.pushed_last = pushed;
-    st.pushed_cum += pushed;
-    st.live[0] += em[0] + em[1] - ab[0] - ab[1];
-    st.live[1] += inj - ab[2] - ab[3];
-
-    const double Vs = c.src_dc + c.src_amp * sin(c.src_w * t + c.src_phase);
-    double h[MAXM], q[MAXM], Dn[MAXM];
-    for (int j = 0; j < M; ++j) h[j] = 15.0 * st.dq[0][j] - 7.0 * st.dq[1][j] + st.dq[2][j];
-    const int gm = c.g;
-    double sigma, qcirc, qstar, phi0;
-    if (mode == 0) {
-      // strict: D = y - z phi0, Q_gap = K - G phi0 (eq. Q4_phi_relation)
-      double y[MAXM];
-      for (int i = 0; i < M; ++i) {
-        double a = c.sb[i] * Vs;
-        for (int j = 0; j < M; ++j)
-          a += c.sL[i * MAXM + j] * h[j] + c.sR[i * MAXM + j] * st.dq[0][j] -
-               c.sS[i * MAXM + j] * st.qprev[j];
-        y[i] = a;
-      }
-      const double K = st.qprev[gm] + y[gm];
-      const double G = c.sz[gm] + c.c_par;
-      // phi0 from eq. Poisson_BC2 closed over the interior rows:
-      // phi0 = (d/eps0) sigma + P, sigma = sigma* - G phi0 / A
-      const double sig_star = st.sigma_prev + (qconv + K - st.qcirc_prev) / A;
-      double u_sol0 = ((c.d / eps0) * sig_star + P) / (1.0 + G * c.d / (eps0 * A));
-      int iters = -1, fb = 0;
-      double r0n = 0.0, rn = 0.0;
-      if (guess != GS_GUESS_DIRECT) {
-        // Newton on u = (V, I_0..I_{M-1}) with the constant Jacobian J
-        const int nu = M + 1;
-        double u[MAXM + 1], r[MAXM + 1];
-        auto residual = [&](const double *uu, double *rr) {
-          // BDF2 increments from the currents: I = (3 D - D1) / (2 dt)
-          double rho_c[MAXM];
-          for (int j = 0; j < M; ++j)
-            rho_c[j] = (2.0 * c.dt * uu[1 + j] + st.dq[0][j]) / 3.0 - y[j];
-          // loop equations in volts: T' D - C' + g V = T' (D - y) + g V
-          for (int i = 0; i < M; ++i) {
-            double a = (i == gm) ? uu[0] : 0.0;
-            for (int j = 0; j < M; ++j) a += c.Tp[i * MAXM + j] * rho_c[j];
-            rr[1 + i] = a / c.v_ref;
-          }
-          // closure: V equals the electrode potential the field gives
-          const double qgap = st.qprev[gm] + (rho_c[gm] + y[gm]) - c.c_par * uu[0];
-          const double sg = st.sigma_prev + (qconv + qgap - st.qcirc_prev) / A;
-          rr[0] = (uu[0] - ((c.d / eps0) * sg + P)) / c.v_ref;
-        };
-        auto norm = [&](const double *rr) {
-          double m = 0.0;
-          for (int i = 0; i < nu; ++i) m = fmax(m, fabs(rr[i]));
-          return m;
-        };
-        // plain guess: quadratic extrapolation of the last three levels
-        double ue[MAXM + 1];
-        for (int i = 0; i < nu; ++i) ue[i] = 3.0 * st.uh[0][i] - 3.0 * st.uh[1][i] + st.uh[2][i];
-        residual(ue, r);
-        double rext = norm(r);
-        bool use_mlp = false;
-        if (guess == GS_GUESS_MLP && p.mlp_u) {
-          for (int i = 0; i < nu; ++i) u[i] = p.mlp_u[(size_t)g * (MAXM + 1) + i];
-          residual(u, r);
-          double rm = norm(r);
-          use_mlp = (rm == rm) && (rm <= rext);
-          if (!use_mlp) fb = 1;
-        }
-        if (!use_mlp) {
-          for (int i = 0; i < nu; ++i) u[i] = ue[i];
-          residual(u, r);
-        }
-        r0n = norm(r);
-        rn = r0n;
-        iters = 0;
-        while (!(rn <= tol) && iters < maxit) {
-          for (int i = 0; i < nu; ++i) {
-            double a = 0.0;
-            for (int j = 0; j < nu; ++j) a += c.Jinv[i * (MAXM + 1) + j] * r[j];
-            ue[i] = u[i] - a;
-          }
-          for (int i = 0; i < nu; ++i) u[i] = ue[i];
-          residual(u, r);
-          rn = norm(r);
-          iters += 1;
-        }
-        if (!(rn <= tol)) atomicOr(p.err, ERR_NOCONV);
-        u_sol0 = u[0];
-      }
-      phi0 = u_sol0;
-      qcirc = K - G * phi0;
-      qstar = qcirc;
-      sigma = st.sigma_prev + (qconv + qcirc - st.qcirc_prev) / A;  // eq. sigma_update
-      for (int j = 0; j < M; ++j) {
-        Dn[j] = y[j] - c.sz[j] * phi0;
-        q[j] = st.qprev[j] + Dn[j];
-      }
-      st.newton_last = iters;
-      st.newton_fb_last = fb;
-      if (iters >= 0) {
-        st.newton_total += iters;
-        st.newton_fallbacks += fb;
-      }
-      st.newton_r0 = r0n;
-      st.newton_r = rn;
-    } else {
-      // weak: the circuit alone with the gap as a capacitor, then the field
-      double y[MAXM];
-      for (int i = 0; i < M; ++i) {
-        double a = c.wb[i] * Vs;
-        for (int j = 0; j < M; ++j)
-          a += c.wL[i * MAXM + j] * h[j] + c.wR[i * MAXM + j] * st.dq[0][j] -
-               c.wS[i * MAXM + j] * st.qprev[j];
-        y[i] = a;
-      }
-      for (int j = 0; j < M; ++j) {
-        q[j] = st.qprev[j] + y[j];
-        Dn[j] = y[j];
-      }
-      const double vstar = q[gm] / (c.cgap + c.c_par);
-      qstar = c.cgap * vstar;
-      sigma = st.sigma_prev + (qconv + qstar - st.qcirc_prev) / A;
-      phi0 = (c.d / eps0) * sigma + P;
-      // re-impose the gap charge the field implies; the increment history stays
-      q[gm] = (c.cgap + c.c_par) * phi0;
-      qcirc = c.cgap * phi0;
-      st.newton_last = -1;
-      st.newton_fb_last = 0;
-    }
-    // state of level n
-    for (int j = 0; j < M; ++j) {
-      st.I[j] = (3.0 * Dn[j] - st.dq[0][j]) / (2.0 * c.dt);
-      st.q[j] = q[j];
-      st.dq[2][j] = st.dq[1][j];
-      st.dq[1][j] = st.dq[0][j];
-      st.dq[0][j] = Dn[j];
-      st.qprev[j] = q[j];
-    }
-    for (int i = 0; i <= M; ++i) {
-      st.uh[2][i] = st.uh[1][i];
-      st.uh[1][i] = st.uh[0][i];
-    }
-    st.uh[0][0] = phi0;
-    for (int j = 0; j < M; ++j) st.uh[0][1 + j] = st.I[j];
-    st.sigma_prev = sigma;
-    st.qcirc_prev = qcirc;
-    st.level = n;
-    st.t = t;
-    st.phi0 = phi0;
-    st.sigma = sigma;
-    st.qcirc = qcirc;
-    st.qcirc_star = qstar;
-    st.qconv = qconv;
-    // particles the coming push sweeps; beam ids of this step
-    for (int s = 0; s < 2; ++s) st.count[s] = (long long)p.next_count[g * 2 + s];
-    st.beam_id0 = st.next_id;
-    st.next_id += c.beam_n;
-    s_sigma = sigma;
-    s_P = P;
+    double sg;
+    solve_level(p, g, sc, ss, P, mode, guess, tol, maxit, &sg, s_work, s_tally);
+    s_sigma = sg;
   }
   __syncthreads();
 
   // 3. half-grid field E_{k+1/2} = (sigma + S_k) / eps0 and the gather table
   const double sigma = s_sigma;
-  for (int k = k0; k < k1; ++k) E[k] = (sigma + E[k]) / eps0;
+  const double rhoN = s_rhoN;
+  const size_t eb = (size_t)sc.ebase;
+#pragma unroll
+  for (int i = 0; i < FCH; ++i) {
+    const int k = k0 + i;
+    if (i < ch && k < N) {
+      const double e = (sigma + Sk[k]) / eps0;
+      E[k] = e;
+      if (fp64)
+        ((double *)p.ehat)[eb + k + 1] = e;
+      else
+        ((float *)p.ehat)[eb + k + 1] = (float)e;
+      if (k == N - 1) {
+        const double ed = e + dx * rhoN / (2.0 * eps0);
+        ss.e_ground = ed;
+        if (fp64)
+          ((double *)p.ehat)[eb + N + 1] = ed;
+        else
+          ((float *)p.ehat)[eb + N + 1] = (float)ed;
+      }
+    }
+  }
+  if (tid == 0) {
+    const double e0 = sigma / eps0;
+    if (fp64)
+      ((double *)p.ehat)[eb] = e0;
+    else
+      ((float *)p.ehat)[eb] = (float)e0;
+  }
   __syncthreads();
-  if (fp64) {
-    double *eh = (double *)p.ehat + c.ebase;
-    for (int k = k0; k < k1; ++k) eh[k + 1] = E[k];
-    if (tid == 0) {
-      eh[0] = sigma / eps0;
-      double ed = E[N - 1] + dx * s_rhoN / (2.0 * eps0);
-      eh[N + 1] = ed;
-      st.e_ground = ed;
-    }
-  } else {
-    float *eh = (float *)p.ehat + c.ebase;
-    for (int k = k0; k < k1; ++k) eh[k + 1] = (float)E[k];
-    if (tid == 0) {
-      eh[0] = (float)(sigma / eps0);
-      double ed = E[N - 1] + dx * s_rhoN / (2.0 * eps0);
-      eh[N + 1] = (float)ed;
-      st.e_ground = ed;
-    }
+  {
+    const unsigned long long *a = (const unsigned long long *)&ss;
+    unsigned long long *b = (unsigned long long *)&p.gs[g];
+    for (int i = tid; i < (int)(sizeof(GapState) / 8); i += FBS) b[i] = a[i];
   }
 }
 
 // ---------------------------------------------------------------------------
 // k_push
 // ---------------------------------------------------------------------------
-template <class P>
-struct Acc;
-
-// binary32 particles: 2^-24 weights, unsigned 32-bit LDS cells biased by 2^31;
-// a wrap of a cell is carried into the gap's 64-bit accumulator at once
-template <>
-struct Acc<float> {
+// Charge accumulation in LDS, one cell per node:
+//   Wide64  64-bit cells, non-returning adds (whenever the grid fits in LDS);
+//   Carry32 32-bit cells biased by 2^31 (binary32 particles, largest grids); a
+//           cell that wraps carries +-2^32 into the gap's 64-bit accumulator.
+// Both give the exact integer sum, so the deposit is order independent.
+struct Wide64 {
+  typedef unsigned long long cell;
+  static constexpr unsigned long long ZERO = 0ull;
+  __device__ static inline long long value(cell v) { return (long long)v; }
+};
+struct Carry32 {
   typedef unsigned int cell;
-  static constexpr unsigned int BIAS = 0x80000000u;
-  __device__ static inline void add(cell *lds, unsigned long long *gacc, int j, long long c64) {
-    const int c = (int)c64;
-    const unsigned int uc = (unsigned int)c;
-    const unsigned int old = atomicAdd(&lds[j], uc);
-    long long carry = 0;
-    if (c >= 0) {
-      if (old + uc < old) carry = 1;
-    } else {
-      if (old < (unsigned int)(-c)) carry = -1;
-    }
-    if (carry) atomicAdd(&gacc[j], (unsigned long long)(carry * 4294967296ll));
-  }
-  __device__ static inline long long flush_value(cell v) {
-    return (long long)v - (long long)BIAS;
-  }
-  __device__ static inline cell zero() { return BIAS; }
+  static constexpr unsigned int ZERO = 0x80000000u;
+  __device__ static inline long long value(cell v) { return (long long)v - 2147483648ll; }
 };
 
-// binary64 particles: 2^-44 weights, 64-bit LDS cells
+// 16-byte vectors of particle coordinates
+template <class P>
+struct Vec;
 template <>
-struct Acc<double> {
-  typedef unsigned long long cell;
-  __device__ static inline void add(cell *lds, unsigned long long *, int j, long long c) {
-    atomicAdd(&lds[j], (unsigned long long)c);
+struct Vec<float> {
+  typedef float4 type;
+  static constexpr int n = 4;
+  __device__ static inline float &at(float4 &v, int k) {
+    return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
   }
-  __device__ static inline long long flush_value(cell v) { return (long long)v; }
-  __device__ static inline cell zero() { return 0ull; }
+};
+template <>
+struct Vec<double> {
+  typedef double2 type;
+  static constexpr int n = 2;
+  __device__ static inline double &at(double2 &v, int k) { return k == 0 ? v.x : v.y; }
 };
 
 template <class P>
@@ -443,8 +535,7 @@ struct Prec<double> {
 // Linear gather from the extended half-grid table eh[0..N+1]:
 // eh[0] = surface field at node 0, eh[k] = E_{k-1/2}, eh[N+1] = field at node N.
 template <class P>
-__device__ inline P gather(const P *eh, P xi, int N) {
-  const P Nf = (P)N;
+__device__ inline P gather(const P *eh, P xi, int N, P Nf) {
   int k;
   P t;
   if (xi < (P)0.5) {
@@ -467,132 +558,133 @@ __device__ inline P gather(const P *eh, P xi, int N) {
   return a + m;
 }
 
-template <class P>
-struct PushShared {
-  P *eh;
-  typename Acc<P>::cell *acc;
-  int *prefix;          // [G + 1]
-  unsigned int *tally;  // [T_N]
-};
-
-// tiles of gap g: electrons, then ions, then beam injections
-__device__ inline void gap_tiles(const GapState &st, const GapConst &c, int tile, int &te, int &ti,
-                                 int &tb) {
-  te = (int)((st.count[0] + tile - 1) / tile);
-  ti = (int)((st.count[1] + tile - 1) / tile);
-  tb = (int)((c.beam_n + tile - 1) / tile);
+__device__ inline void carry_add(unsigned long long *gacc, int j, unsigned int old, long long c) {
+  const unsigned int uc = (unsigned int)(int)c;
+  long long carry = 0;
+  if (c >= 0) {
+    if (old + uc < old) carry = 1;
+  } else if (old < (unsigned int)(-(int)c)) {
+    carry = -1;
+  }
+  if (carry) atomicAdd(&gacc[j], (unsigned long long)(carry * 4294967296ll));
 }
 
-template <class P>
-__device__ void flush_gap(const DevPtrs &p, const GapConst &c, int g, PushShared<P> &sh) {
+// add one contribution c (two's complement) to node j
+template <class AC>
+__device__ inline void acc_add(typename AC::cell *lds, unsigned long long *gacc, int j, long long c);
+template <>
+__device__ inline void acc_add<Wide64>(unsigned long long *lds, unsigned long long *, int j, long long c) {
+  atomicAdd(&lds[j], (unsigned long long)c);
+}
+template <>
+__device__ inline void acc_add<Carry32>(unsigned int *lds, unsigned long long *gacc, int j, long long c) {
+  const unsigned int old = atomicAdd(&lds[j], (unsigned int)(int)c);
+  carry_add(gacc, j, old, c);
+}
+
+constexpr int EVQ = 128;  // absorbed-ion events a push workgroup queues in LDS
+
+template <class P, class AC>
+struct PushShared {
+  P *eh;
+  typename AC::cell *acc;
+  int *prefix;          // [G + 1]
+  unsigned int *tally;  // [T_N]
+  Event *evq;           // [EVQ]
+  unsigned int *evq_n;
+};
+
+// push tiles of gap g: electrons, then ions
+__device__ inline void gap_tiles(const GapState &st, int tile, int &te, int &ti) {
+  te = (int)((st.count[0] + tile - 1) / tile);
+  ti = (int)((st.count[1] + tile - 1) / tile);
+}
+
+template <class P, class AC>
+__device__ void flush_gap(const DevPtrs &p, const GapConst &c, int g, PushShared<P, AC> &sh) {
   __syncthreads();
   unsigned long long *gacc = p.acc + c.nbase;
   for (int j = threadIdx.x; j <= c.N; j += blockDim.x) {
-    long long v = Acc<P>::flush_value(sh.acc[j]);
+    const long long v = AC::value(sh.acc[j]);
     if (v != 0) atomicAdd(&gacc[j], (unsigned long long)v);
   }
   if (threadIdx.x < T_N) {
-    unsigned int v = sh.tally[threadIdx.x];
+    const unsigned int v = sh.tally[threadIdx.x];
     if (v) atomicAdd(&p.tally[(size_t)g * T_N + threadIdx.x], (unsigned long long)v);
   }
+  // queued events: one reservation for the whole queue
+  const unsigned int nq = min(*sh.evq_n, (unsigned int)EVQ);
+  __shared__ unsigned long long q_base;
+  if (threadIdx.x == 0 && nq) q_base = atomicAdd(&p.ev_count[g], (unsigned long long)nq);
   __syncthreads();
-}
-
-template <class P>
-__device__ void load_gap(const DevPtrs &p, const GapConst &c, PushShared<P> &sh) {
-  const P *geh = (const P *)p.ehat + c.ebase;
-  for (int j = threadIdx.x; j <= c.N + 1; j += blockDim.x) sh.eh[j] = geh[j];
-  for (int j = threadIdx.x; j <= c.N; j += blockDim.x) sh.acc[j] = Acc<P>::zero();
-  if (threadIdx.x < T_N) sh.tally[threadIdx.x] = 0u;
-  __syncthreads();
-}
-
-__device__ inline unsigned long long reserve(unsigned long long *counter, unsigned int n) {
-  return atomicAdd(counter, (unsigned long long)n);
-}
-
-// secondary electrons of one absorbed ion (Alg. 2); returns how many were emitted
-template <class P>
-__device__ int emit_electrons(const DevPtrs &p, const GapConst &c, const GapState &st, int g,
-                              int sel, uint32_t ion_id, P u_ion, int wall) {
-  const double v_ion = ((double)u_ion * c.dx) / c.dt;
-  const double e_ion = 0.5 * c.mass[1] * v_ion * v_ion / c.ev;
-  const double rr = e_ion / c.see_E0;
-  double lam = c.see_amp * rr / (1.0 + rr);
-  if (lam < 0.0) lam = 0.0;
-  uint64_t blk[4];
-  rng_block(c.seed, (uint64_t)st.level, (uint64_t)ion_id, 1, 0, blk);
-  const int k = poisson_inverse(lam, unit_open(blk[0]), c.see_max);
-  if (k == 0) return 0;
-  unsigned long long slot = reserve(&p.next_count[g * 2 + 0], (unsigned int)k);
-  P *X = (P *)p.X[sel];
-  P *U = (P *)p.U[sel];
-  uint32_t *ID = p.ID[sel];
-  const P xw = wall == 0 ? (P)0 : (P)c.N;
-  int emitted = 0;
-  for (int e = 0; e < k; ++e) {
-    const int slotw = e + 1;
-    if ((slotw & 3) == 0)
-      rng_block(c.seed, (uint64_t)st.level, (uint64_t)ion_id, 1, (uint64_t)(slotw >> 2), blk);
-    const double uu = unit_open(blk[slotw & 3]);
-    const double E_se = (c.see_law == GS_SEE_EXP) ? -c.see_E * log(uu) : c.see_E;
-    const double v_se = sqrt(2.0 * E_se * c.ev / c.mass[0]);
-    const double v_si = wall == 0 ? v_se : -v_se;
-    const P u_new = (P)((v_si * c.dt) / c.dx);
-    const unsigned long long s = slot + (unsigned long long)e;
-    if (s >= (unsigned long long)c.cap[0]) {
+  for (unsigned int i = threadIdx.x; i < nq; i += blockDim.x) {
+    const unsigned long long e = q_base + i;
+    if (e < (unsigned long long)c.evcap) {
+      p.ev[c.evbase + e] = sh.evq[i];
+    } else {
       atomicOr(&p.err[0], ERR_CAPACITY);
       atomicCAS(&p.err[1], 0xFFFFFFFFu, (unsigned int)g);
-      continue;
     }
-    const size_t i = (size_t)c.pbase[0] + s;
-    X[i] = xw;
-    U[i] = u_new;
-    ID[i] = NO_ID;
-    emitted += 1;
   }
-  return emitted;
+  __syncthreads();
 }
 
-template <class P, int BS, int PPT>
+template <class P, class AC>
+__device__ void load_gap(const DevPtrs &p, const GapConst &c, PushShared<P, AC> &sh) {
+  const P *geh = (const P *)p.ehat + c.ebase;
+  for (int j = threadIdx.x; j <= c.N + 1; j += blockDim.x) sh.eh[j] = geh[j];
+  for (int j = threadIdx.x; j <= c.N; j += blockDim.x) sh.acc[j] = AC::ZERO;
+  if (threadIdx.x < T_N) sh.tally[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) *sh.evq_n = 0u;
+  __syncthreads();
+}
+
+template <class P, class AC, int BS, int PPT>
 __global__ __launch_bounds__(BS) void k_push(DevPtrs p, int G, int tile, int nmax) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  typedef typename Acc<P>::cell cell;
+  typedef typename AC::cell cell;
   __shared__ int scan_sh[BS];
+  __shared__ Event evq[EVQ];
+  __shared__ unsigned int evq_n;
   // layout: tally[T_N] | prefix[G+1] | eh[nmax+2] (P) | acc[nmax+1] (cell)
-  PushShared<P> sh;
+  PushShared<P, AC> sh;
+  sh.evq = evq;
+  sh.evq_n = &evq_n;
   sh.tally = (unsigned int *)lds_raw;
   sh.prefix = (int *)(lds_raw + 64);
   const size_t off = 64 + (((size_t)(G + 1) * 4 + 15) / 16) * 16;
   sh.eh = (P *)(lds_raw + off);
   sh.acc = (cell *)(lds_raw + off + ((((size_t)(nmax + 2) * sizeof(P)) + 15) / 16) * 16);
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
   const int sel = (int)(*p.epoch & 1);
 
   // tiles per gap and their prefix (each workgroup builds its own copy in LDS)
-  const int per = (G + BS - 1) / BS;
-  int mine = 0;
-  for (int q = 0; q < per; ++q) {
-    const int g = tid * per + q;
-    if (g < G) {
-      int te, ti, tb;
-      gap_tiles(p.gs[g], p.gc[g], tile, te, ti, tb);
-      mine += te + ti + tb;
+  {
+    const int per = (G + BS - 1) / BS;
+    int mine = 0;
+    for (int q = 0; q < per; ++q) {
+      const int g = tid * per + q;
+      if (g < G) {
+        int te, ti;
+        gap_tiles(p.gs[g], tile, te, ti);
+        mine += te + ti;
+      }
     }
-  }
-  int tot_tiles;
-  int run = block_exclusive_scan_int(mine, scan_sh, &tot_tiles);
-  for (int q = 0; q < per; ++q) {
-    const int g = tid * per + q;
-    if (g < G) {
-      sh.prefix[g] = run;
-      int te, ti, tb;
-      gap_tiles(p.gs[g], p.gc[g], tile, te, ti, tb);
-      run += te + ti + tb;
+    int tot_tiles;
+    int run = block_exclusive_scan<int>(mine, scan_sh, &tot_tiles);
+    for (int q = 0; q < per; ++q) {
+      const int g = tid * per + q;
+      if (g < G) {
+        sh.prefix[g] = run;
+        int te, ti;
+        gap_tiles(p.gs[g], tile, te, ti);
+        run += te + ti;
+      }
     }
+    if (tid == 0) sh.prefix[G] = tot_tiles;
+    __syncthreads();
   }
-  if (tid == 0) sh.prefix[G] = tot_tiles;
-  __syncthreads();
 
   const int total = sh.prefix[G];
   const int t0 = (int)(((long long)blockIdx.x * total) / gridDim.x);
@@ -604,116 +696,350 @@ __global__ __launch_bounds__(BS) void k_push(DevPtrs p, int G, int tile, int nma
     const GapConst &c = p.gc[g];
     const GapState &st = p.gs[g];
     if (g != cur) {
-      if (cur >= 0) flush_gap<P>(p, p.gc[cur], cur, sh);
-      load_gap<P>(p, c, sh);
+      if (cur >= 0) flush_gap<P, AC>(p, p.gc[cur], cur, sh);
+      load_gap<P, AC>(p, c, sh);
       cur = g;
     }
     unsigned long long *gacc = p.acc + c.nbase;
-    int te, ti, tb;
-    gap_tiles(st, c, tile, te, ti, tb);
+    int te, ti;
+    gap_tiles(st, tile, te, ti);
     int lt = t - sh.prefix[g];
     const int N = c.N;
     const P Nf = (P)N;
-    if (lt < te + ti) {
+    {
       const int s = lt < te ? 0 : 1;
       if (s == 1) lt -= te;
-      const long long cnt = st.count[s];
-      P *X = (P *)p.X[sel] + c.pbase[s];
-      P *U = (P *)p.U[sel] + c.pbase[s];
-      const P alpha = (P)c.alpha[s];
-      const int Z = c.Z[s];
-      const bool see = (s == 1) && (c.see_amp > 0.0) && (Z > 0);
       const long long i0 = (long long)lt * tile;
-      unsigned int n_pushed = 0, n_abs0 = 0, n_abs1 = 0, n_em0 = 0, n_em1 = 0;
-      for (int r = 0; r < tile; r += BS * PPT) {
-        P xv[PPT], uv[PPT];
-        long long ii[PPT];
+      const int n_here = (int)min((long long)tile, st.count[s] - i0);
+      P *X = (P *)p.X[sel] + c.pbase[s] + i0;
+      P *U = (P *)p.U[sel] + c.pbase[s] + i0;
+      const uint32_t *IDt = p.ID[sel] + c.pbase[s] + i0;
+      const P alpha = (P)c.alpha[s];
+      const long long Z = c.Z[s];
+      const bool see = (s == 1) && (c.see_amp > 0.0) && (c.Z[1] > 0);
+      unsigned int n_pushed = 0, n_abs0 = 0, n_abs1 = 0;
+      // Each thread owns PPT consecutive slots per chunk, moved with 16-byte
+      // vector loads/stores; the next chunk's loads are in flight while this one
+      // is processed.  A chunk that straddles the end of the swept range goes
+      // slot by slot: slots past it may be receiving appended particles.
+      typedef typename Vec<P>::type V;
+      constexpr int VN = Vec<P>::n;   // particles per 16-byte vector
+      constexpr int NV = PPT / VN;    // vectors per thread per chunk
+      // deposit words: Z * 2^24 fits 32 bits for binary32 particles
+      typedef typename std::conditional<sizeof(P) == 8, long long, int>::type DepT;
+      constexpr int CH = BS * PPT;
+      V xa[NV], ua[NV], xb[NV], ub[NV];
+      // thread tid owns slots r0 + (v*BS + tid)*VN .. +VN-1 for v < NV
+      auto load_chunk = [&](int r0, V *xo, V *uo) {
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          ii[k] = i0 + r + (long long)k * BS + tid;
-          xv[k] = (P)-1;
-          uv[k] = (P)0;
-          if (ii[k] < cnt && ii[k] < i0 + tile) {
-            xv[k] = X[ii[k]];
-            uv[k] = U[ii[k]];
+        for (int v = 0; v < NV; ++v) {
+          const int i = r0 + (v * BS + tid) * VN;
+          if (i + VN <= n_here) {
+            xo[v] = *(const V *)(X + i);
+            uo[v] = *(const V *)(U + i);
+          } else {
+#pragma unroll
+            for (int k = 0; k < VN; ++k) {
+              Vec<P>::at(xo[v], k) = (i + k < n_here) ? X[i + k] : (P)-1;
+              Vec<P>::at(uo[v], k) = (i + k < n_here) ? U[i + k] : (P)0;
+            }
           }
+        }
+      };
+      load_chunk(0, xa, ua);
+      for (int r = 0; r < n_here; r += CH) {
+        if (r + CH < n_here) load_chunk(r + CH, xb, ub);
+        int jj[PPT];
+        DepT c0[PPT], c1[PPT];
+        unsigned int dep = 0, hit = 0;  // bit k: slot k deposits / is an absorbed ion (wall in bit k+16)
+        P u_hit[PPT];
+        V xw[NV], uw[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          xw[v] = xa[v];
+          uw[v] = ua[v];
         }
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-          P xi = xv[k];
-          if (!(xi >= (P)0)) continue;  // empty slot or absorbed earlier
-          n_pushed += 1;
-          // gather, then the leapfrog (eq. vel_update_main, eq. pos_update_main)
-          P Ep = gather<P>(sh.eh, xi, N);
-          P du = alpha * Ep;
-          P u1 = uv[k] + du;
-          P x1 = xi + u1;
-          int wall = -1;
-          if (x1 <= (P)0) wall = 0;
-          else if (x1 >= Nf) wall = 1;
-          if (wall >= 0) {
-            X[ii[k]] = (P)-1;
-            if (wall == 0) n_abs0 += 1;
-            else n_abs1 += 1;
-            if (see) {
-              const uint32_t id = p.ID[sel][c.pbase[s] + ii[k]];
-              int ne = emit_electrons<P>(p, c, st, g, sel, id, u1, wall);
-              if (ne) {
-                // an electron on the wall node carries its full weight there
-                const long long cw = (long long)c.Z[0] * Prec<P>::W;
-                for (int e = 0; e < ne; ++e) Acc<P>::add(sh.acc, gacc, wall == 0 ? 0 : N, cw);
-                if (wall == 0) n_em0 += ne;
-                else n_em1 += ne;
+          const int v = k / VN, kk = k % VN;
+          const P xi = Vec<P>::at(xa[v], kk);
+          jj[k] = 0;
+          c0[k] = c1[k] = 0;
+          u_hit[k] = (P)0;
+          if (xi >= (P)0) {  // empty slots and absorbed particles hold -1
+            n_pushed += 1;
+            // gather, then the leapfrog (eq. vel_update_main, eq. pos_update_main)
+            const P Ep = gather<P>(sh.eh, xi, N, Nf);
+            const P du = alpha * Ep;
+            const P u1 = Vec<P>::at(ua[v], kk) + du;
+            const P x1 = xi + u1;
+            const bool w0 = x1 <= (P)0;
+            const bool w1 = !w0 && x1 >= Nf;
+            if (w0 || w1) {
+              Vec<P>::at(xw[v], kk) = (P)-1;
+              n_abs0 += w0;
+              n_abs1 += w1;
+              hit |= (1u << k) | ((unsigned int)w1 << (k + 16));
+              u_hit[k] = u1;
+            } else {
+              Vec<P>::at(xw[v], kk) = x1;
+              Vec<P>::at(uw[v], kk) = u1;
+              // deposit with the gather's weights (App. C)
+              int j = (int)x1;
+              if (j > N - 1) j = N - 1;
+              const P f = x1 - (P)j;
+              const long long w1q = Prec<P>::wq(f);
+              const long long w0q = Prec<P>::W - w1q;
+              dep |= 1u << k;
+              jj[k] = j;
+              c0[k] = (DepT)(Z * w0q);
+              c1[k] = (DepT)(Z * w1q);
+            }
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const int i = r + (v * BS + tid) * VN;
+          if (i + VN <= n_here) {
+            *(V *)(X + i) = xw[v];
+            *(V *)(U + i) = uw[v];
+          } else {
+#pragma unroll
+            for (int k = 0; k < VN; ++k)
+              if (i + k < n_here) {
+                X[i + k] = Vec<P>::at(xw[v], k);
+                U[i + k] = Vec<P>::at(uw[v], k);
+              }
+          }
+        }
+        if constexpr (sizeof(cell) == 8) {
+#pragma unroll
+          for (int k = 0; k < PPT; ++k)
+            if (dep & (1u << k)) {
+              atomicAdd(&sh.acc[jj[k]], (unsigned long long)(long long)c0[k]);
+              atomicAdd(&sh.acc[jj[k] + 1], (unsigned long long)(long long)c1[k]);
+            }
+        } else {
+          // issue every returning add first, then look for wrapped cells
+          unsigned int o0[PPT], o1[PPT];
+#pragma unroll
+          for (int k = 0; k < PPT; ++k) {
+            o0[k] = o1[k] = 0u;
+            if (dep & (1u << k)) {
+              o0[k] = atomicAdd(&sh.acc[jj[k]], (unsigned int)(int)c0[k]);
+              o1[k] = atomicAdd(&sh.acc[jj[k] + 1], (unsigned int)(int)c1[k]);
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < PPT; ++k)
+            if (dep & (1u << k)) {
+              carry_add(gacc, jj[k], o0[k], c0[k]);
+              carry_add(gacc, jj[k] + 1, o1[k], c1[k]);
+            }
+        }
+        // absorbed ions are queued for secondary emission (k_source): in LDS,
+        // or straight to the gap's list when the workgroup's queue is full
+        if (see && hit != 0u) {
+#pragma unroll
+          for (int k = 0; k < PPT; ++k) {
+            if (!((hit >> k) & 1u)) continue;
+            Event ev;
+            ev.u = (double)u_hit[k];
+            ev.id = IDt[r + ((k / VN) * BS + tid) * VN + k % VN];
+            ev.wall = (hit >> (k + 16)) & 1u;
+            const unsigned int q = atomicAdd(sh.evq_n, 1u);
+            if (q < (unsigned int)EVQ) {
+              sh.evq[q] = ev;
+            } else {
+              const unsigned long long e = atomicAdd(&p.ev_count[g], 1ull);
+              if (e < (unsigned long long)c.evcap) {
+                p.ev[c.evbase + e] = ev;
+              } else {
+                atomicOr(&p.err[0], ERR_CAPACITY);
+                atomicCAS(&p.err[1], 0xFFFFFFFFu, (unsigned int)g);
               }
             }
-            continue;
           }
-          X[ii[k]] = x1;
-          U[ii[k]] = u1;
-          // deposit with the gather's weights (App. C)
-          int j = (int)x1;
-          if (j > N - 1) j = N - 1;
-          P f = x1 - (P)j;
-          long long w1 = Prec<P>::wq(f);
-          long long w0 = Prec<P>::W - w1;
-          Acc<P>::add(sh.acc, gacc, j, Z * w0);
-          Acc<P>::add(sh.acc, gacc, j + 1, Z * w1);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          xa[v] = xb[v];
+          ua[v] = ub[v];
         }
       }
       // wave-level sums, then one LDS atomic per wave
-      unsigned int v[5] = {n_pushed, n_abs0, n_abs1, n_em0, n_em1};
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        unsigned int a = v[q];
-        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-        v[q] = a;
+      const unsigned int v0 = wave_sum(n_pushed), v1 = wave_sum(n_abs0), v2 = wave_sum(n_abs1);
+      if (lane == 0) {
+        if (v0) atomicAdd(&sh.tally[T_PUSHED], v0);
+        if (v1) atomicAdd(&sh.tally[T_ABS + s * 2 + 0], v1);
+        if (v2) atomicAdd(&sh.tally[T_ABS + s * 2 + 1], v2);
       }
-      if ((tid & 63) == 0) {
-        if (v[0]) atomicAdd(&sh.tally[T_PUSHED], v[0]);
-        if (v[1]) atomicAdd(&sh.tally[T_ABS + s * 2 + 0], v[1]);
-        if (v[2]) atomicAdd(&sh.tally[T_ABS + s * 2 + 1], v[2]);
-        if (v[3]) atomicAdd(&sh.tally[T_EMIT + 0], v[3]);
-        if (v[4]) atomicAdd(&sh.tally[T_EMIT + 1], v[4]);
+    }
+  }
+  if (cur >= 0) flush_gap<P, AC>(p, p.gc[cur], cur, sh);
+}
+
+// ---------------------------------------------------------------------------
+// k_source: secondary emission of the ions the push absorbed (Alg. 2) and the
+// ion beam entering at the circuit electrode.  Their charge lands on the wall
+// nodes or within a few cells of node 0, so each workgroup accumulates it in a
+// small LDS window [0, SW) plus a cell for node N.
+// ---------------------------------------------------------------------------
+constexpr int SBS = 256;
+constexpr int SW = 256;
+
+__device__ inline void src_dep(unsigned long long *win, unsigned long long *gacc, int N, int j,
+                               long long c) {
+  if (j < SW)
+    atomicAdd(&win[j], (unsigned long long)c);
+  else if (j == N)
+    atomicAdd(&win[SW], (unsigned long long)c);
+  else
+    atomicAdd(&gacc[j], (unsigned long long)c);
+}
+
+__device__ inline void src_flush(const DevPtrs &p, const GapConst &c, int g, unsigned long long *win,
+                                 unsigned int *tally) {
+  __syncthreads();
+  unsigned long long *gacc = p.acc + c.nbase;
+  const int nw = min(SW, c.N + 1);
+  for (int j = threadIdx.x; j < nw; j += blockDim.x)
+    if (win[j]) atomicAdd(&gacc[j], win[j]);
+  if (threadIdx.x == 0 && c.N >= SW && win[SW]) atomicAdd(&gacc[c.N], win[SW]);
+  if (threadIdx.x < T_N && tally[threadIdx.x])
+    atomicAdd(&p.tally[(size_t)g * T_N + threadIdx.x], (unsigned long long)tally[threadIdx.x]);
+  __syncthreads();
+}
+
+template <class P>
+__global__ __launch_bounds__(SBS) void k_source(DevPtrs p, int G, int tile) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  int *prefix = (int *)lds_raw;  // [G + 1]
+  __shared__ unsigned long long win[SW + 1];
+  __shared__ unsigned int tally[T_N];
+  __shared__ int scan_sh[SBS];
+  __shared__ unsigned long long s_base;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int sel = (int)(*p.epoch & 1);
+  // tiles of gap g: its absorbed-ion events, then its beam
+  {
+    const int per = (G + SBS - 1) / SBS;
+    int mine = 0;
+    for (int q = 0; q < per; ++q) {
+      const int g = tid * per + q;
+      if (g < G) {
+        const long long ne = min((long long)p.ev_count[g], p.gc[g].evcap);
+        mine += (int)((ne + tile - 1) / tile + (p.gc[g].beam_n + tile - 1) / tile);
+      }
+    }
+    int tot;
+    int run = block_exclusive_scan<int>(mine, scan_sh, &tot);
+    for (int q = 0; q < per; ++q) {
+      const int g = tid * per + q;
+      if (g < G) {
+        prefix[g] = run;
+        const long long ne = min((long long)p.ev_count[g], p.gc[g].evcap);
+        run += (int)((ne + tile - 1) / tile + (p.gc[g].beam_n + tile - 1) / tile);
+      }
+    }
+    if (tid == 0) prefix[G] = tot;
+    __syncthreads();
+  }
+  const int total = prefix[G];
+  const int t0 = (int)(((long long)blockIdx.x * total) / gridDim.x);
+  const int t1 = (int)(((long long)(blockIdx.x + 1) * total) / gridDim.x);
+  int cur = -1, g = 0;
+  for (int t = t0; t < t1; ++t) {
+    while (prefix[g + 1] <= t) ++g;
+    const GapConst &c = p.gc[g];
+    const GapState &st = p.gs[g];
+    if (g != cur) {
+      if (cur >= 0) src_flush(p, p.gc[cur], cur, win, tally);
+      for (int j = tid; j <= SW; j += SBS) win[j] = 0ull;
+      if (tid < T_N) tally[tid] = 0u;
+      __syncthreads();
+      cur = g;
+    }
+    unsigned long long *gacc = p.acc + c.nbase;
+    const int N = c.N;
+    const long long nev = min((long long)p.ev_count[g], c.evcap);
+    const int tev = (int)((nev + tile - 1) / tile);
+    const int lt = t - prefix[g];
+    if (lt < tev) {
+      // secondary electrons: Poisson(gamma(E)) per ion, leaving the wall normally
+      P *X = (P *)p.X[sel] + c.pbase[0];
+      P *U = (P *)p.U[sel] + c.pbase[0];
+      uint32_t *ID = p.ID[sel] + c.pbase[0];
+      const long long cw = (long long)c.Z[0] * Prec<P>::W;
+      unsigned int em0 = 0, em1 = 0;
+      for (int r = 0; r < tile; r += SBS) {
+        const long long k = (long long)lt * tile + r + tid;
+        if ((long long)lt * tile + r >= nev) break;
+        int nk = 0, wall = 0;
+        uint32_t ion_id = 0;
+        uint64_t blk[4];
+        if (k < nev) {
+          const Event ev = p.ev[c.evbase + k];
+          ion_id = ev.id;
+          wall = (int)ev.wall;
+          const double v_ion = (ev.u * c.dx) / c.dt;
+          const double e_ion = 0.5 * c.mass[1] * v_ion * v_ion / c.ev;
+          const double rr = e_ion / c.see_E0;
+          double lam = c.see_amp * rr / (1.0 + rr);
+          if (lam < 0.0) lam = 0.0;
+          rng_block(c.seed, (uint64_t)st.level, (uint64_t)ion_id, 1, 0, blk);
+          nk = poisson_inverse(lam, unit_open(blk[0]), c.see_max);
+        }
+        // one slot reservation per workgroup for this round's electrons
+        int btot;
+        const int excl = block_exclusive_scan<int>(nk, scan_sh, &btot);
+        if (btot == 0) continue;
+        if (tid == 0) s_base = atomicAdd(&p.next_count[g * 2 + 0], (unsigned long long)btot);
+        __syncthreads();
+        const unsigned long long base = s_base;
+        const int incl = excl + nk;
+        __syncthreads();
+        const P xw = wall == 0 ? (P)0 : (P)N;
+        const int jn = wall == 0 ? 0 : N;
+        for (int e = 0; e < nk; ++e) {
+          const int slotw = e + 1;  // word 0 of block 0 drew the count
+          if ((slotw & 3) == 0)
+            rng_block(c.seed, (uint64_t)st.level, (uint64_t)ion_id, 1, (uint64_t)(slotw >> 2), blk);
+          const double uu = unit_open(blk[slotw & 3]);
+          const double E_se = (c.see_law == GS_SEE_EXP) ? -c.see_E * log(uu) : c.see_E;
+          const double v_se = sqrt(2.0 * E_se * c.ev / c.mass[0]);
+          const double v_si = wall == 0 ? v_se : -v_se;
+          const unsigned long long sl = base + (unsigned long long)(incl - nk + e);
+          if (sl >= (unsigned long long)c.cap[0]) {
+            atomicOr(&p.err[0], ERR_CAPACITY);
+            atomicCAS(&p.err[1], 0xFFFFFFFFu, (unsigned int)g);
+            continue;
+          }
+          X[sl] = xw;
+          U[sl] = (P)((v_si * c.dt) / c.dx);
+          ID[sl] = NO_ID;
+          // an electron on the wall node carries its full weight there
+          src_dep(win, gacc, N, jn, cw);
+          if (wall == 0) ++em0;
+          else ++em1;
+        }
+      }
+      const unsigned int a0 = wave_sum(em0), a1 = wave_sum(em1);
+      if (lane == 0) {
+        if (a0) atomicAdd(&tally[T_EMIT + 0], a0);
+        if (a1) atomicAdd(&tally[T_EMIT + 1], a1);
       }
     } else {
-      // beam ions entering at the circuit electrode
-      lt -= te + ti;
+      // beam ions entering at the circuit electrode, a random fraction of one
+      // step's flight into the gap
+      const int lb = lt - tev;
       P *X = (P *)p.X[sel] + c.pbase[1];
       P *U = (P *)p.U[sel] + c.pbase[1];
       uint32_t *ID = p.ID[sel] + c.pbase[1];
       unsigned int n_inj = 0;
-      for (int r = tid; r < tile; r += BS) {
-        const long long k = (long long)lt * tile + r;
-        const bool valid = k < c.beam_n;
-        const unsigned long long mask = __ballot(valid);
-        if (mask == 0ull) break;
-        const int lane = tid & 63;
-        const int first = __ffsll((long long)mask) - 1;
-        const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-        unsigned long long base = 0;
-        if (lane == first) base = reserve(&p.next_count[g * 2 + 1], (unsigned int)__popcll(mask));
-        base = __shfl(base, first);
-        if (!valid) continue;
+      for (int r = tid; r < tile; r += SBS) {
+        const long long k = (long long)lb * tile + r;
+        if (k >= c.beam_n) break;
         uint64_t blk[4];
         rng_block(c.seed, (uint64_t)st.level, (uint64_t)k, 2, 0, blk);
         const double E = c.beam_Emin + (c.beam_Emax - c.beam_Emin) * unit_open(blk[0]);
@@ -721,7 +1047,8 @@ __global__ __launch_bounds__(BS) void k_push(DevPtrs p, int G, int tile, int nma
         const double x = unit_open(blk[1]) * v * c.dt;
         const P xi = (P)(x / c.dx);
         const P u = (P)((v * c.dt) / c.dx);
-        const unsigned long long slot = base + (unsigned long long)rank;
+        // slots count[1] .. count[1] + beam_n - 1 were set aside by the field solve
+        const unsigned long long slot = (unsigned long long)st.count[1] + (unsigned long long)k;
         if (slot >= (unsigned long long)c.cap[1]) {
           atomicOr(&p.err[0], ERR_CAPACITY);
           atomicCAS(&p.err[1], 0xFFFFFFFFu, (unsigned int)g);
@@ -733,23 +1060,24 @@ __global__ __launch_bounds__(BS) void k_push(DevPtrs p, int G, int tile, int nma
         n_inj += 1;
         int j = (int)xi;
         if (j > N - 1) j = N - 1;
-        P f = xi - (P)j;
-        long long w1 = Prec<P>::wq(f);
-        long long w0 = Prec<P>::W - w1;
-        Acc<P>::add(sh.acc, gacc, j, c.Z[1] * w0);
-        Acc<P>::add(sh.acc, gacc, j + 1, c.Z[1] * w1);
+        const P f = xi - (P)j;
+        const long long w1 = Prec<P>::wq(f);
+        const long long w0 = Prec<P>::W - w1;
+        src_dep(win, gacc, N, j, (long long)c.Z[1] * w0);
+        src_dep(win, gacc, N, j + 1, (long long)c.Z[1] * w1);
       }
-      unsigned int a = n_inj;
-      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-      if ((tid & 63) == 0 && a) atomicAdd(&sh.tally[T_INJ], a);
+      const unsigned int a = wave_sum(n_inj);
+      if (lane == 0 && a) atomicAdd(&tally[T_INJ], a);
     }
   }
-  if (cur >= 0) flush_gap<P>(p, p.gc[cur], cur, sh);
+  if (cur >= 0) src_flush(p, p.gc[cur], cur, win, tally);
 }
 
 // ---------------------------------------------------------------------------
-// k_compact: copy live slots of every (gap, species) region into the other
-// buffer; order inside a region is not kept (nothing depends on it)
+// k_compact: copy the live slots of every (gap, species) region into the other
+// buffer.  Each workgroup owns a contiguous run of tiles: it counts the live
+// slots of each region in its run, reserves them with one atomic per region,
+// then writes them.  Order inside a region is not kept (nothing depends on it).
 // ---------------------------------------------------------------------------
 template <class P, int BS>
 __global__ __launch_bounds__(BS) void k_compact(DevPtrs p, int G, int tile) {
@@ -757,74 +1085,81 @@ __global__ __launch_bounds__(BS) void k_compact(DevPtrs p, int G, int tile) {
   int *prefix = (int *)lds_raw;  // [2G + 1]
   __shared__ int scan_sh[BS];
   __shared__ unsigned int wave_cnt[BS / 64];
-  __shared__ unsigned long long blk_base;
-  const int tid = threadIdx.x;
+  __shared__ unsigned long long seg_base;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int src = (int)(*p.epoch & 1), dst = src ^ 1;
   const int R = 2 * G;
-  const int per = (R + BS - 1) / BS;
-  int mine = 0;
-  for (int q = 0; q < per; ++q) {
-    const int r = tid * per + q;
-    if (r < R) mine += (int)(((long long)p.next_count[r] + tile - 1) / tile);
-  }
-  int total_t;
-  int run = block_exclusive_scan_int(mine, scan_sh, &total_t);
-  for (int q = 0; q < per; ++q) {
-    const int r = tid * per + q;
-    if (r < R) {
-      prefix[r] = run;
-      run += (int)(((long long)p.next_count[r] + tile - 1) / tile);
+  {
+    const int per = (R + BS - 1) / BS;
+    int mine = 0;
+    for (int q = 0; q < per; ++q) {
+      const int r = tid * per + q;
+      if (r < R) mine += (int)((min((long long)p.next_count[r], p.gc[r >> 1].cap[r & 1]) + tile - 1) / tile);
     }
-  }
-  if (tid == 0) prefix[R] = total_t;
-  __syncthreads();
-  const int total = prefix[2 * G];
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
-    int lo = 0, hi = 2 * G;  // find region r with prefix[r] <= t < prefix[r+1]
-    while (hi - lo > 1) {
-      int mid = (lo + hi) / 2;
-      if (prefix[mid] <= t) lo = mid;
-      else hi = mid;
+    int total_t;
+    int run = block_exclusive_scan<int>(mine, scan_sh, &total_t);
+    for (int q = 0; q < per; ++q) {
+      const int r = tid * per + q;
+      if (r < R) {
+        prefix[r] = run;
+        run += (int)((min((long long)p.next_count[r], p.gc[r >> 1].cap[r & 1]) + tile - 1) / tile);
+      }
     }
-    const int r = lo;
+    if (tid == 0) prefix[R] = total_t;
+    __syncthreads();
+  }
+  const int total = prefix[R];
+  const int t0 = (int)(((long long)blockIdx.x * total) / gridDim.x);
+  const int t1 = (int)(((long long)(blockIdx.x + 1) * total) / gridDim.x);
+  int r = 0;
+  for (int t = t0; t < t1;) {
+    while (prefix[r + 1] <= t) ++r;
+    const int tend = min(t1, prefix[r + 1]);
     const int g = r >> 1, s = r & 1;
     const GapConst &c = p.gc[g];
-    const long long n = (long long)p.next_count[g * 2 + s];
-    const long long i0 = (long long)(t - prefix[r]) * tile;
+    const long long n = min((long long)p.next_count[r], c.cap[s]);
+    const long long i_beg = (long long)(t - prefix[r]) * tile;
+    const long long i_end = min(n, (long long)(tend - prefix[r]) * tile);
     const P *Xs = (const P *)p.X[src] + c.pbase[s];
+    // pass 1: live slots of this region in the run
+    int cnt = 0;
+    for (long long i = i_beg + tid; i < i_end; i += BS) cnt += Xs[i] >= (P)0;
+    int tot_live;
+    (void)block_exclusive_scan<int>(cnt, scan_sh, &tot_live);
+    if (tid == 0)
+      seg_base = tot_live ? atomicAdd(&p.cursor[r], (unsigned long long)tot_live) : 0ull;
+    __syncthreads();
+    const unsigned long long base = seg_base;
+    // pass 2: write them, in order of the run
     const P *Us = (const P *)p.U[src] + c.pbase[s];
     const uint32_t *Is = p.ID[src] + c.pbase[s];
     P *Xd = (P *)p.X[dst] + c.pbase[s];
     P *Ud = (P *)p.U[dst] + c.pbase[s];
     uint32_t *Id = p.ID[dst] + c.pbase[s];
-    for (int rr = 0; rr < tile; rr += BS) {
-      const long long i = i0 + rr + tid;
-      P x = (P)-1;
-      if (i < n && rr + tid < tile) x = Xs[i];
+    unsigned long long written = 0;
+    for (long long i0 = i_beg; i0 < i_end; i0 += BS) {
+      const long long i = i0 + tid;
+      const P x = i < i_end ? Xs[i] : (P)-1;
       const bool live = x >= (P)0;
       const unsigned long long mask = __ballot(live);
-      const int lane = tid & 63, w = tid >> 6;
       if (lane == 0) wave_cnt[w] = (unsigned int)__popcll(mask);
       __syncthreads();
-      if (tid == 0) {
-        unsigned int tot = 0;
-        for (int q = 0; q < BS / 64; ++q) {
-          unsigned int a = wave_cnt[q];
-          wave_cnt[q] = tot;
-          tot += a;
-        }
-        blk_base = tot ? atomicAdd(&p.cursor[g * 2 + s], (unsigned long long)tot) : 0ull;
+      unsigned int before = 0, all = 0;
+      for (int q = 0; q < BS / 64; ++q) {
+        if (q < w) before += wave_cnt[q];
+        all += wave_cnt[q];
       }
-      __syncthreads();
       if (live) {
         const unsigned long long o =
-            blk_base + wave_cnt[w] + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
+            base + written + before + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
         Xd[o] = x;
         Ud[o] = Us[i];
         Id[o] = Is[i];
       }
+      written += all;
       __syncthreads();
     }
+    t = tend;
   }
 }
 
@@ -853,8 +1188,9 @@ __global__ void k_inject(DevPtrs p, int gap, int species, long long n, const dou
   const int lane = threadIdx.x & 63;
   const int first = __ffsll((long long)mask) - 1;
   unsigned long long base = 0;
-  if (lane == first) base = atomicAdd(&p.next_count[gap * 2 + species], (unsigned long long)__popcll(mask));
-  base = __shfl(base, first);
+  if (lane == first)
+    base = atomicAdd(&p.next_count[gap * 2 + species], (unsigned long long)__popcll(mask));
+  base = __shfl(base, first, 64);
   if (!valid) return;
   if (i == 0) {
     atomicAdd((unsigned long long *)&p.gs[gap].live[species], (unsigned long long)n);
@@ -879,42 +1215,41 @@ __global__ void k_inject(DevPtrs p, int gap, int species, long long n, const dou
   p.ID[sel][k] = (uint32_t)(id0 + i);
   int j = (int)xi;
   if (j > c.N - 1) j = c.N - 1;
-  P f = xi - (P)j;
-  long long w1 = Prec<P>::wq(f);
-  long long w0 = Prec<P>::W - w1;
+  const P f = xi - (P)j;
+  const long long w1 = Prec<P>::wq(f);
+  const long long w0 = Prec<P>::W - w1;
   unsigned long long *gacc = p.acc + c.nbase;
   atomicAdd(&gacc[j], (unsigned long long)(c.Z[species] * w0));
   atomicAdd(&gacc[j + 1], (unsigned long long)(c.Z[species] * w1));
 }
 
 // phi_i = dx sum_{k >= i} E_{k+1/2}, phi_N = 0 (one gap, one workgroup)
-__global__ __launch_bounds__(FBS) void k_phi(DevPtrs p, int gap) {
+constexpr int PBS = 256;
+__global__ __launch_bounds__(PBS) void k_phi(DevPtrs p, int gap) {
   const GapConst &c = p.gc[gap];
-  __shared__ double sh[FBS];
+  __shared__ double sh[PBS];
   const int N = c.N, tid = threadIdx.x;
   const double *E = p.E64 + c.nbase;
   double *phi = p.phi64 + c.nbase;
-  const int chunk = (N + FBS - 1) / FBS;
-  // thread t owns the reversed range
+  const int chunk = (N + PBS - 1) / PBS;
+  // thread t owns reversed positions k0..k1-1, i.e. nodes N-1-k counted from the ground
   const int k0 = tid * chunk, k1 = min(k0 + chunk, N);
   double loc = 0.0;
-  for (int k = k1 - 1; k >= k0; --k) loc += c.dx * E[N - 1 - k];
+  for (int k = k0; k < k1; ++k) loc += c.dx * E[N - 1 - k];
   double tot;
-  double run = block_exclusive_scan(loc, sh, &tot);
+  double run = block_exclusive_scan<double>(loc, sh, &tot);
   for (int k = k0; k < k1; ++k) {
-    // reversed index m = N - 1 - k walks down from the grounded end
     run += c.dx * E[N - 1 - k];
     phi[N - 1 - k] = run;
   }
-  (void)tot;
   if (tid == 0) phi[N] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-size_t push_lds_bytes(int nmax, int fp64, int G) {
-  const size_t ps = fp64 ? 8 : 4, cs = fp64 ? 8 : 4;
+size_t push_lds_bytes(int nmax, int fp64, int G, int wide) {
+  const size_t ps = fp64 ? 8 : 4, cs = (fp64 || wide) ? 8 : 4;
   size_t off = 64 + (((size_t)(G + 1) * 4 + 15) / 16) * 16;
   off += (((size_t)(nmax + 2) * ps + 15) / 16) * 16;
   off += (size_t)(nmax + 1) * cs;
@@ -922,43 +1257,68 @@ size_t push_lds_bytes(int nmax, int fp64, int G) {
 }
 
 hipError_t launch_field(const DevPtrs &p, int G, int mode, int guess, double tol, int maxit,
-                        int fp64, hipStream_t s) {
-  hipLaunchKernelGGL(k_field, dim3(G), dim3(FBS), 0, s, p, mode, guess, tol, maxit, fp64);
+                        int fp64, int nmax, hipStream_t s) {
+  const size_t lds = (size_t)nmax * 8;
+  static size_t attr_set = 32768;
+  if (lds > attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_field, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = lds;
+  }
+  hipLaunchKernelGGL(k_field, dim3(G), dim3(FBS), lds, s, p, mode, guess, tol, maxit, fp64);
   return hipGetLastError();
 }
 
-template <class P, int BS, int PPT>
+template <class P, class AC, int BS, int PPT>
 static hipError_t push_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s) {
-  const size_t lds = push_lds_bytes(lc.nmax, lc.fp64, G);
+  const size_t lds = push_lds_bytes(lc.nmax, lc.fp64, G, sizeof(typename AC::cell) == 8);
   // opt in to more than 64 KiB of dynamic LDS (gfx950 has 160 KiB per CU)
   static size_t attr_set = 65536;
   if (lds > attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_push<P, BS, PPT>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_push<P, AC, BS, PPT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_set = lds;
   }
-  hipLaunchKernelGGL((k_push<P, BS, PPT>), dim3(lc.grid), dim3(BS), lds, s, p, G, lc.tile, lc.nmax);
+  hipLaunchKernelGGL((k_push<P, AC, BS, PPT>), dim3(lc.grid), dim3(BS), lds, s, p, G, lc.tile, lc.nmax);
   return hipGetLastError();
 }
 
-hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s) {
-  if (lc.fp64) {
-    switch (lc.block) {
-      case 256: return push_t<double, 256, 2>(p, G, lc, s);
-      case 512: return push_t<double, 512, 2>(p, G, lc, s);
-      default: return push_t<double, 1024, 2>(p, G, lc, s);
-    }
-  }
+template <class P, class AC, int PPT>
+static hipError_t push_bp(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s) {
   switch (lc.block) {
-    case 256: return push_t<float, 256, 4>(p, G, lc, s);
-    case 512: return push_t<float, 512, 4>(p, G, lc, s);
-    default: return push_t<float, 1024, 4>(p, G, lc, s);
+    case 256: return push_t<P, AC, 256, PPT>(p, G, lc, s);
+    case 512: return push_t<P, AC, 512, PPT>(p, G, lc, s);
+    default: return push_t<P, AC, 1024, PPT>(p, G, lc, s);
   }
 }
 
+template <class P, class AC>
+static hipError_t push_b(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s) {
+  if (lc.ppt >= 2 * Vec<P>::n) return push_bp<P, AC, 2 * Vec<P>::n>(p, G, lc, s);
+  return push_bp<P, AC, Vec<P>::n>(p, G, lc, s);
+}
+
+hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s) {
+  if (lc.fp64) return push_b<double, Wide64>(p, G, lc, s);
+  if (lc.wide) return push_b<float, Wide64>(p, G, lc, s);
+  return push_b<float, Carry32>(p, G, lc, s);
+}
+
+hipError_t launch_source(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s) {
+  const int grid = lc.source_grid > 0 ? lc.source_grid : 256;
+  const size_t lds = ((size_t)(G + 1) * 4 + 15) / 16 * 16;
+  const int tile = SBS;
+  if (lc.fp64)
+    hipLaunchKernelGGL(k_source<double>, dim3(grid), dim3(SBS), lds, s, p, G, tile);
+  else
+    hipLaunchKernelGGL(k_source<float>, dim3(grid), dim3(SBS), lds, s, p, G, tile);
+  return hipGetLastError();
+}
+
 hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s) {
-  const int grid = lc.grid > 0 ? lc.grid * 2 : 1024;
+  const int grid = lc.compact_grid > 0 ? lc.compact_grid : 1024;
   const size_t lds = ((size_t)(2 * G + 1) * 4 + 15) / 16 * 16;
   if (lc.fp64)
     hipLaunchKernelGGL((k_compact<double, 256>), dim3(grid), dim3(256), lds, s, p, G, lc.tile);
@@ -983,7 +1343,7 @@ hipError_t launch_inject(const DevPtrs &p, int gap, int species, long long n, co
 }
 
 hipError_t launch_phi(const DevPtrs &p, int gap, hipStream_t s) {
-  hipLaunchKernelGGL(k_phi, dim3(1), dim3(FBS), 0, s, p, gap);
+  hipLaunchKernelGGL(k_phi, dim3(1), dim3(PBS), 0, s, p, gap);
   return hipGetLastError();
 }
 

@@ -7,8 +7,10 @@ library is missing or no GPU is present, construction fails loudly.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from typing import Iterable, List, Optional, Sequence, Union
 
 import numpy as np
@@ -20,7 +22,7 @@ MAX_MESH = 8
 GS_OK, GS_EINVAL, GS_ENOMEM, GS_ECAPACITY, GS_EDEVICE, GS_ENOCONV, GS_ESTATE = 0, -1, -2, -3, -4, -5, -6
 GUESS_DIRECT, GUESS_EXTRAP, GUESS_MLP = 0, 1, 2
 OPT_BLOCK, OPT_TILE, OPT_GRID, OPT_COMPACT_EVERY, OPT_GRAPH, OPT_TIMING = 1, 2, 3, 4, 5, 6
-OPT_NEWTON_TOL, OPT_NEWTON_MAXIT = 7, 8
+OPT_NEWTON_TOL, OPT_NEWTON_MAXIT, OPT_DEPOSIT, OPT_COMPACT_GRID, OPT_PPT = 7, 8, 9, 10, 11
 
 EXPORTED = [
     "gs_init", "gs_destroy", "gs_inject", "gs_step_strict", "gs_step_weak", "gs_read_diagnostics",
@@ -76,7 +78,9 @@ class GsDiag(C.Structure):
 class GsTiming(C.Structure):
     _fields_ = [
         ("push_ms", C.c_double), ("field_ms", C.c_double), ("compact_ms", C.c_double),
+        ("source_ms", C.c_double),
         ("push_launches", C.c_int64), ("field_launches", C.c_int64), ("compact_launches", C.c_int64),
+        ("source_launches", C.c_int64),
     ]
 
 
@@ -168,6 +172,19 @@ def validate(cfg, particle_fp: int = 32, capacity=(1 << 20, 1 << 20)) -> Optiona
     return None if rc == GS_OK else buf.value.decode()
 
 
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # release device memory while torch is still importable
+    for sim in list(_live):
+        try:
+            sim.close()
+        except Exception:
+            pass
+
+
 class GapSim:
     """Gaps advanced together on one GPU stream."""
 
@@ -193,12 +210,21 @@ class GapSim:
         if torch_alloc:
             dev_index = self.device.index
             stream_handle = self.stream
+            # bound now: at interpreter exit the torch module may already be gone
+            alloc_fn = torch.cuda.caching_allocator_alloc
+            delete_fn = torch.cuda.caching_allocator_delete
 
             def _a(nbytes, user):
-                return torch.cuda.caching_allocator_alloc(int(nbytes), dev_index, stream_handle)
+                try:
+                    return alloc_fn(int(nbytes), dev_index, stream_handle)
+                except Exception:
+                    return None
 
             def _r(ptr, user):
-                torch.cuda.caching_allocator_delete(ptr)
+                try:
+                    delete_fn(ptr)
+                except Exception:
+                    pass
 
             self._alloc = GsAllocator(ALLOC_FN(_a), RELEASE_FN(_r), None)
             alloc_p = C.byref(self._alloc)
@@ -207,6 +233,7 @@ class GapSim:
         if rc != GS_OK:
             raise GapsimError(rc, lib().gs_last_error(None).decode())
         self._h = h
+        _live.add(self)
 
     # -- helpers ----------------------------------------------------------
     def _chk(self, rc: int):
@@ -218,6 +245,7 @@ class GapSim:
         if h is not None and h.value:
             lib().gs_destroy(h)
         self._h = None
+        _live.discard(self)
 
     def __del__(self):
         try:
@@ -302,5 +330,6 @@ class GapSim:
         T = GsTiming()
         self._chk(lib().gs_get_timing(self._h, C.byref(T), 1 if reset else 0))
         return dict(push_ms=T.push_ms, field_ms=T.field_ms, compact_ms=T.compact_ms,
-                    push_launches=T.push_launches, field_launches=T.field_launches,
-                    compact_launches=T.compact_launches)
+                    source_ms=T.source_ms, push_launches=T.push_launches,
+                    field_launches=T.field_launches, compact_launches=T.compact_launches,
+                    source_launches=T.source_launches)

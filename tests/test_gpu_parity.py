@@ -249,8 +249,14 @@ def test_launch_shapes_and_graph_agree():
     variants = [
         {gs.OPT_COMPACT_EVERY: 8, gs.OPT_GRAPH: 1},
         {gs.OPT_COMPACT_EVERY: 1},
-        {gs.OPT_COMPACT_EVERY: 5, gs.OPT_BLOCK: 512, gs.OPT_TILE: 512 * 4},
-        {gs.OPT_COMPACT_EVERY: 3, gs.OPT_BLOCK: 1024, gs.OPT_TILE: 1024 * 12, gs.OPT_GRID: 7},
+        {gs.OPT_COMPACT_EVERY: 5, gs.OPT_BLOCK: 512, gs.OPT_TILE: 512 * 8, gs.OPT_DEPOSIT: 2},
+        {gs.OPT_COMPACT_EVERY: 6, gs.OPT_PPT: 2, gs.OPT_TILE: 512 * 24},
+        {gs.OPT_COMPACT_EVERY: 7, gs.OPT_PPT: 2, gs.OPT_DEPOSIT: 2, gs.OPT_BLOCK: 256},
+        {gs.OPT_COMPACT_EVERY: 3, gs.OPT_BLOCK: 1024, gs.OPT_TILE: 1024 * 16, gs.OPT_GRID: 7,
+         gs.OPT_DEPOSIT: 1},
+        {gs.OPT_COMPACT_EVERY: 2, gs.OPT_BLOCK: 256, gs.OPT_TILE: 256 * 24, gs.OPT_DEPOSIT: 2,
+         gs.OPT_COMPACT_GRID: 3},
+        {gs.OPT_COMPACT_EVERY: 4, gs.OPT_GRAPH: 1, gs.OPT_DEPOSIT: 2, gs.OPT_GRID: 33},
     ]
     for opts in variants:
         d, E, ions, els = _cfg2_state(opts)
