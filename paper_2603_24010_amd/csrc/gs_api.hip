@@ -376,7 +376,7 @@ static gs_status setup(gs_ctx *ctx) {
   HIPCHK(ctx, hipDeviceGetAttribute(&ctx->ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
   ctx->lc.fp64 = ctx->fp64;
   ctx->lc.nmax = ctx->nmax;
-  ctx->lc.block = 512;
+  ctx->lc.block = 256;
   ctx->lc.tile = ctx->lc.block * 16;
   ctx->lc.wide = 1;
   ctx->lc.compact_grid = 4 * ctx->ncu;
