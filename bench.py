@@ -13,6 +13,8 @@ CPU oracle timed on a bounded sample on the host.
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +28,13 @@ if ROOT not in sys.path:
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 BYTES_PER_PUSH_F32 = 16  # read x, v and write x, v (binary32)
+
+# HBM traffic of the push kernel, taken with rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs of this script; it is reported only while the sources it was measured
+# on are unchanged and the run is the one that was measured.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_push_traffic_beam_gap_4096c_2e7p_weak.json")
+KERNEL_SOURCES = ["paper_2603_24010_amd/csrc/gs_kernels.hip", "paper_2603_24010_amd/csrc/gs_api.hip",
+                  "paper_2603_24010_amd/csrc/gs_internal.h"]
 
 WORKLOADS = {
     # name: (config builder kwargs, initial H+ count, coupling)
@@ -58,6 +67,59 @@ def make_sim(name, spec, total_steps):
     for sp, (x, v) in loads.items():
         sim.inject(0, sp, x, v)
     return sim, cfg, loads
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload, steps, warmup, compact_every, tuned):
+    """Bytes per push launch from the committed counter record, or None."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    run = rec.get("run", {})
+    if (rec.get("source_sha256") != kernel_source_hash() or tuned
+            or run != {"workload": workload, "steps": steps, "warmup": warmup, "compact_every": compact_every}):
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def _counter_rows(path, counter):
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                yield int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])
+
+
+def pmc_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mb, kernel, last_n):
+    """Per-launch HBM bytes of `kernel` over its last `last_n` dispatches.
+
+    FETCH_SIZE / WRITE_SIZE (KiB per dispatch) are scaled by what the same
+    counter reads for a plain device copy of copy_mb MiB, so the result is in
+    bytes that the copy itself moved.
+    """
+    copy_bytes = copy_mb * (1 << 20)
+    factors = []
+    for path, counter in ((copy_fetch_csv, "FETCH_SIZE"), (copy_write_csv, "WRITE_SIZE")):
+        vals = [v for _, k, v in _counter_rows(path, counter) if "copyBuffer" in k]
+        vals = [v for v in vals if v * 1024 > copy_bytes / 8]  # the 1 GiB copies, not small staging ones
+        factors.append(copy_bytes / (sum(vals) / len(vals) * 1024))
+    out = {}
+    for (path, counter), fac, key in zip(((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")), factors,
+                                         ("fetch", "write")):
+        rows = sorted((d, v) for d, k, v in _counter_rows(path, counter) if k.startswith(kernel))
+        rows = rows[-last_n:]
+        out[f"{key}_bytes_per_launch"] = sum(v for _, v in rows) / len(rows) * 1024 * fac
+        out[f"{key}_copy_factor"] = fac
+        out[f"{key}_launches"] = len(rows)
+    return out
 
 
 def cpu_baseline(spec, steps: int):
@@ -100,7 +162,20 @@ def main():
     ap.add_argument("--copy-reference-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times): the "
                          "reference that scales rocprof's FETCH_SIZE / WRITE_SIZE to bytes")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="no GPU work: reduce rocprofv3 counter CSVs of a bench run (same --steps) and of a "
+                         "--copy-reference-mb 1024 run to the push kernel's bytes per launch, and write the record "
+                         "that later bench runs report as roofline.traffic")
     args = ap.parse_args()
+    if args.pmc_summary:
+        rec = pmc_summary(*args.pmc_summary, copy_mb=1024, kernel="k_push", last_n=args.steps)
+        rec["source_sha256"] = kernel_source_hash()
+        rec["run"] = {"workload": args.workload, "steps": args.steps, "warmup": args.warmup,
+                      "compact_every": args.compact_every}
+        with open(TRAFFIC_RECORD, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this method has no multi-GPU path in this build "
               "(independent gaps would shard across GPUs with no exchange)", file=sys.stderr)
@@ -132,6 +207,7 @@ def main():
         sim.set_option(gapsim.OPT_DEPOSIT, args.deposit)
     if args.ppt:
         sim.set_option(gapsim.OPT_PPT, args.ppt)
+    tuned = bool(args.block or args.tile or args.grid or args.deposit or args.ppt or args.graph)
     mode = spec["mode"]
     log(f"[bench] warmup {args.warmup} steps")
     sim.step(mode, args.warmup)
@@ -158,6 +234,7 @@ def main():
     value = pushed / el
     push_s = tm["push_ms"] * 1e-3
     achieved = BYTES_PER_PUSH_F32 * pushed / push_s / 1e9 if push_s > 0 else None
+    traffic = recorded_traffic(args.workload, args.steps, args.warmup, args.compact_every, tuned)
     out = {
         "metric": "particle-steps/s",
         "value": value,
@@ -176,11 +253,13 @@ def main():
                    "particles": "binary32", "field_circuit": "binary64",
                    "live_particles_end": int(d1["n_live"].sum())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel": "k_push", "bytes_per_particle_step": BYTES_PER_PUSH_F32,
+                     "algorithmic_bytes_per_launch": BYTES_PER_PUSH_F32 * pushed / max(1, tm["push_launches"]),
                      "avg_launch_ms": tm["push_ms"] / max(1, tm["push_launches"]),
                      "launches": tm["push_launches"]},
-        "timed_with": "hip graphs" if args.graph else "eager launches, HIP events per kernel",
+        "timed_with": "hip graphs" if args.graph else "eager launches, HIP events recorded by each kernel's dispatch",
         "kernel_ms_per_step": {"push": tm["push_ms"] / args.steps, "field": tm["field_ms"] / args.steps,
                                "source": tm["source_ms"] / args.steps,
                                "compact": tm["compact_ms"] / args.steps},

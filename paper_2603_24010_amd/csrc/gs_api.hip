@@ -526,30 +526,32 @@ static hipEvent_t ev_get(gs_ctx *ctx) {
   return e;
 }
 
+// Runs launch(t); when timing is on, t carries two events that the kernel's
+// own dispatch packets record, so the elapsed time is the kernel's alone.
 template <class F>
 static hipError_t timed(gs_ctx *ctx, int kind, F &&launch) {
-  if (!ctx->timing) return launch();
-  hipEvent_t a = ev_get(ctx), b = ev_get(ctx);
-  (void)hipEventRecord(a, ctx->stream);
-  hipError_t e = launch();
-  (void)hipEventRecord(b, ctx->stream);
-  ctx->pend.push_back({kind, a, b});
+  if (!ctx->timing) return launch(KTime{});
+  KTime t;
+  t.a = ev_get(ctx);
+  t.b = ev_get(ctx);
+  hipError_t e = launch(t);
+  ctx->pend.push_back({kind, t.a, t.b});
   return e;
 }
 
 static gs_status one_step(gs_ctx *ctx, int mode, int guess) {
-  hipError_t e = timed(ctx, 1, [&] {
+  hipError_t e = timed(ctx, 1, [&](KTime t) {
     return launch_field(ctx->dp, ctx->G, mode, guess, ctx->newton_tol, ctx->newton_maxit, ctx->fp64,
-                        ctx->nmax, ctx->stream);
+                        ctx->nmax, ctx->stream, t);
   });
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "field launch: %s", hipGetErrorString(e));
-  e = timed(ctx, 0, [&] { return launch_push(ctx->dp, ctx->G, ctx->lc, ctx->stream); });
+  e = timed(ctx, 0, [&](KTime t) { return launch_push(ctx->dp, ctx->G, ctx->lc, ctx->stream, t); });
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "push launch: %s", hipGetErrorString(e));
-  e = timed(ctx, 3, [&] { return launch_source(ctx->dp, ctx->G, ctx->lc, ctx->stream); });
+  e = timed(ctx, 3, [&](KTime t) { return launch_source(ctx->dp, ctx->G, ctx->lc, ctx->stream, t); });
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "source launch: %s", hipGetErrorString(e));
   ctx->since_compact += 1;
   if (ctx->since_compact >= ctx->compact_every) {
-    e = timed(ctx, 2, [&] { return launch_compact(ctx->dp, ctx->G, ctx->lc, ctx->stream); });
+    e = timed(ctx, 2, [&](KTime t) { return launch_compact(ctx->dp, ctx->G, ctx->lc, ctx->stream, t); });
     if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "compact launch: %s", hipGetErrorString(e));
     ctx->since_compact = 0;
     ctx->epoch += 1;

@@ -123,11 +123,18 @@ struct LaunchCfg {
 };
 
 // launchers (gs_kernels.hip)
+// Optional timing: when `a` is set, the start and end of the launched kernel(s)
+// are recorded into these events by the dispatch packets themselves
+// (hipExtLaunchKernel), so the elapsed time holds no launch latency.
+struct KTime {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
 hipError_t launch_field(const DevPtrs &p, int G, int mode, int guess, double newton_tol,
-                        int newton_maxit, int fp64, int nmax, hipStream_t s);
-hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s);
-hipError_t launch_source(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s);
-hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s);
+                        int newton_maxit, int fp64, int nmax, hipStream_t s, KTime t = {});
+hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t = {});
+hipError_t launch_source(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t = {});
+hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t = {});
 hipError_t launch_inject(const DevPtrs &p, int gap, int species, long long n, const double *x_dev,
                          const double *v_dev, long long id0, int fp64, hipStream_t s);
 hipError_t launch_phi(const DevPtrs &p, int gap, hipStream_t s);

@@ -12,6 +12,7 @@
 //
 // Compiled with -ffp-contract=off: the binary32 particle arithmetic is a fixed
 // sequence of IEEE operations (no fused multiply-adds).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -1256,8 +1257,19 @@ size_t push_lds_bytes(int nmax, int fp64, int G, int wide) {
   return off;
 }
 
+// Launch with or without packet-recorded timing events.
+template <typename K, typename... A>
+static hipError_t launch_k(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t ea,
+                           hipEvent_t eb, A... args) {
+  if (ea || eb)
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, ea, eb, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+  return hipGetLastError();
+}
+
 hipError_t launch_field(const DevPtrs &p, int G, int mode, int guess, double tol, int maxit,
-                        int fp64, int nmax, hipStream_t s) {
+                        int fp64, int nmax, hipStream_t s, KTime t) {
   const size_t lds = (size_t)nmax * 8;
   static size_t attr_set = 32768;
   if (lds > attr_set) {
@@ -1266,12 +1278,11 @@ hipError_t launch_field(const DevPtrs &p, int G, int mode, int guess, double tol
     if (e != hipSuccess) return e;
     attr_set = lds;
   }
-  hipLaunchKernelGGL(k_field, dim3(G), dim3(FBS), lds, s, p, mode, guess, tol, maxit, fp64);
-  return hipGetLastError();
+  return launch_k(k_field, dim3(G), dim3(FBS), lds, s, t.a, t.b, p, mode, guess, tol, maxit, fp64);
 }
 
 template <class P, class AC, int BS, int PPT>
-static hipError_t push_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s) {
+static hipError_t push_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
   const size_t lds = push_lds_bytes(lc.nmax, lc.fp64, G, sizeof(typename AC::cell) == 8);
   // opt in to more than 64 KiB of dynamic LDS (gfx950 has 160 KiB per CU)
   static size_t attr_set = 65536;
@@ -1281,53 +1292,49 @@ static hipError_t push_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream
     if (e != hipSuccess) return e;
     attr_set = lds;
   }
-  hipLaunchKernelGGL((k_push<P, AC, BS, PPT>), dim3(lc.grid), dim3(BS), lds, s, p, G, lc.tile, lc.nmax);
-  return hipGetLastError();
+  return launch_k(k_push<P, AC, BS, PPT>, dim3(lc.grid), dim3(BS), lds, s, t.a, t.b, p, G, lc.tile,
+                  lc.nmax);
 }
 
 template <class P, class AC, int PPT>
-static hipError_t push_bp(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s) {
+static hipError_t push_bp(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
   switch (lc.block) {
-    case 256: return push_t<P, AC, 256, PPT>(p, G, lc, s);
-    case 512: return push_t<P, AC, 512, PPT>(p, G, lc, s);
-    default: return push_t<P, AC, 1024, PPT>(p, G, lc, s);
+    case 256: return push_t<P, AC, 256, PPT>(p, G, lc, s, t);
+    case 512: return push_t<P, AC, 512, PPT>(p, G, lc, s, t);
+    default: return push_t<P, AC, 1024, PPT>(p, G, lc, s, t);
   }
 }
 
 template <class P, class AC>
-static hipError_t push_b(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s) {
-  if (lc.ppt >= 2 * Vec<P>::n) return push_bp<P, AC, 2 * Vec<P>::n>(p, G, lc, s);
-  return push_bp<P, AC, Vec<P>::n>(p, G, lc, s);
+static hipError_t push_b(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+  if (lc.ppt >= 2 * Vec<P>::n) return push_bp<P, AC, 2 * Vec<P>::n>(p, G, lc, s, t);
+  return push_bp<P, AC, Vec<P>::n>(p, G, lc, s, t);
 }
 
-hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s) {
-  if (lc.fp64) return push_b<double, Wide64>(p, G, lc, s);
-  if (lc.wide) return push_b<float, Wide64>(p, G, lc, s);
-  return push_b<float, Carry32>(p, G, lc, s);
+hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+  if (lc.fp64) return push_b<double, Wide64>(p, G, lc, s, t);
+  if (lc.wide) return push_b<float, Wide64>(p, G, lc, s, t);
+  return push_b<float, Carry32>(p, G, lc, s, t);
 }
 
-hipError_t launch_source(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s) {
+hipError_t launch_source(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
   const int grid = lc.source_grid > 0 ? lc.source_grid : 256;
   const size_t lds = ((size_t)(G + 1) * 4 + 15) / 16 * 16;
   const int tile = SBS;
-  if (lc.fp64)
-    hipLaunchKernelGGL(k_source<double>, dim3(grid), dim3(SBS), lds, s, p, G, tile);
-  else
-    hipLaunchKernelGGL(k_source<float>, dim3(grid), dim3(SBS), lds, s, p, G, tile);
-  return hipGetLastError();
+  if (lc.fp64) return launch_k(k_source<double>, dim3(grid), dim3(SBS), lds, s, t.a, t.b, p, G, tile);
+  return launch_k(k_source<float>, dim3(grid), dim3(SBS), lds, s, t.a, t.b, p, G, tile);
 }
 
-hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s) {
+hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
   const int grid = lc.compact_grid > 0 ? lc.compact_grid : 1024;
   const size_t lds = ((size_t)(2 * G + 1) * 4 + 15) / 16 * 16;
-  if (lc.fp64)
-    hipLaunchKernelGGL((k_compact<double, 256>), dim3(grid), dim3(256), lds, s, p, G, lc.tile);
-  else
-    hipLaunchKernelGGL((k_compact<float, 256>), dim3(grid), dim3(256), lds, s, p, G, lc.tile);
-  hipError_t e = hipGetLastError();
+  // the start event goes with the compaction, the end event with the commit
+  hipError_t e = lc.fp64 ? launch_k(k_compact<double, 256>, dim3(grid), dim3(256), lds, s, t.a, nullptr, p, G,
+                                    lc.tile)
+                         : launch_k(k_compact<float, 256>, dim3(grid), dim3(256), lds, s, t.a, nullptr, p, G,
+                                    lc.tile);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_commit, dim3((2 * G + 255) / 256), dim3(256), 0, s, p, G);
-  return hipGetLastError();
+  return launch_k(k_commit, dim3((2 * G + 255) / 256), dim3(256), 0, s, nullptr, t.b, p, G);
 }
 
 hipError_t launch_inject(const DevPtrs &p, int gap, int species, long long n, const double *x,
