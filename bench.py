@@ -193,6 +193,18 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_reference_bytes_per_launch": 4 * n, "launches": 5}), flush=True)
         return
+    # achievable HBM rate: a plain 1 GiB device-to-device copy, timed with events
+    ca = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        cb.copy_(ca)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * ca.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del ca, cb
     spec = WORKLOADS[args.workload]
     log(f"[bench] building workload {args.workload}")
     sim, cfg, _ = make_sim(args.workload, spec, args.warmup + args.steps)
@@ -258,6 +270,7 @@ def main():
                      "kernel": "k_push", "bytes_per_particle_step": BYTES_PER_PUSH_F32,
                      "algorithmic_bytes_per_launch": BYTES_PER_PUSH_F32 * pushed / max(1, tm["push_launches"]),
                      "avg_launch_ms": tm["push_ms"] / max(1, tm["push_launches"]),
+                     "copy_GBps": copy_gbs,
                      "launches": tm["push_launches"]},
         "timed_with": "hip graphs" if args.graph else "eager launches, HIP events recorded by each kernel's dispatch",
         "kernel_ms_per_step": {"push": tm["push_ms"] / args.steps, "field": tm["field_ms"] / args.steps,

@@ -145,17 +145,19 @@ typedef struct {
 
 /* Options for gs_set_option. */
 enum {
-  GS_OPT_BLOCK = 1,        /* push threads per block: 256, 512 or 1024 */
-  GS_OPT_TILE = 2,         /* particles per work tile (multiple of 8 x the block size) */
+  GS_OPT_BLOCK = 1,        /* push threads per block: 256 (default), 512 or 1024 */
+  GS_OPT_TILE = 2,         /* granularity at which particles are split between push
+                              blocks (a multiple of 8 x the block size; default 8 x) */
   GS_OPT_GRID = 3,         /* push blocks; 0 = from occupancy */
   GS_OPT_COMPACT_EVERY = 4,/* steps between reclaiming absorbed slots (>= 1) */
   GS_OPT_GRAPH = 5,        /* 1: replay steps through a captured hipGraph */
   GS_OPT_TIMING = 6,       /* 1: time each kernel launch with HIP events */
   GS_OPT_NEWTON_TOL = 7,   /* value * 1e-12 = scaled residual tolerance (default 1e-10) */
-  GS_OPT_NEWTON_MAXIT = 8,
+  GS_OPT_NEWTON_MAXIT = 8, /* Newton corrections allowed per level, 0..64 (default 8) */
   GS_OPT_DEPOSIT = 9,      /* binary32 deposit cells: 0 auto, 1 64-bit, 2 32-bit with carries */
   GS_OPT_COMPACT_GRID = 10,/* workgroups of the compaction kernel (>= 1) */
-  GS_OPT_PPT = 11          /* 16-byte particle vectors per thread per chunk: 1 or 2 */
+  GS_OPT_PPT = 11          /* 16-byte particle vectors per thread per chunk: 1 or 2
+                              (default 2 for binary32 particles, 1 for binary64) */
 };
 
 typedef struct gs_ctx gs_ctx;
@@ -203,7 +205,10 @@ gs_status gs_step_weak(gs_ctx *ctx, int32_t n_steps);
 /* Read one gap's state (synchronises the stream).  phi (n_cells + 1 values),
  * E (n_cells half-grid values E_{k+1/2}) and rho (n_cells + 1 nodal densities,
  * electrode nodes already doubled) of the last solved level are written to the
- * caller's host arrays when not NULL.  Errors: GS_EINVAL, GS_EDEVICE. */
+ * caller's host arrays when not NULL.  Errors: GS_EINVAL, GS_EDEVICE; the sticky
+ * errors of the steps (GS_ECAPACITY, GS_EINVAL for a bad device-side injection);
+ * GS_ENOCONV once after a strict Newton solve missed its tolerance (the outputs
+ * are filled and the state stays valid: the last iterate was used). */
 gs_status gs_read_diagnostics(gs_ctx *ctx, int32_t gap, gs_diag *out, double *phi, double *E,
                               double *rho);
 

@@ -377,11 +377,11 @@ static gs_status setup(gs_ctx *ctx) {
   ctx->lc.fp64 = ctx->fp64;
   ctx->lc.nmax = ctx->nmax;
   ctx->lc.block = 256;
-  ctx->lc.tile = ctx->lc.block * 16;
+  ctx->lc.tile = ctx->lc.block * 8;
   ctx->lc.wide = 1;
   ctx->lc.compact_grid = 4 * ctx->ncu;
   ctx->lc.source_grid = ctx->ncu;
-  ctx->lc.ppt = ctx->fp64 ? 2 : 4;
+  ctx->lc.ppt = ctx->fp64 ? 2 : 8;
   choose_launch(ctx);
   return GS_OK;
 }
@@ -479,6 +479,13 @@ static gs_status check_sticky(gs_ctx *ctx, bool sync) {
   if (e[0] & ERR_BADINJECT) {
     ctx->sticky = GS_EINVAL;
     return fail(ctx, GS_EINVAL, "an injected position was outside [0, d]");
+  }
+  if (e[0] & ERR_NOCONV) {
+    // reported once: the state stays valid (the last iterate was used)
+    const unsigned int keep = e[0] & ~(unsigned int)ERR_NOCONV;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->dp.err, &keep, 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return fail(ctx, GS_ENOCONV, "a strict Newton solve missed its tolerance within its iteration cap");
   }
   return GS_OK;
 }
@@ -738,7 +745,7 @@ extern "C" gs_status gs_set_option(gs_ctx *ctx, int32_t option, int64_t value) {
     case GS_OPT_BLOCK:
       if (value != 256 && value != 512 && value != 1024) return fail(ctx, GS_EINVAL, "block must be 256, 512 or 1024");
       ctx->lc.block = (int)value;
-      if (ctx->lc.tile % (8 * ctx->lc.block)) ctx->lc.tile = ctx->lc.block * 16;
+      if (ctx->lc.tile % (8 * ctx->lc.block)) ctx->lc.tile = ctx->lc.block * 8;
       break;
     case GS_OPT_TILE:
       if (value < 8 * ctx->lc.block || value % (8 * ctx->lc.block) || value > (1 << 24))

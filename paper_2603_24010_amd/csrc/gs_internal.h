@@ -81,8 +81,8 @@ struct GapState {
 
 // An ion absorbed by an electrode, waiting for its secondary emission.
 struct Event {
-  double u;     // impact velocity in cells per step
-  uint32_t id;  // the ion's id (keys its random draws)
+  double u;       // impact velocity in cells per step
+  uint32_t slot;  // the ion's slot in its region (its id keys the random draws)
   uint32_t wall;
 };
 

@@ -484,20 +484,19 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
 // ---------------------------------------------------------------------------
 // k_push
 // ---------------------------------------------------------------------------
-// Charge accumulation in LDS, one cell per node:
+// Charge accumulation in LDS, one cell per node.  The push deposits the
+// unsigned CIC weights of one species (in units of 2^-24 or 2^-44 of a
+// macroparticle); the species' charge number multiplies the sums when they are
+// flushed to the gap's 64-bit node row.
 //   Wide64  64-bit cells, non-returning adds (whenever the grid fits in LDS);
-//   Carry32 32-bit cells biased by 2^31 (binary32 particles, largest grids); a
-//           cell that wraps carries +-2^32 into the gap's 64-bit accumulator.
+//   Carry32 32-bit cells (binary32 particles, largest grids); a cell that wraps
+//           carries Z * 2^32 into the gap's row.
 // Both give the exact integer sum, so the deposit is order independent.
 struct Wide64 {
   typedef unsigned long long cell;
-  static constexpr unsigned long long ZERO = 0ull;
-  __device__ static inline long long value(cell v) { return (long long)v; }
 };
 struct Carry32 {
   typedef unsigned int cell;
-  static constexpr unsigned int ZERO = 0x80000000u;
-  __device__ static inline long long value(cell v) { return (long long)v - 2147483648ll; }
 };
 
 // 16-byte vectors of particle coordinates
@@ -524,63 +523,53 @@ template <>
 struct Prec<float> {
   static constexpr float ONE_W = 16777216.0f;  // 2^24
   static constexpr long long W = 16777216ll;
-  __device__ static inline long long wq(float f) { return (long long)__float2uint_rn(f * ONE_W); }
+  typedef unsigned int wt;
+  __device__ static inline wt wq(float f) { return __float2uint_rn(f * ONE_W); }
 };
 template <>
 struct Prec<double> {
   static constexpr double ONE_W = 17592186044416.0;  // 2^44
   static constexpr long long W = 17592186044416ll;
-  __device__ static inline long long wq(double f) { return __double2ll_rn(f * ONE_W); }
+  typedef unsigned long long wt;
+  __device__ static inline wt wq(double f) { return (unsigned long long)__double2ll_rn(f * ONE_W); }
 };
 
 // Linear gather from the extended half-grid table eh[0..N+1]:
 // eh[0] = surface field at node 0, eh[k] = E_{k-1/2}, eh[N+1] = field at node N.
+// All three cases are evaluated and one is selected (no divergent branches);
+// each case is the same IEEE operation sequence as its branch form.
 template <class P>
-__device__ inline P gather(const P *eh, P xi, int N, P Nf) {
-  int k;
-  P t;
-  if (xi < (P)0.5) {
-    k = 0;
-    t = xi + xi;
-  } else if (xi >= Nf - (P)0.5) {
-    k = N;
-    t = xi - (Nf - (P)0.5);
-    t = t + t;
-  } else {
-    P h = xi - (P)0.5;
-    int j = (int)h;
-    t = h - (P)j;
-    k = j + 1;
-  }
-  P a = eh[k];
-  P b = eh[k + 1];
-  P dlt = b - a;
-  P m = t * dlt;
+__device__ inline P gather(const P *eh, P xi, int N, P Nh) {
+  const P h = xi - (P)0.5;
+  const int j = (int)h;
+  const P ti = h - (P)j;
+  const P tl = xi + xi;
+  P tr = xi - Nh;
+  tr = tr + tr;
+  const bool L = xi < (P)0.5, R = xi >= Nh;
+  const int k = L ? 0 : (R ? N : j + 1);
+  const P t = L ? tl : (R ? tr : ti);
+  const P a = eh[k];
+  const P b = eh[k + 1];
+  const P dlt = b - a;
+  const P m = t * dlt;
   return a + m;
 }
 
-__device__ inline void carry_add(unsigned long long *gacc, int j, unsigned int old, long long c) {
-  const unsigned int uc = (unsigned int)(int)c;
-  long long carry = 0;
-  if (c >= 0) {
-    if (old + uc < old) carry = 1;
-  } else if (old < (unsigned int)(-(int)c)) {
-    carry = -1;
-  }
-  if (carry) atomicAdd(&gacc[j], (unsigned long long)(carry * 4294967296ll));
-}
-
-// add one contribution c (two's complement) to node j
 template <class AC>
-__device__ inline void acc_add(typename AC::cell *lds, unsigned long long *gacc, int j, long long c);
+__device__ inline void acc_add(typename AC::cell *lds, unsigned long long *gacc, int j, unsigned long long w,
+                               long long zhi);
 template <>
-__device__ inline void acc_add<Wide64>(unsigned long long *lds, unsigned long long *, int j, long long c) {
-  atomicAdd(&lds[j], (unsigned long long)c);
+__device__ inline void acc_add<Wide64>(unsigned long long *lds, unsigned long long *, int j,
+                                       unsigned long long w, long long) {
+  atomicAdd(&lds[j], w);
 }
 template <>
-__device__ inline void acc_add<Carry32>(unsigned int *lds, unsigned long long *gacc, int j, long long c) {
-  const unsigned int old = atomicAdd(&lds[j], (unsigned int)(int)c);
-  carry_add(gacc, j, old, c);
+__device__ inline void acc_add<Carry32>(unsigned int *lds, unsigned long long *gacc, int j, unsigned long long w,
+                                        long long zhi) {
+  const unsigned int uw = (unsigned int)w;
+  const unsigned int old = atomicAdd(&lds[j], uw);
+  if (old + uw < old) atomicAdd(&gacc[j], (unsigned long long)zhi);
 }
 
 constexpr int EVQ = 128;  // absorbed-ion events a push workgroup queues in LDS
@@ -601,13 +590,15 @@ __device__ inline void gap_tiles(const GapState &st, int tile, int &te, int &ti)
   ti = (int)((st.count[1] + tile - 1) / tile);
 }
 
+// Hand one (gap, species) segment's LDS state to the gap: node sums times the
+// charge number Z, tallies, queued events.
 template <class P, class AC>
-__device__ void flush_gap(const DevPtrs &p, const GapConst &c, int g, PushShared<P, AC> &sh) {
+__device__ void flush_seg(const DevPtrs &p, const GapConst &c, int g, long long Z, PushShared<P, AC> &sh) {
   __syncthreads();
   unsigned long long *gacc = p.acc + c.nbase;
   for (int j = threadIdx.x; j <= c.N; j += blockDim.x) {
-    const long long v = AC::value(sh.acc[j]);
-    if (v != 0) atomicAdd(&gacc[j], (unsigned long long)v);
+    const unsigned long long v = (unsigned long long)sh.acc[j];
+    if (v != 0ull) atomicAdd(&gacc[j], (unsigned long long)(Z * (long long)v));
   }
   if (threadIdx.x < T_N) {
     const unsigned int v = sh.tally[threadIdx.x];
@@ -631,13 +622,192 @@ __device__ void flush_gap(const DevPtrs &p, const GapConst &c, int g, PushShared
 }
 
 template <class P, class AC>
-__device__ void load_gap(const DevPtrs &p, const GapConst &c, PushShared<P, AC> &sh) {
+__device__ void load_seg(const DevPtrs &p, const GapConst &c, PushShared<P, AC> &sh) {
   const P *geh = (const P *)p.ehat + c.ebase;
   for (int j = threadIdx.x; j <= c.N + 1; j += blockDim.x) sh.eh[j] = geh[j];
-  for (int j = threadIdx.x; j <= c.N; j += blockDim.x) sh.acc[j] = AC::ZERO;
+  for (int j = threadIdx.x; j <= c.N; j += blockDim.x) sh.acc[j] = 0;
   if (threadIdx.x < T_N) sh.tally[threadIdx.x] = 0u;
   if (threadIdx.x == 0) *sh.evq_n = 0u;
   __syncthreads();
+}
+
+// Per-thread running counts of one segment.
+struct SegCount {
+  unsigned int pushed = 0, abs0 = 0, abs1 = 0;
+};
+
+// The gap constants one segment's push needs, held in registers (a reference
+// into global memory would be re-read after every store).
+struct SegK {
+  int N;
+  int g;
+  long long evbase, evcap;
+  unsigned long long *gacc;
+};
+
+// Push one chunk of BS * PPT slots starting at slot r0 (relative to the region
+// base): thread tid owns slots r0 + (v * BS + tid) * VN + kk.  FULL: every slot
+// lies below n_here, so vectors are stored whole; otherwise slot by slot.
+template <class P, class AC, int BS, int PPT, bool FULL>
+__device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P, AC> &sh, P *X, P *U,
+                                  long long r0, long long n_here, typename Vec<P>::type *xv,
+                                  typename Vec<P>::type *uv, P alpha, bool see, long long zhi, SegCount &cnt) {
+  typedef typename Vec<P>::type V;
+  constexpr int VN = Vec<P>::n;
+  constexpr int NV = PPT / VN;
+  const int tid = threadIdx.x;
+  const int N = c.N;
+  const int g = c.g;
+  const P Nf = (P)N;
+  const P Nh = Nf - (P)0.5;
+  int jj[PPT];
+  typename Prec<P>::wt w0[PPT], w1[PPT];
+  unsigned int dep = 0, hit = 0;  // bit k: slot k deposits / is absorbed (wall in bit k+16)
+  P u_hit[PPT];
+  V xw[NV], uw[NV];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int v = k / VN, kk = k % VN;
+    const P xi = Vec<P>::at(xv[v], kk);
+    const P u0 = Vec<P>::at(uv[v], kk);
+    // empty slots and absorbed particles hold -1
+    const bool live = xi >= (P)0;
+    // gather, then the leapfrog (eq. vel_update_main, eq. pos_update_main)
+    const P Ep = gather<P>(sh.eh, xi, N, Nh);
+    const P du = alpha * Ep;
+    const P u1 = u0 + du;
+    const P x1 = xi + u1;
+    const bool a0 = x1 <= (P)0;
+    const bool a1 = !a0 && x1 >= Nf;
+    const bool gone = live && (a0 || a1);
+    const bool stay = live && !(a0 || a1);
+    Vec<P>::at(xw[v], kk) = stay ? x1 : (P)-1;
+    Vec<P>::at(uw[v], kk) = stay ? u1 : u0;
+    cnt.pushed += live;
+    cnt.abs0 += live && a0;
+    cnt.abs1 += live && a1;
+    hit |= ((unsigned int)gone << k) | ((unsigned int)(live && a1) << (k + 16));
+    u_hit[k] = u1;
+    // deposit with the gather's weights (App. C)
+    const P xs = stay ? x1 : (P)0;
+    int j = (int)xs;
+    j = j > N - 1 ? N - 1 : j;
+    const P f = xs - (P)j;
+    const typename Prec<P>::wt q1 = Prec<P>::wq(f);
+    dep |= (unsigned int)stay << k;
+    jj[k] = j;
+    w1[k] = q1;
+    w0[k] = (typename Prec<P>::wt)Prec<P>::W - q1;
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const long long i = r0 + (long long)(v * BS + tid) * VN;
+    if (FULL) {
+      *(V *)(X + i) = xw[v];
+      *(V *)(U + i) = uw[v];
+    } else {
+#pragma unroll
+      for (int k = 0; k < VN; ++k)
+        if (i + k < n_here) {
+          X[i + k] = Vec<P>::at(xw[v], k);
+          U[i + k] = Vec<P>::at(uw[v], k);
+        }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PPT; ++k)
+    if (dep & (1u << k)) {
+      acc_add<AC>(sh.acc, c.gacc, jj[k], (unsigned long long)w0[k], zhi);
+      acc_add<AC>(sh.acc, c.gacc, jj[k] + 1, (unsigned long long)w1[k], zhi);
+    }
+  // absorbed ions are queued for secondary emission (k_source): in LDS, or
+  // straight to the gap's list when the workgroup's queue is full
+  if (see && (hit & 0xFFFFu) != 0u) {
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      if (!((hit >> k) & 1u)) continue;
+      Event ev;
+      ev.u = (double)u_hit[k];
+      ev.slot = (uint32_t)(r0 + (long long)((k / VN) * BS + tid) * VN + k % VN);
+      ev.wall = (hit >> (k + 16)) & 1u;
+      const unsigned int q = atomicAdd(sh.evq_n, 1u);
+      if (q < (unsigned int)EVQ) {
+        sh.evq[q] = ev;
+      } else {
+        const unsigned long long e = atomicAdd(&p.ev_count[g], 1ull);
+        if (e < (unsigned long long)c.evcap) {
+          p.ev[c.evbase + e] = ev;
+        } else {
+          atomicOr(&p.err[0], ERR_CAPACITY);
+          atomicCAS(&p.err[1], 0xFFFFFFFFu, (unsigned int)g);
+        }
+      }
+    }
+  }
+}
+
+template <class P, int BS, int PPT>
+__device__ inline void load_chunk(const P *X, const P *U, long long r0, typename Vec<P>::type *xo,
+                                  typename Vec<P>::type *uo) {
+  typedef typename Vec<P>::type V;
+  constexpr int VN = Vec<P>::n;
+#pragma unroll
+  for (int v = 0; v < PPT / VN; ++v) {
+    const long long i = r0 + (long long)(v * BS + threadIdx.x) * VN;
+    xo[v] = *(const V *)(X + i);
+    uo[v] = *(const V *)(U + i);
+  }
+}
+
+// The slots [a, b) of one (gap, species) region, as a stream of chunks.  Full
+// chunks are software-pipelined two deep: the loads of the next chunk are in
+// flight while this one is pushed.  Every load in the loop is unconditional
+// (past the last full chunk it repeats that chunk's, whose data is dropped), so
+// the wait before each chunk covers that chunk's loads only.  The remainder
+// goes slot by slot: slots past b may be receiving appended particles.
+template <class P, class AC, int BS, int PPT>
+__device__ void push_range(const DevPtrs &p, const GapConst &gc, int g, int s, int sel, PushShared<P, AC> &sh,
+                           long long a, long long b, SegCount &cnt) {
+  typedef typename Vec<P>::type V;
+  constexpr int VN = Vec<P>::n;
+  constexpr int NV = PPT / VN;
+  constexpr int CH = BS * PPT;
+  SegK c;
+  c.N = gc.N;
+  c.g = g;
+  c.evbase = gc.evbase;
+  c.evcap = gc.evcap;
+  c.gacc = p.acc + gc.nbase;
+  P *X = (P *)p.X[sel] + gc.pbase[s];
+  P *U = (P *)p.U[sel] + gc.pbase[s];
+  const P alpha = (P)gc.alpha[s];
+  const bool see = (s == 1) && (gc.see_amp > 0.0) && (gc.Z[1] > 0);
+  const long long zhi = (long long)gc.Z[s] * 4294967296ll;
+  const long long nfull = (b - a) / CH;
+  V xa[NV], ua[NV], xb[NV], ub[NV];
+  if (nfull > 0) {
+    load_chunk<P, BS, PPT>(X, U, a, xa, ua);
+    for (long long q = 0; q < nfull; q += 2) {
+      load_chunk<P, BS, PPT>(X, U, a + min(q + 1, nfull - 1) * CH, xb, ub);
+      push_chunk<P, AC, BS, PPT, true>(p, c, sh, X, U, a + q * CH, b, xa, ua, alpha, see, zhi, cnt);
+      if (q + 1 >= nfull) break;
+      load_chunk<P, BS, PPT>(X, U, a + min(q + 2, nfull - 1) * CH, xa, ua);
+      push_chunk<P, AC, BS, PPT, true>(p, c, sh, X, U, a + (q + 1) * CH, b, xb, ub, alpha, see, zhi, cnt);
+    }
+  }
+  const long long r0 = a + nfull * CH;
+  if (r0 < b) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const long long i = r0 + (long long)(v * BS + threadIdx.x) * VN;
+#pragma unroll
+      for (int k = 0; k < VN; ++k) {
+        Vec<P>::at(xa[v], k) = (i + k < b) ? X[i + k] : (P)-1;
+        Vec<P>::at(ua[v], k) = (i + k < b) ? U[i + k] : (P)0;
+      }
+    }
+    push_chunk<P, AC, BS, PPT, false>(p, c, sh, X, U, r0, b, xa, ua, alpha, see, zhi, cnt);
+  }
 }
 
 template <class P, class AC, int BS, int PPT>
@@ -687,197 +857,38 @@ __global__ __launch_bounds__(BS) void k_push(DevPtrs p, int G, int tile, int nma
     __syncthreads();
   }
 
+  // this workgroup's contiguous run of tiles, taken one (gap, species)
+  // segment at a time
   const int total = sh.prefix[G];
-  const int t0 = (int)(((long long)blockIdx.x * total) / gridDim.x);
   const int t1 = (int)(((long long)(blockIdx.x + 1) * total) / gridDim.x);
-  int cur = -1;
+  int t = (int)(((long long)blockIdx.x * total) / gridDim.x);
   int g = 0;
-  for (int t = t0; t < t1; ++t) {
+  while (t < t1) {
     while (sh.prefix[g + 1] <= t) ++g;
     const GapConst &c = p.gc[g];
     const GapState &st = p.gs[g];
-    if (g != cur) {
-      if (cur >= 0) flush_gap<P, AC>(p, p.gc[cur], cur, sh);
-      load_gap<P, AC>(p, c, sh);
-      cur = g;
-    }
-    unsigned long long *gacc = p.acc + c.nbase;
     int te, ti;
     gap_tiles(st, tile, te, ti);
-    int lt = t - sh.prefix[g];
-    const int N = c.N;
-    const P Nf = (P)N;
-    {
-      const int s = lt < te ? 0 : 1;
-      if (s == 1) lt -= te;
-      const long long i0 = (long long)lt * tile;
-      const int n_here = (int)min((long long)tile, st.count[s] - i0);
-      P *X = (P *)p.X[sel] + c.pbase[s] + i0;
-      P *U = (P *)p.U[sel] + c.pbase[s] + i0;
-      const uint32_t *IDt = p.ID[sel] + c.pbase[s] + i0;
-      const P alpha = (P)c.alpha[s];
-      const long long Z = c.Z[s];
-      const bool see = (s == 1) && (c.see_amp > 0.0) && (c.Z[1] > 0);
-      unsigned int n_pushed = 0, n_abs0 = 0, n_abs1 = 0;
-      // Each thread owns PPT consecutive slots per chunk, moved with 16-byte
-      // vector loads/stores; the next chunk's loads are in flight while this one
-      // is processed.  A chunk that straddles the end of the swept range goes
-      // slot by slot: slots past it may be receiving appended particles.
-      typedef typename Vec<P>::type V;
-      constexpr int VN = Vec<P>::n;   // particles per 16-byte vector
-      constexpr int NV = PPT / VN;    // vectors per thread per chunk
-      // deposit words: Z * 2^24 fits 32 bits for binary32 particles
-      typedef typename std::conditional<sizeof(P) == 8, long long, int>::type DepT;
-      constexpr int CH = BS * PPT;
-      V xa[NV], ua[NV], xb[NV], ub[NV];
-      // thread tid owns slots r0 + (v*BS + tid)*VN .. +VN-1 for v < NV
-      auto load_chunk = [&](int r0, V *xo, V *uo) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const int i = r0 + (v * BS + tid) * VN;
-          if (i + VN <= n_here) {
-            xo[v] = *(const V *)(X + i);
-            uo[v] = *(const V *)(U + i);
-          } else {
-#pragma unroll
-            for (int k = 0; k < VN; ++k) {
-              Vec<P>::at(xo[v], k) = (i + k < n_here) ? X[i + k] : (P)-1;
-              Vec<P>::at(uo[v], k) = (i + k < n_here) ? U[i + k] : (P)0;
-            }
-          }
-        }
-      };
-      load_chunk(0, xa, ua);
-      for (int r = 0; r < n_here; r += CH) {
-        if (r + CH < n_here) load_chunk(r + CH, xb, ub);
-        int jj[PPT];
-        DepT c0[PPT], c1[PPT];
-        unsigned int dep = 0, hit = 0;  // bit k: slot k deposits / is an absorbed ion (wall in bit k+16)
-        P u_hit[PPT];
-        V xw[NV], uw[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          xw[v] = xa[v];
-          uw[v] = ua[v];
-        }
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          const int v = k / VN, kk = k % VN;
-          const P xi = Vec<P>::at(xa[v], kk);
-          jj[k] = 0;
-          c0[k] = c1[k] = 0;
-          u_hit[k] = (P)0;
-          if (xi >= (P)0) {  // empty slots and absorbed particles hold -1
-            n_pushed += 1;
-            // gather, then the leapfrog (eq. vel_update_main, eq. pos_update_main)
-            const P Ep = gather<P>(sh.eh, xi, N, Nf);
-            const P du = alpha * Ep;
-            const P u1 = Vec<P>::at(ua[v], kk) + du;
-            const P x1 = xi + u1;
-            const bool w0 = x1 <= (P)0;
-            const bool w1 = !w0 && x1 >= Nf;
-            if (w0 || w1) {
-              Vec<P>::at(xw[v], kk) = (P)-1;
-              n_abs0 += w0;
-              n_abs1 += w1;
-              hit |= (1u << k) | ((unsigned int)w1 << (k + 16));
-              u_hit[k] = u1;
-            } else {
-              Vec<P>::at(xw[v], kk) = x1;
-              Vec<P>::at(uw[v], kk) = u1;
-              // deposit with the gather's weights (App. C)
-              int j = (int)x1;
-              if (j > N - 1) j = N - 1;
-              const P f = x1 - (P)j;
-              const long long w1q = Prec<P>::wq(f);
-              const long long w0q = Prec<P>::W - w1q;
-              dep |= 1u << k;
-              jj[k] = j;
-              c0[k] = (DepT)(Z * w0q);
-              c1[k] = (DepT)(Z * w1q);
-            }
-          }
-        }
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const int i = r + (v * BS + tid) * VN;
-          if (i + VN <= n_here) {
-            *(V *)(X + i) = xw[v];
-            *(V *)(U + i) = uw[v];
-          } else {
-#pragma unroll
-            for (int k = 0; k < VN; ++k)
-              if (i + k < n_here) {
-                X[i + k] = Vec<P>::at(xw[v], k);
-                U[i + k] = Vec<P>::at(uw[v], k);
-              }
-          }
-        }
-        if constexpr (sizeof(cell) == 8) {
-#pragma unroll
-          for (int k = 0; k < PPT; ++k)
-            if (dep & (1u << k)) {
-              atomicAdd(&sh.acc[jj[k]], (unsigned long long)(long long)c0[k]);
-              atomicAdd(&sh.acc[jj[k] + 1], (unsigned long long)(long long)c1[k]);
-            }
-        } else {
-          // issue every returning add first, then look for wrapped cells
-          unsigned int o0[PPT], o1[PPT];
-#pragma unroll
-          for (int k = 0; k < PPT; ++k) {
-            o0[k] = o1[k] = 0u;
-            if (dep & (1u << k)) {
-              o0[k] = atomicAdd(&sh.acc[jj[k]], (unsigned int)(int)c0[k]);
-              o1[k] = atomicAdd(&sh.acc[jj[k] + 1], (unsigned int)(int)c1[k]);
-            }
-          }
-#pragma unroll
-          for (int k = 0; k < PPT; ++k)
-            if (dep & (1u << k)) {
-              carry_add(gacc, jj[k], o0[k], c0[k]);
-              carry_add(gacc, jj[k] + 1, o1[k], c1[k]);
-            }
-        }
-        // absorbed ions are queued for secondary emission (k_source): in LDS,
-        // or straight to the gap's list when the workgroup's queue is full
-        if (see && hit != 0u) {
-#pragma unroll
-          for (int k = 0; k < PPT; ++k) {
-            if (!((hit >> k) & 1u)) continue;
-            Event ev;
-            ev.u = (double)u_hit[k];
-            ev.id = IDt[r + ((k / VN) * BS + tid) * VN + k % VN];
-            ev.wall = (hit >> (k + 16)) & 1u;
-            const unsigned int q = atomicAdd(sh.evq_n, 1u);
-            if (q < (unsigned int)EVQ) {
-              sh.evq[q] = ev;
-            } else {
-              const unsigned long long e = atomicAdd(&p.ev_count[g], 1ull);
-              if (e < (unsigned long long)c.evcap) {
-                p.ev[c.evbase + e] = ev;
-              } else {
-                atomicOr(&p.err[0], ERR_CAPACITY);
-                atomicCAS(&p.err[1], 0xFFFFFFFFu, (unsigned int)g);
-              }
-            }
-          }
-        }
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          xa[v] = xb[v];
-          ua[v] = ub[v];
-        }
-      }
-      // wave-level sums, then one LDS atomic per wave
-      const unsigned int v0 = wave_sum(n_pushed), v1 = wave_sum(n_abs0), v2 = wave_sum(n_abs1);
-      if (lane == 0) {
-        if (v0) atomicAdd(&sh.tally[T_PUSHED], v0);
-        if (v1) atomicAdd(&sh.tally[T_ABS + s * 2 + 0], v1);
-        if (v2) atomicAdd(&sh.tally[T_ABS + s * 2 + 1], v2);
-      }
+    const int lt = t - sh.prefix[g];
+    const int s = lt < te ? 0 : 1;
+    const int seg_end = min(s == 0 ? te : te + ti, t1 - sh.prefix[g]);
+    const int ls = s == 0 ? lt : lt - te;
+    const int le = s == 0 ? seg_end : seg_end - te;
+    load_seg<P, AC>(p, c, sh);
+    SegCount cnt;
+    const long long a = (long long)ls * tile;
+    const long long b = min((long long)le * tile, st.count[s]);
+    push_range<P, AC, BS, PPT>(p, c, g, s, sel, sh, a, b, cnt);
+    // wave-level sums, then one LDS atomic per wave
+    const unsigned int v0 = wave_sum(cnt.pushed), v1 = wave_sum(cnt.abs0), v2 = wave_sum(cnt.abs1);
+    if (lane == 0) {
+      if (v0) atomicAdd(&sh.tally[T_PUSHED], v0);
+      if (v1) atomicAdd(&sh.tally[T_ABS + s * 2 + 0], v1);
+      if (v2) atomicAdd(&sh.tally[T_ABS + s * 2 + 1], v2);
     }
+    flush_seg<P, AC>(p, c, g, (long long)c.Z[s], sh);
+    t += seg_end - lt;
   }
-  if (cur >= 0) flush_gap<P, AC>(p, p.gc[cur], cur, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -981,7 +992,7 @@ __global__ __launch_bounds__(SBS) void k_source(DevPtrs p, int G, int tile) {
         uint64_t blk[4];
         if (k < nev) {
           const Event ev = p.ev[c.evbase + k];
-          ion_id = ev.id;
+          ion_id = p.ID[sel][c.pbase[1] + ev.slot];
           wall = (int)ev.wall;
           const double v_ion = (ev.u * c.dx) / c.dt;
           const double e_ion = 0.5 * c.mass[1] * v_ion * v_ion / c.ev;

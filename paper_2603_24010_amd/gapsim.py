@@ -289,7 +289,11 @@ class GapSim:
 
     def diag(self, gap: int = 0) -> dict:
         D = GsDiag()
-        self._chk(lib().gs_read_diagnostics(self._h, gap, C.byref(D), None, None, None))
+        rc = lib().gs_read_diagnostics(self._h, gap, C.byref(D), None, None, None)
+        # a missed Newton tolerance is reported once with the outputs filled
+        converged = rc != GS_ENOCONV
+        if converged:
+            self._chk(rc)
         M = self.cfgs[gap].n_mesh
         return dict(step=D.step, t=D.t, phi0=D.phi0, sigma=D.sigma, qcirc=D.qcirc,
                     qcirc_star=D.qcirc_star, qconv=D.qconv, e_ground=D.e_ground,
@@ -299,6 +303,7 @@ class GapSim:
                     emit_step=np.array(D.emit_step[:]), inj_step=D.inj_step,
                     abs_cum=np.array([[D.abs_cum[a][b] for b in range(2)] for a in range(2)]),
                     emit_cum=np.array(D.emit_cum[:]), inj_cum=D.inj_cum, pushed_cum=D.pushed_cum,
+                    newton_converged=converged,
                     newton_last=D.newton_last, newton_fallback_last=D.newton_fallback_last,
                     newton_total=D.newton_total, newton_fallbacks=D.newton_fallbacks,
                     newton_resid0=D.newton_resid0, newton_resid=D.newton_resid)

@@ -1,0 +1,143 @@
+"""Strict coupling solved by Newton on u = (gap voltage, loop currents).
+
+The residual (loop equations in volts plus the closure V = phi0(sigma(u))) is
+affine in u, so with the exact constant Jacobian one correction lands on the
+solution of the closed strict system (Sec. 2.4.2, eq. Poisson_BC2).  A guess
+already within the tolerance is kept.  The bars: with a tolerance below what the
+extrapolated guess reaches, the Newton path agrees with the oracle's direct
+tridiagonal solve to the same 1e-12 as the direct GPU path; at most one
+correction per level; the final scaled residual is below the tolerance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_24010_amd import workloads as W
+
+from test_gpu_parity import _gapsim, check_run, check_fields
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(cfg, loads, nsteps, guess, fp32, opts=None, cap=(200_000, 200_000)):
+    gs = _gapsim()
+    sim = gs.GapSim(cfg, particle_fp=32 if fp32 else 64, capacity=cap)
+    for k, v in (opts or {}).items():
+        sim.set_option(k, v)
+    for sp in sorted(loads):
+        sim.inject(0, sp, *loads[sp])
+    recs = []
+    for _ in range(nsteps):
+        sim.step_strict(1, guess)
+        recs.append(sim.diag(0))
+    return sim, recs
+
+
+def _case(which):
+    if which == "rc":
+        cfg = W.config1(n_cells=256)
+        loads = W.load_config1(n_per_species=20000, seed=4)
+        loads = {s: (x, v * 30.0) for s, (x, v) in loads.items()}
+    else:
+        cfg = W.config2(n_cells=512, beam_per_step=300)
+        loads = W.load_config2(n=30000, seed=4)
+    return cfg, loads
+
+
+def _oracle_strict(cfg, loads, n):
+    orc = oracle.OracleSim(cfg, fp32=False)
+    for sp in sorted(loads):
+        orc.inject(sp, *loads[sp])
+    ods = []
+    for _ in range(n):
+        orc.step(oracle.STRICT, 1)
+        ods.append(orc.diag())
+    return orc, ods
+
+
+# The scaled residual cannot go below the rounding of its own terms: a loop
+# row holds L dI/dt and R I in volts, individually far larger than their sum
+# for the 10 mH secondary at dt = 1 ps, so its floor sits near 1e-12 there.
+@pytest.mark.parametrize("which,floor", [("rc", 1e-12), ("coupled_lc", 1e-11)])
+def test_newton_one_correction_reaches_the_direct_solve(which, floor):
+    """One correction from the extrapolated guess (tolerance 1e-12, at most one
+    update) lands on the oracle's direct solve to 1e-12, down to the residual's
+    rounding floor."""
+    gs = _gapsim()
+    cfg, loads = _case(which)
+    n = 60
+    orc, ods = _oracle_strict(cfg, loads, n)
+    sim, nds = _run(cfg, loads, n, gs.GUESS_EXTRAP, fp32=False,
+                    opts={gs.OPT_NEWTON_TOL: 1, gs.OPT_NEWTON_MAXIT: 1})
+    check_run(list(zip(nds, ods)), 1e-12, cfg.n_mesh)
+    check_fields(sim, orc, 1e-12)
+    its = np.array([d["newton_last"] for d in nds])
+    res = np.array([d["newton_resid"] for d in nds])
+    res0 = np.array([d["newton_resid0"] for d in nds])
+    print(f"{which}: corrections per level {np.bincount(its)}; scaled residual of the "
+          f"extrapolated guess: median {np.median(res0[3:]):.2e}, max {res0[3:].max():.2e}; "
+          f"after one correction: max {res.max():.2e}")
+    assert np.all((its == 1) | (res0 <= 1e-12)), its
+    assert np.all(res <= floor), res.max()
+    assert nds[-1]["newton_total"] == its.sum() and nds[-1]["newton_fallbacks"] == 0
+
+
+@pytest.mark.parametrize("which", ["rc", "coupled_lc"])
+def test_newton_default_tolerance(which):
+    """Tolerance 1e-10: at most one correction per level; a guess already inside
+    the tolerance is kept, so the levels differ from the direct solve by what
+    that residual allows."""
+    gs = _gapsim()
+    cfg, loads = _case(which)
+    n = 60
+    _, ods = _oracle_strict(cfg, loads, n)
+    _, nds = _run(cfg, loads, n, gs.GUESS_EXTRAP, fp32=False)
+    its = np.array([d["newton_last"] for d in nds])
+    res = np.array([d["newton_resid"] for d in nds])
+    assert its.min() >= 0 and its.max() <= 1 and np.all(res <= 1e-10)
+    for dg, do in zip(nds, ods):
+        assert dg["step"] == do["step"]
+    v = np.array([d["phi0"] for d in nds])
+    vo = np.array([o["phi0"] for o in ods])
+    # a residual of 1e-10 in units of v_ref bounds the voltage error by about
+    # that much (the closure row has unit slope in V); allow a factor 10
+    assert np.abs(v - vo).max() <= 10 * 1e-10 * cfg.v_ref
+
+
+def test_newton_tight_tolerance_binary32():
+    """Binary32 particles, three-mesh circuit: one correction per level down to
+    the residual's rounding floor, and the run stays with the direct solve
+    (binary32 casts of the field may differ in the last bit, so only closeness
+    is asked)."""
+    gs = _gapsim()
+    cfg = W.config2(n_cells=1024, beam_per_step=500)
+    loads = W.load_config2(n=50000, seed=6)
+    _, direct = _run(cfg, loads, 40, gs.GUESS_DIRECT, fp32=True)
+    _, newton = _run(cfg, loads, 40, gs.GUESS_EXTRAP, fp32=True,
+                     opts={gs.OPT_NEWTON_TOL: 1, gs.OPT_NEWTON_MAXIT: 1})
+    assert all(d["newton_last"] == -1 for d in direct)
+    its = np.array([d["newton_last"] for d in newton])
+    assert its.max() <= 1 and all(d["newton_resid"] <= 1e-11 for d in newton)
+    for key in ("phi0", "sigma", "qcirc"):
+        a = np.array([d[key] for d in newton])
+        b = np.array([d[key] for d in direct])
+        assert np.abs(a - b).max() <= 1e-6 * np.abs(b).max(), key
+
+
+def test_newton_missed_tolerance_is_reported_once():
+    """No corrections allowed: the extrapolated guess misses the tolerance, the
+    step keeps it, and the next read reports GS_ENOCONV once."""
+    gs = _gapsim()
+    cfg = W.config2(n_cells=256, beam_per_step=100)
+    loads = W.load_config2(n=5000, seed=7)
+    sim = gs.GapSim(cfg, particle_fp=32, capacity=(50_000, 50_000))
+    for sp in sorted(loads):
+        sim.inject(0, sp, *loads[sp])
+    sim.set_option(gs.OPT_NEWTON_MAXIT, 0)
+    sim.step_strict(5, gs.GUESS_EXTRAP)
+    d = sim.diag(0)
+    assert not d["newton_converged"] and d["newton_last"] == 0 and d["newton_resid"] > 1e-10
+    sim.set_option(gs.OPT_NEWTON_MAXIT, 8)
+    sim.step_strict(2, gs.GUESS_EXTRAP)
+    d = sim.diag(0)
+    assert d["newton_converged"] and d["newton_resid"] <= 1e-10
