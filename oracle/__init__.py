@@ -19,11 +19,11 @@ STRICT, WEAK = 0, 1
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c with gcc (plain -O2, no FMA contraction, no fast-math)."""
+    """Compile oracle.c and mlp.c with gcc (plain -O2, no FMA contraction, no fast-math)."""
     if force or not os.path.exists(LIB_PATH):
         cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
                "-fPIC", "-shared", "-Wall", "-o", LIB_PATH + ".tmp", os.path.join(HERE, "oracle.c"),
-               "-lm"]
+               os.path.join(HERE, "mlp.c"), "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(LIB_PATH + ".tmp", LIB_PATH)
     return LIB_PATH
@@ -106,6 +106,17 @@ def lib():
         L.or_gather32.restype = C.c_float
         L.or_circuit_run.argtypes = [C.POINTER(OrParams), C.c_int64, P, P]
         L.or_circuit_run.restype = C.c_int32
+        L.or_gelu.argtypes = [C.c_double]
+        L.or_gelu.restype = C.c_double
+        L.or_gelu_grad.argtypes = [C.c_double]
+        L.or_gelu_grad.restype = C.c_double
+        L.or_mlp_forward.argtypes = [P, P, C.c_int64, P]
+        L.or_mlp_loss_grad.argtypes = [P, P, P, C.c_int64, P]
+        L.or_mlp_loss_grad.restype = C.c_double
+        L.or_adam_step.argtypes = [P, P, P, C.c_int64, P, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                   C.c_double]
+        L.or_round_bf16.argtypes = [C.c_float]
+        L.or_round_bf16.restype = C.c_float
         _lib = L
     return _lib
 
@@ -183,6 +194,60 @@ def circuit_run(cfg, nsteps: int):
     if rc:
         raise RuntimeError(f"or_circuit_run failed: {rc}")
     return q.reshape(nsteps, cfg.n_mesh), v
+
+
+# ---------------------------------------------------------------------------
+# guess network (mlp.c)
+# ---------------------------------------------------------------------------
+MLP_IN, MLP_HIDDEN, MLP_OUT = 48, 128, 3
+MLP_NPARAM = 39683
+# (name, offset, shape) of each parameter block in the flat vector
+MLP_LAYOUT = []
+_o = 0
+for _name, _shape in (("W1", (128, 48)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)),
+                      ("W3", (128, 128)), ("b3", (128,)), ("W4", (3, 128)), ("b4", (3,))):
+    MLP_LAYOUT.append((_name, _o, _shape))
+    _o += int(np.prod(_shape))
+assert _o == MLP_NPARAM
+
+
+def gelu(z: float) -> float:
+    return float(lib().or_gelu(float(z)))
+
+
+def gelu_grad(z: float) -> float:
+    return float(lib().or_gelu_grad(float(z)))
+
+
+def mlp_forward(theta, x) -> np.ndarray:
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, MLP_IN)
+    y = np.zeros((x.shape[0], MLP_OUT))
+    lib().or_mlp_forward(_dp(theta), _dp(x), x.shape[0], _dp(y))
+    return y
+
+
+def mlp_loss_grad(theta, x, t):
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, MLP_IN)
+    t = np.ascontiguousarray(t, dtype=np.float64).reshape(-1, MLP_OUT)
+    g = np.zeros(MLP_NPARAM)
+    loss = lib().or_mlp_loss_grad(_dp(theta), _dp(x), _dp(t), x.shape[0], _dp(g))
+    return float(loss), g
+
+
+def adam_step(theta, m, v, t: int, g, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In place on float64 arrays theta, m, v."""
+    for a in (theta, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    lib().or_adam_step(_dp(theta), _dp(m), _dp(v), int(t), _dp(g), theta.size, lr, beta1, beta2, eps)
+
+
+def round_bf16(a) -> np.ndarray:
+    a = np.asarray(a, dtype=np.float32)
+    f = lib().or_round_bf16
+    return np.array([f(float(v)) for v in a.ravel()], dtype=np.float32).reshape(a.shape)
 
 
 class OracleSim:

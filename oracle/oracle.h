@@ -128,6 +128,26 @@ float or_gather32(int32_t n_cells, const float *ehat, float xi);
  * v_out[n] = gap voltage, for levels 0..nsteps-1 */
 int32_t or_circuit_run(const or_params *p, int64_t nsteps, double *q_out, double *v_out);
 
+/* Guess network of the Newton form of the strict step (mlp.c): layer sizes,
+ * flat parameter layout W1 b1 W2 b2 W3 b3 W4 b4 (weights row-major [out][in]),
+ * GELU hidden layers, linear output. */
+#define OR_MLP_IN 48
+#define OR_MLP_HIDDEN 128
+#define OR_MLP_OUT 3
+#define OR_MLP_NPARAM 39683
+double or_gelu(double z);
+double or_gelu_grad(double z);
+/* y[n][3] for x[n][48] */
+void or_mlp_forward(const double *theta, const double *x, int64_t n, double *y);
+/* mean squared error over n samples and 3 outputs; grad (may be NULL) receives
+ * its gradient with respect to theta */
+double or_mlp_loss_grad(const double *theta, const double *x, const double *t, int64_t n, double *grad);
+/* one Adam update, step number t >= 1 */
+void or_adam_step(double *theta, double *m, double *v, int64_t t, const double *g, int64_t np, double lr,
+                  double beta1, double beta2, double eps);
+/* binary32 rounded to bfloat16, returned as binary32 */
+float or_round_bf16(float x);
+
 #ifdef __cplusplus
 }
 #endif

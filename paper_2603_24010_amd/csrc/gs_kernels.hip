@@ -162,7 +162,7 @@ __device__ inline unsigned int wave_sum(unsigned int a) {
 // k_field: level n of one gap per workgroup
 // ---------------------------------------------------------------------------
 constexpr int FBS = 1024;
-constexpr int FCH = 16;  // nodes per thread: n_cells <= FBS * FCH = 16384
+// n_cells <= 16384: S_k of every cell is held in LDS (128 KiB at the maximum)
 
 __device__ inline double node_rho(double s0, double dx, unsigned long long a, int j, int N, int fp64) {
   const double scale = fp64 ? 5.684341886080801486968994140625e-14 /* 2^-44 */
@@ -394,43 +394,30 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   double *rho = p.rho64 + sc.nbase;
   double *E = p.E64 + sc.nbase;
 
-  // 1. nodal density of level n; prefix sums S_k = dx rho_0/2 + dx sum_{1..k} rho_j
+  // 1. nodal density of level n (to global rho and, as the cell terms of the
+  //    prefix sums, to LDS); the accumulator is cleared for the next push
+  for (int k = tid; k <= N; k += FBS) {
+    const double r = node_rho(s0, dx, acc[k], k, N, fp64);
+    rho[k] = r;
+    acc[k] = 0ull;
+    if (k < N)
+      Sk[k] = (k == 0) ? dx * r / 2.0 : dx * r;
+    else
+      s_rhoN = r;
+  }
+  __syncthreads();
+  // prefix sums S_k = dx rho_0/2 + dx sum_{1..k} rho_j over contiguous chunks
   const int ch = (N + FBS - 1) / FBS;
-  const int k0 = tid * ch;
-  double rv[FCH];
+  const int k0 = min(tid * ch, N), k1 = min(k0 + ch, N);
   double loc = 0.0;
-#pragma unroll
-  for (int i = 0; i < FCH; ++i) {
-    rv[i] = 0.0;
-    const int k = k0 + i;
-    if (i < ch && k < N) rv[i] = node_rho(s0, dx, acc[k], k, N, fp64);
-  }
-#pragma unroll
-  for (int i = 0; i < FCH; ++i) {
-    const int k = k0 + i;
-    if (i < ch && k < N) {
-      rho[k] = rv[i];
-      acc[k] = 0ull;
-      loc += (k == 0) ? dx * rv[i] / 2.0 : dx * rv[i];
-    }
-  }
-  if (tid == FBS - 1) {
-    const double r = node_rho(s0, dx, acc[N], N, N, fp64);
-    rho[N] = r;
-    acc[N] = 0ull;
-    s_rhoN = r;
-  }
+  for (int k = k0; k < k1; ++k) loc += Sk[k];
   double tot;
   double run = block_exclusive_scan_w(loc, wsum, &tot);
   double sumS = 0.0;
-#pragma unroll
-  for (int i = 0; i < FCH; ++i) {
-    const int k = k0 + i;
-    if (i < ch && k < N) {
-      run += (k == 0) ? dx * rv[i] / 2.0 : dx * rv[i];
-      Sk[k] = run;
-      sumS += run;
-    }
+  for (int k = k0; k < k1; ++k) {
+    run += Sk[k];
+    Sk[k] = run;
+    sumS += run;
   }
   const double P = block_sum_w(sumS, wsum) * dx / eps0;
 
@@ -446,24 +433,20 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   const double sigma = s_sigma;
   const double rhoN = s_rhoN;
   const size_t eb = (size_t)sc.ebase;
-#pragma unroll
-  for (int i = 0; i < FCH; ++i) {
-    const int k = k0 + i;
-    if (i < ch && k < N) {
-      const double e = (sigma + Sk[k]) / eps0;
-      E[k] = e;
+  for (int k = tid; k < N; k += FBS) {
+    const double e = (sigma + Sk[k]) / eps0;
+    E[k] = e;
+    if (fp64)
+      ((double *)p.ehat)[eb + k + 1] = e;
+    else
+      ((float *)p.ehat)[eb + k + 1] = (float)e;
+    if (k == N - 1) {
+      const double ed = e + dx * rhoN / (2.0 * eps0);
+      ss.e_ground = ed;
       if (fp64)
-        ((double *)p.ehat)[eb + k + 1] = e;
+        ((double *)p.ehat)[eb + N + 1] = ed;
       else
-        ((float *)p.ehat)[eb + k + 1] = (float)e;
-      if (k == N - 1) {
-        const double ed = e + dx * rhoN / (2.0 * eps0);
-        ss.e_ground = ed;
-        if (fp64)
-          ((double *)p.ehat)[eb + N + 1] = ed;
-        else
-          ((float *)p.ehat)[eb + N + 1] = (float)ed;
-      }
+        ((float *)p.ehat)[eb + N + 1] = (float)ed;
     }
   }
   if (tid == 0) {
