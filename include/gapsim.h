@@ -134,6 +134,9 @@ typedef struct {
   int64_t newton_fallbacks;
   double newton_resid0;   /* infinity norm of the scaled residual at the initial guess */
   double newton_resid;    /* ... after the last update */
+  double newton_guess[GS_MAX_MESH + 1]; /* initial guess u = (V, I_0, ..) of the last solve
+                                           (direct solve: the extrapolation) */
+  double mlp_proposal[3]; /* the guess network's u at the last GS_GUESS_MLP solve, used or not */
 } gs_diag;
 
 /* Accumulated device time of the library's kernels, measured with HIP events
@@ -191,8 +194,9 @@ gs_status gs_inject(gs_ctx *ctx, int32_t gap, int32_t species, int64_t n, const 
  * GS_GUESS_MLP instead runs Newton on u = (gap voltage, loop currents) from a
  * quadratic extrapolation or from the network set by gs_mlp_set_weights (the
  * Newton iteration decides convergence; a non-finite or worse MLP guess falls
- * back to the extrapolation).  Asynchronous.  Errors: GS_EINVAL, GS_ECAPACITY
- * (sticky), GS_EDEVICE. */
+ * back to the extrapolation).  Asynchronous.  Errors: GS_EINVAL (bad mode; the
+ * network needs every gap to have two meshes), GS_ESTATE (GS_GUESS_MLP before
+ * weights were set), GS_ECAPACITY (sticky), GS_EDEVICE. */
 gs_status gs_step_strict(gs_ctx *ctx, int32_t n_steps, int32_t guess);
 
 /* Advance every gap n_steps steps with weak coupling (Sec. 2.4.3): the circuit
@@ -218,6 +222,69 @@ gs_status gs_read_diagnostics(gs_ctx *ctx, int32_t gap, gs_diag *out, double *ph
  * At most max_n are written; *n_out receives the live count.  Synchronises. */
 gs_status gs_read_particles(gs_ctx *ctx, int32_t gap, int32_t species, void *xi, void *u,
                             uint32_t *id, int64_t max_n, int64_t *n_out);
+
+/* ---- Newton guess network --------------------------------------------------
+ * Not part of the paper: the paper solves the strict step (Sec. 2.4.2) in one
+ * linear pass.  Its Newton form (gs_step_strict with a guess mode) starts from
+ * a guess of u = (gap voltage, I_0, I_1); a small network can propose it.  The
+ * network is 48 -> 128 -> 128 -> 128 -> 3, GELU hidden layers (exact erf
+ * form), linear output.  Parameters: one array of GS_MLP_NPARAM binary32 values
+ * W1[128][48] b1[128] W2[128][128] b2[128] W3[128][128] b3[128] W4[3][128]
+ * b4[3] (weights row-major [out][in]).
+ * Input: the last 8 solved levels k = 1..8 (level n-k) of (V, I_0, I_1,
+ * sigma_+, Q_abs, Q_em) at feature 6(k-1) + q, where Q_abs is the charge the
+ * circuit electrode absorbed in the push before that level and Q_em the charge
+ * of the electrons it emitted (Q_conv = Q_abs - Q_em), normalised as
+ * (x - x_mean) / x_scale.  Output y: u = u_extrap + y_mean + y_scale * y, with
+ * u_extrap the quadratic extrapolation 3 u_{n-1} - 3 u_{n-2} + u_{n-3}.
+ * norm: GS_MLP_NORM binary64 values x_mean[48] x_scale[48] y_mean[3]
+ * y_scale[3]. */
+#define GS_MLP_IN 48
+#define GS_MLP_OUT 3
+#define GS_MLP_NPARAM 39683
+#define GS_MLP_NORM 102
+
+/* Install the network used by gs_step_strict(..., GS_GUESS_MLP): theta (host,
+ * n = GS_MLP_NPARAM finite values) is rounded to bfloat16 (nearest, ties to
+ * even) for evaluation with binary32 sums; norm (host, GS_MLP_NORM values,
+ * scales > 0) is copied.  Synchronises.  Errors: GS_EINVAL, GS_ENOMEM,
+ * GS_EDEVICE. */
+gs_status gs_mlp_set_weights(gs_ctx *ctx, const float *theta, int64_t n, const double *norm);
+
+/* Evaluate the installed network (bfloat16 weights, binary32 sums, the same
+ * device routine the strict step uses) on n normalised inputs: x [n][48] and
+ * y [n][3] in device memory, caller-owned.  Asynchronous on the context's
+ * stream.  Errors: GS_ESTATE (no weights), GS_EINVAL, GS_EDEVICE. */
+gs_status gs_mlp_forward(gs_ctx *ctx, const float *x, int64_t n, float *y);
+
+/* Record training samples from the following strict steps: the field solve of
+ * level n of gap g writes sample (n - n0) * n_gaps + g, where n0 is the level
+ * the next step solves, while that index is below capacity: x [.][48] the raw
+ * (unnormalised) input of that level, y [.][3] the raw target u* - u_extrap,
+ * u* being the level's solution (V, I_0, I_1).  Levels whose history reaches
+ * before level 0 see zeros there.  x and y are device memory owned by the
+ * caller, written asynchronously and kept until recording is switched off
+ * (x or y NULL, or capacity 0).  Errors: GS_EINVAL. */
+gs_status gs_mlp_record(gs_ctx *ctx, float *x, float *y, int64_t capacity);
+
+/* Bytes of device workspace gs_mlp_train needs for a batch size (0 if batch < 1). */
+size_t gs_mlp_train_workspace(int32_t batch);
+
+/* Train the network by Adam (Kingma and Ba 2015; bias-corrected moments) on
+ * the mean squared error, in binary32, on the GPU.  Device arrays, caller-owned:
+ * x [n][48] normalised inputs, t [n][3] normalised targets; order [n_order]
+ * sample indices, taken batch by batch (n_order / batch steps; a remainder is
+ * ignored; an index outside [0, n) is replaced by 0 and makes the call return
+ * GS_EINVAL); theta, adam_m, adam_v [GS_MLP_NPARAM] updated in place; step0 =
+ * Adam steps already taken; loss [steps] (may be NULL) receives each step's
+ * batch loss before its update; grad_last [GS_MLP_NPARAM] (may be NULL) the
+ * last step's gradient; work (work_bytes >= gs_mlp_train_workspace(batch)).
+ * Runs on hip_stream (a hipStream_t, NULL = default) and synchronises it at
+ * the end.  Errors: GS_EINVAL, GS_EDEVICE. */
+gs_status gs_mlp_train(const float *x, const float *t, int64_t n, const int32_t *order, int64_t n_order,
+                       int32_t batch, float *theta, float *adam_m, float *adam_v, int64_t step0, double lr,
+                       double beta1, double beta2, double eps, float *loss, float *grad_last, void *work,
+                       size_t work_bytes, void *hip_stream);
 
 /* Tune or switch parts of the launch configuration (see GS_OPT_*). */
 gs_status gs_set_option(gs_ctx *ctx, int32_t option, int64_t value);

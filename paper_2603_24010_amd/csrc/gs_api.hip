@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "gs_internal.h"
+#include "gs_mlp_dev.h"
 
 using namespace gs;
 
@@ -52,7 +53,9 @@ struct gs_ctx {
   // graph cache: one captured chunk of `compact_every` steps per (mode, guess)
   hipGraphExec_t gexec[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
   int gexec_len[2][3] = {{0, 0, 0}, {0, 0, 0}};
-  double *mlp_u = nullptr;
+  // guess network
+  uint16_t *mlp_w = nullptr;
+  double *mlp_norm = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -349,11 +352,11 @@ static gs_status setup(gs_ctx *ctx) {
   ALLOC(d.err, unsigned int *, 8);
   ALLOC(d.gc, const GapConst *, sizeof(GapConst) * (size_t)G);
   ALLOC(d.gs, GapState *, sizeof(GapState) * (size_t)G);
-  ALLOC(ctx->mlp_u, double *, sizeof(double) * (size_t)G * (MAXM + 1));
 #undef ALLOC
-  d.tile_prefix = nullptr;
-  d.done_counter = nullptr;
-  d.mlp_u = nullptr;
+  d.mlp_w = nullptr;
+  d.mlp_norm = nullptr;
+  d.rec_x = d.rec_y = nullptr;
+  d.rec_cap = d.rec_level0 = 0;
   hipStream_t s = ctx->stream;
   std::vector<GapState> hs(G);
   for (int g = 0; g < G; ++g) init_state(ctx->params[g], ctx->hc[g], hs[g]);
@@ -573,7 +576,6 @@ static gs_status run_steps(gs_ctx *ctx, int n_steps, int mode, int guess) {
   if (n_steps < 0) return fail(ctx, GS_EINVAL, "n_steps < 0");
   gs_status st = check_sticky(ctx, false);
   if (st != GS_OK) return st;
-  if (guess == GS_GUESS_MLP) ctx->dp.mlp_u = ctx->mlp_u;
   int left = n_steps;
   // graph replay: whole chunks that start right after a compaction
   if (ctx->use_graph && !ctx->timing) {
@@ -629,6 +631,12 @@ static gs_status run_steps(gs_ctx *ctx, int n_steps, int mode, int guess) {
 extern "C" gs_status gs_step_strict(gs_ctx *ctx, int32_t n_steps, int32_t guess) {
   if (!ctx) return GS_ESTATE;
   if (guess < GS_GUESS_DIRECT || guess > GS_GUESS_MLP) return fail(ctx, GS_EINVAL, "bad guess mode");
+  if (guess == GS_GUESS_MLP) {
+    if (!ctx->mlp_w) return fail(ctx, GS_ESTATE, "no guess network weights (gs_mlp_set_weights)");
+    for (int g = 0; g < ctx->G; ++g)
+      if (ctx->hc[g].M != 2)
+        return fail(ctx, GS_EINVAL, "gap %d: the guess network needs a two-mesh circuit (u = V, I_0, I_1)", g);
+  }
   return run_steps(ctx, n_steps, 0, guess);
 }
 
@@ -697,6 +705,8 @@ extern "C" gs_status gs_read_diagnostics(gs_ctx *ctx, int32_t gap, gs_diag *out,
   out->newton_fallbacks = s.newton_fallbacks;
   out->newton_resid0 = s.newton_r0;
   out->newton_resid = s.newton_r;
+  for (int j = 0; j <= c.M; ++j) out->newton_guess[j] = s.guess[j];
+  for (int j = 0; j < 3; ++j) out->mlp_proposal[j] = s.mlp_prop[j];
   return check_sticky(ctx, true);
 }
 
@@ -735,6 +745,82 @@ extern "C" gs_status gs_read_particles(gs_ctx *ctx, int32_t gap, int32_t species
   }
   if (n_out) *n_out = live;
   return check_sticky(ctx, true);
+}
+
+// ---------------------------------------------------------------------------
+// Newton guess network
+// ---------------------------------------------------------------------------
+// Captured graphs hold the device pointer block by value: drop them when it changes.
+static void drop_graphs(gs_ctx *ctx) {
+  for (int m = 0; m < 2; ++m)
+    for (int k = 0; k < 3; ++k) {
+      if (ctx->gexec[m][k]) (void)hipGraphExecDestroy(ctx->gexec[m][k]);
+      ctx->gexec[m][k] = nullptr;
+      ctx->gexec_len[m][k] = 0;
+    }
+}
+
+// binary32 -> bfloat16 bits, round to nearest, ties to even (NaN kept quiet)
+static uint16_t to_bf16(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+extern "C" gs_status gs_mlp_set_weights(gs_ctx *ctx, const float *theta, int64_t n, const double *norm) {
+  if (!ctx) return GS_ESTATE;
+  if (!theta || !norm || n != MLP_NPARAM)
+    return fail(ctx, GS_EINVAL, "theta must hold %d values and norm %d", MLP_NPARAM, MLP_NORM);
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(theta[i])) return fail(ctx, GS_EINVAL, "theta[%lld] is not finite", (long long)i);
+  for (int i = 0; i < MLP_NORM; ++i) {
+    const bool scale = (i >= MLP_IN && i < 2 * MLP_IN) || i >= 2 * MLP_IN + MLP_OUT;
+    if (!std::isfinite(norm[i]) || (scale && !(norm[i] > 0.0)))
+      return fail(ctx, GS_EINVAL, "norm[%d] must be finite (and positive for a scale)", i);
+  }
+  std::vector<uint16_t> wb((size_t)n);
+  for (int64_t i = 0; i < n; ++i) wb[(size_t)i] = to_bf16(theta[i]);
+  if (!ctx->mlp_w) {
+    ctx->mlp_w = (uint16_t *)dev_alloc(ctx, sizeof(uint16_t) * MLP_NPARAM);
+    ctx->mlp_norm = (double *)dev_alloc(ctx, sizeof(double) * MLP_NORM);
+    if (!ctx->mlp_w || !ctx->mlp_norm) return fail(ctx, GS_ENOMEM, "guess network weights");
+  }
+  HIPCHK(ctx, hipMemcpyAsync(ctx->mlp_w, wb.data(), sizeof(uint16_t) * MLP_NPARAM, hipMemcpyHostToDevice,
+                             ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->mlp_norm, norm, sizeof(double) * MLP_NORM, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->dp.mlp_w = ctx->mlp_w;
+  ctx->dp.mlp_norm = ctx->mlp_norm;
+  drop_graphs(ctx);
+  return GS_OK;
+}
+
+extern "C" gs_status gs_mlp_forward(gs_ctx *ctx, const float *x, int64_t n, float *y) {
+  if (!ctx) return GS_ESTATE;
+  if (!ctx->mlp_w) return fail(ctx, GS_ESTATE, "no guess network weights (gs_mlp_set_weights)");
+  if (n < 0 || (n > 0 && (!x || !y))) return fail(ctx, GS_EINVAL, "bad x, y or n");
+  if (n == 0) return GS_OK;
+  hipError_t e = launch_mlp_forward(ctx->mlp_w, x, n, y, ctx->stream);
+  if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "guess network launch: %s", hipGetErrorString(e));
+  return GS_OK;
+}
+
+extern "C" gs_status gs_mlp_record(gs_ctx *ctx, float *x, float *y, int64_t capacity) {
+  if (!ctx) return GS_ESTATE;
+  if (capacity < 0) return fail(ctx, GS_EINVAL, "capacity < 0");
+  if (!x || !y || capacity == 0) {
+    ctx->dp.rec_x = ctx->dp.rec_y = nullptr;
+    ctx->dp.rec_cap = 0;
+  } else {
+    ctx->dp.rec_x = x;
+    ctx->dp.rec_y = y;
+    ctx->dp.rec_cap = capacity;
+    ctx->dp.rec_level0 = ctx->steps_done;
+  }
+  drop_graphs(ctx);
+  return GS_OK;
 }
 
 extern "C" gs_status gs_set_option(gs_ctx *ctx, int32_t option, int64_t value) {

@@ -77,6 +77,12 @@ struct GapState {
   int32_t newton_last, newton_fb_last;
   int64_t newton_total, newton_fallbacks;
   double newton_r0, newton_r;
+  double guess[MAXM + 1];  // the u the last Newton solve started from
+  double mlp_prop[3];      // the guess network's proposal at the last solve (used or not)
+  // ring of the last 8 levels' (V, I_0, I_1, sigma, Q_abs, Q_em): the guess
+  // network's input; hist_head is the slot the next level goes to
+  double hist[8][6];
+  int32_t hist_head, pad1;
 };
 
 // An ion absorbed by an electrode, waiting for its secondary emission.
@@ -100,12 +106,18 @@ struct DevPtrs {
   double *rho64, *E64, *phi64;     // node / half-grid / node arrays (nbase offsets; E uses nbase too)
   void *ehat;                      // field table for the push, binary32 or binary64
   int64_t *epoch;                  // compaction epoch (device)
-  int32_t *tile_prefix;            // [G + 1] push work tiles per gap, prefix
-  unsigned int *done_counter;      // for the last-block pattern of the field kernel
   unsigned int *err;               // [0] flags, [1] gap of first error
-  const double *mlp_u;             // [G][MAXM+1] MLP guesses (or null)
   Event *ev;                       // absorbed-ion events, per-gap lists
   unsigned long long *ev_count;    // [G]
+  // Newton guess network: bfloat16 weights (flat layout of gs_mlp_dev.h) and
+  // the normalisation block; null until weights are set
+  const uint16_t *mlp_w;
+  const double *mlp_norm;
+  // sample recording for training: level n of gap g goes to sample
+  // (n - rec_level0) * G + g when that is below rec_cap
+  float *rec_x;  // [rec_cap][48] raw features
+  float *rec_y;  // [rec_cap][3] raw targets u* - u_extrapolated
+  int64_t rec_cap, rec_level0;
 };
 
 enum { ERR_CAPACITY = 1u, ERR_BADINJECT = 2u, ERR_NOCONV = 4u };
@@ -138,6 +150,8 @@ hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStrea
 hipError_t launch_inject(const DevPtrs &p, int gap, int species, long long n, const double *x_dev,
                          const double *v_dev, long long id0, int fp64, hipStream_t s);
 hipError_t launch_phi(const DevPtrs &p, int gap, hipStream_t s);
+// guess network (gs_mlp.hip): y[n][3] = net(x[n][48]) with bfloat16 weights W
+hipError_t launch_mlp_forward(const uint16_t *W, const float *x, long long n, float *y, hipStream_t s);
 size_t push_lds_bytes(int nmax, int fp64, int G, int wide);
 
 }  // namespace gs

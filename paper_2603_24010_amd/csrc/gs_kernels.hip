@@ -18,6 +18,7 @@
 #include <type_traits>
 
 #include "gs_internal.h"
+#include "gs_mlp_dev.h"
 
 namespace gs {
 
@@ -177,7 +178,7 @@ __device__ inline double node_rho(double s0, double dx, unsigned long long a, in
 // potential the space charge alone gives the electrode.
 __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState &st, double P,
                             int mode, int guess, double tol, int maxit, double *sigma_out,
-                            double *wk, const unsigned long long *tl) {
+                            double *wk, const unsigned long long *tl, const double *mlp_u) {
   const int M = c.M, gm = c.g;
   const double A = c.A, eps0 = c.eps0;
   const long long n = st.level + 1;
@@ -235,7 +236,10 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
     phi0 = ((c.d / eps0) * sig_star + P) / (1.0 + G * c.d / (eps0 * A));
     int iters = -1, fb = 0;
     double r0n = 0.0, rn = 0.0;
-    if (guess != GS_GUESS_DIRECT) {
+    if (guess == GS_GUESS_DIRECT) {
+      // the direct solve starts from nothing; report the extrapolation
+      for (int i = 0; i <= M; ++i) st.guess[i] = 3.0 * st.uh[0][i] - 3.0 * st.uh[1][i] + st.uh[2][i];
+    } else {
       // Newton on u = (V, I_0..I_{M-1}); the residual is affine in u
       const int nu = M + 1;
       auto residual = [&](const double *uu, double *rr) {
@@ -262,8 +266,9 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
       residual(ue, r);
       const double rext = norm(r);
       bool use_mlp = false;
-      if (guess == GS_GUESS_MLP && p.mlp_u) {
-        for (int i = 0; i < nu; ++i) u[i] = p.mlp_u[(size_t)g * (MAXM + 1) + i];
+      if (guess == GS_GUESS_MLP && mlp_u) {
+        for (int i = 0; i < nu; ++i) u[i] = mlp_u[i];
+        for (int i = 0; i < 3; ++i) st.mlp_prop[i] = mlp_u[i];
         residual(u, r);
         const double rm = norm(r);
         use_mlp = (rm == rm) && (rm <= rext);
@@ -273,6 +278,7 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
         for (int i = 0; i < nu; ++i) u[i] = ue[i];
         residual(u, r);
       }
+      for (int i = 0; i < nu; ++i) st.guess[i] = u[i];
       r0n = norm(r);
       rn = r0n;
       iters = 0;
@@ -342,6 +348,18 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
   }
   st.uh[0][0] = phi0;
   for (int j = 0; j < M; ++j) st.uh[0][1 + j] = st.I[j];
+  {
+    // the guess network's history: this level's voltage, first two loop
+    // currents, surface charge and the absorbed / emitted charge behind Q_conv
+    const int hh = st.hist_head;
+    st.hist[hh][0] = phi0;
+    st.hist[hh][1] = st.I[0];
+    st.hist[hh][2] = M > 1 ? st.I[1] : 0.0;
+    st.hist[hh][3] = sigma;
+    st.hist[hh][4] = qsh_i * (double)ab[1 * 2 + 0] + qsh_e * (double)ab[0 * 2 + 0];
+    st.hist[hh][5] = qsh_e * (double)em[0];
+    st.hist_head = (hh + 1) & 7;
+  }
   st.sigma_prev = sigma;
   st.qcirc_prev = qcirc;
   st.level = n;
@@ -373,6 +391,8 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   __shared__ double s_sigma, s_rhoN;
   __shared__ double s_work[8 * MAXM + 8];
   __shared__ unsigned long long s_tally[T_N];
+  __shared__ float s_x[MLP_IN], s_h0[MLP_H], s_h1[MLP_H], s_y[MLP_OUT];
+  __shared__ double s_ue[MAXM + 1], s_mu[MAXM + 1];
   // stage the gap's constants, state and last push's tallies in LDS
   if (tid < T_N) {
     unsigned long long *tl = p.tally + (size_t)g * T_N;
@@ -388,6 +408,30 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
     for (int i = tid; i < (int)(sizeof(GapState) / 8); i += FBS) b[i] = a[i];
   }
   __syncthreads();
+
+  // 0. strict coupling: the guess network's input (the last 8 levels from the
+  //    history ring), recorded for training and/or evaluated for the guess
+  const bool want_mlp = mode == 0 && guess == GS_GUESS_MLP && p.mlp_w != nullptr;
+  const bool want_rec = mode == 0 && p.rec_x != nullptr;
+  const long long rec_idx = (ss.level + 1 - p.rec_level0) * (long long)gridDim.x + g;
+  const bool rec_here = want_rec && rec_idx >= 0 && rec_idx < p.rec_cap;
+  if (want_mlp || rec_here) {
+    if (tid < MLP_IN) {
+      const int kk = tid / 6 + 1, q = tid % 6;
+      const double raw = ss.hist[(ss.hist_head - kk) & 7][q];
+      if (rec_here) p.rec_x[rec_idx * MLP_IN + tid] = (float)raw;
+      if (want_mlp) s_x[tid] = (float)((raw - p.mlp_norm[tid]) / p.mlp_norm[MLP_IN + tid]);
+    }
+    if (tid == 0)
+      for (int i = 0; i <= sc.M; ++i) s_ue[i] = 3.0 * ss.uh[0][i] - 3.0 * ss.uh[1][i] + ss.uh[2][i];
+    if (want_mlp) {
+      mlp_eval_block(p.mlp_w, s_x, s_h0, s_h1, s_y);
+      if (tid == 0)
+        for (int i = 0; i < MLP_OUT; ++i)
+          s_mu[i] = s_ue[i] + p.mlp_norm[2 * MLP_IN + i] + p.mlp_norm[2 * MLP_IN + MLP_OUT + i] * (double)s_y[i];
+    }
+  }
+
   const int N = sc.N;
   const double dx = sc.dx, eps0 = sc.eps0, s0 = sc.s0;
   unsigned long long *acc = p.acc + sc.nbase;
@@ -424,8 +468,11 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   // 2. circuit and surface charge
   if (tid == 0) {
     double sg;
-    solve_level(p, g, sc, ss, P, mode, guess, tol, maxit, &sg, s_work, s_tally);
+    solve_level(p, g, sc, ss, P, mode, guess, tol, maxit, &sg, s_work, s_tally, want_mlp ? s_mu : nullptr);
     s_sigma = sg;
+    if (rec_here)
+      for (int i = 0; i < MLP_OUT; ++i)
+        p.rec_y[rec_idx * MLP_OUT + i] = i <= sc.M ? (float)(ss.uh[0][i] - s_ue[i]) : 0.0f;
   }
   __syncthreads();
 

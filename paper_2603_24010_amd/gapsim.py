@@ -27,8 +27,10 @@ OPT_NEWTON_TOL, OPT_NEWTON_MAXIT, OPT_DEPOSIT, OPT_COMPACT_GRID, OPT_PPT = 7, 8,
 EXPORTED = [
     "gs_init", "gs_destroy", "gs_inject", "gs_step_strict", "gs_step_weak", "gs_read_diagnostics",
     "gs_read_particles", "gs_set_option", "gs_get_timing", "gs_validate_params", "gs_last_error",
-    "gs_version",
+    "gs_version", "gs_mlp_set_weights", "gs_mlp_forward", "gs_mlp_record", "gs_mlp_train_workspace",
+    "gs_mlp_train",
 ]
+MLP_IN, MLP_OUT, MLP_NPARAM, MLP_NORM = 48, 3, 39683, 102
 
 Mat = (C.c_double * MAX_MESH) * MAX_MESH
 
@@ -72,6 +74,8 @@ class GsDiag(C.Structure):
         ("newton_last", C.c_int32), ("newton_fallback_last", C.c_int32),
         ("newton_total", C.c_int64), ("newton_fallbacks", C.c_int64),
         ("newton_resid0", C.c_double), ("newton_resid", C.c_double),
+        ("newton_guess", C.c_double * (MAX_MESH + 1)),
+        ("mlp_proposal", C.c_double * 3),
     ]
 
 
@@ -126,6 +130,18 @@ def lib():
         L.gs_last_error.argtypes = [vp]
         L.gs_last_error.restype = C.c_char_p
         L.gs_version.restype = C.c_char_p
+        L.gs_mlp_set_weights.argtypes = [vp, C.POINTER(C.c_float), C.c_int64, P]
+        L.gs_mlp_set_weights.restype = C.c_int
+        L.gs_mlp_forward.argtypes = [vp, vp, C.c_int64, vp]
+        L.gs_mlp_forward.restype = C.c_int
+        L.gs_mlp_record.argtypes = [vp, vp, vp, C.c_int64]
+        L.gs_mlp_record.restype = C.c_int
+        L.gs_mlp_train_workspace.argtypes = [C.c_int32]
+        L.gs_mlp_train_workspace.restype = C.c_size_t
+        L.gs_mlp_train.argtypes = [vp, vp, C.c_int64, vp, C.c_int64, C.c_int32, vp, vp, vp, C.c_int64,
+                                   C.c_double, C.c_double, C.c_double, C.c_double, vp, vp, vp, C.c_size_t,
+                                   vp]
+        L.gs_mlp_train.restype = C.c_int
         _lib = L
     return _lib
 
@@ -306,7 +322,41 @@ class GapSim:
                     newton_converged=converged,
                     newton_last=D.newton_last, newton_fallback_last=D.newton_fallback_last,
                     newton_total=D.newton_total, newton_fallbacks=D.newton_fallbacks,
-                    newton_resid0=D.newton_resid0, newton_resid=D.newton_resid)
+                    newton_resid0=D.newton_resid0, newton_resid=D.newton_resid,
+                    newton_guess=np.array(D.newton_guess[:M + 1]),
+                    mlp_proposal=np.array(D.mlp_proposal[:]))
+
+    # -- Newton guess network -------------------------------------------------
+    def mlp_set_weights(self, theta, norm):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        norm = np.ascontiguousarray(norm, dtype=np.float64)
+        if norm.size != MLP_NORM:
+            raise ValueError(f"norm must hold {MLP_NORM} values")
+        self._chk(lib().gs_mlp_set_weights(self._h, theta.ctypes.data_as(C.POINTER(C.c_float)), theta.size,
+                                           norm.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def mlp_forward(self, x):
+        """x: float32 device tensor [n, 48] (normalised); returns [n, 3]."""
+        import torch
+        x = x.contiguous()
+        assert x.is_cuda and x.dtype == torch.float32 and x.shape[-1] == MLP_IN
+        y = torch.empty((x.shape[0], MLP_OUT), dtype=torch.float32, device=x.device)
+        self._chk(lib().gs_mlp_forward(self._h, C.c_void_p(x.data_ptr()), x.shape[0],
+                                       C.c_void_p(y.data_ptr())))
+        return y
+
+    def mlp_record(self, x=None, y=None):
+        """Record (raw input, raw target) samples of the following strict steps
+        into float32 device tensors x [cap, 48], y [cap, 3]; no arguments stop it."""
+        if x is None or y is None:
+            self._rec = None
+            self._chk(lib().gs_mlp_record(self._h, None, None, 0))
+            return
+        assert x.is_cuda and y.is_cuda and x.is_contiguous() and y.is_contiguous()
+        assert x.shape[1] == MLP_IN and y.shape[1] == MLP_OUT and x.shape[0] == y.shape[0]
+        self._rec = (x, y)  # keep the buffers alive while the library writes them
+        self._chk(lib().gs_mlp_record(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                      x.shape[0]))
 
     def fields(self, gap: int = 0):
         N = self.cfgs[gap].n_cells
@@ -338,3 +388,32 @@ class GapSim:
                     source_ms=T.source_ms, push_launches=T.push_launches,
                     field_launches=T.field_launches, compact_launches=T.compact_launches,
                     source_launches=T.source_launches)
+
+
+def mlp_train(x, t, order, batch: int, theta, adam_m, adam_v, step0: int = 0, lr: float = 1e-3,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, want_grad: bool = False,
+              stream=None):
+    """Adam on the guess network, on the GPU (gs_mlp_train).  x [n, 48], t [n, 3],
+    theta / adam_m / adam_v [39683]: float32 device tensors (the last three are
+    updated in place); order: int32 device tensor of sample indices.  Returns
+    (per-step losses, last gradient or None) as float32 device tensors."""
+    import torch
+    dev = x.device
+    for a in (x, t, theta, adam_m, adam_v):
+        assert a.is_cuda and a.dtype == torch.float32 and a.is_contiguous()
+    assert order.is_cuda and order.dtype == torch.int32 and order.is_contiguous()
+    steps = order.numel() // batch
+    loss = torch.zeros(max(steps, 1), dtype=torch.float32, device=dev)
+    grad = torch.zeros(MLP_NPARAM, dtype=torch.float32, device=dev) if want_grad else None
+    nbytes = lib().gs_mlp_train_workspace(batch)
+    work = torch.empty(max(nbytes, 4), dtype=torch.uint8, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    rc = lib().gs_mlp_train(C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), x.shape[0],
+                            C.c_void_p(order.data_ptr()), order.numel(), batch, C.c_void_p(theta.data_ptr()),
+                            C.c_void_p(adam_m.data_ptr()), C.c_void_p(adam_v.data_ptr()), step0, lr, beta1,
+                            beta2, eps, C.c_void_p(loss.data_ptr()),
+                            C.c_void_p(grad.data_ptr()) if grad is not None else None,
+                            C.c_void_p(work.data_ptr()), nbytes, C.c_void_p(st.cuda_stream))
+    if rc != GS_OK:
+        raise GapsimError(rc, "gs_mlp_train failed (bad arguments or an index outside [0, n))")
+    return loss[:steps], grad
