@@ -122,6 +122,253 @@ def pmc_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mb, k
     return out
 
 
+# ---------------------------------------------------------------------------
+# batched gaps (independent gaps of uneven particle counts and circuits)
+# ---------------------------------------------------------------------------
+BATCHED = {"batched_512gaps_512c_strict": dict(gaps=512, cells=512, seed0=0)}
+MLP_WORKLOAD = "mlp_guess_512gaps_strict"
+
+
+def make_batched(gaps, cells, seed0, total_steps, np_lo=50_000, np_hi=500_000):
+    from paper_2603_24010_amd import gapsim, workloads as W
+    cfgs, loads, caps = [], [], []
+    for g in range(seed0, seed0 + gaps):
+        cfg, n_p, e_b = W.config4_gap(g, n_cells=cells, np_lo=np_lo, np_hi=np_hi)
+        cfgs.append(cfg)
+        loads.append(W.load_config4_gap(n_p, e_b, g))
+        # the beam keeps about n_p ions resident; room for fluctuations and for
+        # the ions in flight when the run ends
+        caps.append((n_p // 2 + 65536, int(1.3 * n_p) + 64 * cfg.beam_per_step + 4096))
+    sim = gapsim.GapSim(cfgs, particle_fp=32, capacity=caps)
+    for g in range(gaps):
+        for sp, (x, v) in loads[g].items():
+            sim.inject(g, sp, x, v)
+    return sim, cfgs, sum(len(loads[g][1][0]) for g in range(gaps))
+
+
+def pushed_total(sim):
+    return sum(sim.diag(g)["pushed_cum"] for g in range(sim.G))
+
+
+def eager_kernel_pass(sim, step, steps):
+    """Per-kernel times over an eager pass with dispatch-recorded events."""
+    from paper_2603_24010_amd import gapsim
+    sim.set_option(gapsim.OPT_GRAPH, 0)
+    sim.set_option(gapsim.OPT_TIMING, 1)
+    sim.timing(reset=True)
+    p0 = pushed_total(sim)
+    step(steps)
+    tm = sim.timing(reset=True)
+    sim.set_option(gapsim.OPT_TIMING, 0)
+    return tm, pushed_total(sim) - p0
+
+
+def run_batched(args, name, copy_gbs):
+    import torch
+    from paper_2603_24010_amd import gapsim
+    spec = BATCHED[name]
+    log(f"[bench] building {spec['gaps']} gaps")
+    sim, cfgs, n0 = make_batched(spec["gaps"], spec["cells"], spec["seed0"], args.warmup + args.steps)
+    log(f"[bench] {n0} initial particles; warmup {args.warmup} steps")
+    step = lambda n: sim.step_strict(n, gapsim.GUESS_DIRECT)
+    step(args.warmup)
+    tuning = sim.autotune(0, gapsim.GUESS_DIRECT, trial_steps=8)
+    log(f"[bench] autotuned: {tuning}")
+    sim.set_option(gapsim.OPT_GRAPH, 1)
+    torch.cuda.synchronize()
+    p0 = pushed_total(sim)
+    t0 = time.perf_counter()
+    step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pushed = pushed_total(sim) - p0
+    tm, kp = eager_kernel_pass(sim, step, 64)
+    push_s = tm["push_ms"] * 1e-3
+    achieved = BYTES_PER_PUSH_F32 * kp / push_s / 1e9 if push_s > 0 else None
+    live = sum(int(sim.diag(g)["n_live"].sum()) for g in range(sim.G))
+    sim.close()
+    out = {
+        "metric": "particle-steps/s", "value": pushed / el, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": name, "gaps": spec["gaps"], "cells": spec["cells"], "initial_particles": n0,
+                   "coupling": "strict", "particles": "binary32", "field_circuit": "binary64",
+                   "live_particles_end": live, "tuning": tuning},
+        "timed_with": "hip graphs, one per compaction interval",
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": None,
+                     "kernel": "k_push", "bytes_per_particle_step": BYTES_PER_PUSH_F32,
+                     "avg_launch_ms": tm["push_ms"] / max(1, tm["push_launches"]), "copy_GBps": copy_gbs,
+                     "measured_over": "64 eager steps after the timed region, HIP events recorded by each "
+                                      "kernel's dispatch"},
+        "kernel_ms_per_step": {k[:-3]: tm[k] / 64 for k in ("push_ms", "field_ms", "source_ms", "compact_ms")},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batched(spec, 5 * args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def run_mlp(args, copy_gbs):
+    """Newton guess network on batched strict gaps: record (input, target) pairs
+    from the direct strict solve of a training ensemble, train the network on
+    the GPU, then run held-out gaps with the plain extrapolated guess, the
+    trained network and the untrained network, and one gap alone."""
+    import torch
+    from paper_2603_24010_amd import gapsim
+    G, cells, steps_train, steps_eval = args.mlp_gaps, 512, args.mlp_train_steps, args.mlp_eval_steps
+    skip = 11  # levels whose 8-level history and extrapolation reach before level 0
+    # 1. training data
+    log(f"[bench] mlp: {G} training gaps, {steps_train} recorded strict steps")
+    sim, _, n0 = make_batched(G, cells, 0, steps_train)
+    xr = torch.zeros((G * steps_train, 48), dtype=torch.float32, device="cuda")
+    yr = torch.zeros((G * steps_train, 3), dtype=torch.float32, device="cuda")
+    sim.mlp_record(xr, yr)
+    sim.set_option(gapsim.OPT_GRAPH, 1)
+    t0 = time.perf_counter()
+    sim.step_strict(steps_train, gapsim.GUESS_DIRECT)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    sim.mlp_record()
+    sim.close()
+    x = xr[skip * G:].double()
+    y = yr[skip * G:].double()
+    x_mean, x_sd = x.mean(0), x.std(0)
+    x_sd = torch.maximum(x_sd, 1e-6 * x.abs().max(0).values)
+    x_sd[x_sd == 0] = 1.0
+    y_mean, y_sd = y.mean(0), y.std(0)
+    y_sd[y_sd == 0] = 1.0
+    norm = torch.cat([x_mean, x_sd, y_mean, y_sd]).cpu().numpy()
+    xn_all = ((x - x_mean) / x_sd).float()
+    yn_all = ((y - y_mean) / y_sd).float()
+    # how much of the target any linear function of the inputs explains (least
+    # squares on the normalised data): the ceiling of an affine guess
+    rng = np.random.default_rng(5)
+    perm = torch.from_numpy(rng.permutation(xn_all.shape[0])).cuda()
+    n_val = xn_all.shape[0] // 10
+    val, trn = perm[:n_val], perm[n_val:]
+    A = torch.cat([xn_all.double(), torch.ones((xn_all.shape[0], 1), dtype=torch.float64, device="cuda")], 1)
+    wls = torch.linalg.lstsq(A[trn].cpu(), yn_all[trn].double().cpu()).solution.cuda()
+    r_lin = yn_all[val].double() - A[val] @ wls
+    r2_lin = (1.0 - r_lin.var(0) / yn_all[val].double().var(0)).cpu().numpy()
+    xn = xn_all[trn].contiguous()
+    yn = yn_all[trn].contiguous()
+    xv = xn_all[val].contiguous()
+    yv = yn_all[val].contiguous()
+    del xr, yr, x, y, A, xn_all, yn_all
+    n = xn.shape[0]
+    # 2. training (Adam, batch 1024), seeded shuffles
+    parts = []
+    for fi, fo in ((48, 128), (128, 128), (128, 128), (128, 3)):
+        bound = 1.0 / np.sqrt(fi)
+        parts += [rng.uniform(-bound, bound, fo * fi), rng.uniform(-bound, bound, fo)]
+    theta0 = np.concatenate(parts).astype(np.float32)
+    th = torch.from_numpy(theta0.copy()).cuda()
+    m, v = torch.zeros_like(th), torch.zeros_like(th)
+    order = torch.from_numpy(np.concatenate([rng.permutation(n) for _ in range(args.mlp_epochs)])
+                             .astype(np.int32)).cuda()
+    B = 1024
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses, _ = gapsim.mlp_train(xn, yn, order, B, th, m, v, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    losses = losses.cpu().numpy()
+    n_steps_opt = len(losses)
+    per_epoch = max(1, n_steps_opt // args.mlp_epochs)
+    theta = th.cpu().numpy()
+    # validation error of the bfloat16 network (the evaluation the strict step uses)
+    probe, _, _ = make_batched(1, cells, 0, 1, np_lo=1000, np_hi=1000)
+
+    def val_mse(weights):
+        probe.mlp_set_weights(weights, norm)
+        return float(((probe.mlp_forward(xv) - yv) ** 2).mean())
+
+    val = {"trained": val_mse(theta), "untrained": val_mse(theta0), "zero": float((yv ** 2).mean())}
+    probe.close()
+    log(f"[bench] trained on {n} samples, {args.mlp_epochs} epochs: mean batch loss first epoch "
+        f"{losses[:per_epoch].mean():.4g}, last epoch {losses[-per_epoch:].mean():.4g}; validation MSE {val}; "
+        f"linear R^2 {r2_lin}")
+
+    # 3. held-out gaps
+    def evaluate(guess, weights, gaps, seed0, label):
+        s, _, _ = make_batched(gaps, cells, seed0, steps_eval)
+        if weights is not None:
+            s.mlp_set_weights(weights, norm)
+        s.set_option(gapsim.OPT_GRAPH, 1)
+        r0 = []
+        el = 0.0
+        chunk = 100
+        done = 0
+        while done < steps_eval:
+            k = min(chunk, steps_eval - done)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s.step_strict(k, guess)
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t1
+            done += k
+            if done > skip:
+                r0 += [s.diag(g)["newton_resid0"] for g in range(gaps)]
+        ds = [s.diag(g) for g in range(gaps)]
+        s.close()
+        tot = sum(d["newton_total"] for d in ds)
+        lev = sum(d["newton_levels"] for d in ds)
+        r0 = np.array(r0)
+        res = {"corrections_per_level": tot / max(1, lev), "max_corrections": max(d["newton_max"] for d in ds),
+               "levels": lev, "fallbacks": sum(d["newton_fallbacks"] for d in ds),
+               "initial_residual": {"median": float(np.median(r0)), "p90": float(np.quantile(r0, 0.9)),
+                                    "max": float(r0.max()), "below_tol": float(np.mean(r0 <= 1e-10)),
+                                    "samples": int(r0.size)},
+               "ms_per_step": el * 1e3 / steps_eval, "us_per_gap_step": el * 1e6 / (steps_eval * gaps)}
+        log(f"[bench] {label}: {res}")
+        return res
+
+    plain = evaluate(gapsim.GUESS_EXTRAP, None, G, 512, "batched plain")
+    trained = evaluate(gapsim.GUESS_MLP, theta, G, 512, "batched + trained network")
+    untrained = evaluate(gapsim.GUESS_MLP, theta0, G, 512, "batched + untrained network")
+    single = evaluate(gapsim.GUESS_EXTRAP, None, 1, 512, "single gap plain")
+    flop_per_sample = 2 * 3 * (48 * 128 + 2 * 128 * 128 + 128 * 3)
+    out = {
+        "metric": "strict-step Newton updates per level at 1e-10 residual, network vs plain",
+        "value": trained["corrections_per_level"], "unit": "updates/level", "n_gpus": 1,
+        "steps": steps_eval, "warmup": 0, "ms_per_step": trained["ms_per_step"], "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 particles, f64 field/circuit, bf16 network",
+        "data": "synthetic",
+        "config": {"workload": MLP_WORKLOAD, "gaps": G, "cells": cells, "train_gaps_seeds": [0, G - 1],
+                   "eval_gaps_seeds": [512, 512 + G - 1], "initial_particles_train": n0},
+        "plain": plain, "trained": trained, "untrained": untrained, "single_gap_plain": single,
+        "training": {"samples": n, "recorded_steps": steps_train, "generation_s": t_gen, "epochs": args.mlp_epochs,
+                     "batch": B, "optimizer_steps": n_steps_opt,
+                     "loss_first_epoch": float(losses[:per_epoch].mean()),
+                     "loss_last_epoch": float(losses[-per_epoch:].mean()),
+                     "validation_mse_normalised": val, "linear_least_squares_R2": [float(v) for v in r2_lin],
+                     "seconds": t_train,
+                     "samples_per_s": n_steps_opt * B / t_train,
+                     "TFLOPs": n_steps_opt * B * flop_per_sample / t_train / 1e12},
+        "copy_GBps": copy_gbs,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batched(spec, steps):
+    import oracle
+    from paper_2603_24010_amd import workloads as W
+    gaps = 8
+    pushed, el = 0, 0.0
+    for g in range(spec["seed0"], spec["seed0"] + gaps):
+        cfg, n_p, e_b = W.config4_gap(g, n_cells=spec["cells"])
+        s = oracle.OracleSim(cfg, fp32=True)
+        for sp, (x, v) in W.load_config4_gap(n_p, e_b, g).items():
+            s.inject(sp, x, v)
+        t0 = time.perf_counter()
+        s.step(oracle.STRICT, steps)
+        el += time.perf_counter() - t0
+        pushed += s.diag()["pushed_cum"]
+    return {"value": pushed / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {gaps} gaps of the ensemble, {steps} strict steps each, binary32 oracle mode, "
+                      f"{pushed} particle-steps in {el:.1f} s"}
+
+
 def cpu_baseline(spec, steps: int):
     """The oracle (binary32 mode, one thread) on the workload's initial state."""
     import oracle
@@ -149,7 +396,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="beam_gap_4096c_2e7p_weak", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="beam_gap_4096c_2e7p_weak",
+                    choices=sorted(WORKLOADS) + sorted(BATCHED) + [MLP_WORKLOAD])
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compact-every", type=int, default=32)
@@ -159,6 +407,10 @@ def main():
     ap.add_argument("--deposit", type=int, default=0, help="0 auto, 1 64-bit LDS cells, 2 32-bit")
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--ppt", type=int, default=0, help="16-byte particle vectors per thread (1, 2)")
+    ap.add_argument("--mlp-gaps", type=int, default=512)
+    ap.add_argument("--mlp-train-steps", type=int, default=2000)
+    ap.add_argument("--mlp-eval-steps", type=int, default=500)
+    ap.add_argument("--mlp-epochs", type=int, default=10)
     ap.add_argument("--copy-reference-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times): the "
                          "reference that scales rocprof's FETCH_SIZE / WRITE_SIZE to bytes")
@@ -205,6 +457,10 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 10 * 2 * ca.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del ca, cb
+    if args.workload in BATCHED:
+        return run_batched(args, args.workload, copy_gbs)
+    if args.workload == MLP_WORKLOAD:
+        return run_mlp(args, copy_gbs)
     spec = WORKLOADS[args.workload]
     log(f"[bench] building workload {args.workload}")
     sim, cfg, _ = make_sim(args.workload, spec, args.warmup + args.steps)

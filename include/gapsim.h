@@ -132,6 +132,8 @@ typedef struct {
   int32_t newton_fallback_last; /* 1 if the last step fell back from the MLP guess */
   int64_t newton_total;   /* Newton updates summed over strict steps */
   int64_t newton_fallbacks;
+  int32_t newton_max;     /* most updates any one level needed */
+  int32_t newton_levels;  /* levels solved by Newton (not the direct solve) */
   double newton_resid0;   /* infinity norm of the scaled residual at the initial guess */
   double newton_resid;    /* ... after the last update */
   double newton_guess[GS_MAX_MESH + 1]; /* initial guess u = (V, I_0, ..) of the last solve
@@ -194,7 +196,11 @@ gs_status gs_inject(gs_ctx *ctx, int32_t gap, int32_t species, int64_t n, const 
  * GS_GUESS_MLP instead runs Newton on u = (gap voltage, loop currents) from a
  * quadratic extrapolation or from the network set by gs_mlp_set_weights (the
  * Newton iteration decides convergence; a non-finite or worse MLP guess falls
- * back to the extrapolation).  Asynchronous.  Errors: GS_EINVAL (bad mode; the
+ * back to the extrapolation).  The iteration stops when the scaled residual is
+ * within the tolerance (GS_OPT_NEWTON_TOL) or when an update changed no
+ * component by more than 8 units in its last place (the residual of the
+ * representable u nearest the solution can exceed the tolerance when loop
+ * currents are large), else at GS_OPT_NEWTON_MAXIT updates (GS_ENOCONV).  Asynchronous.  Errors: GS_EINVAL (bad mode; the
  * network needs every gap to have two meshes), GS_ESTATE (GS_GUESS_MLP before
  * weights were set), GS_ECAPACITY (sticky), GS_EDEVICE. */
 gs_status gs_step_strict(gs_ctx *ctx, int32_t n_steps, int32_t guess);
@@ -231,11 +237,12 @@ gs_status gs_read_particles(gs_ctx *ctx, int32_t gap, int32_t species, void *xi,
  * form), linear output.  Parameters: one array of GS_MLP_NPARAM binary32 values
  * W1[128][48] b1[128] W2[128][128] b2[128] W3[128][128] b3[128] W4[3][128]
  * b4[3] (weights row-major [out][in]).
- * Input: the last 8 solved levels k = 1..8 (level n-k) of (V, I_0, I_1,
- * sigma_+, Q_abs, Q_em) at feature 6(k-1) + q, where Q_abs is the charge the
- * circuit electrode absorbed in the push before that level and Q_em the charge
- * of the electrons it emitted (Q_conv = Q_abs - Q_em), normalised as
- * (x - x_mean) / x_scale.  Output y: u = u_extrap + y_mean + y_scale * y, with
+ * Input for level n: the last 8 steps k = 1..8, features 6(k-1) + q: (V,
+ * I_0, I_1, sigma_+) of level n-k and (Q_abs, Q_em) of the push that followed
+ * it (for k = 1 the push into level n, whose charge is known before level n
+ * is solved), where Q_abs is the charge the circuit electrode absorbed and
+ * Q_em the charge of the electrons it emitted (Q_conv = Q_abs - Q_em);
+ * normalised as (x - x_mean) / x_scale.  Output y: u = u_extrap + y_mean + y_scale * y, with
  * u_extrap the quadratic extrapolation 3 u_{n-1} - 3 u_{n-2} + u_{n-3}.
  * norm: GS_MLP_NORM binary64 values x_mean[48] x_scale[48] y_mean[3]
  * y_scale[3]. */
@@ -285,6 +292,32 @@ gs_status gs_mlp_train(const float *x, const float *t, int64_t n, const int32_t 
                        int32_t batch, float *theta, float *adam_m, float *adam_v, int64_t step0, double lr,
                        double beta1, double beta2, double eps, float *loss, float *grad_last, void *work,
                        size_t work_bytes, void *hip_stream);
+
+/* A launch configuration chosen by gs_autotune. */
+typedef struct {
+  int32_t block;          /* push threads per workgroup */
+  int32_t tile;           /* particles per work tile */
+  int32_t grid;           /* push workgroups */
+  int32_t ppt;            /* 16-byte particle vectors per thread per chunk (1 or 2) */
+  int32_t deposit;        /* GS_OPT_DEPOSIT value */
+  int32_t compact_every;  /* steps between compactions */
+  double ms_per_step;     /* measured time per step of the chosen configuration */
+} gs_tuning;
+
+/* Choose the push launch shape (block, vectors per thread, tile, grid) and then
+ * the compaction interval for this context's gaps by timing candidates on its
+ * own current state: every device buffer and host counter is saved first and
+ * put back afterwards, so the state after the call is the state before it.
+ * mode 0 strict (with guess) or 1 weak; trial_steps timed steps per shape
+ * candidate (at least 64 per compaction candidate).  Needs room for one copy
+ * of the context's device memory.  cache_path (may be NULL): a text file of
+ * earlier choices keyed by the gap count, grid size, precision, mode, guess,
+ * log2 of the live particles and CU count; a hit is applied without trials and
+ * a new choice is appended.  The choice stays in effect (as if set with
+ * gs_set_option) and is written to *out when not NULL.  Synchronises.  Errors:
+ * GS_EINVAL, GS_ESTATE, GS_ENOMEM, GS_EDEVICE and the step errors. */
+gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32_t trial_steps, const char *cache_path,
+                      gs_tuning *out);
 
 /* Tune or switch parts of the launch configuration (see GS_OPT_*). */
 gs_status gs_set_option(gs_ctx *ctx, int32_t option, int64_t value);

@@ -6,6 +6,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -26,6 +28,7 @@ struct gs_ctx {
   hipStream_t cap_stream = nullptr;  // private stream graphs are captured on
   gs_allocator alloc{nullptr, nullptr, nullptr};
   std::vector<void *> blocks;
+  std::vector<size_t> block_bytes;
   DevPtrs dp{};
   LaunchCfg lc{};
   int compact_every = 32;
@@ -89,7 +92,10 @@ static void *dev_alloc(gs_ctx *c, size_t bytes) {
   } else if (hipMalloc(&p, bytes) != hipSuccess) {
     p = nullptr;
   }
-  if (p) c->blocks.push_back(p);
+  if (p) {
+    c->blocks.push_back(p);
+    c->block_bytes.push_back(bytes);
+  }
   return p;
 }
 
@@ -101,6 +107,7 @@ static void dev_free_all(gs_ctx *c) {
       (void)hipFree(p);
   }
   c->blocks.clear();
+  c->block_bytes.clear();
 }
 
 // Gauss-Jordan inverse in extended precision; returns false if singular
@@ -703,6 +710,8 @@ extern "C" gs_status gs_read_diagnostics(gs_ctx *ctx, int32_t gap, gs_diag *out,
   out->newton_fallback_last = s.newton_fb_last;
   out->newton_total = s.newton_total;
   out->newton_fallbacks = s.newton_fallbacks;
+  out->newton_max = s.newton_max;
+  out->newton_levels = s.newton_levels;
   out->newton_resid0 = s.newton_r0;
   out->newton_resid = s.newton_r;
   for (int j = 0; j <= c.M; ++j) out->newton_guess[j] = s.guess[j];
@@ -820,6 +829,204 @@ extern "C" gs_status gs_mlp_record(gs_ctx *ctx, float *x, float *y, int64_t capa
     ctx->dp.rec_level0 = ctx->steps_done;
   }
   drop_graphs(ctx);
+  return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+namespace {
+struct HostCounters {
+  int64_t epoch, steps_done;
+  int since_compact;
+  std::vector<int64_t> next_id;
+};
+
+std::string tune_key(const gs_ctx *ctx, int mode, int guess, long long live) {
+  int lg = 0;
+  while ((1ll << (lg + 1)) <= live) ++lg;
+  std::ostringstream k;
+  k << "G=" << ctx->G << ",nmax=" << ctx->nmax << ",fp=" << (ctx->fp64 ? 64 : 32) << ",mode=" << mode
+    << ",guess=" << guess << ",log2live=" << lg << ",cu=" << ctx->ncu;
+  return k.str();
+}
+}  // namespace
+
+static void apply_tuning(gs_ctx *ctx, const gs_tuning &t) {
+  ctx->lc.block = t.block;
+  ctx->lc.ppt = t.ppt * (ctx->fp64 ? 2 : 4);
+  ctx->lc.tile = t.tile;
+  ctx->deposit_opt = t.deposit;
+  ctx->grid_opt = 1;
+  ctx->lc.grid = t.grid;
+  ctx->compact_every = t.compact_every;
+  choose_launch(ctx);
+  ctx->lc.grid = t.grid;
+  drop_graphs(ctx);
+}
+
+extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32_t trial_steps,
+                                 const char *cache_path, gs_tuning *out) {
+  if (!ctx) return GS_ESTATE;
+  if (mode != 0 && mode != 1) return fail(ctx, GS_EINVAL, "mode must be 0 (strict) or 1 (weak)");
+  if (guess < GS_GUESS_DIRECT || guess > GS_GUESS_MLP || (mode == 1 && guess != GS_GUESS_DIRECT))
+    return fail(ctx, GS_EINVAL, "bad guess mode");
+  if (guess == GS_GUESS_MLP && !ctx->mlp_w) return fail(ctx, GS_ESTATE, "no guess network weights");
+  if (trial_steps < 1 || trial_steps > 4096) return fail(ctx, GS_EINVAL, "trial_steps must be in 1..4096");
+  gs_status st = check_sticky(ctx, true);
+  if (st != GS_OK) return st;
+  // live particles (for the cache key)
+  long long live = 0;
+  {
+    std::vector<GapState> hs(ctx->G);
+    HIPCHK(ctx, hipMemcpy(hs.data(), ctx->dp.gs, sizeof(GapState) * ctx->G, hipMemcpyDeviceToHost));
+    for (const GapState &s : hs) live += s.live[0] + s.live[1];
+  }
+  const std::string key = tune_key(ctx, mode, guess, live);
+  if (cache_path && *cache_path) {
+    std::ifstream f(cache_path);
+    std::string line;
+    while (std::getline(f, line)) {
+      const size_t bar = line.find('|');
+      if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+      gs_tuning t{};
+      std::istringstream v(line.substr(bar + 1));
+      if (v >> t.block >> t.tile >> t.grid >> t.ppt >> t.deposit >> t.compact_every >> t.ms_per_step) {
+        const LaunchCfg keep = ctx->lc;
+        apply_tuning(ctx, t);
+        if (!launch_fits(ctx)) {
+          ctx->lc = keep;
+          continue;
+        }
+        if (out) *out = t;
+        return GS_OK;
+      }
+    }
+  }
+  // snapshot every device block and the host counters; trials run on the
+  // live state and it is put back afterwards
+  std::vector<void *> backup(ctx->blocks.size(), nullptr);
+  auto free_backup = [&]() {
+    for (void *b : backup)
+      if (b) (void)hipFree(b);
+  };
+  for (size_t i = 0; i < ctx->blocks.size(); ++i) {
+    if (hipMalloc(&backup[i], ctx->block_bytes[i]) != hipSuccess) {
+      backup[i] = nullptr;
+      free_backup();
+      return fail(ctx, GS_ENOMEM, "autotune: no device memory for a snapshot of the state");
+    }
+    if (hipMemcpyAsync(backup[i], ctx->blocks[i], ctx->block_bytes[i], hipMemcpyDeviceToDevice, ctx->stream) !=
+        hipSuccess) {
+      free_backup();
+      return fail(ctx, GS_EDEVICE, "autotune: snapshot copy failed");
+    }
+  }
+  const HostCounters hc0{ctx->epoch, ctx->steps_done, ctx->since_compact, ctx->next_id};
+  const LaunchCfg lc0 = ctx->lc;
+  const int dep0 = ctx->deposit_opt, grid_opt0 = ctx->grid_opt, ce0 = ctx->compact_every;
+  const int graph0 = ctx->use_graph, timing0 = ctx->timing;
+  float *rx = ctx->dp.rec_x, *ry = ctx->dp.rec_y;
+  ctx->dp.rec_x = ctx->dp.rec_y = nullptr;  // trials record nothing
+  ctx->use_graph = 0;
+  ctx->timing = 0;
+  auto restore = [&]() -> gs_status {
+    for (size_t i = 0; i < ctx->blocks.size(); ++i)
+      HIPCHK(ctx, hipMemcpyAsync(ctx->blocks[i], backup[i], ctx->block_bytes[i], hipMemcpyDeviceToDevice,
+                                 ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->epoch = hc0.epoch;
+    ctx->steps_done = hc0.steps_done;
+    ctx->since_compact = hc0.since_compact;
+    ctx->next_id = hc0.next_id;
+    return GS_OK;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  // time one candidate: warm-up steps, then `steps` timed steps, from the snapshot
+  auto trial = [&](const gs_tuning &t, int steps, double *ms) -> gs_status {
+    gs_status r = restore();
+    if (r != GS_OK) return r;
+    apply_tuning(ctx, t);
+    if (!launch_fits(ctx)) {
+      *ms = 1e300;
+      return GS_OK;
+    }
+    for (int k = 0; k < 2; ++k)
+      if ((r = one_step(ctx, mode, guess)) != GS_OK) return r;
+    HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
+    for (int k = 0; k < steps; ++k)
+      if ((r = one_step(ctx, mode, guess)) != GS_OK) return r;
+    HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
+    HIPCHK(ctx, hipEventSynchronize(e1));
+    float f = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&f, e0, e1));
+    *ms = f / steps;
+    return check_sticky(ctx, true);
+  };
+  gs_tuning best{};
+  best.ms_per_step = 1e300;
+  const int vper = ctx->fp64 ? 2 : 4;
+  gs_status r = GS_OK;
+  // launch shape first, at the current compaction interval
+  const int grid_def = lc0.grid > 0 ? lc0.grid : ctx->ncu;
+  for (int block : {256, 512})
+    for (int ppt : {1, 2})
+      for (int tmul : {8, 32})
+        for (int gmul2 : {1, 2, 4}) {  // grid = default * gmul2 / 2
+          gs_tuning t{};
+          t.block = block;
+          t.ppt = ppt;
+          t.tile = block * tmul;
+          if (t.tile % (block * ppt * vper)) continue;
+          t.deposit = dep0;
+          // the default grid is sized for 256-thread blocks; keep threads per CU
+          t.grid = std::max(1, grid_def * gmul2 / 2 * 256 / block);
+          t.compact_every = ce0;
+          double ms = 0;
+          if ((r = trial(t, trial_steps, &ms)) != GS_OK) break;
+          t.ms_per_step = ms;
+          if (ms < best.ms_per_step) best = t;
+        }
+  // then the compaction interval, over a span that includes compactions
+  if (r == GS_OK) {
+    const gs_tuning base = best;
+    best.ms_per_step = 1e300;
+    for (int ce : {16, 32, 64}) {
+      gs_tuning t = base;
+      t.compact_every = ce;
+      double ms = 0;
+      if ((r = trial(t, std::max(trial_steps, 64), &ms)) != GS_OK) break;
+      t.ms_per_step = ms;
+      if (ms < best.ms_per_step) best = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  gs_status rr = restore();
+  free_backup();
+  ctx->dp.rec_x = rx;
+  ctx->dp.rec_y = ry;
+  ctx->use_graph = graph0;
+  ctx->timing = timing0;
+  if (r != GS_OK || rr != GS_OK || best.ms_per_step >= 1e299) {
+    ctx->lc = lc0;
+    ctx->deposit_opt = dep0;
+    ctx->grid_opt = grid_opt0;
+    ctx->compact_every = ce0;
+    drop_graphs(ctx);
+    if (r != GS_OK) return r;
+    if (rr != GS_OK) return rr;
+    return fail(ctx, GS_EINVAL, "autotune: no candidate launch fits");
+  }
+  apply_tuning(ctx, best);
+  if (cache_path && *cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    f << key << "|" << best.block << " " << best.tile << " " << best.grid << " " << best.ppt << " " << best.deposit
+      << " " << best.compact_every << " " << best.ms_per_step << "\n";
+  }
+  if (out) *out = best;
   return GS_OK;
 }
 

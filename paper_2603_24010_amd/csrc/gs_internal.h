@@ -76,6 +76,7 @@ struct GapState {
   int64_t abs_cum[4], emit_cum[2], inj_cum, pushed_cum;
   int32_t newton_last, newton_fb_last;
   int64_t newton_total, newton_fallbacks;
+  int32_t newton_max, newton_levels;  // most corrections at one level; Newton levels solved
   double newton_r0, newton_r;
   double guess[MAXM + 1];  // the u the last Newton solve started from
   double mlp_prop[3];      // the guess network's proposal at the last solve (used or not)

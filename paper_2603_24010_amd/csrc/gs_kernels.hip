@@ -282,18 +282,25 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
       r0n = norm(r);
       rn = r0n;
       iters = 0;
-      while (!(rn <= tol) && iters < maxit) {
+      // stop when the residual is within the tolerance, or when an update no
+      // longer moves any component by more than a few units in its last place
+      // (large loop currents can leave the representable u nearest the
+      // solution with a scaled residual above the tolerance)
+      bool at_roundoff = false;
+      while (!(rn <= tol) && !at_roundoff && iters < maxit) {
+        at_roundoff = true;
         for (int i = 0; i < nu; ++i) {
           double a = 0.0;
           for (int j = 0; j < nu; ++j) a += c.Jinv[i * (MAXM + 1) + j] * r[j];
           ue[i] = u[i] - a;
+          if (!(fabs(a) <= 8.0 * 2.220446049250313e-16 * fabs(u[i]))) at_roundoff = false;
         }
         for (int i = 0; i < nu; ++i) u[i] = ue[i];
         residual(u, r);
         rn = norm(r);
         iters += 1;
       }
-      if (!(rn <= tol)) atomicOr(p.err, ERR_NOCONV);
+      if (!(rn <= tol) && !at_roundoff) atomicOr(p.err, ERR_NOCONV);
       phi0 = u[0];
     }
     qcirc = K - G * phi0;
@@ -308,6 +315,8 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
     if (iters >= 0) {
       st.newton_total += iters;
       st.newton_fallbacks += fb;
+      st.newton_max = max(st.newton_max, iters);
+      st.newton_levels += 1;
     }
     st.newton_r0 = r0n;
     st.newton_r = rn;
@@ -417,8 +426,20 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   const bool rec_here = want_rec && rec_idx >= 0 && rec_idx < p.rec_cap;
   if (want_mlp || rec_here) {
     if (tid < MLP_IN) {
+      // block k = 1..8: (V, I_0, I_1, sigma) of level n-k and the absorbed /
+      // emitted charge of the push that followed it (for k = 1 the push whose
+      // tallies this solve is about to fold in)
       const int kk = tid / 6 + 1, q = tid % 6;
-      const double raw = ss.hist[(ss.hist_head - kk) & 7][q];
+      double raw;
+      if (q < 4) {
+        raw = ss.hist[(ss.hist_head - kk) & 7][q];
+      } else if (kk > 1) {
+        raw = ss.hist[(ss.hist_head - kk + 1) & 7][q];
+      } else {
+        const double qi = sc.A * (sc.s0 * (double)sc.Z[1]), qe = sc.A * (sc.s0 * (double)sc.Z[0]);
+        raw = q == 4 ? qi * (double)(long long)s_tally[T_ABS + 2] + qe * (double)(long long)s_tally[T_ABS + 0]
+                     : qe * (double)(long long)s_tally[T_EMIT + 0];
+      }
       if (rec_here) p.rec_x[rec_idx * MLP_IN + tid] = (float)raw;
       if (want_mlp) s_x[tid] = (float)((raw - p.mlp_norm[tid]) / p.mlp_norm[MLP_IN + tid]);
     }

@@ -28,7 +28,7 @@ EXPORTED = [
     "gs_init", "gs_destroy", "gs_inject", "gs_step_strict", "gs_step_weak", "gs_read_diagnostics",
     "gs_read_particles", "gs_set_option", "gs_get_timing", "gs_validate_params", "gs_last_error",
     "gs_version", "gs_mlp_set_weights", "gs_mlp_forward", "gs_mlp_record", "gs_mlp_train_workspace",
-    "gs_mlp_train",
+    "gs_mlp_train", "gs_autotune",
 ]
 MLP_IN, MLP_OUT, MLP_NPARAM, MLP_NORM = 48, 3, 39683, 102
 
@@ -73,6 +73,7 @@ class GsDiag(C.Structure):
         ("pushed_cum", C.c_int64),
         ("newton_last", C.c_int32), ("newton_fallback_last", C.c_int32),
         ("newton_total", C.c_int64), ("newton_fallbacks", C.c_int64),
+        ("newton_max", C.c_int32), ("newton_levels", C.c_int32),
         ("newton_resid0", C.c_double), ("newton_resid", C.c_double),
         ("newton_guess", C.c_double * (MAX_MESH + 1)),
         ("mlp_proposal", C.c_double * 3),
@@ -86,6 +87,11 @@ class GsTiming(C.Structure):
         ("push_launches", C.c_int64), ("field_launches", C.c_int64), ("compact_launches", C.c_int64),
         ("source_launches", C.c_int64),
     ]
+
+
+class GsTuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("tile", C.c_int32), ("grid", C.c_int32), ("ppt", C.c_int32),
+                ("deposit", C.c_int32), ("compact_every", C.c_int32), ("ms_per_step", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -142,6 +148,8 @@ def lib():
                                    C.c_double, C.c_double, C.c_double, C.c_double, vp, vp, vp, C.c_size_t,
                                    vp]
         L.gs_mlp_train.restype = C.c_int
+        L.gs_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_char_p, C.POINTER(GsTuning)]
+        L.gs_autotune.restype = C.c_int
         _lib = L
     return _lib
 
@@ -322,9 +330,20 @@ class GapSim:
                     newton_converged=converged,
                     newton_last=D.newton_last, newton_fallback_last=D.newton_fallback_last,
                     newton_total=D.newton_total, newton_fallbacks=D.newton_fallbacks,
+                    newton_max=D.newton_max, newton_levels=D.newton_levels,
                     newton_resid0=D.newton_resid0, newton_resid=D.newton_resid,
                     newton_guess=np.array(D.newton_guess[:M + 1]),
                     mlp_proposal=np.array(D.mlp_proposal[:]))
+
+    def autotune(self, mode: int, guess: int = GUESS_DIRECT, trial_steps: int = 8,
+                 cache_path: Optional[str] = None) -> dict:
+        """gs_autotune: pick launch shape and compaction interval on the current
+        state (which it leaves unchanged); returns the choice."""
+        t = GsTuning()
+        self._chk(lib().gs_autotune(self._h, mode, guess, trial_steps,
+                                    cache_path.encode() if cache_path else None, C.byref(t)))
+        return dict(block=t.block, tile=t.tile, grid=t.grid, ppt=t.ppt, deposit=t.deposit,
+                    compact_every=t.compact_every, ms_per_step=t.ms_per_step)
 
     # -- Newton guess network -------------------------------------------------
     def mlp_set_weights(self, theta, norm):

@@ -142,9 +142,11 @@ def test_recorded_samples_match_history():
         ds.append(sim.diag(0))
     sim.mlp_record()
     xr, yr = xr.cpu().numpy(), yr.cpu().numpy()
+    # level m: its (V, I_0, I_1, sigma) and the charge of the push after it,
+    # which the diagnostics read right after level m report as the last push's
     hist = []
-    for k, d in enumerate(ds):
-        qa, qe = _qabs_qem(cfg, ds[k - 1]) if k > 0 else (0.0, 0.0)
+    for d in ds:
+        qa, qe = _qabs_qem(cfg, d)
         hist.append([d["phi0"], d["I"][0], d["I"][1], d["sigma"], qa, qe])
     hist = np.array(hist)
     u = hist[:, :3]
@@ -216,3 +218,66 @@ def test_mlp_guess_needs_weights_and_two_meshes():
         sim.step_strict(1, gs.GUESS_MLP)
     assert e.value.status == gs.GS_EINVAL
     sim.close()
+
+
+def test_trained_network_against_plain_extrapolation():
+    """What the trained network gains: record samples from a small ensemble,
+    train on the GPU, then run held-out gaps with the plain extrapolated guess
+    and with the network.  The network's start is never worse than the
+    extrapolation (worse proposals fall back), so it can only save updates;
+    training must beat the untrained network on held-out samples.  The gain
+    itself is printed, not asserted: these inputs may hold little of what the
+    correction depends on."""
+    import torch
+    import bench
+    gs = _gs()
+    G, steps, skip = 16, 240, 11
+    sim, _, _ = bench.make_batched(G, 256, 0, steps, np_lo=5000, np_hi=20000)
+    xr = torch.zeros((G * steps, 48), dtype=torch.float32, device="cuda")
+    yr = torch.zeros((G * steps, 3), dtype=torch.float32, device="cuda")
+    sim.mlp_record(xr, yr)
+    sim.step_strict(steps, gs.GUESS_DIRECT)
+    sim.mlp_record()
+    sim.close()
+    x, y = xr[skip * G:].double(), yr[skip * G:].double()
+    xm, xs = x.mean(0), x.std(0)
+    xs[xs == 0] = 1.0
+    ym, ys = y.mean(0), y.std(0)
+    ys[ys == 0] = 1.0
+    norm = torch.cat([xm, xs, ym, ys]).cpu().numpy()
+    xn, yn = ((x - xm) / xs).float(), ((y - ym) / ys).float()
+    n = xn.shape[0]
+    perm = torch.from_numpy(rng.permutation(n)).cuda()
+    val, trn = perm[: n // 5], perm[n // 5:]
+    theta0 = _theta(0.05)
+    th = torch.from_numpy(theta0.copy()).cuda()
+    m, v = torch.zeros_like(th), torch.zeros_like(th)
+    order = torch.from_numpy(np.concatenate([rng.permutation(len(trn)) for _ in range(30)]).astype(np.int32)).cuda()
+    gs.mlp_train(xn[trn].contiguous(), yn[trn].contiguous(), order, 64, th, m, v, lr=1e-3)
+    theta = th.cpu().numpy()
+    probe, _, _ = bench.make_batched(1, 64, 0, 1, np_lo=100, np_hi=100)
+    mse = {}
+    for name, w in (("trained", theta), ("untrained", theta0)):
+        probe.mlp_set_weights(w, norm)
+        mse[name] = float(((probe.mlp_forward(xn[val].contiguous()) - yn[val]) ** 2).mean())
+    probe.close()
+    mse["zero"] = float((yn[val] ** 2).mean())
+    print("validation MSE (normalised):", mse)
+    assert mse["trained"] < mse["untrained"]
+
+    def run(guess, weights):
+        s, _, _ = bench.make_batched(G, 256, 100, 80, np_lo=5000, np_hi=20000)
+        if weights is not None:
+            s.mlp_set_weights(weights, norm)
+        s.step_strict(80, guess)
+        ds = [s.diag(g) for g in range(G)]
+        s.close()
+        assert all(d["newton_converged"] for d in ds)
+        return (sum(d["newton_total"] for d in ds) / sum(d["newton_levels"] for d in ds),
+                sum(d["newton_fallbacks"] for d in ds))
+
+    plain, _ = run(gs.GUESS_EXTRAP, None)
+    net, fb = run(gs.GUESS_MLP, theta)
+    print(f"Newton updates per level: plain {plain:.4f}, trained network {net:.4f} "
+          f"(fallbacks to the extrapolation: {fb} of {G * 80} levels)")
+    assert net <= plain + 0.02
