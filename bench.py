@@ -201,7 +201,7 @@ def run_batched(args, name, copy_gbs):
                      "avg_launch_ms": tm["push_ms"] / max(1, tm["push_launches"]), "copy_GBps": copy_gbs,
                      "measured_over": "64 eager steps after the timed region, HIP events recorded by each "
                                       "kernel's dispatch"},
-        "kernel_ms_per_step": {k[:-3]: tm[k] / 64 for k in ("push_ms", "field_ms", "source_ms", "compact_ms")},
+        "kernel_ms_per_step": {k[:-3]: tm[k] / 64 for k in ("push_ms", "field_ms", "compact_ms")},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batched(spec, 5 * args.cpu_steps)
@@ -530,7 +530,6 @@ def main():
                      "launches": tm["push_launches"]},
         "timed_with": "hip graphs" if args.graph else "eager launches, HIP events recorded by each kernel's dispatch",
         "kernel_ms_per_step": {"push": tm["push_ms"] / args.steps, "field": tm["field_ms"] / args.steps,
-                               "source": tm["source_ms"] / args.steps,
                                "compact": tm["compact_ms"] / args.steps},
     }
     sim.close()

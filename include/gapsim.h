@@ -144,13 +144,13 @@ typedef struct {
 /* Accumulated device time of the library's kernels, measured with HIP events
  * on the context's stream while timing is switched on (GS_OPT_TIMING). */
 typedef struct {
-  double push_ms, field_ms, compact_ms, source_ms;
-  int64_t push_launches, field_launches, compact_launches, source_launches;
+  double push_ms, field_ms, compact_ms;
+  int64_t push_launches, field_launches, compact_launches;
 } gs_timing;
 
 /* Options for gs_set_option. */
 enum {
-  GS_OPT_BLOCK = 1,        /* push threads per block: 256 (default), 512 or 1024 */
+  GS_OPT_BLOCK = 1,        /* push threads per block: 256 (default), 512, 768 or 1024 */
   GS_OPT_TILE = 2,         /* granularity at which particles are split between push
                               blocks (a multiple of 8 x the block size; default 8 x) */
   GS_OPT_GRID = 3,         /* push blocks; 0 = from occupancy */

@@ -328,8 +328,10 @@ static gs_status setup(gs_ctx *ctx) {
     c.evbase = (int64_t)events;
     c.evcap = (ctx->params[g].see_amp > 0.0) ? (int64_t)(c.cap[1] / 8 + 4096) : 0;
     events += (size_t)c.evcap;
+    // field tables start on 16-byte boundaries (the push stages them with
+    // 16-byte loads)
     c.ebase = (int64_t)etab;
-    etab += (size_t)c.N + 2;
+    etab += ((size_t)c.N + 2 + 3) / 4 * 4;
     ctx->nmax = std::max(ctx->nmax, c.N);
   }
   const size_t ps = ctx->fp64 ? 8 : 4;
@@ -390,7 +392,6 @@ static gs_status setup(gs_ctx *ctx) {
   ctx->lc.tile = ctx->lc.block * 8;
   ctx->lc.wide = 1;
   ctx->lc.compact_grid = 4 * ctx->ncu;
-  ctx->lc.source_grid = ctx->ncu;
   ctx->lc.ppt = ctx->fp64 ? 2 : 8;
   choose_launch(ctx);
   return GS_OK;
@@ -564,8 +565,6 @@ static gs_status one_step(gs_ctx *ctx, int mode, int guess) {
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "field launch: %s", hipGetErrorString(e));
   e = timed(ctx, 0, [&](KTime t) { return launch_push(ctx->dp, ctx->G, ctx->lc, ctx->stream, t); });
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "push launch: %s", hipGetErrorString(e));
-  e = timed(ctx, 3, [&](KTime t) { return launch_source(ctx->dp, ctx->G, ctx->lc, ctx->stream, t); });
-  if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "source launch: %s", hipGetErrorString(e));
   ctx->since_compact += 1;
   if (ctx->since_compact >= ctx->compact_every) {
     e = timed(ctx, 2, [&](KTime t) { return launch_compact(ctx->dp, ctx->G, ctx->lc, ctx->stream, t); });
@@ -607,7 +606,6 @@ static gs_status run_steps(gs_ctx *ctx, int n_steps, int mode, int guess) {
           e1 = launch_field(ctx->dp, ctx->G, mode, guess, ctx->newton_tol, ctx->newton_maxit, ctx->fp64,
                             ctx->nmax, cs);
           if (e1 == hipSuccess) e2 = launch_push(ctx->dp, ctx->G, ctx->lc, cs);
-          if (e2 == hipSuccess) e2 = launch_source(ctx->dp, ctx->G, ctx->lc, cs);
         }
         if (e1 == hipSuccess && e2 == hipSuccess) e3 = launch_compact(ctx->dp, ctx->G, ctx->lc, cs);
         hipError_t ec = hipStreamEndCapture(cs, &graph);
@@ -971,7 +969,7 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
   gs_status r = GS_OK;
   // launch shape first, at the current compaction interval
   const int grid_def = lc0.grid > 0 ? lc0.grid : ctx->ncu;
-  for (int block : {256, 512})
+  for (int block : {256, 512, 768})
     for (int ppt : {1, 2})
       for (int tmul : {8, 32})
         for (int gmul2 : {1, 2, 4}) {  // grid = default * gmul2 / 2
@@ -1036,7 +1034,8 @@ extern "C" gs_status gs_set_option(gs_ctx *ctx, int32_t option, int64_t value) {
   const int keep_dep = ctx->deposit_opt, keep_grid = ctx->grid_opt;
   switch (option) {
     case GS_OPT_BLOCK:
-      if (value != 256 && value != 512 && value != 1024) return fail(ctx, GS_EINVAL, "block must be 256, 512 or 1024");
+      if (value != 256 && value != 512 && value != 768 && value != 1024)
+        return fail(ctx, GS_EINVAL, "block must be 256, 512, 768 or 1024");
       ctx->lc.block = (int)value;
       if (ctx->lc.tile % (8 * ctx->lc.block)) ctx->lc.tile = ctx->lc.block * 8;
       break;
@@ -1113,9 +1112,6 @@ extern "C" gs_status gs_get_timing(gs_ctx *ctx, gs_timing *out, int32_t reset) {
     } else if (pe.kind == 1) {
       ctx->tm.field_ms += ms;
       ctx->tm.field_launches += 1;
-    } else if (pe.kind == 3) {
-      ctx->tm.source_ms += ms;
-      ctx->tm.source_launches += 1;
     } else {
       ctx->tm.compact_ms += ms;
       ctx->tm.compact_launches += 1;

@@ -131,7 +131,6 @@ struct LaunchCfg {
   int fp64;          // particle precision
   int wide;          // binary32: 64-bit LDS deposit cells (else 32-bit cells with carries)
   int compact_grid;  // compaction blocks
-  int source_grid;   // emission / injection blocks
   int ppt;           // particles per thread per chunk (one or two 16-byte vectors)
 };
 
@@ -146,7 +145,6 @@ struct KTime {
 hipError_t launch_field(const DevPtrs &p, int G, int mode, int guess, double newton_tol,
                         int newton_maxit, int fp64, int nmax, hipStream_t s, KTime t = {});
 hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t = {});
-hipError_t launch_source(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t = {});
 hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t = {});
 hipError_t launch_inject(const DevPtrs &p, int gap, int species, long long n, const double *x_dev,
                          const double *v_dev, long long id0, int fp64, hipStream_t s);

@@ -1,13 +1,14 @@
 // Device side of the circuit-coupled 1D ES-PIC step for gfx950.
 //
-// Per step three kernels run on the context's stream:
+// Per step two kernels run on the context's stream:
 //   k_field   one workgroup per gap: charge accumulator -> rho, prefix scans for
 //             the half-grid field, the circuit/surface-charge update (strict or
 //             weak), the binary32/64 field table the push gathers from.
 //   k_push    persistent workgroups over tiles of every gap's particles: gather,
 //             leapfrog, wall test and the charge deposit, privatised in LDS per
-//             workgroup; absorbed ions are queued for emission.
-//   k_source  secondary emission of the queued ions and the ion beam.
+//             workgroup; at the end of each of its ion segments a workgroup
+//             emits the secondary electrons of the ions it absorbed and injects
+//             its share of the beam.
 // Every few steps k_compact reclaims the slots of absorbed particles.
 //
 // Compiled with -ffp-contract=off: the binary32 particle arithmetic is a fixed
@@ -143,6 +144,26 @@ __device__ inline double block_sum_w(double v, double *wsum) {
 }
 
 // wave-wide inclusive prefix sum (64 lanes)
+__device__ inline int wave_incl_scan(int v);
+
+// block-wide exclusive scan of ints from wave scans: two barriers (wsum: one
+// slot per wave)
+__device__ inline int block_exclusive_scan_i(int v, int *wsum, int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int incl = wave_incl_scan(v);
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int q = 0; q < nw; ++q) {
+    const int a = wsum[q];
+    if (q < w) before += a;
+    all += a;
+  }
+  *total = all;
+  __syncthreads();
+  return before + incl - v;
+}
+
 __device__ inline int wave_incl_scan(int v) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -157,6 +178,86 @@ __device__ inline unsigned int wave_sum(unsigned int a) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
   return a;
+}
+
+// Secondary emission (Alg. 2), in two parts.  see_count: an absorbed ion's
+// energy E = m v^2 / 2 from its impact velocity, the mean yield
+// a (E/E0) / (1 + E/E0) and the Poisson count by inversion, drawn from the
+// stream keyed by (level, ion id); blk keeps the block for the energies.
+__device__ inline int see_count(const GapConst &c, long long level, uint32_t ion_id, double u_imp, uint64_t blk[4]) {
+  const double v_ion = (u_imp * c.dx) / c.dt;
+  const double e_ion = 0.5 * c.mass[1] * v_ion * v_ion / c.ev;
+  const double rr = e_ion / c.see_E0;
+  double lam = c.see_amp * rr / (1.0 + rr);
+  if (lam < 0.0) lam = 0.0;
+  rng_block(c.seed, (uint64_t)level, (uint64_t)ion_id, 1, 0, blk);
+  return poisson_inverse(lam, unit_open(blk[0]), c.see_max);
+}
+
+// see_write: the ion's nk electrons, energies fixed or exponential, placed on
+// the wall node with the inward speed of their energy, in slots base.. of the
+// electron region; counts per wall added to n[0], n[1].
+template <class P>
+__device__ inline void see_write(const DevPtrs &p, const GapConst &c, long long level, int g, int sel,
+                                 uint32_t ion_id, int wall, int nk, uint64_t blk[4], unsigned long long base,
+                                 unsigned int n[2]) {
+  P *X = (P *)p.X[sel] + c.pbase[0];
+  P *U = (P *)p.U[sel] + c.pbase[0];
+  uint32_t *ID = p.ID[sel] + c.pbase[0];
+  const P xw = wall == 0 ? (P)0 : (P)c.N;
+  for (int e = 0; e < nk; ++e) {
+    const int slotw = e + 1;  // word 0 of block 0 drew the count
+    if ((slotw & 3) == 0) rng_block(c.seed, (uint64_t)level, (uint64_t)ion_id, 1, (uint64_t)(slotw >> 2), blk);
+    const double uu = unit_open(blk[slotw & 3]);
+    const double E_se = (c.see_law == GS_SEE_EXP) ? -c.see_E * log(uu) : c.see_E;
+    const double v_se = sqrt(2.0 * E_se * c.ev / c.mass[0]);
+    const double v_si = wall == 0 ? v_se : -v_se;
+    const unsigned long long sl = base + (unsigned long long)e;
+    if (sl >= (unsigned long long)c.cap[0]) {
+      atomicOr(&p.err[0], ERR_CAPACITY);
+      atomicCAS(&p.err[1], 0xFFFFFFFFu, (unsigned int)g);
+      continue;
+    }
+    X[sl] = xw;
+    U[sl] = (P)((v_si * c.dt) / c.dx);
+    ID[sl] = NO_ID;
+    n[wall] += 1;
+  }
+}
+
+// Emission for ne events of gap g listed in evs, one event per thread and
+// pass, slots from one reservation per pass; emitted counts per wall added to
+// emit_cnt (LDS).  Every thread of the block calls it.
+template <class P>
+__device__ void see_emit(const DevPtrs &p, const GapConst &c, long long level, int g, int sel, const Event *evs,
+                         int ne, int *wsum, unsigned long long *s_base, unsigned int *emit_cnt) {
+  const uint32_t *IDi = p.ID[sel] + c.pbase[1];
+  for (int r = 0; r < ne; r += blockDim.x) {
+    const int k = r + threadIdx.x;
+    int nk = 0, wall = 0;
+    uint32_t ion_id = 0;
+    uint64_t blk[4] = {0, 0, 0, 0};
+    if (k < ne) {
+      const Event ev = evs[k];
+      ion_id = IDi[ev.slot];
+      wall = (int)ev.wall;
+      nk = see_count(c, level, ion_id, ev.u, blk);
+    }
+    int btot;
+    const int excl = block_exclusive_scan_i(nk, wsum, &btot);
+    if (btot == 0) continue;
+    if (threadIdx.x == 0) *s_base = atomicAdd(&p.next_count[g * 2 + 0], (unsigned long long)btot);
+    __syncthreads();
+    const unsigned long long base = *s_base;
+    __syncthreads();
+    unsigned int n[2] = {0u, 0u};
+    see_write<P>(p, c, level, g, sel, ion_id, wall, nk, blk, base + (unsigned long long)excl, n);
+    const unsigned int a0 = wave_sum(n[0]), a1 = wave_sum(n[1]);
+    if ((threadIdx.x & 63) == 0) {
+      if (a0) atomicAdd(&emit_cnt[0], a0);
+      if (a1) atomicAdd(&emit_cnt[1], a1);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -402,6 +503,9 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   __shared__ unsigned long long s_tally[T_N];
   __shared__ float s_x[MLP_IN], s_h0[MLP_H], s_h1[MLP_H], s_y[MLP_OUT];
   __shared__ double s_ue[MAXM + 1], s_mu[MAXM + 1];
+  __shared__ int s_wsum_i[FBS / 64];
+  __shared__ unsigned long long s_ebase;
+  __shared__ unsigned int s_emit[2];
   // stage the gap's constants, state and last push's tallies in LDS
   if (tid < T_N) {
     unsigned long long *tl = p.tally + (size_t)g * T_N;
@@ -416,7 +520,30 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
     b = (unsigned long long *)&ss;
     for (int i = tid; i < (int)(sizeof(GapState) / 8); i += FBS) b[i] = a[i];
   }
+  if (tid < 2) s_emit[tid] = 0u;
   __syncthreads();
+
+  // absorbed ions the push could not queue in LDS (a full queue): their
+  // secondary electrons are emitted here, keyed by the push's level
+  unsigned long long ex0 = 0ull, exN = 0ull;
+  {
+    const long long nov = min((long long)p.ev_count[g], sc.evcap);
+    if (nov > 0) {
+      if (fp64)
+        see_emit<double>(p, sc, ss.level, g, (int)(*p.epoch & 1), p.ev + sc.evbase, (int)nov, s_wsum_i, &s_ebase,
+                         s_emit);
+      else
+        see_emit<float>(p, sc, ss.level, g, (int)(*p.epoch & 1), p.ev + sc.evbase, (int)nov, s_wsum_i, &s_ebase,
+                        s_emit);
+      __syncthreads();
+      const long long ze = (long long)sc.Z[0] * (fp64 ? (1ll << F64_BITS) : (1ll << F32_BITS));
+      ex0 = (unsigned long long)(ze * (long long)s_emit[0]);
+      exN = (unsigned long long)(ze * (long long)s_emit[1]);
+      __syncthreads();
+      if (tid < 2) s_tally[T_EMIT + tid] += s_emit[tid];
+      __syncthreads();
+    }
+  }
 
   // 0. strict coupling: the guess network's input (the last 8 levels from the
   //    history ring), recorded for training and/or evaluated for the guess
@@ -462,7 +589,7 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   // 1. nodal density of level n (to global rho and, as the cell terms of the
   //    prefix sums, to LDS); the accumulator is cleared for the next push
   for (int k = tid; k <= N; k += FBS) {
-    const double r = node_rho(s0, dx, acc[k], k, N, fp64);
+    const double r = node_rho(s0, dx, acc[k] + (k == 0 ? ex0 : 0ull) + (k == N ? exN : 0ull), k, N, fp64);
     rho[k] = r;
     acc[k] = 0ull;
     if (k < N)
@@ -633,49 +760,152 @@ struct PushShared {
   unsigned int *tally;  // [T_N]
   Event *evq;           // [EVQ]
   unsigned int *evq_n;
+  int *wsum;            // [BS / 64] scan scratch
 };
 
-// push tiles of gap g: electrons, then ions
-__device__ inline void gap_tiles(const GapState &st, int tile, int &te, int &ti) {
+// push tiles of gap g: electrons, then ions (a gap with a beam has at least
+// one ion tile: the workgroups holding its ion tiles inject the beam)
+__device__ inline void gap_tiles(const GapState &st, long long beam_n, int tile, int &te, int &ti) {
   te = (int)((st.count[0] + tile - 1) / tile);
   ti = (int)((st.count[1] + tile - 1) / tile);
+  if (beam_n > 0 && ti == 0) ti = 1;
 }
 
-// Hand one (gap, species) segment's LDS state to the gap: node sums times the
-// charge number Z, tallies, queued events.
+
+// Beam ions k0..k1-1 of gap g entering at the circuit electrode: energy
+// uniform in [E_min, E_max], placed a random fraction of one step's flight into
+// the gap, keyed by (level, k); slots count[1] + k and ids beam_id0 + k were
+// set aside by the field solve.  Their charge goes to the ion segment's LDS
+// accumulator.
 template <class P, class AC>
-__device__ void flush_seg(const DevPtrs &p, const GapConst &c, int g, long long Z, PushShared<P, AC> &sh) {
+__device__ void beam_inject(const DevPtrs &p, const GapConst &c, const GapState &st, int g, int sel, long long k0,
+                            long long k1, typename AC::cell *acc, unsigned int *n_inj) {
+  P *X = (P *)p.X[sel] + c.pbase[1];
+  P *U = (P *)p.U[sel] + c.pbase[1];
+  uint32_t *ID = p.ID[sel] + c.pbase[1];
+  unsigned long long *gacc = p.acc + c.nbase;
+  const int N = c.N;
+  const long long zhi = (long long)c.Z[1] * 4294967296ll;
+  unsigned int cnt = 0;
+  for (long long k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+    uint64_t blk[4];
+    rng_block(c.seed, (uint64_t)st.level, (uint64_t)k, 2, 0, blk);
+    const double E = c.beam_Emin + (c.beam_Emax - c.beam_Emin) * unit_open(blk[0]);
+    const double v = sqrt(2.0 * E * c.ev / c.mass[1]);
+    const double x = unit_open(blk[1]) * v * c.dt;
+    const P xi = (P)(x / c.dx);
+    const P u = (P)((v * c.dt) / c.dx);
+    const unsigned long long slot = (unsigned long long)st.count[1] + (unsigned long long)k;
+    if (slot >= (unsigned long long)c.cap[1]) {
+      atomicOr(&p.err[0], ERR_CAPACITY);
+      atomicCAS(&p.err[1], 0xFFFFFFFFu, (unsigned int)g);
+      continue;
+    }
+    X[slot] = xi;
+    U[slot] = u;
+    ID[slot] = (uint32_t)(st.beam_id0 + k);
+    cnt += 1;
+    int j = (int)xi;
+    if (j > N - 1) j = N - 1;
+    const P f = xi - (P)j;
+    const typename Prec<P>::wt w1 = Prec<P>::wq(f);
+    const typename Prec<P>::wt w0 = (typename Prec<P>::wt)Prec<P>::W - w1;
+    acc_add<AC>(acc, gacc, j, (unsigned long long)w0, zhi);
+    acc_add<AC>(acc, gacc, j + 1, (unsigned long long)w1, zhi);
+  }
+  const unsigned int a = wave_sum(cnt);
+  if ((threadIdx.x & 63) == 0 && a) atomicAdd(n_inj, a);
+}
+
+// Close one (gap, species) segment: for the ion segment inject this
+// workgroup's share of the beam and emit the secondary electrons of the ions it
+// absorbed (at most EVQ <= blockDim, one per thread), then hand the node sums
+// times the charge number, the emitted electrons' wall charge and the tallies
+// to the gap.  The latencies overlap: the ions' ids are loaded while the beam
+// is drawn, and the electrons' slot reservation is in flight while the node
+// sums are flushed.
+template <class P, class AC>
+__device__ void flush_seg(const DevPtrs &p, const GapConst &c, const GapState &st, int g, int s, int sel,
+                          long long kb0, long long kb1, PushShared<P, AC> &sh) {
+  __shared__ unsigned long long s_base;
   __syncthreads();
   unsigned long long *gacc = p.acc + c.nbase;
-  for (int j = threadIdx.x; j <= c.N; j += blockDim.x) {
+  const int nq = s == 1 ? (int)min(*sh.evq_n, (unsigned int)EVQ) : 0;
+  uint32_t ion_id = 0;
+  int wall = 0, nk = 0;
+  double u_imp = 0.0;
+  if ((int)threadIdx.x < nq) {
+    const Event ev = sh.evq[threadIdx.x];
+    ion_id = p.ID[sel][c.pbase[1] + ev.slot];
+    wall = (int)ev.wall;
+    u_imp = ev.u;
+  }
+  if (s == 1 && kb1 > kb0) beam_inject<P, AC>(p, c, st, g, sel, kb0, kb1, sh.acc, &sh.tally[T_INJ]);
+  uint64_t blk[4] = {0, 0, 0, 0};
+  if ((int)threadIdx.x < nq) nk = see_count(c, st.level, ion_id, u_imp, blk);
+  int btot = 0, excl = 0;
+  if (nq > 0)
+    excl = block_exclusive_scan_i(nk, sh.wsum, &btot);
+  else
+    __syncthreads();  // the beam's deposits are in before the node sums go out
+  unsigned long long base = 0;
+  if (threadIdx.x == 0 && btot > 0) base = atomicAdd(&p.next_count[g * 2 + 0], (unsigned long long)btot);
+  // node sums; each workgroup starts at its own node so that the workgroups
+  // flushing at the same time add to different addresses
+  const long long Z = (long long)c.Z[s];
+  const int nn = c.N + 1;
+  const int rot = (int)(((long long)blockIdx.x * 977) % nn);
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    int j = i + rot;
+    j = j >= nn ? j - nn : j;
     const unsigned long long v = (unsigned long long)sh.acc[j];
     if (v != 0ull) atomicAdd(&gacc[j], (unsigned long long)(Z * (long long)v));
+  }
+  if (btot > 0) {
+    if (threadIdx.x == 0) s_base = base;
+    __syncthreads();
+    unsigned int n[2] = {0u, 0u};
+    if (nk > 0) see_write<P>(p, c, st.level, g, sel, ion_id, wall, nk, blk, s_base + (unsigned long long)excl, n);
+    const unsigned int a0 = wave_sum(n[0]), a1 = wave_sum(n[1]);
+    if ((threadIdx.x & 63) == 0) {
+      if (a0) atomicAdd(&sh.tally[T_EMIT], a0);
+      if (a1) atomicAdd(&sh.tally[T_EMIT + 1], a1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      // an emitted electron carries its full weight on its wall node
+      const long long ze = (long long)c.Z[0] * Prec<P>::W;
+      const unsigned int e0 = sh.tally[T_EMIT], e1 = sh.tally[T_EMIT + 1];
+      if (e0) atomicAdd(&gacc[0], (unsigned long long)(ze * (long long)e0));
+      if (e1) atomicAdd(&gacc[c.N], (unsigned long long)(ze * (long long)e1));
+    }
   }
   if (threadIdx.x < T_N) {
     const unsigned int v = sh.tally[threadIdx.x];
     if (v) atomicAdd(&p.tally[(size_t)g * T_N + threadIdx.x], (unsigned long long)v);
   }
-  // queued events: one reservation for the whole queue
-  const unsigned int nq = min(*sh.evq_n, (unsigned int)EVQ);
-  __shared__ unsigned long long q_base;
-  if (threadIdx.x == 0 && nq) q_base = atomicAdd(&p.ev_count[g], (unsigned long long)nq);
-  __syncthreads();
-  for (unsigned int i = threadIdx.x; i < nq; i += blockDim.x) {
-    const unsigned long long e = q_base + i;
-    if (e < (unsigned long long)c.evcap) {
-      p.ev[c.evbase + e] = sh.evq[i];
-    } else {
-      atomicOr(&p.err[0], ERR_CAPACITY);
-      atomicCAS(&p.err[1], 0xFFFFFFFFu, (unsigned int)g);
-    }
-  }
   __syncthreads();
 }
 
+// Stage the gap's field table (16-byte aligned, N + 2 entries) in LDS with
+// 16-byte loads, four in flight per thread, and clear the accumulator.
 template <class P, class AC>
 __device__ void load_seg(const DevPtrs &p, const GapConst &c, PushShared<P, AC> &sh) {
-  const P *geh = (const P *)p.ehat + c.ebase;
-  for (int j = threadIdx.x; j <= c.N + 1; j += blockDim.x) sh.eh[j] = geh[j];
+  typedef typename Vec<P>::type V;
+  constexpr int VN = Vec<P>::n;
+  const V *geh = (const V *)((const P *)p.ehat + c.ebase);
+  V *leh = (V *)sh.eh;
+  const int nv = (c.N + 2 + VN - 1) / VN;
+  const int bs = blockDim.x;
+  for (int j0 = threadIdx.x; j0 < nv; j0 += 4 * bs) {
+    V t[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (j0 + q * bs < nv) t[q] = geh[j0 + q * bs];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (j0 + q * bs < nv) leh[j0 + q * bs] = t[q];
+  }
   for (int j = threadIdx.x; j <= c.N; j += blockDim.x) sh.acc[j] = 0;
   if (threadIdx.x < T_N) sh.tally[threadIdx.x] = 0u;
   if (threadIdx.x == 0) *sh.evq_n = 0u;
@@ -771,8 +1001,9 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
       acc_add<AC>(sh.acc, c.gacc, jj[k], (unsigned long long)w0[k], zhi);
       acc_add<AC>(sh.acc, c.gacc, jj[k] + 1, (unsigned long long)w1[k], zhi);
     }
-  // absorbed ions are queued for secondary emission (k_source): in LDS, or
-  // straight to the gap's list when the workgroup's queue is full
+  // absorbed ions are queued for secondary emission: in LDS (emitted at the
+  // segment's flush), or straight to the gap's list (emitted by the next field
+  // solve) when the workgroup's queue is full
   if (see && (hit & 0xFFFFu) != 0u) {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -862,16 +1093,18 @@ __device__ void push_range(const DevPtrs &p, const GapConst &gc, int g, int s, i
 }
 
 template <class P, class AC, int BS, int PPT>
-__global__ __launch_bounds__(BS) void k_push(DevPtrs p, int G, int tile, int nmax) {
+__global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int nmax) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   typedef typename AC::cell cell;
   __shared__ int scan_sh[BS];
   __shared__ Event evq[EVQ];
   __shared__ unsigned int evq_n;
+  __shared__ int wsum_sh[BS / 64];
   // layout: tally[T_N] | prefix[G+1] | eh[nmax+2] (P) | acc[nmax+1] (cell)
   PushShared<P, AC> sh;
   sh.evq = evq;
   sh.evq_n = &evq_n;
+  sh.wsum = wsum_sh;
   sh.tally = (unsigned int *)lds_raw;
   sh.prefix = (int *)(lds_raw + 64);
   const size_t off = 64 + (((size_t)(G + 1) * 4 + 15) / 16) * 16;
@@ -889,18 +1122,18 @@ __global__ __launch_bounds__(BS) void k_push(DevPtrs p, int G, int tile, int nma
       const int g = tid * per + q;
       if (g < G) {
         int te, ti;
-        gap_tiles(p.gs[g], tile, te, ti);
+        gap_tiles(p.gs[g], p.gc[g].beam_n, tile, te, ti);
         mine += te + ti;
       }
     }
     int tot_tiles;
-    int run = block_exclusive_scan<int>(mine, scan_sh, &tot_tiles);
+    int run = block_exclusive_scan_i(mine, scan_sh, &tot_tiles);
     for (int q = 0; q < per; ++q) {
       const int g = tid * per + q;
       if (g < G) {
         sh.prefix[g] = run;
         int te, ti;
-        gap_tiles(p.gs[g], tile, te, ti);
+        gap_tiles(p.gs[g], p.gc[g].beam_n, tile, te, ti);
         run += te + ti;
       }
     }
@@ -919,7 +1152,7 @@ __global__ __launch_bounds__(BS) void k_push(DevPtrs p, int G, int tile, int nma
     const GapConst &c = p.gc[g];
     const GapState &st = p.gs[g];
     int te, ti;
-    gap_tiles(st, tile, te, ti);
+    gap_tiles(st, c.beam_n, tile, te, ti);
     const int lt = t - sh.prefix[g];
     const int s = lt < te ? 0 : 1;
     const int seg_end = min(s == 0 ? te : te + ti, t1 - sh.prefix[g]);
@@ -937,203 +1170,11 @@ __global__ __launch_bounds__(BS) void k_push(DevPtrs p, int G, int tile, int nma
       if (v1) atomicAdd(&sh.tally[T_ABS + s * 2 + 0], v1);
       if (v2) atomicAdd(&sh.tally[T_ABS + s * 2 + 1], v2);
     }
-    flush_seg<P, AC>(p, c, g, (long long)c.Z[s], sh);
+    // this workgroup's share of the beam: in proportion to its ion tiles
+    const long long kb0 = s == 1 ? c.beam_n * ls / ti : 0, kb1 = s == 1 ? c.beam_n * le / ti : 0;
+    flush_seg<P, AC>(p, c, st, g, s, sel, kb0, kb1, sh);
     t += seg_end - lt;
   }
-}
-
-// ---------------------------------------------------------------------------
-// k_source: secondary emission of the ions the push absorbed (Alg. 2) and the
-// ion beam entering at the circuit electrode.  Their charge lands on the wall
-// nodes or within a few cells of node 0, so each workgroup accumulates it in a
-// small LDS window [0, SW) plus a cell for node N.
-// ---------------------------------------------------------------------------
-constexpr int SBS = 256;
-constexpr int SW = 256;
-
-__device__ inline void src_dep(unsigned long long *win, unsigned long long *gacc, int N, int j,
-                               long long c) {
-  if (j < SW)
-    atomicAdd(&win[j], (unsigned long long)c);
-  else if (j == N)
-    atomicAdd(&win[SW], (unsigned long long)c);
-  else
-    atomicAdd(&gacc[j], (unsigned long long)c);
-}
-
-__device__ inline void src_flush(const DevPtrs &p, const GapConst &c, int g, unsigned long long *win,
-                                 unsigned int *tally) {
-  __syncthreads();
-  unsigned long long *gacc = p.acc + c.nbase;
-  const int nw = min(SW, c.N + 1);
-  for (int j = threadIdx.x; j < nw; j += blockDim.x)
-    if (win[j]) atomicAdd(&gacc[j], win[j]);
-  if (threadIdx.x == 0 && c.N >= SW && win[SW]) atomicAdd(&gacc[c.N], win[SW]);
-  if (threadIdx.x < T_N && tally[threadIdx.x])
-    atomicAdd(&p.tally[(size_t)g * T_N + threadIdx.x], (unsigned long long)tally[threadIdx.x]);
-  __syncthreads();
-}
-
-template <class P>
-__global__ __launch_bounds__(SBS) void k_source(DevPtrs p, int G, int tile) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  int *prefix = (int *)lds_raw;  // [G + 1]
-  __shared__ unsigned long long win[SW + 1];
-  __shared__ unsigned int tally[T_N];
-  __shared__ int scan_sh[SBS];
-  __shared__ unsigned long long s_base;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int sel = (int)(*p.epoch & 1);
-  // tiles of gap g: its absorbed-ion events, then its beam
-  {
-    const int per = (G + SBS - 1) / SBS;
-    int mine = 0;
-    for (int q = 0; q < per; ++q) {
-      const int g = tid * per + q;
-      if (g < G) {
-        const long long ne = min((long long)p.ev_count[g], p.gc[g].evcap);
-        mine += (int)((ne + tile - 1) / tile + (p.gc[g].beam_n + tile - 1) / tile);
-      }
-    }
-    int tot;
-    int run = block_exclusive_scan<int>(mine, scan_sh, &tot);
-    for (int q = 0; q < per; ++q) {
-      const int g = tid * per + q;
-      if (g < G) {
-        prefix[g] = run;
-        const long long ne = min((long long)p.ev_count[g], p.gc[g].evcap);
-        run += (int)((ne + tile - 1) / tile + (p.gc[g].beam_n + tile - 1) / tile);
-      }
-    }
-    if (tid == 0) prefix[G] = tot;
-    __syncthreads();
-  }
-  const int total = prefix[G];
-  const int t0 = (int)(((long long)blockIdx.x * total) / gridDim.x);
-  const int t1 = (int)(((long long)(blockIdx.x + 1) * total) / gridDim.x);
-  int cur = -1, g = 0;
-  for (int t = t0; t < t1; ++t) {
-    while (prefix[g + 1] <= t) ++g;
-    const GapConst &c = p.gc[g];
-    const GapState &st = p.gs[g];
-    if (g != cur) {
-      if (cur >= 0) src_flush(p, p.gc[cur], cur, win, tally);
-      for (int j = tid; j <= SW; j += SBS) win[j] = 0ull;
-      if (tid < T_N) tally[tid] = 0u;
-      __syncthreads();
-      cur = g;
-    }
-    unsigned long long *gacc = p.acc + c.nbase;
-    const int N = c.N;
-    const long long nev = min((long long)p.ev_count[g], c.evcap);
-    const int tev = (int)((nev + tile - 1) / tile);
-    const int lt = t - prefix[g];
-    if (lt < tev) {
-      // secondary electrons: Poisson(gamma(E)) per ion, leaving the wall normally
-      P *X = (P *)p.X[sel] + c.pbase[0];
-      P *U = (P *)p.U[sel] + c.pbase[0];
-      uint32_t *ID = p.ID[sel] + c.pbase[0];
-      const long long cw = (long long)c.Z[0] * Prec<P>::W;
-      unsigned int em0 = 0, em1 = 0;
-      for (int r = 0; r < tile; r += SBS) {
-        const long long k = (long long)lt * tile + r + tid;
-        if ((long long)lt * tile + r >= nev) break;
-        int nk = 0, wall = 0;
-        uint32_t ion_id = 0;
-        uint64_t blk[4];
-        if (k < nev) {
-          const Event ev = p.ev[c.evbase + k];
-          ion_id = p.ID[sel][c.pbase[1] + ev.slot];
-          wall = (int)ev.wall;
-          const double v_ion = (ev.u * c.dx) / c.dt;
-          const double e_ion = 0.5 * c.mass[1] * v_ion * v_ion / c.ev;
-          const double rr = e_ion / c.see_E0;
-          double lam = c.see_amp * rr / (1.0 + rr);
-          if (lam < 0.0) lam = 0.0;
-          rng_block(c.seed, (uint64_t)st.level, (uint64_t)ion_id, 1, 0, blk);
-          nk = poisson_inverse(lam, unit_open(blk[0]), c.see_max);
-        }
-        // one slot reservation per workgroup for this round's electrons
-        int btot;
-        const int excl = block_exclusive_scan<int>(nk, scan_sh, &btot);
-        if (btot == 0) continue;
-        if (tid == 0) s_base = atomicAdd(&p.next_count[g * 2 + 0], (unsigned long long)btot);
-        __syncthreads();
-        const unsigned long long base = s_base;
-        const int incl = excl + nk;
-        __syncthreads();
-        const P xw = wall == 0 ? (P)0 : (P)N;
-        const int jn = wall == 0 ? 0 : N;
-        for (int e = 0; e < nk; ++e) {
-          const int slotw = e + 1;  // word 0 of block 0 drew the count
-          if ((slotw & 3) == 0)
-            rng_block(c.seed, (uint64_t)st.level, (uint64_t)ion_id, 1, (uint64_t)(slotw >> 2), blk);
-          const double uu = unit_open(blk[slotw & 3]);
-          const double E_se = (c.see_law == GS_SEE_EXP) ? -c.see_E * log(uu) : c.see_E;
-          const double v_se = sqrt(2.0 * E_se * c.ev / c.mass[0]);
-          const double v_si = wall == 0 ? v_se : -v_se;
-          const unsigned long long sl = base + (unsigned long long)(incl - nk + e);
-          if (sl >= (unsigned long long)c.cap[0]) {
-            atomicOr(&p.err[0], ERR_CAPACITY);
-            atomicCAS(&p.err[1], 0xFFFFFFFFu, (unsigned int)g);
-            continue;
-          }
-          X[sl] = xw;
-          U[sl] = (P)((v_si * c.dt) / c.dx);
-          ID[sl] = NO_ID;
-          // an electron on the wall node carries its full weight there
-          src_dep(win, gacc, N, jn, cw);
-          if (wall == 0) ++em0;
-          else ++em1;
-        }
-      }
-      const unsigned int a0 = wave_sum(em0), a1 = wave_sum(em1);
-      if (lane == 0) {
-        if (a0) atomicAdd(&tally[T_EMIT + 0], a0);
-        if (a1) atomicAdd(&tally[T_EMIT + 1], a1);
-      }
-    } else {
-      // beam ions entering at the circuit electrode, a random fraction of one
-      // step's flight into the gap
-      const int lb = lt - tev;
-      P *X = (P *)p.X[sel] + c.pbase[1];
-      P *U = (P *)p.U[sel] + c.pbase[1];
-      uint32_t *ID = p.ID[sel] + c.pbase[1];
-      unsigned int n_inj = 0;
-      for (int r = tid; r < tile; r += SBS) {
-        const long long k = (long long)lb * tile + r;
-        if (k >= c.beam_n) break;
-        uint64_t blk[4];
-        rng_block(c.seed, (uint64_t)st.level, (uint64_t)k, 2, 0, blk);
-        const double E = c.beam_Emin + (c.beam_Emax - c.beam_Emin) * unit_open(blk[0]);
-        const double v = sqrt(2.0 * E * c.ev / c.mass[1]);
-        const double x = unit_open(blk[1]) * v * c.dt;
-        const P xi = (P)(x / c.dx);
-        const P u = (P)((v * c.dt) / c.dx);
-        // slots count[1] .. count[1] + beam_n - 1 were set aside by the field solve
-        const unsigned long long slot = (unsigned long long)st.count[1] + (unsigned long long)k;
-        if (slot >= (unsigned long long)c.cap[1]) {
-          atomicOr(&p.err[0], ERR_CAPACITY);
-          atomicCAS(&p.err[1], 0xFFFFFFFFu, (unsigned int)g);
-          continue;
-        }
-        X[slot] = xi;
-        U[slot] = u;
-        ID[slot] = (uint32_t)(st.beam_id0 + k);
-        n_inj += 1;
-        int j = (int)xi;
-        if (j > N - 1) j = N - 1;
-        const P f = xi - (P)j;
-        const long long w1 = Prec<P>::wq(f);
-        const long long w0 = Prec<P>::W - w1;
-        src_dep(win, gacc, N, j, (long long)c.Z[1] * w0);
-        src_dep(win, gacc, N, j + 1, (long long)c.Z[1] * w1);
-      }
-      const unsigned int a = wave_sum(n_inj);
-      if (lane == 0 && a) atomicAdd(&tally[T_INJ], a);
-    }
-  }
-  if (cur >= 0) src_flush(p, p.gc[cur], cur, win, tally);
 }
 
 // ---------------------------------------------------------------------------
@@ -1363,6 +1404,7 @@ static hipError_t push_bp(const DevPtrs &p, int G, const LaunchCfg &lc, hipStrea
   switch (lc.block) {
     case 256: return push_t<P, AC, 256, PPT>(p, G, lc, s, t);
     case 512: return push_t<P, AC, 512, PPT>(p, G, lc, s, t);
+    case 768: return push_t<P, AC, 768, PPT>(p, G, lc, s, t);
     default: return push_t<P, AC, 1024, PPT>(p, G, lc, s, t);
   }
 }
@@ -1377,14 +1419,6 @@ hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t
   if (lc.fp64) return push_b<double, Wide64>(p, G, lc, s, t);
   if (lc.wide) return push_b<float, Wide64>(p, G, lc, s, t);
   return push_b<float, Carry32>(p, G, lc, s, t);
-}
-
-hipError_t launch_source(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
-  const int grid = lc.source_grid > 0 ? lc.source_grid : 256;
-  const size_t lds = ((size_t)(G + 1) * 4 + 15) / 16 * 16;
-  const int tile = SBS;
-  if (lc.fp64) return launch_k(k_source<double>, dim3(grid), dim3(SBS), lds, s, t.a, t.b, p, G, tile);
-  return launch_k(k_source<float>, dim3(grid), dim3(SBS), lds, s, t.a, t.b, p, G, tile);
 }
 
 hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {

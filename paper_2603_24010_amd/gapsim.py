@@ -83,9 +83,7 @@ class GsDiag(C.Structure):
 class GsTiming(C.Structure):
     _fields_ = [
         ("push_ms", C.c_double), ("field_ms", C.c_double), ("compact_ms", C.c_double),
-        ("source_ms", C.c_double),
         ("push_launches", C.c_int64), ("field_launches", C.c_int64), ("compact_launches", C.c_int64),
-        ("source_launches", C.c_int64),
     ]
 
 
@@ -404,9 +402,8 @@ class GapSim:
         T = GsTiming()
         self._chk(lib().gs_get_timing(self._h, C.byref(T), 1 if reset else 0))
         return dict(push_ms=T.push_ms, field_ms=T.field_ms, compact_ms=T.compact_ms,
-                    source_ms=T.source_ms, push_launches=T.push_launches,
-                    field_launches=T.field_launches, compact_launches=T.compact_launches,
-                    source_launches=T.source_launches)
+                    push_launches=T.push_launches, field_launches=T.field_launches,
+                    compact_launches=T.compact_launches)
 
 
 def mlp_train(x, t, order, batch: int, theta, adam_m, adam_v, step0: int = 0, lr: float = 1e-3,
