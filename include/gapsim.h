@@ -161,8 +161,7 @@ enum {
   GS_OPT_NEWTON_MAXIT = 8, /* Newton corrections allowed per level, 0..64 (default 8) */
   GS_OPT_DEPOSIT = 9,      /* binary32 deposit cells: 0 auto, 1 64-bit, 2 32-bit with carries */
   GS_OPT_COMPACT_GRID = 10,/* workgroups of the compaction kernel (>= 1) */
-  GS_OPT_PPT = 11          /* 16-byte particle vectors per thread per chunk: 1 or 2
-                              (default 2 for binary32 particles, 1 for binary64) */
+  GS_OPT_PPT = 11          /* 16-byte particle vectors per thread per chunk: 1 (default) or 2 */
 };
 
 typedef struct gs_ctx gs_ctx;

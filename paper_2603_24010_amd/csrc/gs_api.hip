@@ -392,7 +392,7 @@ static gs_status setup(gs_ctx *ctx) {
   ctx->lc.tile = ctx->lc.block * 8;
   ctx->lc.wide = 1;
   ctx->lc.compact_grid = 4 * ctx->ncu;
-  ctx->lc.ppt = ctx->fp64 ? 2 : 8;
+  ctx->lc.ppt = ctx->fp64 ? 2 : 4;
   choose_launch(ctx);
   return GS_OK;
 }

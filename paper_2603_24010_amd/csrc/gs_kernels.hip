@@ -29,7 +29,9 @@ namespace gs {
 __device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
   const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
   const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
+  // kept rolled: it runs only at emission and injection, and the push
+  // kernel's instruction footprint matters more than its speed
+#pragma unroll 1
   for (int r = 0; r < 10; ++r) {
     const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
     const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
@@ -817,16 +819,14 @@ __device__ void beam_inject(const DevPtrs &p, const GapConst &c, const GapState 
   if ((threadIdx.x & 63) == 0 && a) atomicAdd(n_inj, a);
 }
 
-// Close one (gap, species) segment: for the ion segment inject this
-// workgroup's share of the beam and emit the secondary electrons of the ions it
-// absorbed (at most EVQ <= blockDim, one per thread), then hand the node sums
-// times the charge number, the emitted electrons' wall charge and the tallies
-// to the gap.  The latencies overlap: the ions' ids are loaded while the beam
-// is drawn, and the electrons' slot reservation is in flight while the node
-// sums are flushed.
+// Close one (gap, species) segment: for the ion segment emit the secondary
+// electrons of the ions this workgroup absorbed (at most EVQ <= blockDim, one
+// per thread), then hand the node sums times the charge number, the emitted
+// electrons' wall charge and the tallies to the gap.  The electrons' slot
+// reservation is in flight while the node sums are flushed.
 template <class P, class AC>
 __device__ void flush_seg(const DevPtrs &p, const GapConst &c, const GapState &st, int g, int s, int sel,
-                          long long kb0, long long kb1, PushShared<P, AC> &sh) {
+                          PushShared<P, AC> &sh) {
   __shared__ unsigned long long s_base;
   __syncthreads();
   unsigned long long *gacc = p.acc + c.nbase;
@@ -840,7 +840,6 @@ __device__ void flush_seg(const DevPtrs &p, const GapConst &c, const GapState &s
     wall = (int)ev.wall;
     u_imp = ev.u;
   }
-  if (s == 1 && kb1 > kb0) beam_inject<P, AC>(p, c, st, g, sel, kb0, kb1, sh.acc, &sh.tally[T_INJ]);
   uint64_t blk[4] = {0, 0, 0, 0};
   if ((int)threadIdx.x < nq) nk = see_count(c, st.level, ion_id, u_imp, blk);
   int btot = 0, excl = 0;
@@ -941,9 +940,12 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
   const int g = c.g;
   const P Nf = (P)N;
   const P Nh = Nf - (P)0.5;
+  // slots that deposit nothing add zero at a node of their own (no
+  // same-address LDS atomics within a wave)
+  const int jdummy = (int)(threadIdx.x % (unsigned int)N);
   int jj[PPT];
   typename Prec<P>::wt w0[PPT], w1[PPT];
-  unsigned int dep = 0, hit = 0;  // bit k: slot k deposits / is absorbed (wall in bit k+16)
+  unsigned int hit = 0;  // bit k: slot k is an absorbed ion (its wall in bit k+16)
   P u_hit[PPT];
   V xw[NV], uw[NV];
 #pragma unroll
@@ -973,12 +975,12 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
     const P xs = stay ? x1 : (P)0;
     int j = (int)xs;
     j = j > N - 1 ? N - 1 : j;
+    j = stay ? j : jdummy;
     const P f = xs - (P)j;
     const typename Prec<P>::wt q1 = Prec<P>::wq(f);
-    dep |= (unsigned int)stay << k;
     jj[k] = j;
-    w1[k] = q1;
-    w0[k] = (typename Prec<P>::wt)Prec<P>::W - q1;
+    w1[k] = stay ? q1 : (typename Prec<P>::wt)0;
+    w0[k] = stay ? (typename Prec<P>::wt)Prec<P>::W - q1 : (typename Prec<P>::wt)0;
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -995,21 +997,26 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
         }
     }
   }
+  // every slot adds (zero weights for slots that do not deposit): no branches
 #pragma unroll
-  for (int k = 0; k < PPT; ++k)
-    if (dep & (1u << k)) {
-      acc_add<AC>(sh.acc, c.gacc, jj[k], (unsigned long long)w0[k], zhi);
-      acc_add<AC>(sh.acc, c.gacc, jj[k] + 1, (unsigned long long)w1[k], zhi);
-    }
+  for (int k = 0; k < PPT; ++k) {
+    acc_add<AC>(sh.acc, c.gacc, jj[k], (unsigned long long)w0[k], zhi);
+    acc_add<AC>(sh.acc, c.gacc, jj[k] + 1, (unsigned long long)w1[k], zhi);
+  }
   // absorbed ions are queued for secondary emission: in LDS (emitted at the
   // segment's flush), or straight to the gap's list (emitted by the next field
   // solve) when the workgroup's queue is full
   if (see && (hit & 0xFFFFu) != 0u) {
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      if (!((hit >> k) & 1u)) continue;
+    unsigned int rest = hit & 0xFFFFu;
+    while (rest) {
+      const int k = __ffs(rest) - 1;
+      rest &= rest - 1u;
       Event ev;
-      ev.u = (double)u_hit[k];
+      P uk = u_hit[0];
+#pragma unroll
+      for (int q = 1; q < PPT; ++q)
+        if (q == k) uk = u_hit[q];
+      ev.u = (double)uk;
       ev.slot = (uint32_t)(r0 + (long long)((k / VN) * BS + tid) * VN + k % VN);
       ev.wall = (hit >> (k + 16)) & 1u;
       const unsigned int q = atomicAdd(sh.evq_n, 1u);
@@ -1042,14 +1049,15 @@ __device__ inline void load_chunk(const P *X, const P *U, long long r0, typename
 }
 
 // The slots [a, b) of one (gap, species) region, as a stream of chunks.  Full
-// chunks are software-pipelined two deep: the loads of the next chunk are in
-// flight while this one is pushed.  Every load in the loop is unconditional
-// (past the last full chunk it repeats that chunk's, whose data is dropped), so
-// the wait before each chunk covers that chunk's loads only.  The remainder
+// chunks are software-pipelined: the loads of the next chunk are in flight
+// while this one is pushed.  Every load in the loop is unconditional (past the
+// last full chunk it repeats that chunk's, whose data is dropped), so the
+// waits count exactly.  The remainder
 // goes slot by slot: slots past b may be receiving appended particles.
 template <class P, class AC, int BS, int PPT>
-__device__ void push_range(const DevPtrs &p, const GapConst &gc, int g, int s, int sel, PushShared<P, AC> &sh,
-                           long long a, long long b, SegCount &cnt) {
+__device__ void push_range(const DevPtrs &p, const GapConst &gc, const GapState &st, int g, int s, int sel,
+                           PushShared<P, AC> &sh, long long a, long long b, long long kb0, long long kb1,
+                           SegCount &cnt) {
   typedef typename Vec<P>::type V;
   constexpr int VN = Vec<P>::n;
   constexpr int NV = PPT / VN;
@@ -1067,14 +1075,22 @@ __device__ void push_range(const DevPtrs &p, const GapConst &gc, int g, int s, i
   const long long zhi = (long long)gc.Z[s] * 4294967296ll;
   const long long nfull = (b - a) / CH;
   V xa[NV], ua[NV], xb[NV], ub[NV];
-  if (nfull > 0) {
-    load_chunk<P, BS, PPT>(X, U, a, xa, ua);
-    for (long long q = 0; q < nfull; q += 2) {
-      load_chunk<P, BS, PPT>(X, U, a + min(q + 1, nfull - 1) * CH, xb, ub);
-      push_chunk<P, AC, BS, PPT, true>(p, c, sh, X, U, a + q * CH, b, xa, ua, alpha, see, zhi, cnt);
-      if (q + 1 >= nfull) break;
-      load_chunk<P, BS, PPT>(X, U, a + min(q + 2, nfull - 1) * CH, xa, ua);
-      push_chunk<P, AC, BS, PPT, true>(p, c, sh, X, U, a + (q + 1) * CH, b, xb, ub, alpha, see, zhi, cnt);
+  // the first chunk's loads are in flight while the field table is staged and
+  // this workgroup's share of the beam is injected (the beam's slots lie past
+  // the swept range; its charge only has to reach the next density)
+  if (nfull > 0) load_chunk<P, BS, PPT>(X, U, a, xa, ua);
+  load_seg<P, AC>(p, gc, sh);
+  if (kb1 > kb0) beam_inject<P, AC>(p, gc, st, g, sel, kb0, kb1, sh.acc, &sh.tally[T_INJ]);
+  // one copy of the chunk body (the kernel's instruction footprint is what
+  // limits it): the next chunk's loads go out before this chunk is pushed,
+  // and the buffers are swapped by register moves
+  for (long long q = 0; q < nfull; ++q) {
+    load_chunk<P, BS, PPT>(X, U, a + min(q + 1, nfull - 1) * CH, xb, ub);
+    push_chunk<P, AC, BS, PPT, true>(p, c, sh, X, U, a + q * CH, b, xa, ua, alpha, see, zhi, cnt);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      xa[v] = xb[v];
+      ua[v] = ub[v];
     }
   }
   const long long r0 = a + nfull * CH;
@@ -1114,8 +1130,14 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
   const int lane = tid & 63;
   const int sel = (int)(*p.epoch & 1);
 
-  // tiles per gap and their prefix (each workgroup builds its own copy in LDS)
-  {
+  // tiles per gap and their prefix (each workgroup builds its own copy in LDS;
+  // one gap needs no scan)
+  int total1 = 0;
+  if (G == 1) {
+    int te, ti;
+    gap_tiles(p.gs[0], p.gc[0].beam_n, tile, te, ti);
+    total1 = te + ti;
+  } else {
     const int per = (G + BS - 1) / BS;
     int mine = 0;
     for (int q = 0; q < per; ++q) {
@@ -1141,28 +1163,31 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
     __syncthreads();
   }
 
+  auto prefix = [&](int i) { return G == 1 ? (i == 0 ? 0 : total1) : sh.prefix[i]; };
+
   // this workgroup's contiguous run of tiles, taken one (gap, species)
   // segment at a time
-  const int total = sh.prefix[G];
+  const int total = prefix(G);
   const int t1 = (int)(((long long)(blockIdx.x + 1) * total) / gridDim.x);
   int t = (int)(((long long)blockIdx.x * total) / gridDim.x);
   int g = 0;
   while (t < t1) {
-    while (sh.prefix[g + 1] <= t) ++g;
+    while (prefix(g + 1) <= t) ++g;
     const GapConst &c = p.gc[g];
     const GapState &st = p.gs[g];
     int te, ti;
     gap_tiles(st, c.beam_n, tile, te, ti);
-    const int lt = t - sh.prefix[g];
+    const int lt = t - prefix(g);
     const int s = lt < te ? 0 : 1;
-    const int seg_end = min(s == 0 ? te : te + ti, t1 - sh.prefix[g]);
+    const int seg_end = min(s == 0 ? te : te + ti, t1 - prefix(g));
     const int ls = s == 0 ? lt : lt - te;
     const int le = s == 0 ? seg_end : seg_end - te;
-    load_seg<P, AC>(p, c, sh);
     SegCount cnt;
     const long long a = (long long)ls * tile;
     const long long b = min((long long)le * tile, st.count[s]);
-    push_range<P, AC, BS, PPT>(p, c, g, s, sel, sh, a, b, cnt);
+    // this workgroup's share of the beam: in proportion to its ion tiles
+    const long long kb0 = s == 1 ? c.beam_n * ls / ti : 0, kb1 = s == 1 ? c.beam_n * le / ti : 0;
+    push_range<P, AC, BS, PPT>(p, c, st, g, s, sel, sh, a, b, kb0, kb1, cnt);
     // wave-level sums, then one LDS atomic per wave
     const unsigned int v0 = wave_sum(cnt.pushed), v1 = wave_sum(cnt.abs0), v2 = wave_sum(cnt.abs1);
     if (lane == 0) {
@@ -1170,9 +1195,7 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
       if (v1) atomicAdd(&sh.tally[T_ABS + s * 2 + 0], v1);
       if (v2) atomicAdd(&sh.tally[T_ABS + s * 2 + 1], v2);
     }
-    // this workgroup's share of the beam: in proportion to its ion tiles
-    const long long kb0 = s == 1 ? c.beam_n * ls / ti : 0, kb1 = s == 1 ? c.beam_n * le / ti : 0;
-    flush_seg<P, AC>(p, c, st, g, s, sel, kb0, kb1, sh);
+    flush_seg<P, AC>(p, c, st, g, s, sel, sh);
     t += seg_end - lt;
   }
 }
