@@ -350,6 +350,136 @@ def run_mlp(args, copy_gbs):
     print(json.dumps(out), flush=True)
 
 
+# ---------------------------------------------------------------------------
+# the binary64 gap: 256 cells, 1e5 particles, series RC driven at 1 MHz
+# ---------------------------------------------------------------------------
+FP64_WORKLOAD = "rc_gap_256c_1e5p_strict_fp64"
+
+
+def run_fp64(args, copy_gbs):
+    import torch
+    import oracle
+    from paper_2603_24010_amd import gapsim, workloads as W
+    cfg = W.config1()
+    loads = W.load_config1(n_per_species=50_000, seed=0)
+    sim = gapsim.GapSim(cfg, particle_fp=64, capacity=(200_000, 200_000))
+    for sp, (x, v) in loads.items():
+        sim.inject(0, sp, x, v)
+    sim.set_option(gapsim.OPT_GRAPH, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step_strict(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    d = sim.diag(0)
+    tm, kp = eager_kernel_pass(sim, lambda n: sim.step_strict(n), 64)
+    sim.close()
+    push_s = tm["push_ms"] * 1e-3
+    achieved = 32 * kp / push_s / 1e9 if push_s > 0 else None
+    out = {
+        "metric": "particle-steps/s", "value": d["pushed_cum"] / el, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 0, "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": FP64_WORKLOAD, "cells": cfg.n_cells, "particles": 100_000, "coupling": "strict"},
+        "timed_with": "hip graphs",
+        "roofline": {"bound": "latency", "kernel": "k_push", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": None,
+                     "bytes_per_particle_step": 32, "avg_launch_ms": tm["push_ms"] / max(1, tm["push_launches"]),
+                     "copy_GBps": copy_gbs,
+                     "note": "1e5 particles move 3.2 MB per step: launch and latency bound, a parity configuration"},
+        "kernel_ms_per_step": {k[:-3]: tm[k] / 64 for k in ("push_ms", "field_ms", "compact_ms")},
+    }
+    if not args.no_cpu_baseline:
+        s = oracle.OracleSim(cfg, fp32=False)
+        for sp, (x, v) in loads.items():
+            s.inject(sp, x, v)
+        t0 = time.perf_counter()
+        s.step(oracle.STRICT, args.steps)
+        elc = time.perf_counter() - t0
+        pc = s.diag()["pushed_cum"]
+        out["cpu_baseline"] = {"value": pc / elc, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the whole run: {args.steps} strict steps, binary64, {pc} particle-steps "
+                                         f"in {elc:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# strict and weak coupling on the same large gap: the divergence between them
+# ---------------------------------------------------------------------------
+DIVERGENCE = "strict_vs_weak_16384c_2e8p"
+
+
+def run_divergence(args, copy_gbs):
+    import torch
+    from paper_2603_24010_amd import gapsim, workloads as W
+    n0, every = args.div_particles, 10
+    cfg = W.config3(beam_per_step=20000)
+    log(f"[bench] loading {n0} particles (Gaussian at 0.9 d, sigma 0.05 d)")
+    loads = W.load_config3(n=n0, seed=3, d=cfg.d)
+    grow = (args.steps + 64) * cfg.beam_per_step
+    # the load sits 0.1 d from the grounded electrode: nearly every ion reaches
+    # it within a few hundred steps, each freeing about a / 2 electrons
+    cap = (int(0.55 * (n0 + grow)) + (1 << 22), n0 + grow + (1 << 20))
+    sims = []
+    for mode in (0, 1):
+        s = gapsim.GapSim(cfg, particle_fp=32, capacity=cap)
+        for sp, (x, v) in loads.items():
+            s.inject(0, sp, x, v)
+        sims.append(s)
+    del loads
+    rec = {0: [], 1: []}
+    el = {0: 0.0, 1: 0.0}
+    pushed = {0: 0, 1: 0}
+    done = 0
+    while done < args.steps:
+        k = min(every, args.steps - done)
+        for mode, s in enumerate(sims):
+            p0 = s.diag(0)["pushed_cum"]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(mode, k)
+            torch.cuda.synchronize()
+            el[mode] += time.perf_counter() - t0
+            d = s.diag(0)
+            pushed[mode] += d["pushed_cum"] - p0
+            rec[mode].append((d["step"], d["phi0"], d["sigma"]))
+        done += k
+        if done % 500 == 0:
+            log(f"[bench] {done} steps")
+    tm = {}
+    for mode, s in enumerate(sims):
+        t, _ = eager_kernel_pass(s, lambda n, s=s, m=mode: s.step(m, n), 32)
+        tm[mode] = t["push_ms"] / max(1, t["push_launches"])
+    live = [int(s.diag(0)["n_live"].sum()) for s in sims]
+    for s in sims:
+        s.close()
+    S, Wk = np.array(rec[0]), np.array(rec[1])
+    dv = np.abs(S[:, 1] - Wk[:, 1])
+    ds = np.abs(S[:, 2] - Wk[:, 2])
+    vscale, sscale = np.abs(S[:, 1]).max(), np.abs(S[:, 2]).max()
+    out = {
+        "metric": "strict-weak divergence of gap voltage and surface charge; particle-steps/s",
+        "value": (pushed[0] + pushed[1]) / (el[0] + el[1]), "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 0, "ms_per_step": (el[0] + el[1]) * 1e3 / (2 * args.steps),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": DIVERGENCE, "cells": cfg.n_cells, "initial_particles": n0,
+                   "beam_per_step": cfg.beam_per_step, "live_particles_end": live},
+        "strict": {"particle_steps_per_s": pushed[0] / el[0], "push_ms": tm[0]},
+        "weak": {"particle_steps_per_s": pushed[1] / el[1], "push_ms": tm[1]},
+        "divergence": {
+            "sampled_every": every,
+            "max_abs_dV": float(dv.max()), "max_rel_dV": float(dv.max() / vscale),
+            "final_abs_dV": float(dv[-1]), "max_abs_dsigma": float(ds.max()),
+            "max_rel_dsigma": float(ds.max() / sscale), "V_scale": float(vscale),
+            "curve": [[int(S[i, 0]), float(S[i, 1]), float(Wk[i, 1]), float(S[i, 2]), float(Wk[i, 2])]
+                      for i in range(0, len(S), max(1, len(S) // 40))],
+        },
+        "roofline": {"bound": "hbm", "kernel": "k_push", "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "achieved": None, "frac": None, "traffic": None, "copy_GBps": copy_gbs},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline_batched(spec, steps):
     import oracle
     from paper_2603_24010_amd import workloads as W
@@ -397,7 +527,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="beam_gap_4096c_2e7p_weak",
-                    choices=sorted(WORKLOADS) + sorted(BATCHED) + [MLP_WORKLOAD])
+                    choices=sorted(WORKLOADS) + sorted(BATCHED) + [MLP_WORKLOAD, DIVERGENCE, FP64_WORKLOAD])
+    ap.add_argument("--div-particles", type=int, default=200_000_000)
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compact-every", type=int, default=32)
@@ -461,6 +592,10 @@ def main():
         return run_batched(args, args.workload, copy_gbs)
     if args.workload == MLP_WORKLOAD:
         return run_mlp(args, copy_gbs)
+    if args.workload == DIVERGENCE:
+        return run_divergence(args, copy_gbs)
+    if args.workload == FP64_WORKLOAD:
+        return run_fp64(args, copy_gbs)
     spec = WORKLOADS[args.workload]
     log(f"[bench] building workload {args.workload}")
     sim, cfg, _ = make_sim(args.workload, spec, args.warmup + args.steps)
