@@ -886,28 +886,46 @@ __device__ void flush_seg(const DevPtrs &p, const GapConst &c, const GapState &s
   __syncthreads();
 }
 
-// Stage the gap's field table (16-byte aligned, N + 2 entries) in LDS with
-// 16-byte loads, four in flight per thread, and clear the accumulator.
+// Stage one (gap, species) segment: clear the node accumulator and the
+// tallies, inject this workgroup's share of the beam, and copy the gap's field
+// table (16-byte aligned, N + 2 entries) into LDS with 16-byte loads, the
+// first TQ per thread issued before anything else.
 template <class P, class AC>
-__device__ void load_seg(const DevPtrs &p, const GapConst &c, PushShared<P, AC> &sh) {
-  typedef typename Vec<P>::type V;
-  constexpr int VN = Vec<P>::n;
+__device__ void load_seg(const DevPtrs &p, const GapConst &c, const GapState &st, int g, int sel,
+                         PushShared<P, AC> &sh, long long kb0, long long kb1) {
+  // the table moves as 16-byte vectors of a native vector type (arrays of it
+  // stay in registers)
+  typedef unsigned int V __attribute__((ext_vector_type(4)));
+  constexpr int TQ = 5;  // table vectors per thread whose loads go out first
   const V *geh = (const V *)((const P *)p.ehat + c.ebase);
   V *leh = (V *)sh.eh;
-  const int nv = (c.N + 2 + VN - 1) / VN;
+  const int nv = (int)(((size_t)(c.N + 2) * sizeof(P) + 15) / 16);
   const int bs = blockDim.x;
-  for (int j0 = threadIdx.x; j0 < nv; j0 += 4 * bs) {
-    V t[4];
+  const int tid = threadIdx.x;
+  // loads past the table repeat its last vector
+  V t[TQ];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (j0 + q * bs < nv) t[q] = geh[j0 + q * bs];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (j0 + q * bs < nv) leh[j0 + q * bs] = t[q];
+  for (int q = 0; q < TQ; ++q) t[q] = geh[min(tid + q * bs, nv - 1)];
+  for (int j = tid; j <= c.N; j += bs) sh.acc[j] = 0;
+  if (tid < T_N) sh.tally[tid] = 0u;
+  if (tid == 0) *sh.evq_n = 0u;
+  // the beam goes in while the table's loads are in flight (the beam's slots
+  // lie past the swept range; its charge only has to reach the next density)
+  if (kb1 > kb0) {
+    __syncthreads();
+    beam_inject<P, AC>(p, c, st, g, sel, kb0, kb1, sh.acc, &sh.tally[T_INJ]);
   }
-  for (int j = threadIdx.x; j <= c.N; j += blockDim.x) sh.acc[j] = 0;
-  if (threadIdx.x < T_N) sh.tally[threadIdx.x] = 0u;
-  if (threadIdx.x == 0) *sh.evq_n = 0u;
+#pragma unroll
+  for (int q = 0; q < TQ; ++q)
+    if (tid + q * bs < nv) leh[tid + q * bs] = t[q];
+  for (int j0 = tid + TQ * bs; j0 < nv; j0 += 4 * bs) {
+    V r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = geh[min(j0 + q * bs, nv - 1)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (j0 + q * bs < nv) leh[j0 + q * bs] = r[q];
+  }
   __syncthreads();
 }
 
@@ -1075,12 +1093,9 @@ __device__ void push_range(const DevPtrs &p, const GapConst &gc, const GapState 
   const long long zhi = (long long)gc.Z[s] * 4294967296ll;
   const long long nfull = (b - a) / CH;
   V xa[NV], ua[NV], xb[NV], ub[NV];
-  // the first chunk's loads are in flight while the field table is staged and
-  // this workgroup's share of the beam is injected (the beam's slots lie past
-  // the swept range; its charge only has to reach the next density)
+  // the first chunk's loads are in flight while the segment is staged
   if (nfull > 0) load_chunk<P, BS, PPT>(X, U, a, xa, ua);
-  load_seg<P, AC>(p, gc, sh);
-  if (kb1 > kb0) beam_inject<P, AC>(p, gc, st, g, sel, kb0, kb1, sh.acc, &sh.tally[T_INJ]);
+  load_seg<P, AC>(p, gc, st, g, sel, sh, kb0, kb1);
   // one copy of the chunk body (the kernel's instruction footprint is what
   // limits it): the next chunk's loads go out before this chunk is pushed,
   // and the buffers are swapped by register moves
