@@ -968,19 +968,18 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
   const int vper = ctx->fp64 ? 2 : 4;
   gs_status r = GS_OK;
   // launch shape first, at the current compaction interval
-  const int grid_def = lc0.grid > 0 ? lc0.grid : ctx->ncu;
   for (int block : {256, 512, 768})
     for (int ppt : {1, 2})
       for (int tmul : {8, 32})
-        for (int gmul2 : {1, 2, 4}) {  // grid = default * gmul2 / 2
+        for (int per_cu : {1, 2, 3, 4, 8}) {  // 256-thread workgroups per CU
           gs_tuning t{};
           t.block = block;
           t.ppt = ppt;
           t.tile = block * tmul;
           if (t.tile % (block * ppt * vper)) continue;
           t.deposit = dep0;
-          // the default grid is sized for 256-thread blocks; keep threads per CU
-          t.grid = std::max(1, grid_def * gmul2 / 2 * 256 / block);
+          // the same threads per CU at other block sizes
+          t.grid = std::max(1, ctx->ncu * per_cu * 256 / block);
           t.compact_every = ce0;
           double ms = 0;
           if ((r = trial(t, trial_steps, &ms)) != GS_OK) break;
