@@ -204,7 +204,7 @@ def run_batched(args, name, copy_gbs):
         "kernel_ms_per_step": {k[:-3]: tm[k] / 64 for k in ("push_ms", "field_ms", "compact_ms")},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_batched(spec, 5 * args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline_batched(spec, 4 * args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 
@@ -483,7 +483,7 @@ def run_divergence(args, copy_gbs):
 def cpu_baseline_batched(spec, steps):
     import oracle
     from paper_2603_24010_amd import workloads as W
-    gaps = 8
+    gaps = 16
     pushed, el = 0, 0.0
     for g in range(spec["seed0"], spec["seed0"] + gaps):
         cfg, n_p, e_b = W.config4_gap(g, n_cells=spec["cells"])
@@ -529,7 +529,7 @@ def main():
     ap.add_argument("--workload", default="beam_gap_4096c_2e7p_weak",
                     choices=sorted(WORKLOADS) + sorted(BATCHED) + [MLP_WORKLOAD, DIVERGENCE, FP64_WORKLOAD])
     ap.add_argument("--div-particles", type=int, default=200_000_000)
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compact-every", type=int, default=32)
     ap.add_argument("--block", type=int, default=0)
