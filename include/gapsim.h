@@ -14,7 +14,8 @@
  *   2. gather from the half-grid field and leapfrog push (Sec. 2.2.2, App. C);
  *   3. absorption at either electrode, convection charge (Sec. 2.4.1) and
  *      ion-induced secondary emission (Sec. 2.3, Alg. 2);
- *   4. optional ion beam entering at the circuit electrode;
+ *   4. optional ion beam entering at either electrode, by a fixed count or a
+ *      per-step schedule (Sec. 4.2);
  *   5. charge deposit with the same linear weights, electrode nodes doubled
  *      (App. C, App. E).
  *
@@ -53,6 +54,8 @@ typedef enum {
 } gs_status;
 
 enum { GS_SEE_FIXED = 0, GS_SEE_EXP = 1 };
+/* electrode the beam enters at */
+enum { GS_BEAM_CIRCUIT = 0, GS_BEAM_GROUND = 1 };
 enum { GS_GUESS_DIRECT = 0, GS_GUESS_EXTRAP = 1, GS_GUESS_MLP = 2 };
 
 /* Device memory hook.  alloc(bytes, user) returns device memory or NULL;
@@ -77,8 +80,17 @@ typedef struct {
  *   see_max, gamma(E) = see_amp (E/see_E0_eV) / (1 + E/see_E0_eV), E the ion's
  *   normal kinetic energy; each leaves the surface normally with energy see_E_eV
  *   (GS_SEE_FIXED) or an exponential draw of mean see_E_eV (GS_SEE_EXP).
- *   Beam: beam_per_step ions per step enter at the circuit electrode with
- *   energies uniform in [beam_Emin_eV, beam_Emax_eV].
+ *   Beam: ions enter at the circuit electrode (beam_side GS_BEAM_CIRCUIT, node 0,
+ *   moving towards the ground) or at the grounded one (GS_BEAM_GROUND, node N,
+ *   moving towards the circuit electrode), with energies uniform in
+ *   [beam_Emin_eV, beam_Emax_eV].  They start uniformly within beam_layer [m]
+ *   of that electrode, or, with beam_layer 0, within the distance they fly in
+ *   one step (as if they entered during the step).  The paper injects its ions
+ *   in a layer next to the grounded electrode with a Gaussian pulse in time
+ *   (Sec. 4.2); a pulse is given as a schedule: with beam_schedule non-NULL the
+ *   step that solves level n injects beam_schedule[n] ions (n <
+ *   beam_schedule_len, none after), else beam_per_step every step.  The
+ *   schedule is copied by gs_init; the caller keeps its array.
  *   particle_fp: 32 (binary32 particles, 2^-24 fixed-point deposit weights) or
  *   64 (binary64 particles, 2^-44 weights); the same for every gap of a context.
  *   capacity[s]: particle slots of species s (live plus not-yet-reclaimed). */
@@ -101,6 +113,10 @@ typedef struct {
   double see_E_eV;
   int64_t beam_per_step;
   double beam_Emin_eV, beam_Emax_eV;
+  int32_t beam_side;
+  double beam_layer;
+  const int64_t *beam_schedule; /* nullable, see above */
+  int64_t beam_schedule_len;
   uint64_t seed;
   int32_t particle_fp;
   int64_t capacity[2];
@@ -217,7 +233,12 @@ gs_status gs_step_weak(gs_ctx *ctx, int32_t n_steps);
  * caller's host arrays when not NULL.  Errors: GS_EINVAL, GS_EDEVICE; the sticky
  * errors of the steps (GS_ECAPACITY, GS_EINVAL for a bad device-side injection);
  * GS_ENOCONV once after a strict Newton solve missed its tolerance (the outputs
- * are filled and the state stays valid: the last iterate was used). */
+ * are filled and the state stays valid: the last iterate was used).
+ * Emission timing: the secondaries of the ions absorbed in a step are emitted
+ * within that step, except when one push workgroup absorbs more than 1152 ions
+ * in a step; the excess is emitted at the start of the next step, before any
+ * particle moves (the physics is the same), so the emitted counts and the
+ * electron population read in between lag by those electrons. */
 gs_status gs_read_diagnostics(gs_ctx *ctx, int32_t gap, gs_diag *out, double *phi, double *E,
                               double *rho);
 

@@ -155,6 +155,7 @@ struct or_sim {
   /* binary32 copies used by the push in fp32 mode: Ehat[0..N+1] */
   float *ehat;
   float alpha32[2];       /* q dt^2 / (m dx) in binary32 */
+  int64_t *sched;         /* own copy of the beam schedule (p.beam_schedule points here) */
   or_diag diag;
 };
 
@@ -198,6 +199,16 @@ or_sim *or_create(const or_params *p) {
   or_sim *s = (or_sim *)calloc(1, sizeof(or_sim));
   if (!s) return NULL;
   s->p = *p;
+  if (p->beam_schedule) {
+    size_t n = p->beam_schedule_len > 0 ? (size_t)p->beam_schedule_len : 1;
+    s->sched = (int64_t *)calloc(n, sizeof(int64_t));
+    if (!s->sched) {
+      free(s);
+      return NULL;
+    }
+    for (int64_t i = 0; i < p->beam_schedule_len; ++i) s->sched[i] = p->beam_schedule[i];
+    s->p.beam_schedule = s->sched;
+  }
   s->N = p->n_cells;
   s->dx = p->d / (double)p->n_cells;
   s->rho = (double *)calloc((size_t)s->N + 1, sizeof(double));
@@ -220,6 +231,7 @@ void or_destroy(or_sim *s) {
   if (!s) return;
   free(s->x); free(s->v); free(s->xf); free(s->uf); free(s->sp); free(s->id);
   free(s->rho); free(s->phi); free(s->E); free(s->ehat);
+  free(s->sched);
   free(s);
 }
 
@@ -692,8 +704,11 @@ int32_t or_step(or_sim *s, int32_t mode) {
   free(hit_v);
   free(hit_wall);
 
-  /* ion beam entering at the circuit electrode */
+  /* ion beam: the step's count, then each ion's energy and depth below its
+   * entry electrode from its own random block */
   int64_t n_inj = p->beam_per_step;
+  if (p->beam_schedule)
+    n_inj = (s->step < p->beam_schedule_len) ? p->beam_schedule[s->step] : 0;
   if (n_inj > 0) {
     if (grow(s, s->n + n_inj)) return -2;
     for (int64_t k = 0; k < n_inj; ++k) {
@@ -701,10 +716,13 @@ int32_t or_step(or_sim *s, int32_t mode) {
       draw_block(p->seed, (uint64_t)s->step, (uint64_t)k, 2, 0, blk);
       double E = p->beam_Emin_eV + (p->beam_Emax_eV - p->beam_Emin_eV) * unit_open(blk[0]);
       double v = sqrt(2.0 * E * p->ev / p->mass[1]);
-      double x = unit_open(blk[1]) * v * dt;
+      double depth = unit_open(blk[1]) * (p->beam_layer > 0.0 ? p->beam_layer : v * dt);
+      double x = (p->beam_side == 1) ? p->d - depth : depth;
       float xi = (float)(x / dx);
-      float u = (float)((v * dt) / dx);
-      append(s, 1, x, v, xi, u, s->next_id);
+      double uv = (v * dt) / dx;
+      float u = (float)((p->beam_side == 1) ? -uv : uv);
+      double vs = (p->beam_side == 1) ? -v : v;
+      append(s, 1, x, vs, xi, u, s->next_id);
       s->next_id += 1;
     }
   }

@@ -61,9 +61,19 @@ typedef struct {
   double see_amp, see_E0_eV;
   int32_t see_law, see_max;
   double see_E_eV;
-  /* ion beam entering at the circuit electrode, energies uniform */
+  /* ion beam, energies uniform in [beam_Emin_eV, beam_Emax_eV], entering at
+   * the circuit electrode (beam_side 0, moving towards the ground) or at the
+   * grounded one (beam_side 1, moving towards the circuit electrode), started
+   * uniformly within beam_layer [m] of it (0: within one step's flight).  The
+   * ions per step are beam_schedule[n] for the step that solves level n (n <
+   * beam_schedule_len, none after) when beam_schedule is non-NULL, else
+   * beam_per_step.  The schedule is copied by or_create. */
   int64_t beam_per_step;
   double beam_Emin_eV, beam_Emax_eV;
+  int32_t beam_side;
+  double beam_layer;
+  const int64_t *beam_schedule;
+  int64_t beam_schedule_len;
   uint64_t seed;
   int32_t fp32;
 } or_params;

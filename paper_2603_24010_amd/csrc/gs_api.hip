@@ -43,6 +43,8 @@ struct gs_ctx {
   int64_t steps_done = 0;
   int64_t epoch = 0;
   std::vector<int64_t> next_id;
+  std::vector<std::vector<int64_t>> sched;  // per gap: copy of the beam schedule (empty: none)
+  std::vector<int> sched_on;                // per gap: the schedule is in force
   std::string err;
   int sticky = 0;  // gs_status of a device error already seen
   // timing
@@ -175,7 +177,24 @@ extern "C" gs_status gs_validate_params(const gs_gap_params *p, char *msg, size_
   if (p->see_max < 0 || p->see_max > 1024) return bad("see_max must be in 0..1024");
   if (!std::isfinite(p->see_E_eV) || p->see_E_eV < 0) return bad("see_E_eV must be >= 0");
   if (p->beam_per_step < 0 || p->beam_per_step > (int64_t)1 << 30) return bad("beam_per_step out of range");
-  if (p->beam_per_step > 0 &&
+  if (p->beam_side != GS_BEAM_CIRCUIT && p->beam_side != GS_BEAM_GROUND)
+    return bad("beam_side must be GS_BEAM_CIRCUIT or GS_BEAM_GROUND");
+  if (!std::isfinite(p->beam_layer) || p->beam_layer < 0 || !(p->beam_layer < p->d))
+    return bad("beam_layer must be in [0, d)");
+  bool any_beam = p->beam_per_step > 0;
+  if (p->beam_schedule) {
+    if (p->beam_schedule_len < 0 || p->beam_schedule_len > ((int64_t)1 << 26))
+      return bad("beam_schedule_len out of range (0..2^26)");
+    any_beam = false;
+    for (int64_t i = 0; i < p->beam_schedule_len; ++i) {
+      if (p->beam_schedule[i] < 0 || p->beam_schedule[i] > (int64_t)1 << 30)
+        return bad("beam_schedule entries must be in 0..2^30");
+      any_beam = any_beam || p->beam_schedule[i] > 0;
+    }
+  } else if (p->beam_schedule_len != 0) {
+    return bad("beam_schedule is NULL but beam_schedule_len is not 0");
+  }
+  if (any_beam &&
       (!finite_pos(p->beam_Emin_eV) || !std::isfinite(p->beam_Emax_eV) || p->beam_Emax_eV < p->beam_Emin_eV))
     return bad("beam energies must satisfy 0 < Emin <= Emax");
   if (!finite_pos(p->v_ref)) return bad("v_ref must be positive");
@@ -195,7 +214,10 @@ static gs_status build_const(gs_ctx *ctx, int g, const gs_gap_params &p, GapCons
   c.see_max = p.see_max;
   c.Z[0] = p.Z[0];
   c.Z[1] = p.Z[1];
-  c.beam_n = p.beam_per_step;
+  // with a schedule the per-step count is ignored (levels past it inject none)
+  c.beam_n = p.beam_schedule ? 0 : p.beam_per_step;
+  c.beam_side = p.beam_side;
+  c.beam_layer = p.beam_layer;
   c.cap[0] = p.capacity[0];
   c.cap[1] = p.capacity[1];
   c.seed = p.seed;
@@ -309,7 +331,7 @@ static void choose_launch(gs_ctx *ctx);
 static gs_status setup(gs_ctx *ctx) {
   const int G = ctx->G;
   ctx->hc.resize(G);
-  size_t slots = 0, nodes = 0, etab = 0, events = 0;
+  size_t slots = 0, nodes = 0, etab = 0, events = 0, nsched = 0;
   ctx->nmax = 0;
   for (int g = 0; g < G; ++g) {
     gs_status st = build_const(ctx, g, ctx->params[g], ctx->hc[g]);
@@ -332,6 +354,9 @@ static gs_status setup(gs_ctx *ctx) {
     // 16-byte loads)
     c.ebase = (int64_t)etab;
     etab += ((size_t)c.N + 2 + 3) / 4 * 4;
+    c.sched_base = (int64_t)nsched;
+    c.sched_len = (int64_t)ctx->sched[g].size();
+    nsched += ctx->sched[g].size();
     ctx->nmax = std::max(ctx->nmax, c.N);
   }
   const size_t ps = ctx->fp64 ? 8 : 4;
@@ -357,6 +382,20 @@ static gs_status setup(gs_ctx *ctx) {
   ALLOC(d.ehat, void *, etab * ps);
   ALLOC(d.ev, Event *, events * sizeof(Event));
   ALLOC(d.ev_count, unsigned long long *, (size_t)G * 8);
+  int64_t *sched_d = nullptr;
+  ALLOC(sched_d, int64_t *, std::max<size_t>(nsched, 1) * 8);
+  d.sched = sched_d;
+  // overflow event regions for up to eight 256-thread push workgroups per CU
+  // (the largest grid the autotuner tries), when any gap emits
+  bool emits = false;
+  for (int g = 0; g < G; ++g) emits = emits || ctx->params[g].see_amp > 0.0;
+  {
+    int dev = 0, ncu = 0;
+    HIPCHK(ctx, hipGetDevice(&dev));
+    HIPCHK(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    d.ovf_wgs = emits ? (int64_t)8 * std::max(ncu, 1) : 0;
+  }
+  ALLOC(d.ovf, Event *, (size_t)std::max<int64_t>(d.ovf_wgs, 1) * OVQ * sizeof(Event));
   ALLOC(d.epoch, int64_t *, 8);
   ALLOC(d.err, unsigned int *, 8);
   ALLOC(d.gc, const GapConst *, sizeof(GapConst) * (size_t)G);
@@ -375,6 +414,10 @@ static gs_status setup(gs_ctx *ctx) {
   HIPCHK(ctx, hipMemsetAsync(d.cursor, 0, (size_t)G * 2 * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.tally, 0, (size_t)G * T_N * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.ev_count, 0, (size_t)G * 8, s));
+  for (int g = 0; g < G; ++g)
+    if (!ctx->sched[g].empty())
+      HIPCHK(ctx, hipMemcpyAsync(sched_d + ctx->hc[g].sched_base, ctx->sched[g].data(), ctx->sched[g].size() * 8,
+                                 hipMemcpyHostToDevice, s));
   HIPCHK(ctx, hipMemsetAsync(d.acc, 0, nodes * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.rho64, 0, nodes * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.E64, 0, nodes * 8, s));
@@ -441,6 +484,17 @@ extern "C" gs_status gs_init(gs_ctx **out, int32_t n_gaps, const gs_gap_params *
   ctx->G = n_gaps;
   ctx->fp64 = params[0].particle_fp == 64;
   ctx->params.assign(params, params + n_gaps);
+  // the schedules are copied; the caller keeps its arrays
+  ctx->sched.assign(n_gaps, std::vector<int64_t>());
+  ctx->sched_on.assign(n_gaps, 0);
+  for (int g = 0; g < n_gaps; ++g) {
+    if (params[g].beam_schedule) {
+      ctx->sched_on[g] = 1;
+      ctx->sched[g].assign(params[g].beam_schedule, params[g].beam_schedule + params[g].beam_schedule_len);
+    }
+    ctx->params[g].beam_schedule = nullptr;
+    ctx->params[g].beam_schedule_len = 0;
+  }
   ctx->stream = (hipStream_t)hip_stream;
   if (alloc) ctx->alloc = *alloc;
   int nm = 0;
@@ -557,6 +611,14 @@ static hipError_t timed(gs_ctx *ctx, int kind, F &&launch) {
   return e;
 }
 
+// beam ions of the step that solves level n (the host's copy of what the
+// field kernel hands the push)
+static int64_t beam_at(const gs_ctx *ctx, int g, int64_t n) {
+  if (!ctx->sched_on[g]) return ctx->params[g].beam_per_step;
+  const std::vector<int64_t> &s = ctx->sched[g];
+  return n >= 0 && n < (int64_t)s.size() ? s[(size_t)n] : 0;
+}
+
 static gs_status one_step(gs_ctx *ctx, int mode, int guess) {
   hipError_t e = timed(ctx, 1, [&](KTime t) {
     return launch_field(ctx->dp, ctx->G, mode, guess, ctx->newton_tol, ctx->newton_maxit, ctx->fp64,
@@ -573,7 +635,7 @@ static gs_status one_step(gs_ctx *ctx, int mode, int guess) {
     ctx->epoch += 1;
   }
   ctx->steps_done += 1;
-  for (int g = 0; g < ctx->G; ++g) ctx->next_id[g] += ctx->params[g].beam_per_step;
+  for (int g = 0; g < ctx->G; ++g) ctx->next_id[g] += beam_at(ctx, g, ctx->steps_done - 1);
   return GS_OK;
 }
 
@@ -623,7 +685,8 @@ static gs_status run_steps(gs_ctx *ctx, int n_steps, int mode, int guess) {
       left -= L;
       ctx->steps_done += L;
       ctx->epoch += 1;
-      for (int g = 0; g < ctx->G; ++g) ctx->next_id[g] += (int64_t)L * ctx->params[g].beam_per_step;
+      for (int g = 0; g < ctx->G; ++g)
+        for (int64_t n = ctx->steps_done - L; n < ctx->steps_done; ++n) ctx->next_id[g] += beam_at(ctx, g, n);
     }
   }
   while (left > 0) {

@@ -28,8 +28,9 @@ struct GapConst {
   int32_t M, g;       // meshes, gap mesh
   int32_t see_law, see_max;
   int32_t Z[2];
-  int32_t pad0;
-  int64_t beam_n;
+  int32_t beam_side;  // GS_BEAM_CIRCUIT or GS_BEAM_GROUND
+  int64_t beam_n;     // ions per step without a schedule
+  int64_t sched_base, sched_len;  // the gap's beam schedule in DevPtrs::sched (len 0: none)
   int64_t cap[2];
   int64_t pbase[2];   // first particle slot of species s
   int64_t nbase;      // offset of the node arrays (N + 1 entries)
@@ -43,6 +44,7 @@ struct GapConst {
   double mass[2], ev;
   double see_amp, see_E0, see_E;
   double beam_Emin, beam_Emax;
+  double beam_layer;  // [m]; 0: one step of flight
   double v_ref;
   double src_dc, src_amp, src_w, src_phase;
   // strict: D = sL h + sR D1 - sS q1 + sb Vs - sz phi0     (h = 15 D1 - 7 D2 + D3)
@@ -64,6 +66,7 @@ struct GapState {
   int64_t live[2];      // live particles after the last push, per species
   int64_t next_id;      // next particle id
   int64_t beam_id0;     // id of beam particle 0 of the current push
+  int64_t beam_now;     // beam ions of the current push
   double qprev[MAXM];   // loop charges q^{n-1}
   double dq[3][MAXM];   // increments D^{n-1}, D^{n-2}, D^{n-3}
   double sigma_prev, qcirc_prev;
@@ -89,7 +92,9 @@ struct GapState {
 // An ion absorbed by an electrode, waiting for its secondary emission.
 struct Event {
   double u;       // impact velocity in cells per step
-  uint32_t slot;  // the ion's slot in its region (its id keys the random draws)
+  uint32_t ref;   // in a push workgroup's LDS queue: the ion's slot in its region;
+                  // in the gap's overflow list: the ion's id (a compaction may move
+                  // the slot before the field kernel emits).  The id keys the draws.
   uint32_t wall;
 };
 
@@ -110,6 +115,9 @@ struct DevPtrs {
   unsigned int *err;               // [0] flags, [1] gap of first error
   Event *ev;                       // absorbed-ion events, per-gap lists
   unsigned long long *ev_count;    // [G]
+  const int64_t *sched;            // beam schedules of all gaps (GapConst::sched_base)
+  Event *ovf;                      // push workgroup b < ovf_wgs: events past its LDS queue,
+  int64_t ovf_wgs;                 //   OVQ of them from ovf + b * OVQ
   // Newton guess network: bfloat16 weights (flat layout of gs_mlp_dev.h) and
   // the normalisation block; null until weights are set
   const uint16_t *mlp_w;
@@ -122,6 +130,10 @@ struct DevPtrs {
 };
 
 enum { ERR_CAPACITY = 1u, ERR_BADINJECT = 2u, ERR_NOCONV = 4u };
+
+// Absorbed-ion events a push workgroup keeps in its global overflow region
+// (past these they go to the gap's list, emitted by the next field solve).
+constexpr int OVQ = 1024;
 
 struct LaunchCfg {
   int block;         // push block size

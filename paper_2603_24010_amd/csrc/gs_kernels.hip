@@ -227,13 +227,13 @@ __device__ inline void see_write(const DevPtrs &p, const GapConst &c, long long 
   }
 }
 
-// Emission for ne events of gap g listed in evs, one event per thread and
-// pass, slots from one reservation per pass; emitted counts per wall added to
-// emit_cnt (LDS).  Every thread of the block calls it.
+// Emission for ne events of gap g listed in evs (each carrying its ion's id),
+// one event per thread and pass, slots in buffer sel from one reservation per
+// pass; emitted counts per wall added to emit_cnt (LDS).  Every thread of the
+// block calls it.
 template <class P>
 __device__ void see_emit(const DevPtrs &p, const GapConst &c, long long level, int g, int sel, const Event *evs,
                          int ne, int *wsum, unsigned long long *s_base, unsigned int *emit_cnt) {
-  const uint32_t *IDi = p.ID[sel] + c.pbase[1];
   for (int r = 0; r < ne; r += blockDim.x) {
     const int k = r + threadIdx.x;
     int nk = 0, wall = 0;
@@ -241,7 +241,7 @@ __device__ void see_emit(const DevPtrs &p, const GapConst &c, long long level, i
     uint64_t blk[4] = {0, 0, 0, 0};
     if (k < ne) {
       const Event ev = evs[k];
-      ion_id = IDi[ev.slot];
+      ion_id = ev.ref;
       wall = (int)ev.wall;
       nk = see_count(c, level, ion_id, ev.u, blk);
     }
@@ -486,10 +486,14 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
   // (append counters can run past the capacity after an overflow, which was
   // flagged when it happened; never sweep past the region)
   for (int s = 0; s < 2; ++s) st.count[s] = min((long long)p.next_count[g * 2 + s], c.cap[s]);
-  p.next_count[g * 2 + 1] = (unsigned long long)(st.count[1] + c.beam_n);
+  // the beam of the step that solves level n: its schedule entry, else the
+  // fixed count
+  const long long nb = n < c.sched_len ? (long long)p.sched[c.sched_base + n] : c.beam_n;
+  st.beam_now = nb;
+  p.next_count[g * 2 + 1] = (unsigned long long)(st.count[1] + nb);
   p.ev_count[g] = 0ull;
   st.beam_id0 = st.next_id;
-  st.next_id += c.beam_n;
+  st.next_id += nb;
   *sigma_out = sigma;
 }
 
@@ -753,6 +757,8 @@ __device__ inline void acc_add<Carry32>(unsigned int *lds, unsigned long long *g
 }
 
 constexpr int EVQ = 128;  // absorbed-ion events a push workgroup queues in LDS
+// (more go to the workgroup's OVQ-event region of a global buffer; both are
+// emitted at the segment's flush, so a step's emission completes in its push)
 
 template <class P, class AC>
 struct PushShared {
@@ -794,9 +800,12 @@ __device__ void beam_inject(const DevPtrs &p, const GapConst &c, const GapState 
     rng_block(c.seed, (uint64_t)st.level, (uint64_t)k, 2, 0, blk);
     const double E = c.beam_Emin + (c.beam_Emax - c.beam_Emin) * unit_open(blk[0]);
     const double v = sqrt(2.0 * E * c.ev / c.mass[1]);
-    const double x = unit_open(blk[1]) * v * c.dt;
+    // depth below the entry electrode: within the layer, or within one step's flight
+    const double depth = unit_open(blk[1]) * (c.beam_layer > 0.0 ? c.beam_layer : v * c.dt);
+    const double x = c.beam_side == GS_BEAM_GROUND ? c.d - depth : depth;
     const P xi = (P)(x / c.dx);
-    const P u = (P)((v * c.dt) / c.dx);
+    const double uv = (v * c.dt) / c.dx;
+    const P u = (P)(c.beam_side == GS_BEAM_GROUND ? -uv : uv);
     const unsigned long long slot = (unsigned long long)st.count[1] + (unsigned long long)k;
     if (slot >= (unsigned long long)c.cap[1]) {
       atomicOr(&p.err[0], ERR_CAPACITY);
@@ -819,69 +828,97 @@ __device__ void beam_inject(const DevPtrs &p, const GapConst &c, const GapState 
   if ((threadIdx.x & 63) == 0 && a) atomicAdd(n_inj, a);
 }
 
-// Close one (gap, species) segment: for the ion segment emit the secondary
-// electrons of the ions this workgroup absorbed (at most EVQ <= blockDim, one
-// per thread), then hand the node sums times the charge number, the emitted
-// electrons' wall charge and the tallies to the gap.  The electrons' slot
-// reservation is in flight while the node sums are flushed.
+// Emission for the events [r0, r0 + blockDim) of a segment's queue (the LDS
+// queue, then the workgroup's overflow region): one per thread, counts drawn,
+// one slot reservation for the electrons, which are written; returns the
+// reservation's total.  The first round also flushes the node sums while its
+// reservation is in flight.
 template <class P, class AC>
-__device__ void flush_seg(const DevPtrs &p, const GapConst &c, const GapState &st, int g, int s, int sel,
-                          PushShared<P, AC> &sh) {
-  __shared__ unsigned long long s_base;
-  __syncthreads();
-  unsigned long long *gacc = p.acc + c.nbase;
-  const int nq = s == 1 ? (int)min(*sh.evq_n, (unsigned int)EVQ) : 0;
+__device__ inline int emit_round(const DevPtrs &p, const GapConst &c, const GapState &st, int g, int s, int sel,
+                                 PushShared<P, AC> &sh, const Event *ovf, int ne, int r0,
+                                 unsigned long long *s_base) {
+  const int i = r0 + (int)threadIdx.x;
   uint32_t ion_id = 0;
   int wall = 0, nk = 0;
   double u_imp = 0.0;
-  if ((int)threadIdx.x < nq) {
-    const Event ev = sh.evq[threadIdx.x];
-    ion_id = p.ID[sel][c.pbase[1] + ev.slot];
+  if (i < ne) {
+    const Event ev = i < EVQ ? sh.evq[i] : ovf[i - EVQ];
+    ion_id = p.ID[sel][c.pbase[1] + ev.ref];
     wall = (int)ev.wall;
     u_imp = ev.u;
   }
   uint64_t blk[4] = {0, 0, 0, 0};
-  if ((int)threadIdx.x < nq) nk = see_count(c, st.level, ion_id, u_imp, blk);
+  if (i < ne) nk = see_count(c, st.level, ion_id, u_imp, blk);
   int btot = 0, excl = 0;
-  if (nq > 0)
+  if (r0 < ne)
     excl = block_exclusive_scan_i(nk, sh.wsum, &btot);
   else
-    __syncthreads();  // the beam's deposits are in before the node sums go out
+    __syncthreads();
   unsigned long long base = 0;
   if (threadIdx.x == 0 && btot > 0) base = atomicAdd(&p.next_count[g * 2 + 0], (unsigned long long)btot);
-  // node sums; each workgroup starts at its own node so that the workgroups
-  // flushing at the same time add to different addresses
-  const long long Z = (long long)c.Z[s];
-  const int nn = c.N + 1;
-  const int rot = (int)(((long long)blockIdx.x * 977) % nn);
-  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
-    int j = i + rot;
-    j = j >= nn ? j - nn : j;
-    const unsigned long long v = (unsigned long long)sh.acc[j];
-    if (v != 0ull) atomicAdd(&gacc[j], (unsigned long long)(Z * (long long)v));
+  if (r0 == 0) {
+    // node sums; each workgroup starts at its own node so that the workgroups
+    // flushing at the same time add to different addresses
+    unsigned long long *gacc = p.acc + c.nbase;
+    const long long Z = (long long)c.Z[s];
+    const int nn = c.N + 1;
+    const int rot = (int)(((long long)blockIdx.x * 977) % nn);
+    for (int q = threadIdx.x; q < nn; q += blockDim.x) {
+      int j = q + rot;
+      j = j >= nn ? j - nn : j;
+      const unsigned long long v = (unsigned long long)sh.acc[j];
+      if (v != 0ull) atomicAdd(&gacc[j], (unsigned long long)(Z * (long long)v));
+    }
   }
   if (btot > 0) {
-    if (threadIdx.x == 0) s_base = base;
+    if (threadIdx.x == 0) *s_base = base;
     __syncthreads();
     unsigned int n[2] = {0u, 0u};
-    if (nk > 0) see_write<P>(p, c, st.level, g, sel, ion_id, wall, nk, blk, s_base + (unsigned long long)excl, n);
+    if (nk > 0) see_write<P>(p, c, st.level, g, sel, ion_id, wall, nk, blk, *s_base + (unsigned long long)excl, n);
     const unsigned int a0 = wave_sum(n[0]), a1 = wave_sum(n[1]);
     if ((threadIdx.x & 63) == 0) {
       if (a0) atomicAdd(&sh.tally[T_EMIT], a0);
       if (a1) atomicAdd(&sh.tally[T_EMIT + 1], a1);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      // an emitted electron carries its full weight on its wall node
-      const long long ze = (long long)c.Z[0] * Prec<P>::W;
-      const unsigned int e0 = sh.tally[T_EMIT], e1 = sh.tally[T_EMIT + 1];
-      if (e0) atomicAdd(&gacc[0], (unsigned long long)(ze * (long long)e0));
-      if (e1) atomicAdd(&gacc[c.N], (unsigned long long)(ze * (long long)e1));
-    }
   }
-  if (threadIdx.x < T_N) {
-    const unsigned int v = sh.tally[threadIdx.x];
-    if (v) atomicAdd(&p.tally[(size_t)g * T_N + threadIdx.x], (unsigned long long)v);
+  return btot;
+}
+
+// Close one (gap, species) segment: for the ion segment emit the secondary
+// electrons of the ions this workgroup absorbed, in rounds of one event per
+// thread (the first round also hands the node sums times the charge number to
+// the gap); then the emitted electrons' wall charge and the tallies.
+template <class P, class AC>
+__device__ void flush_seg(const DevPtrs &p, const GapConst &c, const GapState &st, int g, int s, int sel,
+                          PushShared<P, AC> &sh) {
+  __shared__ unsigned long long s_base;
+  __syncthreads();
+  const int ovq = (long long)blockIdx.x < p.ovf_wgs ? OVQ : 0;
+  const int ne = s == 1 ? (int)min(*sh.evq_n, (unsigned int)(EVQ + ovq)) : 0;
+  const Event *ovf = p.ovf + (size_t)blockIdx.x * OVQ;
+  // one inlined copy of the round (the kernel's instruction footprint matters)
+  int emitted = 0, r0 = 0;
+  do {
+    emitted += emit_round<P, AC>(p, c, st, g, s, sel, sh, ovf, ne, r0, &s_base);
+    r0 += blockDim.x;
+  } while (r0 < ne);
+  if (emitted > 0 && threadIdx.x == 0) {
+    // an emitted electron carries its full weight on its wall node
+    unsigned long long *gacc = p.acc + c.nbase;
+    const long long ze = (long long)c.Z[0] * Prec<P>::W;
+    const unsigned int e0 = sh.tally[T_EMIT], e1 = sh.tally[T_EMIT + 1];
+    if (e0) atomicAdd(&gacc[0], (unsigned long long)(ze * (long long)e0));
+    if (e1) atomicAdd(&gacc[c.N], (unsigned long long)(ze * (long long)e1));
+  }
+  // the tallies, one per thread; the empty asm keeps the compiler from
+  // computing the per-thread address once at the kernel's start and holding it
+  // (spilled) across the push
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  if (t < T_N) {
+    const unsigned int v = sh.tally[t];
+    if (v) atomicAdd(&p.tally[(size_t)g * T_N + t], (unsigned long long)v);
   }
   __syncthreads();
 }
@@ -941,6 +978,7 @@ struct SegK {
   int g;
   long long evbase, evcap;
   unsigned long long *gacc;
+  const uint32_t *ids;  // the region's particle ids (overflowing events carry the id)
 };
 
 // Push one chunk of BS * PPT slots starting at slot r0 (relative to the region
@@ -1035,14 +1073,17 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
       for (int q = 1; q < PPT; ++q)
         if (q == k) uk = u_hit[q];
       ev.u = (double)uk;
-      ev.slot = (uint32_t)(r0 + (long long)((k / VN) * BS + tid) * VN + k % VN);
+      ev.ref = (uint32_t)(r0 + (long long)((k / VN) * BS + tid) * VN + k % VN);
       ev.wall = (hit >> (k + 16)) & 1u;
       const unsigned int q = atomicAdd(sh.evq_n, 1u);
       if (q < (unsigned int)EVQ) {
         sh.evq[q] = ev;
+      } else if (q < (unsigned int)(EVQ + OVQ) && (long long)blockIdx.x < p.ovf_wgs) {
+        p.ovf[(size_t)blockIdx.x * OVQ + (q - EVQ)] = ev;
       } else {
         const unsigned long long e = atomicAdd(&p.ev_count[g], 1ull);
         if (e < (unsigned long long)c.evcap) {
+          ev.ref = c.ids[ev.ref];
           p.ev[c.evbase + e] = ev;
         } else {
           atomicOr(&p.err[0], ERR_CAPACITY);
@@ -1086,6 +1127,7 @@ __device__ void push_range(const DevPtrs &p, const GapConst &gc, const GapState 
   c.evbase = gc.evbase;
   c.evcap = gc.evcap;
   c.gacc = p.acc + gc.nbase;
+  c.ids = p.ID[sel] + gc.pbase[s];
   P *X = (P *)p.X[sel] + gc.pbase[s];
   P *U = (P *)p.U[sel] + gc.pbase[s];
   const P alpha = (P)gc.alpha[s];
@@ -1150,7 +1192,7 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
   int total1 = 0;
   if (G == 1) {
     int te, ti;
-    gap_tiles(p.gs[0], p.gc[0].beam_n, tile, te, ti);
+    gap_tiles(p.gs[0], p.gs[0].beam_now, tile, te, ti);
     total1 = te + ti;
   } else {
     const int per = (G + BS - 1) / BS;
@@ -1159,7 +1201,7 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
       const int g = tid * per + q;
       if (g < G) {
         int te, ti;
-        gap_tiles(p.gs[g], p.gc[g].beam_n, tile, te, ti);
+        gap_tiles(p.gs[g], p.gs[g].beam_now, tile, te, ti);
         mine += te + ti;
       }
     }
@@ -1170,7 +1212,7 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
       if (g < G) {
         sh.prefix[g] = run;
         int te, ti;
-        gap_tiles(p.gs[g], p.gc[g].beam_n, tile, te, ti);
+        gap_tiles(p.gs[g], p.gs[g].beam_now, tile, te, ti);
         run += te + ti;
       }
     }
@@ -1191,7 +1233,7 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
     const GapConst &c = p.gc[g];
     const GapState &st = p.gs[g];
     int te, ti;
-    gap_tiles(st, c.beam_n, tile, te, ti);
+    gap_tiles(st, st.beam_now, tile, te, ti);
     const int lt = t - prefix(g);
     const int s = lt < te ? 0 : 1;
     const int seg_end = min(s == 0 ? te : te + ti, t1 - prefix(g));
@@ -1201,7 +1243,7 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
     const long long a = (long long)ls * tile;
     const long long b = min((long long)le * tile, st.count[s]);
     // this workgroup's share of the beam: in proportion to its ion tiles
-    const long long kb0 = s == 1 ? c.beam_n * ls / ti : 0, kb1 = s == 1 ? c.beam_n * le / ti : 0;
+    const long long kb0 = s == 1 ? st.beam_now * ls / ti : 0, kb1 = s == 1 ? st.beam_now * le / ti : 0;
     push_range<P, AC, BS, PPT>(p, c, st, g, s, sel, sh, a, b, kb0, kb1, cnt);
     // wave-level sums, then one LDS atomic per wave
     const unsigned int v0 = wave_sum(cnt.pushed), v1 = wave_sum(cnt.abs0), v2 = wave_sum(cnt.abs1);

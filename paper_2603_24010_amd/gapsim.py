@@ -54,6 +54,8 @@ class GsGapParams(C.Structure):
         ("see_E_eV", C.c_double),
         ("beam_per_step", C.c_int64),
         ("beam_Emin_eV", C.c_double), ("beam_Emax_eV", C.c_double),
+        ("beam_side", C.c_int32), ("beam_layer", C.c_double),
+        ("beam_schedule", C.POINTER(C.c_int64)), ("beam_schedule_len", C.c_int64),
         ("seed", C.c_uint64),
         ("particle_fp", C.c_int32),
         ("capacity", C.c_int64 * 2),
@@ -179,6 +181,11 @@ def params_from(cfg, particle_fp: int = 32, capacity=(1 << 20, 1 << 20)) -> GsGa
     p.see_E_eV = cfg.see_E_eV
     p.beam_per_step = cfg.beam_per_step
     p.beam_Emin_eV, p.beam_Emax_eV = cfg.beam_Emin_eV, cfg.beam_Emax_eV
+    p.beam_side, p.beam_layer = int(cfg.beam_side), float(cfg.beam_layer)
+    if cfg.beam_schedule is not None:
+        # the config owns this int64 array, so the pointer outlives the call
+        p.beam_schedule = cfg.beam_schedule.ctypes.data_as(C.POINTER(C.c_int64))
+        p.beam_schedule_len = int(cfg.beam_schedule.size)
     p.seed = cfg.seed
     p.particle_fp = particle_fp
     p.capacity[0], p.capacity[1] = int(capacity[0]), int(capacity[1])

@@ -34,6 +34,8 @@ PAPER_M_E_SCALED = 9.1e-28
 
 SEE_FIXED = 0
 SEE_EXP = 1
+BEAM_CIRCUIT = 0
+BEAM_GROUND = 1
 
 
 @dataclasses.dataclass
@@ -68,6 +70,9 @@ class GapConfig:
     beam_per_step: int = 0
     beam_Emin_eV: float = 0.0
     beam_Emax_eV: float = 0.0
+    beam_side: int = 0          # BEAM_CIRCUIT (node 0) or BEAM_GROUND (node N)
+    beam_layer: float = 0.0     # start layer width [m]; 0: one step of flight
+    beam_schedule: np.ndarray = None  # ions per step by level (int64); None: beam_per_step
     seed: int = 0
     v_ref: float = 1.0  # voltage scale for residual norms
 
@@ -81,6 +86,8 @@ class GapConfig:
             if getattr(self, name) is None:
                 setattr(self, name, np.zeros(m))
             setattr(self, name, np.asarray(getattr(self, name), dtype=np.float64).reshape(m))
+        if self.beam_schedule is not None:
+            self.beam_schedule = np.ascontiguousarray(self.beam_schedule, dtype=np.int64).reshape(-1)
 
     def replace(self, **kw) -> "GapConfig":
         return dataclasses.replace(self, **kw)
@@ -162,6 +169,39 @@ def config2(n_cells: int = 4096, beam_per_step: int = 20000, weight: float = 2.5
                      see_amp=0.5, see_law=SEE_EXP, see_E_eV=3.0, beam_per_step=beam_per_step,
                      beam_Emin_eV=1e3, beam_Emax_eV=50e3, seed=seed, v_ref=3e3,
                      **circuit_coupled_lc(1e-6, 1e-6, 1e-2, 50e-12, 0.6, 3e3))
+
+
+M_TI = 7.95e-26             # ion mass of the paper's integrated run (tab:space_time_variable)
+M_ELECTRON_X1000 = 9.1e-28  # its electron mass, raised 1000-fold (Sec. 4.2)
+
+
+def gaussian_schedule(n_steps: int, peak: float, center: float, width: float) -> np.ndarray:
+    """Ions per step of a Gaussian pulse: round(peak exp(-(n - center)^2 / (2 width^2)))
+    for the step that solves level n = 0 .. n_steps - 1."""
+    n = np.arange(n_steps, dtype=np.float64)
+    return np.rint(peak * np.exp(-0.5 * ((n - center) / width) ** 2)).astype(np.int64)
+
+
+def config_tesla(n_cells: int = 600, n_steps: int = 575, peak: float = 40000.0, center: float = 300.0,
+                 width: float = 50.0, layer: float = 2e-3, see_amp: float = 3.0, see_E0_eV: float = 2e4,
+                 E_lo: float = 10.0, E_hi: float = 50.0, seed: int = 5) -> GapConfig:
+    """The paper's integrated Tesla run (Sec. 4.2, tab:space_time_variable,
+    tab:circuit_parameters): 80 mm gap of 2.53e-2 m^2 on 600 cells, dt 15 ns, 575
+    steps (8.62 us), Ti+ ions and electrons of 1000 times their mass, superparticle
+    ratio 2.5e7, the five-loop Tesla circuit with C1 at 3 kV.  Ions enter in a
+    layer next to the grounded electrode with a Gaussian pulse in time.  The paper
+    shows the pulse, the layer, the ions' entry energies and the yield curve only
+    as figures; peak / center / width (ions per step, steps), layer [m], energies
+    [eV] and the yield law's a and E0 here are stand-ins.  The pulse is centred on
+    the first swing that drives the circuit electrode negative (it attracts the
+    ions), at 4.5 us."""
+    return GapConfig(n_cells=n_cells, d=0.08, area=2.53e-2, eps0=EPS0, dt=15e-9,
+                     mass=(M_ELECTRON_X1000, M_TI), weight=2.5e7,
+                     see_amp=see_amp, see_E0_eV=see_E0_eV, see_law=SEE_EXP, see_E_eV=3.0,
+                     beam_side=BEAM_GROUND, beam_layer=layer,
+                     beam_schedule=gaussian_schedule(n_steps, peak, center, width),
+                     beam_Emin_eV=E_lo, beam_Emax_eV=E_hi, seed=seed, v_ref=1e4,
+                     **circuit_tesla())
 
 
 def config3(n_cells: int = 16384, **kw) -> GapConfig:

@@ -39,6 +39,8 @@ def test_version_string():
     (lambda: W.config4_gap(3)[0], 32, (100_000, 700_000)),
     (lambda: W.config_paper_validation(), 64, (16, 16)),
     (lambda: W.config2(n_cells=600).replace(**W.circuit_tesla()), 32, (1000, 1000)),
+    (lambda: W.config_tesla(), 32, (3_000_000, 4_000_000)),
+    (lambda: W.config_tesla().replace(beam_schedule=np.zeros(0, dtype=np.int64)), 32, (10, 10)),
 ])
 def test_valid_configs_pass(make, fp, cap):
     assert gapsim.validate(make(), fp, cap) is None
@@ -59,6 +61,11 @@ def test_valid_configs_pass(make, fp, cap):
     (dict(), 16, (10, 10), "particle_fp"),
     (dict(), 64, (1 << 19, 1 << 19), "2^19"),
     (dict(), 32, (-1, 10), "capacity"),
+    (dict(beam_side=2), 32, (10, 10), "beam_side"),
+    (dict(beam_layer=0.01), 32, (10, 10), "beam_layer"),
+    (dict(beam_layer=-1e-3), 32, (10, 10), "beam_layer"),
+    (dict(beam_schedule=np.array([3, -1])), 32, (10, 10), "beam_schedule"),
+    (dict(beam_schedule=np.array([0, 5])), 32, (10, 10), "beam energies"),
 ])
 def test_invalid_params_rejected(change, fp, cap, needle):
     cfg = W.config1(n_cells=64).replace(**change)

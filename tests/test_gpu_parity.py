@@ -69,11 +69,14 @@ def check_run(recs, tol, M):
     for key in ("phi0", "sigma", "qcirc", "qcirc_star"):
         r = _series_rel([d[key] for d, _ in recs], [o[key] for _, o in recs])
         assert r <= tol, (key, r)
-    for j in range(M):
-        r = _series_rel([d["I"][j] for d, _ in recs], [o["I"][j] for _, o in recs])
-        assert r <= tol, ("I", j, r)
-        r = _series_rel([d["q"][j] for d, _ in recs], [o["q"][j] for _, o in recs])
-        assert r <= tol, ("q", j, r)
+    # loop currents and charges norm-wise: the largest deviation over all loops
+    # against the largest value over all loops (a loop closed by a large
+    # resistor carries currents many orders below the others)
+    for key in ("I", "q"):
+        g = np.array([[d[key][j] for j in range(M)] for d, _ in recs])
+        o = np.array([[od[key][j] for j in range(M)] for _, od in recs])
+        r = _series_rel(g, o)
+        assert r <= tol, (key, r)
 
 
 def check_fields(sim, orc, tol):
@@ -135,7 +138,9 @@ def test_paper_worked_value_on_gpu():
 
 
 @pytest.mark.parametrize("make", [lambda: W.config1(n_cells=64),
-                                  lambda: W.config2(n_cells=64, beam_per_step=0)])
+                                  lambda: W.config2(n_cells=64, beam_per_step=0),
+                                  lambda: W.config_tesla(n_cells=64).replace(
+                                      beam_schedule=np.zeros(0, dtype=np.int64))])
 @pytest.mark.parametrize("mode", [oracle.STRICT, oracle.WEAK])
 def test_vacuum_circuit_parity(make, mode):
     cfg = make()
@@ -168,6 +173,34 @@ def test_fp32_beam_gap_parity(mode, n_cells):
         a, b = sorted_state(xg, ug), sorted_state(xo, uo)
         np.testing.assert_array_equal(a[0], b[0])
         np.testing.assert_array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("mode", [oracle.STRICT, oracle.WEAK])
+@pytest.mark.parametrize("layer", [2e-3, 0.0])
+def test_fp32_tesla_ground_pulse_parity(mode, layer):
+    """The paper's integrated-run shape (Sec. 4.2): five-loop Tesla circuit, ions
+    entering next to the grounded electrode by a Gaussian schedule (here early and
+    short, so that 80 steps see it rise and fall), emission on."""
+    # started within one step's flight of the electrode the ions of a step are
+    # absorbed together, in the workgroup holding them: a smaller pulse keeps
+    # them within the 1152 events a workgroup emits in the same step
+    sched = W.gaussian_schedule(80, 3000.0 if layer > 0 else 500.0, 35.0, 10.0)
+    cfg = W.config_tesla(layer=layer).replace(beam_schedule=sched, see_amp=30.0)
+    opts = {_gapsim().OPT_COMPACT_EVERY: 9}
+    sim, orc, recs = run_pair(cfg, {}, mode, 80, True, (200_000, 200_000), opts=opts)
+    check_run(recs, 1e-5, cfg.n_mesh)
+    check_fields(sim, orc, 1e-5)
+    d = recs[-1][0]
+    assert d["inj_cum"] == int(sched.sum())
+    assert d["abs_cum"][1].sum() > 1000 and d["emit_cum"].sum() > 100, (d["abs_cum"], d["emit_cum"])
+    for sp in (0, 1):
+        xg, ug, _ = sim.particles(0, sp)
+        xo, uo, _ = orc.particles_f32(sp)
+        assert len(xg) == len(xo)
+        a, b = sorted_state(xg, ug), sorted_state(xo, uo)
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+    sim.close()
 
 
 def test_fp32_error_against_fp64_oracle():
@@ -313,3 +346,46 @@ def test_inject_rejects_outside_positions():
     with pytest.raises(gs.GapsimError) as e:
         sim.inject(0, 0, np.array([2 * cfg.d]), np.array([0.0]))
     assert e.value.status == gs.GS_EINVAL
+
+
+def test_event_overflow_emits_next_step():
+    """Past 1152 absorbed ions in one workgroup and step the excess is emitted at
+    the start of the next step: absorbed counts, voltages and fields stay equal to
+    the oracle's; the emitted count read between steps may only lag."""
+    sched = W.gaussian_schedule(60, 3000.0, 30.0, 8.0)
+    cfg = W.config_tesla(layer=0.0).replace(beam_schedule=sched, see_amp=30.0)
+    sim, orc, recs = run_pair(cfg, {}, oracle.STRICT, 60, True, (200_000, 200_000))
+    lagged = 0
+    for dg, do in recs:
+        np.testing.assert_array_equal(dg["abs_cum"], do["abs_cum"])
+        assert dg["inj_cum"] == do["inj_cum"]
+        assert dg["emit_cum"].sum() <= do["emit_cum"].sum()
+        lagged += dg["emit_cum"].sum() < do["emit_cum"].sum()
+    print("steps with emission pending:", lagged)
+    for key in ("phi0", "sigma", "qcirc"):
+        assert _series_rel([d[key] for d, _ in recs], [o[key] for _, o in recs]) <= 1e-5, key
+    check_fields(sim, orc, 1e-5)
+    sim.close()
+
+
+def test_tesla_scenario_waveform_matches_oracle():
+    """The whole stand-in Tesla run (575 steps, 5e6 ions injected, emission on)
+    on the GPU against the oracle's binary32 mode.  Past the parity horizon single
+    particles part ways, so the bar is on the gap-voltage waveform: its largest
+    deviation stays within 1% of the swing, and the injected count is exact."""
+    cfg = W.config_tesla()
+    gs = _gapsim()
+    sim = gs.GapSim(cfg, particle_fp=32, capacity=(3_000_000, 4_000_000))
+    orc = oracle.OracleSim(cfg, fp32=True)
+    Vg, Vo = [], []
+    for _ in range(575):
+        sim.step_strict(1)
+        orc.step(oracle.STRICT, 1)
+        Vg.append(sim.diag(0)["phi0"])
+        Vo.append(orc.diag()["phi0"])
+    Vg, Vo = np.array(Vg), np.array(Vo)
+    dev = np.abs(Vg - Vo).max() / np.abs(Vo).max()
+    print(f"largest |V_gpu - V_oracle| / max|V| = {dev:.2e}")
+    assert dev < 1e-2
+    assert sim.diag(0)["inj_cum"] == orc.diag()["inj_cum"] == int(cfg.beam_schedule.sum())
+    sim.close()
