@@ -480,6 +480,86 @@ def run_divergence(args, copy_gbs):
     print(json.dumps(out), flush=True)
 
 
+TESLA_WORKLOAD = "tesla_600c_ground_pulse"
+
+
+def _collapse_metrics(V, dt):
+    """Bottom of the negative swing the pulse rides on, the first step after it
+    with V above -3 kV, and the next positive peak."""
+    lo = 250 + int(np.argmin(V[250:400]))
+    up = lo + int(np.argmax(V[lo:] > -3e3))
+    return {"swing_bottom_kV": float(V[lo] / 1e3), "swing_bottom_us": lo * dt * 1e6,
+            "above_minus3kV_us": up * dt * 1e6, "next_peak_kV": float(V[lo:].max() / 1e3)}
+
+
+def run_tesla(args, copy_gbs):
+    """The paper's integrated Tesla run (Sec. 4.2) with stand-in pulse, layer,
+    entry energies and yield law: strict and weak, with and without ion-induced
+    emission, the whole 575 steps each on the GPU; the oracle (binary32 mode)
+    timed on the same runs."""
+    import torch
+    import oracle
+    from paper_2603_24010_amd import gapsim, workloads as W
+    cfg0 = W.config_tesla()
+    steps = len(cfg0.beam_schedule)
+    cases = [("strict_see", oracle.STRICT, cfg0), ("weak_see", oracle.WEAK, cfg0),
+             ("strict_no_see", oracle.STRICT, cfg0.replace(see_amp=0.0)),
+             ("weak_no_see", oracle.WEAK, cfg0.replace(see_amp=0.0))]
+    res, curves, el_all, pushed_all = {}, {}, 0.0, 0
+    for name, mode, cfg in cases:
+        s = gapsim.GapSim(cfg, particle_fp=32, capacity=(3_000_000, 4_000_000))
+        V = np.zeros(steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        el = 0.0
+        for n in range(steps):
+            s.step(mode, 1)
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t0
+            V[n] = s.diag(0)["phi0"]
+            t0 = time.perf_counter()
+        d = s.diag(0)
+        s.close()
+        el_all += el
+        pushed_all += d["pushed_cum"]
+        curves[name] = V
+        res[name] = dict(_collapse_metrics(V, cfg.dt), particle_steps=int(d["pushed_cum"]),
+                         wall_s=el, injected=int(d["inj_cum"]), emitted=int(d["emit_cum"].sum()),
+                         absorbed=[int(x) for x in d["abs_cum"].ravel()])
+        log(f"[bench] {name}: {res[name]}")
+    rmse = lambda a, b: float(np.sqrt(np.mean((curves[a] - curves[b]) ** 2)) / 1e3)
+    out = {
+        "metric": "Tesla-run waveform (collapse with vs without SEE, strict vs weak RMSE); particle-steps/s",
+        "value": pushed_all / el_all, "unit": "particle-steps/s", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": el_all * 1e3 / (len(cases) * steps), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": TESLA_WORKLOAD, "cells": cfg0.n_cells, "dt_ns": cfg0.dt * 1e9,
+                   "beam": "Gaussian pulse at the grounded electrode, stand-in: peak 4e4 ions/step at 4.5 us, "
+                           "width 50 steps, 2 mm layer, 10-50 eV; yield 3 E/(E + 20 keV)",
+                   "injected": int(cfg0.beam_schedule.sum())},
+        "cases": res,
+        "strict_weak_rmse_kV": {"see": rmse("strict_see", "weak_see"), "no_see": rmse("strict_no_see", "weak_no_see"),
+                                "paper_context_kV": 0.228},
+        "curve_kV": [[round(n * cfg0.dt * 1e6, 3)] + [round(float(curves[c][n]) / 1e3, 3) for c, _, _ in cases]
+                     for n in range(0, steps, 5)],
+        "roofline": {"bound": "latency", "kernel": "k_push", "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "achieved": None, "frac": None, "traffic": None, "copy_GBps": copy_gbs,
+                     "note": "at most ~1.3e6 live particles: each step is a few launches of short kernels"},
+    }
+    if not args.no_cpu_baseline:
+        pc, elc = 0, 0.0
+        for name, mode, cfg in cases:
+            o = oracle.OracleSim(cfg, fp32=True)
+            t0 = time.perf_counter()
+            o.step(mode, steps)
+            elc += time.perf_counter() - t0
+            pc += o.diag()["pushed_cum"]
+        out["cpu_baseline"] = {"value": pc / elc, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the same four runs, {steps} steps each, binary32 oracle mode, "
+                                         f"{pc} particle-steps in {elc:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline_batched(spec, steps):
     import oracle
     from paper_2603_24010_amd import workloads as W
@@ -527,7 +607,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="beam_gap_4096c_2e7p_weak",
-                    choices=sorted(WORKLOADS) + sorted(BATCHED) + [MLP_WORKLOAD, DIVERGENCE, FP64_WORKLOAD])
+                    choices=sorted(WORKLOADS) + sorted(BATCHED) + [MLP_WORKLOAD, DIVERGENCE, FP64_WORKLOAD,
+                                                                   TESLA_WORKLOAD])
     ap.add_argument("--div-particles", type=int, default=200_000_000)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -596,6 +677,8 @@ def main():
         return run_divergence(args, copy_gbs)
     if args.workload == FP64_WORKLOAD:
         return run_fp64(args, copy_gbs)
+    if args.workload == TESLA_WORKLOAD:
+        return run_tesla(args, copy_gbs)
     spec = WORKLOADS[args.workload]
     log(f"[bench] building workload {args.workload}")
     sim, cfg, _ = make_sim(args.workload, spec, args.warmup + args.steps)
