@@ -53,7 +53,9 @@ typedef enum {
   GS_ESTATE = -6      /* call out of order (e.g. no context) */
 } gs_status;
 
-enum { GS_SEE_FIXED = 0, GS_SEE_EXP = 1 };
+enum { GS_SEE_FIXED = 0, GS_SEE_EXP = 1, GS_SEE_LOGNORMAL = 2 };
+/* mean secondary yield as a function of the ion's energy */
+enum { GS_YIELD_SATURATING = 0, GS_YIELD_POLY = 1 };
 /* electrode the beam enters at */
 enum { GS_BEAM_CIRCUIT = 0, GS_BEAM_GROUND = 1 };
 enum { GS_GUESS_DIRECT = 0, GS_GUESS_EXTRAP = 1, GS_GUESS_MLP = 2 };
@@ -76,10 +78,17 @@ typedef struct {
  *   the gap element (the gap itself, eps0 area / d, in parallel with c_par) lying
  *   in mesh gap_mesh.  q0 holds the loop charges before t = 0 (switch closes at
  *   t = 0).  Matrices are row-major, only the leading n_mesh x n_mesh used.
- *   SEE: an ion hitting either electrode frees Poisson(gamma) electrons, at most
- *   see_max, gamma(E) = see_amp (E/see_E0_eV) / (1 + E/see_E0_eV), E the ion's
- *   normal kinetic energy; each leaves the surface normally with energy see_E_eV
- *   (GS_SEE_FIXED) or an exponential draw of mean see_E_eV (GS_SEE_EXP).
+ *   SEE (Sec. 2.3, Alg. 2): an ion hitting either electrode frees
+ *   Poisson(gamma) electrons, at most see_max, E the ion's normal kinetic energy:
+ *     GS_YIELD_SATURATING: gamma = see_amp (E/see_E0_eV) / (1 + E/see_E0_eV);
+ *     GS_YIELD_POLY: gamma = see_amp max(f(x), 0), f(x) = sum_k see_poly[k] x^k
+ *       (the paper's fifth-order fit), x = min(E, see_poly_Emax_eV) / 1 keV
+ *       (evaluated by Horner's rule from see_poly[5]).
+ *   Each electron leaves the surface normally with energy see_E_eV
+ *   (GS_SEE_FIXED), an exponential draw of mean see_E_eV (GS_SEE_EXP), or
+ *   exp(see_ln_mu + see_ln_sigma Z) eV, Z standard normal (GS_SEE_LOGNORMAL,
+ *   the paper's law; Z = sqrt(-2 ln u1) cos(2 pi u2) from two of the ion's
+ *   stream words).  see_amp > 0 switches emission on.
  *   Beam: ions enter at the circuit electrode (beam_side GS_BEAM_CIRCUIT, node 0,
  *   moving towards the ground) or at the grounded one (GS_BEAM_GROUND, node N,
  *   moving towards the circuit electrode), with energies uniform in
@@ -111,6 +120,10 @@ typedef struct {
   double see_amp, see_E0_eV;
   int32_t see_law, see_max;
   double see_E_eV;
+  int32_t see_yield;
+  double see_poly[6];
+  double see_poly_Emax_eV;
+  double see_ln_mu, see_ln_sigma;
   int64_t beam_per_step;
   double beam_Emin_eV, beam_Emax_eV;
   int32_t beam_side;

@@ -50,6 +50,8 @@ class OrParams(C.Structure):
         ("see_amp", C.c_double), ("see_E0_eV", C.c_double),
         ("see_law", C.c_int32), ("see_max", C.c_int32),
         ("see_E_eV", C.c_double),
+        ("see_yield", C.c_int32), ("see_poly", C.c_double * 6), ("see_poly_Emax_eV", C.c_double),
+        ("see_ln_mu", C.c_double), ("see_ln_sigma", C.c_double),
         ("beam_per_step", C.c_int64),
         ("beam_Emin_eV", C.c_double), ("beam_Emax_eV", C.c_double),
         ("beam_side", C.c_int32), ("beam_layer", C.c_double),
@@ -146,6 +148,10 @@ def params_from(cfg, fp32: bool = False) -> OrParams:
     p.c_par = cfg.c_par
     p.see_amp, p.see_E0_eV, p.see_law, p.see_max = cfg.see_amp, cfg.see_E0_eV, cfg.see_law, cfg.see_max
     p.see_E_eV = cfg.see_E_eV
+    p.see_yield = int(cfg.see_yield)
+    for j in range(6):
+        p.see_poly[j] = float(cfg.see_poly[j])
+    p.see_poly_Emax_eV, p.see_ln_mu, p.see_ln_sigma = cfg.see_poly_Emax_eV, cfg.see_ln_mu, cfg.see_ln_sigma
     p.beam_per_step = cfg.beam_per_step
     p.beam_Emin_eV, p.beam_Emax_eV = cfg.beam_Emin_eV, cfg.beam_Emax_eV
     p.beam_side, p.beam_layer = int(cfg.beam_side), float(cfg.beam_layer)

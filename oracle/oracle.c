@@ -595,18 +595,42 @@ static void emit_electrons(or_sim *s, uint32_t ion_id, double v_ion, int wall,
                            int64_t *n_emitted) {
   const or_params *p = &s->p;
   if (p->see_amp <= 0.0) return;
+  /* Alg. 2: the incident energy, the mean yield (clipped at zero), the count */
   double e_ion = 0.5 * p->mass[1] * v_ion * v_ion / p->ev; /* eV */
-  double r = e_ion / p->see_E0_eV;
-  double lam = p->see_amp * r / (1.0 + r);
+  double lam;
+  if (p->see_yield == OR_YIELD_POLY) {
+    double x = (e_ion < p->see_poly_Emax_eV ? e_ion : p->see_poly_Emax_eV) / 1000.0;
+    double f = p->see_poly[5];
+    for (int j = 4; j >= 0; --j) f = f * x + p->see_poly[j];
+    lam = p->see_amp * (f > 0.0 ? f : 0.0);
+  } else {
+    double r = e_ion / p->see_E0_eV;
+    lam = p->see_amp * r / (1.0 + r);
+  }
   if (lam < 0.0) lam = 0.0;
   uint64_t blk[4];
   draw_block(p->seed, (uint64_t)s->step, (uint64_t)ion_id, 1, 0, blk);
   int32_t k = or_poisson_draw(lam, unit_open(blk[0]), p->see_max);
+  /* the electrons' energies take the ion's stream words from 1 on, in order:
+   * one per electron (fixed, exponential) or two (lognormal) */
+  int32_t w = 1;
   for (int32_t e = 0; e < k; ++e) {
-    int32_t slot = e + 1; /* word 0 of block 0 was the count */
-    if (slot % 4 == 0) draw_block(p->seed, (uint64_t)s->step, (uint64_t)ion_id, 1, (uint64_t)(slot / 4), blk);
-    double u = unit_open(blk[slot % 4]);
-    double E_se = (p->see_law == OR_SEE_EXP) ? -p->see_E_eV * log(u) : p->see_E_eV;
+    double E_se;
+    if (p->see_law == OR_SEE_LOGNORMAL) {
+      if (w % 4 == 0) draw_block(p->seed, (uint64_t)s->step, (uint64_t)ion_id, 1, (uint64_t)(w / 4), blk);
+      double u1 = unit_open(blk[w % 4]);
+      w += 1;
+      if (w % 4 == 0) draw_block(p->seed, (uint64_t)s->step, (uint64_t)ion_id, 1, (uint64_t)(w / 4), blk);
+      double u2 = unit_open(blk[w % 4]);
+      w += 1;
+      double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+      E_se = exp(p->see_ln_mu + p->see_ln_sigma * z);
+    } else {
+      if (w % 4 == 0) draw_block(p->seed, (uint64_t)s->step, (uint64_t)ion_id, 1, (uint64_t)(w / 4), blk);
+      double u = unit_open(blk[w % 4]);
+      w += 1;
+      E_se = (p->see_law == OR_SEE_EXP) ? -p->see_E_eV * log(u) : p->see_E_eV;
+    }
     double v_se = sqrt(2.0 * E_se * p->ev / p->mass[0]);
     /* normal emission into the gap, starting on the surface */
     double x_si = wall == 0 ? 0.0 : p->d;

@@ -32,7 +32,8 @@ extern "C" {
 #define OR_MAX_MESH 8
 
 enum { OR_STRICT = 0, OR_WEAK = 1 };
-enum { OR_SEE_FIXED = 0, OR_SEE_EXP = 1 };
+enum { OR_SEE_FIXED = 0, OR_SEE_EXP = 1, OR_SEE_LOGNORMAL = 2 };
+enum { OR_YIELD_SATURATING = 0, OR_YIELD_POLY = 1 };
 
 typedef struct {
   /* gap and grid, SI.  Node 0 (x = 0) is the circuit electrode, node N
@@ -56,11 +57,17 @@ typedef struct {
   double src_dc, src_amp, src_freq, src_phase;
   double c_par;
   double q0[OR_MAX_MESH]; /* loop charges for t < 0 (switch closes at t = 0) */
-  /* secondary emission by ions: yield amp*(E/E0)/(1+E/E0), Poisson count
-   * capped at see_max per impact; emitted energy fixed or exponential. */
+  /* secondary emission by ions (Sec. 2.3, Alg. 2): Poisson count of mean
+   * amp*(E/E0)/(1+E/E0) (saturating) or amp*max(poly(min(E, Emax)/1 keV), 0)
+   * (the paper's fifth-order fit), capped at see_max per impact; emitted
+   * energy fixed, exponential of mean see_E_eV, or lognormal exp(mu + sigma Z). */
   double see_amp, see_E0_eV;
   int32_t see_law, see_max;
   double see_E_eV;
+  int32_t see_yield;
+  double see_poly[6];
+  double see_poly_Emax_eV;
+  double see_ln_mu, see_ln_sigma;
   /* ion beam, energies uniform in [beam_Emin_eV, beam_Emax_eV], entering at
    * the circuit electrode (beam_side 0, moving towards the ground) or at the
    * grounded one (beam_side 1, moving towards the circuit electrode), started

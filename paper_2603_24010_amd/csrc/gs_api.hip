@@ -173,7 +173,17 @@ extern "C" gs_status gs_validate_params(const gs_gap_params *p, char *msg, size_
     return bad("source parameters must be finite");
   if (!std::isfinite(p->see_amp) || p->see_amp < 0) return bad("see_amp must be >= 0");
   if (!finite_pos(p->see_E0_eV)) return bad("see_E0_eV must be positive");
-  if (p->see_law != GS_SEE_FIXED && p->see_law != GS_SEE_EXP) return bad("see_law must be FIXED or EXP");
+  if (p->see_law != GS_SEE_FIXED && p->see_law != GS_SEE_EXP && p->see_law != GS_SEE_LOGNORMAL)
+    return bad("see_law must be FIXED, EXP or LOGNORMAL");
+  if (p->see_yield != GS_YIELD_SATURATING && p->see_yield != GS_YIELD_POLY)
+    return bad("see_yield must be SATURATING or POLY");
+  for (int j = 0; j < 6; ++j)
+    if (!std::isfinite(p->see_poly[j])) return bad("see_poly coefficients must be finite");
+  if (p->see_yield == GS_YIELD_POLY && !finite_pos(p->see_poly_Emax_eV))
+    return bad("see_poly_Emax_eV must be positive");
+  if (p->see_law == GS_SEE_LOGNORMAL &&
+      (!std::isfinite(p->see_ln_mu) || !std::isfinite(p->see_ln_sigma) || p->see_ln_sigma < 0))
+    return bad("see_ln_mu must be finite and see_ln_sigma >= 0");
   if (p->see_max < 0 || p->see_max > 1024) return bad("see_max must be in 0..1024");
   if (!std::isfinite(p->see_E_eV) || p->see_E_eV < 0) return bad("see_E_eV must be >= 0");
   if (p->beam_per_step < 0 || p->beam_per_step > (int64_t)1 << 30) return bad("beam_per_step out of range");
@@ -238,6 +248,11 @@ static gs_status build_const(gs_ctx *ctx, int g, const gs_gap_params &p, GapCons
   c.see_amp = p.see_amp;
   c.see_E0 = p.see_E0_eV;
   c.see_E = p.see_E_eV;
+  c.see_yield = p.see_yield;
+  for (int j = 0; j < 6; ++j) c.see_poly[j] = p.see_poly[j];
+  c.see_pEmax = p.see_poly_Emax_eV;
+  c.see_mu = p.see_ln_mu;
+  c.see_sig = p.see_ln_sigma;
   c.beam_Emin = p.beam_Emin_eV;
   c.beam_Emax = p.beam_Emax_eV;
   c.v_ref = p.v_ref;

@@ -27,6 +27,7 @@ struct GapConst {
   int32_t N;          // cells
   int32_t M, g;       // meshes, gap mesh
   int32_t see_law, see_max;
+  int32_t see_yield, pad_y;
   int32_t Z[2];
   int32_t beam_side;  // GS_BEAM_CIRCUIT or GS_BEAM_GROUND
   int64_t beam_n;     // ions per step without a schedule
@@ -43,6 +44,8 @@ struct GapConst {
   double alpha[2];     // Z q dt^2 / (m dx): velocity change in cells/step per V/m
   double mass[2], ev;
   double see_amp, see_E0, see_E;
+  double see_poly[6], see_pEmax;  // GS_YIELD_POLY: coefficients in powers of E / 1 keV, E clamp [eV]
+  double see_mu, see_sig;         // GS_SEE_LOGNORMAL: ln E ~ N(mu, sig^2), E in eV
   double beam_Emin, beam_Emax;
   double beam_layer;  // [m]; 0: one step of flight
   double v_ref;

@@ -60,7 +60,9 @@ __device__ inline void rng_block(uint64_t seed, uint64_t a, uint64_t b, uint64_t
   philox4x64_10(out, seed, 0);
 }
 
-__device__ inline int poisson_inverse(double lam, double u, int kmax) {
+// (not inlined: the constants of the exponential would otherwise be held in
+// registers across the whole push kernel)
+__device__ __attribute__((noinline)) int poisson_inverse(double lam, double u, int kmax) {
   double p = exp(-lam);
   double F = p;
   int k = 0;
@@ -183,22 +185,47 @@ __device__ inline unsigned int wave_sum(unsigned int a) {
 }
 
 // Secondary emission (Alg. 2), in two parts.  see_count: an absorbed ion's
-// energy E = m v^2 / 2 from its impact velocity, the mean yield
-// a (E/E0) / (1 + E/E0) and the Poisson count by inversion, drawn from the
-// stream keyed by (level, ion id); blk keeps the block for the energies.
+// energy E = m v^2 / 2 from its impact velocity, the mean yield (saturating
+// a (E/E0) / (1 + E/E0), or a times the fifth-order fit clipped at zero) and
+// the Poisson count by inversion, drawn from the stream keyed by (level, ion
+// id); blk keeps the block for the energies.
 __device__ inline int see_count(const GapConst &c, long long level, uint32_t ion_id, double u_imp, uint64_t blk[4]) {
   const double v_ion = (u_imp * c.dx) / c.dt;
   const double e_ion = 0.5 * c.mass[1] * v_ion * v_ion / c.ev;
-  const double rr = e_ion / c.see_E0;
-  double lam = c.see_amp * rr / (1.0 + rr);
+  double lam;
+  if (c.see_yield == GS_YIELD_POLY) {
+    const double x = (e_ion < c.see_pEmax ? e_ion : c.see_pEmax) / 1000.0;
+    double f = c.see_poly[5];
+#pragma unroll
+    for (int j = 4; j >= 0; --j) f = f * x + c.see_poly[j];
+    lam = c.see_amp * (f > 0.0 ? f : 0.0);
+  } else {
+    const double rr = e_ion / c.see_E0;
+    lam = c.see_amp * rr / (1.0 + rr);
+  }
   if (lam < 0.0) lam = 0.0;
   rng_block(c.seed, (uint64_t)level, (uint64_t)ion_id, 1, 0, blk);
   return poisson_inverse(lam, unit_open(blk[0]), c.see_max);
 }
 
-// see_write: the ion's nk electrons, energies fixed or exponential, placed on
-// the wall node with the inward speed of their energy, in slots base.. of the
-// electron region; counts per wall added to n[0], n[1].
+// An emitted electron's energy [eV] from its one or two uniform draws: fixed,
+// exponential of mean E, or lognormal exp(mu + sig Z) with the Box-Muller
+// normal Z = sqrt(-2 ln u0) cos(2 pi u1), evaluated as cospi(2 u1), whose
+// argument needs no general range reduction.  (Not inlined, as
+// poisson_inverse.)
+__device__ __attribute__((noinline)) double see_energy(int law, double E, double mu, double sig, double u0,
+                                                       double u1) {
+  const double L = log(u0);
+  if (law == GS_SEE_EXP) return -E * L;
+  if (law == GS_SEE_LOGNORMAL) return exp(mu + sig * (sqrt(-2.0 * L) * cospi(2.0 * u1)));
+  return E;
+}
+
+// see_write: the ion's nk electrons, energies fixed, exponential or lognormal
+// (from the ion's stream words 1, 2, .. in order: one per electron, two for the
+// lognormal's normal draw), placed on the wall node with the inward speed of
+// their energy, in slots base.. of the electron region; counts per wall added
+// to n[0], n[1].
 template <class P>
 __device__ inline void see_write(const DevPtrs &p, const GapConst &c, long long level, int g, int sel,
                                  uint32_t ion_id, int wall, int nk, uint64_t blk[4], unsigned long long base,
@@ -207,11 +234,20 @@ __device__ inline void see_write(const DevPtrs &p, const GapConst &c, long long 
   P *U = (P *)p.U[sel] + c.pbase[0];
   uint32_t *ID = p.ID[sel] + c.pbase[0];
   const P xw = wall == 0 ? (P)0 : (P)c.N;
+  // one copy of each draw and function (cold code: its size is what costs)
+  const int nw = c.see_law == GS_SEE_LOGNORMAL ? 2 : 1;
+  int w = 1;  // word 0 of block 0 drew the count
   for (int e = 0; e < nk; ++e) {
-    const int slotw = e + 1;  // word 0 of block 0 drew the count
-    if ((slotw & 3) == 0) rng_block(c.seed, (uint64_t)level, (uint64_t)ion_id, 1, (uint64_t)(slotw >> 2), blk);
-    const double uu = unit_open(blk[slotw & 3]);
-    const double E_se = (c.see_law == GS_SEE_EXP) ? -c.see_E * log(uu) : c.see_E;
+    double u[2] = {0.5, 0.5};
+#pragma unroll 1
+    for (int t = 0; t < nw; ++t) {
+      if ((w & 3) == 0) rng_block(c.seed, (uint64_t)level, (uint64_t)ion_id, 1, (uint64_t)(w >> 2), blk);
+      const double uw = unit_open(blk[w & 3]);
+      u[0] = t == 0 ? uw : u[0];
+      u[1] = t == 1 ? uw : u[1];
+      w += 1;
+    }
+    const double E_se = see_energy(c.see_law, c.see_E, c.see_mu, c.see_sig, u[0], u[1]);
     const double v_se = sqrt(2.0 * E_se * c.ev / c.mass[0]);
     const double v_si = wall == 0 ? v_se : -v_se;
     const unsigned long long sl = base + (unsigned long long)e;
@@ -773,9 +809,16 @@ struct PushShared {
 
 // push tiles of gap g: electrons, then ions (a gap with a beam has at least
 // one ion tile: the workgroups holding its ion tiles inject the beam)
+// (counts are below 2^31: 32-bit division, a fraction of the 64-bit code)
+__device__ inline int tiles_of(long long count, int tile) {
+  const unsigned int c = (unsigned int)count, t = (unsigned int)tile;
+  const unsigned int q = c / t;
+  return (int)(q + (c - q * t != 0u ? 1u : 0u));
+}
+
 __device__ inline void gap_tiles(const GapState &st, long long beam_n, int tile, int &te, int &ti) {
-  te = (int)((st.count[0] + tile - 1) / tile);
-  ti = (int)((st.count[1] + tile - 1) / tile);
+  te = tiles_of(st.count[0], tile);
+  ti = tiles_of(st.count[1], tile);
   if (beam_n > 0 && ti == 0) ti = 1;
 }
 
@@ -834,9 +877,14 @@ __device__ void beam_inject(const DevPtrs &p, const GapConst &c, const GapState 
 // reservation's total.  The first round also flushes the node sums while its
 // reservation is in flight.
 template <class P, class AC>
-__device__ inline int emit_round(const DevPtrs &p, const GapConst &c, const GapState &st, int g, int s, int sel,
+__device__ inline int emit_round(const DevPtrs &p, const GapConst &c0, const GapState &st, int g, int s, int sel,
                                  PushShared<P, AC> &sh, const Event *ovf, int ne, int r0,
                                  unsigned long long *s_base) {
+  // the emission's constants are read here, not at the kernel's start (held
+  // in registers across the push they would spill)
+  const GapConst *cp = &c0;
+  asm volatile("" : "+s"(cp));
+  const GapConst &c = *cp;
   const int i = r0 + (int)threadIdx.x;
   uint32_t ion_id = 0;
   int wall = 0, nk = 0;

@@ -34,6 +34,9 @@ PAPER_M_E_SCALED = 9.1e-28
 
 SEE_FIXED = 0
 SEE_EXP = 1
+SEE_LOGNORMAL = 2
+YIELD_SATURATING = 0
+YIELD_POLY = 1
 BEAM_CIRCUIT = 0
 BEAM_GROUND = 1
 
@@ -67,6 +70,11 @@ class GapConfig:
     see_law: int = SEE_FIXED
     see_max: int = 32
     see_E_eV: float = 2.0
+    see_yield: int = 0                # YIELD_SATURATING or YIELD_POLY
+    see_poly: np.ndarray = None       # YIELD_POLY: c_0..c_5 in powers of E / 1 keV
+    see_poly_Emax_eV: float = 8e4     # YIELD_POLY: energy clamp (the fit's range)
+    see_ln_mu: float = 0.0            # SEE_LOGNORMAL: ln E ~ N(mu, sigma^2), E in eV
+    see_ln_sigma: float = 0.0
     beam_per_step: int = 0
     beam_Emin_eV: float = 0.0
     beam_Emax_eV: float = 0.0
@@ -86,6 +94,8 @@ class GapConfig:
             if getattr(self, name) is None:
                 setattr(self, name, np.zeros(m))
             setattr(self, name, np.asarray(getattr(self, name), dtype=np.float64).reshape(m))
+        self.see_poly = (np.zeros(6) if self.see_poly is None
+                         else np.asarray(self.see_poly, dtype=np.float64).reshape(6))
         if self.beam_schedule is not None:
             self.beam_schedule = np.ascontiguousarray(self.beam_schedule, dtype=np.int64).reshape(-1)
 

@@ -62,6 +62,10 @@ def test_valid_configs_pass(make, fp, cap):
     (dict(), 64, (1 << 19, 1 << 19), "2^19"),
     (dict(), 32, (-1, 10), "capacity"),
     (dict(beam_side=2), 32, (10, 10), "beam_side"),
+    (dict(see_yield=2), 32, (10, 10), "see_yield"),
+    (dict(see_yield=1, see_poly_Emax_eV=0.0), 32, (10, 10), "see_poly_Emax_eV"),
+    (dict(see_poly=np.array([0, 0, float("inf"), 0, 0, 0])), 32, (10, 10), "see_poly"),
+    (dict(see_law=2, see_ln_sigma=-1.0), 32, (10, 10), "see_ln"),
     (dict(beam_layer=0.01), 32, (10, 10), "beam_layer"),
     (dict(beam_layer=-1e-3), 32, (10, 10), "beam_layer"),
     (dict(beam_schedule=np.array([3, -1])), 32, (10, 10), "beam_schedule"),

@@ -203,6 +203,31 @@ def test_fp32_tesla_ground_pulse_parity(mode, layer):
     sim.close()
 
 
+@pytest.mark.parametrize("mode", [oracle.WEAK, oracle.STRICT])
+def test_fp32_paper_see_laws_parity(mode):
+    """The paper's SEE laws (Sec. 2.3, Alg. 2): the fifth-order yield clipped at
+    zero and lognormal electron energies, on the beam gap."""
+    cfg = cfg2_small().replace(see_amp=1.0, see_yield=W.YIELD_POLY,
+                               see_poly=np.array([0.05, 0.12, -2.0e-3, 2.0e-5, -1.0e-7, 2.0e-10]),
+                               see_poly_Emax_eV=8e4, see_law=W.SEE_LOGNORMAL,
+                               see_ln_mu=math.log(8.0), see_ln_sigma=0.7)
+    loads = W.load_config2(n=200_000, seed=12)
+    opts = {_gapsim().OPT_COMPACT_EVERY: 7}
+    sim, orc, recs = run_pair(cfg, loads, mode, 50, True, (400_000, 600_000), opts=opts)
+    check_run(recs, 1e-5, cfg.n_mesh)
+    check_fields(sim, orc, 1e-5)
+    d = recs[-1][0]
+    assert d["abs_cum"][1].sum() > 100 and d["emit_cum"].sum() > 100, (d["abs_cum"], d["emit_cum"])
+    for sp in (0, 1):
+        xg, ug, _ = sim.particles(0, sp)
+        xo, uo, _ = orc.particles_f32(sp)
+        assert len(xg) == len(xo)
+        a, b = sorted_state(xg, ug), sorted_state(xo, uo)
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+    sim.close()
+
+
 def test_fp32_error_against_fp64_oracle():
     """What binary32 particles cost, stated against the binary64 oracle (no bar
     beyond staying small over 50 steps)."""

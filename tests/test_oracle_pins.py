@@ -540,6 +540,56 @@ def test_see_yield_through_the_step():
     assert abs(e.mean() - 3.0) < 5 * 3.0 / math.sqrt(e.size)
 
 
+# the paper's fit: a fifth-order polynomial in keV (coefficients illustrative:
+# the Ar+-on-Cu data it was fitted to are not available)
+PAPER_LIKE_POLY = np.array([0.05, 0.12, -2.0e-3, 2.0e-5, -1.0e-7, 2.0e-10])
+
+
+def _impacts(cfg, E_eV, n=20000):
+    """n ions of energy E_eV one step from the circuit electrode; one step."""
+    v = -math.sqrt(2 * E_eV * cfg.ev / cfg.mass[1])
+    s = oracle.OracleSim(cfg)
+    s.inject(1, np.full(n, 1e-9), np.full(n, v))
+    s.step(oracle.STRICT, 1)
+    return s, s.diag()
+
+
+@pytest.mark.parametrize("E_eV", [5e3, 40e3, 120e3])
+def test_see_polynomial_yield(E_eV):
+    """Alg. 2 with the polynomial yield: the mean count per impact is the
+    polynomial at min(E, Emax) in keV (Emax clamps the fit's range), and a
+    polynomial that is negative there emits nothing."""
+    base = W.config1(n_cells=64).replace(see_amp=1.0, weight=0.0, see_yield=W.YIELD_POLY,
+                                         see_poly=PAPER_LIKE_POLY, see_poly_Emax_eV=8e4)
+    _, d = _impacts(base, E_eV)
+    x = min(E_eV, 8e4) / 1e3
+    gamma = float(np.polynomial.polynomial.polyval(x, PAPER_LIKE_POLY))
+    n = d["abs_step"][1][0]
+    mean = d["emit_step"][0] / n
+    assert abs(mean - gamma) < 5 * math.sqrt(gamma / n), (mean, gamma)
+    neg = base.replace(see_poly=-PAPER_LIKE_POLY)
+    _, d = _impacts(neg, E_eV, 2000)
+    assert d["emit_step"].sum() == 0
+
+
+def test_see_lognormal_energies():
+    """Alg. 2's energy law: the emitted electrons' energies follow
+    Lognormal(mu, sigma) (a one-sample KS test against its closed-form CDF)."""
+    from scipy import stats
+    mu, sig = math.log(8.0), 0.7
+    cfg = W.config1(n_cells=64).replace(see_amp=3.0, weight=0.0, see_law=W.SEE_LOGNORMAL,
+                                        see_ln_mu=mu, see_ln_sigma=sig)
+    s, d = _impacts(cfg, 20e3)
+    xe, ve, _ = s.particles(0)
+    assert xe.size == d["emit_step"][0] > 20000
+    assert np.all(xe == 0.0) and np.all(ve > 0)
+    e = 0.5 * cfg.mass[0] * ve**2 / cfg.ev
+    ks = stats.kstest(e, stats.lognorm(s=sig, scale=math.exp(mu)).cdf)
+    assert ks.pvalue > 0.01, ks
+    # the median of a lognormal is exp(mu)
+    assert abs(np.median(e) / math.exp(mu) - 1) < 0.03
+
+
 # ---------------------------------------------------------------------------
 # binary32 mode against binary64
 # ---------------------------------------------------------------------------
