@@ -50,7 +50,8 @@ typedef enum {
   GS_ECAPACITY = -3,  /* a gap ran out of particle slots; new particles were dropped */
   GS_EDEVICE = -4,    /* a HIP call failed; the context is unusable */
   GS_ENOCONV = -5,    /* a Newton solve missed its tolerance within its iteration cap */
-  GS_ESTATE = -6      /* call out of order (e.g. no context) */
+  GS_ESTATE = -6,     /* call out of order (e.g. no context) */
+  GS_ECALLBACK = -7   /* an external circuit engine reported failure; that step was not taken */
 } gs_status;
 
 enum { GS_SEE_FIXED = 0, GS_SEE_EXP = 1, GS_SEE_LOGNORMAL = 2 };
@@ -168,6 +169,8 @@ typedef struct {
   double newton_guess[GS_MAX_MESH + 1]; /* initial guess u = (V, I_0, ..) of the last solve
                                            (direct solve: the extrapolation) */
   double mlp_proposal[3]; /* the guess network's u at the last GS_GUESS_MLP solve, used or not */
+  double qcirc_step;      /* qcirc_star minus the previous level's qcirc: the charge the
+                             circuit moved onto the gap over the last step [C] */
 } gs_diag;
 
 /* Accumulated device time of the library's kernels, measured with HIP events
@@ -239,6 +242,70 @@ gs_status gs_step_strict(gs_ctx *ctx, int32_t n_steps, int32_t guess);
  * charge is re-imposed as C_gap phi0 (the circuit's increment history kept).
  * Asynchronous.  Errors as gs_step_strict. */
 gs_status gs_step_weak(gs_ctx *ctx, int32_t n_steps);
+
+/* Weak coupling with an external circuit engine (the SPICE-based solver option
+ * of Sec. 2.1 with Alg. 1, coupled as in Sec. 2.4.3).  The engine holds the
+ * circuit; for every step and gap the library calls
+ *   fn(user, gap, level, dt, phi0_prev, &v_gap)
+ * in gap order, on the calling thread, before any device work of that step:
+ * level n is the level about to be solved, phi0_prev the electrode potential of
+ * level n-1 (for n = 0: q0[gap_mesh] / (C_gap + c_par)).  The engine restarts
+ * its gap capacitor from phi0_prev (the reset Q_circ^{n-1} = C_gap phi0^{n-1}),
+ * advances its circuit over [t_{n-1}, t_n] and writes the gap voltage V* it
+ * reaches; the library takes Q_circ^n* = C_gap V* into the surface-charge
+ * update (eq. top_plate_charge), solves the field with the plain Gauss row
+ * (eq. Poisson_BC3), re-imposes Q_circ^n = C_gap phi0^n and pushes.  C_gap =
+ * eps0 area / d; an engine with c_par in its own circuit sees the parallel
+ * capacitor there.  The library's own loop charges are not advanced (the gap
+ * mesh holds (C_gap + c_par) phi0, the others keep their values, and the
+ * loop currents in gs_diag are not the engine's).  Any non-zero return from fn,
+ * or a non-finite v_gap, stops the call before that step's device work:
+ * GS_ECALLBACK (GS_EINVAL for a non-finite v_gap), with every earlier step
+ * done.  Synchronises the stream once per step; never uses a captured graph.
+ * Errors: GS_EINVAL (fn NULL, n_steps < 0), GS_ECALLBACK and those of
+ * gs_step_weak. */
+typedef int32_t (*gs_circuit_fn)(void *user, int32_t gap, int64_t level, double dt, double phi0_prev,
+                                 double *v_gap);
+gs_status gs_step_weak_external(gs_ctx *ctx, int32_t n_steps, gs_circuit_fn fn, void *user);
+
+/* Highest ringing angular frequency omega_max of a gap's circuit (App. D,
+ * circuit-resolution constraint), host only: the largest |Im lambda| over the
+ * finite roots of det(lambda^2 L + lambda R + S') = 0, the free response of
+ * the circuit in the parameters with S' = S plus the gap element's elastance
+ * 1 / (C_gap + c_par) in the gap mesh.  0 when no root oscillates (e.g. no
+ * inductance).  Errors: GS_EINVAL (invalid parameters, or the roots could not
+ * be found). */
+gs_status gs_circuit_resonance(const gs_gap_params *p, double *omega_max);
+
+/* Time-step check of one gap against the constraints of App. D (time segment
+ * selection), a posteriori, at the last completed step:
+ *   omega_max  gs_circuit_resonance of the gap's parameters (an external
+ *              circuit engine may run another circuit); n_omega = 1 /
+ *              (omega_max dt), infinite when omega_max is 0, to be at least
+ *              N_omega (20..50);
+ *   beta[s]    largest |v_x| dt / dx over live particles of species s (the
+ *              cell-crossing number, at most 0.2..0.5); v_max[s] that |v_x|;
+ *   n_e_max    largest live-electron density in one cell, count * weight / dx
+ *              [m^-3]; omega_pe = sqrt(n_e_max e^2 / (eps0 m_e)) with
+ *              e = q_unit |Z[0]|, m_e = mass[0]; alpha = omega_pe dt (at most
+ *              0.1..0.2);
+ *   eta        |qcirc_step| / max(|qcirc_star|, |previous qcirc|): the
+ *              circuit's relative charge change over the step, dt I_ref /
+ *              Q_ref with I_ref = |qcirc_step| / dt (at most 0.05..0.2; 0
+ *              when both charges are 0).
+ * flags: bit 0 n_omega < 20, bit 1 a beta above 0.5, bit 2 alpha > 0.2, bit 3
+ * eta > 0.2 (the permissive end of each of the paper's ranges).  Synchronises;
+ * the scan runs on the device.  Errors: GS_EINVAL, GS_ENOMEM, GS_EDEVICE, the
+ * sticky step errors. */
+typedef struct {
+  double dt;
+  double omega_max, n_omega;
+  double v_max[2], beta[2];
+  double n_e_max, omega_pe, alpha;
+  double eta;
+  int32_t flags;
+} gs_dt_report;
+gs_status gs_dt_check(gs_ctx *ctx, int32_t gap, gs_dt_report *out);
 
 /* Read one gap's state (synchronises the stream).  phi (n_cells + 1 values),
  * E (n_cells half-grid values E_{k+1/2}) and rho (n_cells + 1 nodal densities,

@@ -7,6 +7,7 @@ does not import this module, and this module does not import the GPU binding).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -15,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 MAX_MESH = 8
-STRICT, WEAK = 0, 1
+STRICT, WEAK, WEAK_EXT = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -70,7 +71,7 @@ class OrDiag(C.Structure):
         ("n_live", C.c_int64 * 2),
         ("abs_step", (C.c_int64 * 2) * 2), ("emit_step", C.c_int64 * 2), ("inj_step", C.c_int64),
         ("abs_cum", (C.c_int64 * 2) * 2), ("emit_cum", C.c_int64 * 2), ("inj_cum", C.c_int64),
-        ("pushed_cum", C.c_int64),
+        ("pushed_cum", C.c_int64), ("qcirc_step", C.c_double),
     ]
 
 
@@ -95,6 +96,10 @@ def lib():
         L.or_step.argtypes = [C.c_void_p, C.c_int32]
         L.or_step.restype = C.c_int32
         L.or_get_diag.argtypes = [C.c_void_p, C.POINTER(OrDiag)]
+        L.or_step_external.argtypes = [C.c_void_p, C.c_double]
+        L.or_step_external.restype = C.c_int32
+        L.or_phi0_prev.argtypes = [C.c_void_p]
+        L.or_phi0_prev.restype = C.c_double
         L.or_get_fields.argtypes = [C.c_void_p, P, P, P]
         L.or_count.argtypes = [C.c_void_p, C.c_int32]
         L.or_count.restype = C.c_int64
@@ -263,6 +268,35 @@ def round_bf16(a) -> np.ndarray:
     return np.array([f(float(v)) for v in a.ravel()], dtype=np.float32).reshape(a.shape)
 
 
+def circuit_resonance(cfg) -> float:
+    """Highest ringing angular frequency of a gap's circuit (App. D,
+    circuit-resolution constraint): the largest |Im lambda| over the finite roots
+    of det(lambda^2 L + lambda R + S') = 0, S' = S plus 1 / (C_gap + c_par) in the
+    gap mesh.  With lambda = w0 mu, w0 = sqrt(|S'| / |L|) (largest entries), and
+    the matrices divided by |S'|, the scaled roots mu are the finite generalized
+    eigenvalues of the first-order pencil A z = mu B z, z = (q, q'),
+    A = [[0, I], [-S~, -R~]], B = [[I, 0], [0, L~]] (LAPACK's QZ through scipy);
+    an eigenvalue whose beta is below 1e-12 of its alpha is infinite.  0 when
+    no root oscillates."""
+    import scipy.linalg as sl
+    M, g = cfg.n_mesh, cfg.gap_mesh
+    S = np.array(cfg.S, dtype=np.float64).copy()
+    S[g, g] += 1.0 / (cfg.eps0 * cfg.area / cfg.d + cfg.c_par)
+    L = np.asarray(cfg.L, dtype=np.float64)
+    R = np.asarray(cfg.R, dtype=np.float64)
+    if np.abs(L).max() == 0.0:
+        return 0.0
+    s = np.abs(S).max()
+    w0 = math.sqrt(s / np.abs(L).max())
+    Z, I = np.zeros((M, M)), np.eye(M)
+    A = np.block([[Z, I], [-S / s, -R * (w0 / s)]])
+    B = np.block([[I, Z], [Z, L * (w0 * w0 / s)]])
+    (a, b), _ = sl.eig(A, B, homogeneous_eigvals=True)
+    fin = np.abs(b) > 1e-12 * np.abs(a)
+    lam = w0 * (a[fin] / b[fin])
+    return float(np.abs(lam.imag).max()) if lam.size else 0.0
+
+
 class OracleSim:
     """One gap advanced by the oracle."""
 
@@ -271,6 +305,7 @@ class OracleSim:
         self.fp32 = fp32
         self._p = params_from(cfg, fp32)
         self._h = lib().or_create(C.byref(self._p))
+        self._stepped = False
         if not self._h:
             raise ValueError("oracle rejected the parameters")
 
@@ -292,6 +327,7 @@ class OracleSim:
             rc = lib().or_step(self._h, mode)
             if rc:
                 raise RuntimeError(f"or_step failed: {rc}")
+            self._stepped = True
 
     def diag(self) -> dict:
         D = OrDiag()
@@ -305,7 +341,58 @@ class OracleSim:
                     emit_step=np.array(D.emit_step[:]), inj_step=D.inj_step,
                     abs_cum=np.array([[D.abs_cum[a][b] for b in range(2)] for a in range(2)]),
                     emit_cum=np.array(D.emit_cum[:]), inj_cum=D.inj_cum,
-                    pushed_cum=D.pushed_cum)
+                    pushed_cum=D.pushed_cum, qcirc_step=D.qcirc_step)
+
+    def phi0_prev(self) -> float:
+        return float(lib().or_phi0_prev(self._h))
+
+    def step_external(self, engine, n: int = 1, gap: int = 0):
+        """Weak steps with an external circuit engine (Alg. 1 coupled as in Sec. 2.4.3):
+        engine(gap, level, dt, phi0_prev) returns the gap voltage V* its circuit reaches
+        at that level after restarting the gap capacitor from phi0_prev."""
+        for _ in range(n):
+            level = self.diag()["step"] + 1 if self._stepped else 0
+            v = float(engine(gap, level, self.cfg.dt, self.phi0_prev()))
+            rc = lib().or_step_external(self._h, v)
+            if rc:
+                raise RuntimeError(f"or_step_external failed: {rc}")
+            self._stepped = True
+
+    def dt_report(self) -> dict:
+        """The time-step constraints of App. D at the last completed level, from the
+        oracle's own state: circuit_resonance below, the largest |v_x| dt / dx per
+        species, the most live electrons in one cell (count * weight / dx), the plasma
+        frequency that density gives, and the relative change of the circuit charge
+        over the last step."""
+        cfg = self.cfg
+        dx = cfg.d / cfg.n_cells
+        beta = np.zeros(2)
+        cells = np.zeros(cfg.n_cells, dtype=np.int64)
+        for sp in range(2):
+            if self.fp32:
+                xi, u, _ = self.particles_f32(sp)
+                xi = xi.astype(np.float64)
+                u = u.astype(np.float64)
+            else:
+                x, v, _ = self.particles(sp)
+                xi, u = x / dx, v * cfg.dt / dx
+            if u.size:
+                beta[sp] = np.abs(u).max()
+            if sp == 0 and xi.size:
+                np.add.at(cells, np.minimum(np.floor(xi).astype(np.int64), cfg.n_cells - 1), 1)
+        w = circuit_resonance(cfg)
+        n_e = cells.max() * cfg.weight / dx
+        qe = cfg.q_unit * abs(cfg.Z[0])
+        w_pe = np.sqrt(n_e * qe * qe / (cfg.eps0 * cfg.mass[0]))
+        D = self.diag()
+        q_prev = D["qcirc_star"] - D["qcirc_step"]
+        q_ref = max(abs(D["qcirc_star"]), abs(q_prev))
+        eta = abs(D["qcirc_step"]) / q_ref if q_ref > 0 else 0.0
+        n_omega = 1.0 / (w * cfg.dt) if w > 0 else np.inf
+        alpha = w_pe * cfg.dt
+        flags = ((n_omega < 20) * 1) | ((beta.max() > 0.5) * 2) | ((alpha > 0.2) * 4) | ((eta > 0.2) * 8)
+        return dict(dt=cfg.dt, omega_max=w, n_omega=n_omega, beta=beta, v_max=beta * dx / cfg.dt,
+                    n_e_max=n_e, omega_pe=w_pe, alpha=alpha, eta=eta, flags=int(flags))
 
     def fields(self):
         N = self.cfg.n_cells

@@ -156,6 +156,7 @@ struct or_sim {
   float *ehat;
   float alpha32[2];       /* q dt^2 / (m dx) in binary32 */
   int64_t *sched;         /* own copy of the beam schedule (p.beam_schedule points here) */
+  double v_ext;           /* OR_WEAK_EXT: the external engine's gap voltage for the level */
   or_diag diag;
 };
 
@@ -477,6 +478,22 @@ static int solve_level(or_sim *s, int mode) {
       Dn[j] = y[j] - z[j] * phi0;
       q[j] = s->qprev[j] + Dn[j];
     }
+  } else if (mode == OR_WEAK_EXT) {
+    /* an external engine has stepped the circuit (Alg. 1) and handed over the
+     * gap voltage it reached: Q_gap* = C3 V* enters eq. top_plate_charge */
+    qstar = cgap * s->v_ext;
+    sigma = s->sigma_prev + (qconv + qstar - s->qcirc_prev) / A;
+    or_poisson_gauss(N, dx, eps0, sigma, s->rho, s->phi);
+    const double phi0 = s->phi[0];
+    /* the engine holds the circuit: the own loops stay where they are, only
+     * the gap mesh carries the re-imposed charge Q4^n = C3 phi0^n */
+    for (int j = 0; j < M; ++j) {
+      q[j] = s->qprev[j];
+      Dn[j] = 0.0;
+    }
+    q[g] = (cgap + p->c_par) * phi0;
+    Dn[g] = q[g] - s->qprev[g];
+    qcirc = cgap * phi0;
   } else {
     /* circuit first, with the gap as a capacitor: Q_gap* = C3 V_C3 */
     double D[OR_MAX_MESH] = {0}, qs[OR_MAX_MESH] = {0};
@@ -522,6 +539,7 @@ static int solve_level(or_sim *s, int mode) {
     D->I[j] = 0.0;
   }
   D->qcirc_star = qstar;
+  D->qcirc_step = qstar - s->qcirc_prev;
   for (int j = 0; j < M; ++j) {
     D->q[j] = q[j];
     D->I[j] = (3.0 * Dn[j] - s->dq[0][j]) / (2.0 * p->dt);
@@ -775,6 +793,19 @@ int32_t or_step(or_sim *s, int32_t mode) {
   D->pushed_cum += n_old;
   s->step += 1;
   return 0;
+}
+
+int32_t or_step_external(or_sim *s, double v_star) {
+  s->v_ext = v_star;
+  return or_step(s, OR_WEAK_EXT);
+}
+
+double or_phi0_prev(const or_sim *s) {
+  if (s->step == 0) {
+    const double cgap = s->p.eps0 * s->p.area / s->p.d;
+    return s->p.q0[s->p.gap_mesh] / (cgap + s->p.c_par);
+  }
+  return s->phi[0];
 }
 
 void or_get_diag(const or_sim *s, or_diag *out) {

@@ -31,7 +31,7 @@ extern "C" {
 
 #define OR_MAX_MESH 8
 
-enum { OR_STRICT = 0, OR_WEAK = 1 };
+enum { OR_STRICT = 0, OR_WEAK = 1, OR_WEAK_EXT = 2 };
 enum { OR_SEE_FIXED = 0, OR_SEE_EXP = 1, OR_SEE_LOGNORMAL = 2 };
 enum { OR_YIELD_SATURATING = 0, OR_YIELD_POLY = 1 };
 
@@ -105,6 +105,7 @@ typedef struct {
   int64_t emit_cum[2];
   int64_t inj_cum;
   int64_t pushed_cum;     /* particle pushes so far (particle-steps) */
+  double qcirc_step;      /* qcirc_star - Q_circ^{n-1} */
 } or_diag;
 
 typedef struct or_sim or_sim;
@@ -121,6 +122,14 @@ void or_destroy(or_sim *s);
 int32_t or_inject(or_sim *s, int32_t species, int64_t n, const double *x, const double *v);
 /* one time step: solve level n (strict or weak), push to n+1 */
 int32_t or_step(or_sim *s, int32_t mode);
+/* One weak step with an external circuit engine (Alg. 1 coupled as in
+ * Sec. 2.4.3): v_star is the gap voltage the engine reached at level n after
+ * restarting its gap capacitor from or_phi0_prev.  Or_step with OR_WEAK_EXT
+ * uses the value given last. */
+int32_t or_step_external(or_sim *s, double v_star);
+/* Electrode potential of the last solved level (before level 0: the gap mesh's
+ * initial charge over C_gap + c_par). */
+double or_phi0_prev(const or_sim *s);
 void or_get_diag(const or_sim *s, or_diag *out);
 /* level-n fields of the last solve: phi[N+1], E[N] (half-grid), rho[N+1] */
 void or_get_fields(const or_sim *s, double *phi, double *E, double *rho);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -45,6 +46,7 @@ struct gs_ctx {
   std::vector<int64_t> next_id;
   std::vector<std::vector<int64_t>> sched;  // per gap: copy of the beam schedule (empty: none)
   std::vector<int> sched_on;                // per gap: the schedule is in force
+  std::vector<double> ext_phi, ext_v;       // host staging of the external circuit engine's exchange
   std::string err;
   int sticky = 0;  // gs_status of a device error already seen
   // timing
@@ -400,6 +402,9 @@ static gs_status setup(gs_ctx *ctx) {
   int64_t *sched_d = nullptr;
   ALLOC(sched_d, int64_t *, std::max<size_t>(nsched, 1) * 8);
   d.sched = sched_d;
+  double *ext_d = nullptr;
+  ALLOC(ext_d, double *, (size_t)G * 8);
+  d.ext_v = ext_d;
   // overflow event regions for up to eight 256-thread push workgroups per CU
   // (the largest grid the autotuner tries), when any gap emits
   bool emits = false;
@@ -429,6 +434,7 @@ static gs_status setup(gs_ctx *ctx) {
   HIPCHK(ctx, hipMemsetAsync(d.cursor, 0, (size_t)G * 2 * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.tally, 0, (size_t)G * T_N * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.ev_count, 0, (size_t)G * 8, s));
+  HIPCHK(ctx, hipMemsetAsync(ext_d, 0, (size_t)G * 8, s));
   for (int g = 0; g < G; ++g)
     if (!ctx->sched[g].empty())
       HIPCHK(ctx, hipMemcpyAsync(sched_d + ctx->hc[g].sched_base, ctx->sched[g].data(), ctx->sched[g].size() * 8,
@@ -728,6 +734,339 @@ extern "C" gs_status gs_step_weak(gs_ctx *ctx, int32_t n_steps) {
   return run_steps(ctx, n_steps, 1, GS_GUESS_DIRECT);
 }
 
+extern "C" gs_status gs_step_weak_external(gs_ctx *ctx, int32_t n_steps, gs_circuit_fn fn, void *user) {
+  if (!ctx) return GS_ESTATE;
+  if (!fn || n_steps < 0) return fail(ctx, GS_EINVAL, "fn is NULL or n_steps < 0");
+  gs_status st = check_sticky(ctx, false);
+  if (st != GS_OK) return st;
+  const int G = ctx->G;
+  ctx->ext_phi.resize(G);
+  ctx->ext_v.resize(G);
+  for (int k = 0; k < n_steps; ++k) {
+    const int64_t n = ctx->steps_done;  // the level this step solves
+    if (n == 0) {
+      // before the first level the electrode holds the gap mesh's initial charge
+      for (int g = 0; g < G; ++g) {
+        const GapConst &c = ctx->hc[g];
+        ctx->ext_phi[g] = ctx->params[g].q0[c.g] / (c.cgap + c.c_par);
+      }
+    } else {
+      HIPCHK(ctx, hipMemcpy2DAsync(ctx->ext_phi.data(), 8, &ctx->dp.gs[0].phi0, sizeof(GapState), 8, (size_t)G,
+                                   hipMemcpyDeviceToHost, ctx->stream));
+    }
+    // also waits for the previous step (and the last upload from ext_v)
+    if ((st = check_sticky(ctx, true)) != GS_OK) return st;
+    for (int g = 0; g < G; ++g) {
+      double v = 0.0;
+      const int32_t rc = fn(user, g, n, ctx->hc[g].dt, ctx->ext_phi[g], &v);
+      if (rc != 0)
+        return fail(ctx, GS_ECALLBACK, "circuit engine returned %d for gap %d at level %lld; step not taken", rc, g,
+                    (long long)n);
+      if (!std::isfinite(v))
+        return fail(ctx, GS_EINVAL, "circuit engine gave a non-finite gap voltage for gap %d at level %lld", g,
+                    (long long)n);
+      ctx->ext_v[g] = v;
+    }
+    HIPCHK(ctx, hipMemcpyAsync((void *)ctx->dp.ext_v, ctx->ext_v.data(), (size_t)G * 8, hipMemcpyHostToDevice,
+                               ctx->stream));
+    if ((st = one_step(ctx, 2, GS_GUESS_DIRECT)) != GS_OK) return st;
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return check_sticky(ctx, false);
+}
+
+// ---------------------------------------------------------------------------
+// circuit resonance (App. D, circuit-resolution constraint)
+// ---------------------------------------------------------------------------
+typedef std::complex<double> cplx;
+
+// Eigenvalues of a real n x n matrix (row-major, n <= 2 MAXM): diagonal
+// balancing by powers of two (Parlett and Reinsch), Householder reduction to
+// Hessenberg form, then single-shift complex QR steps with Givens rotations
+// (Wilkinson shift from the trailing 2 x 2 block, an ad hoc shift after 10
+// and 20 steps without deflation), deflating one eigenvalue at a time.
+// Returns false when some eigenvalue did not converge in 60 steps.
+static bool eigenvalues(int n, double *A, cplx *ev) {
+  auto at = [&](int i, int j) -> double & { return A[i * n + j]; };
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (int i = 0; i < n; ++i) {
+      double c = 0.0, r = 0.0;
+      for (int j = 0; j < n; ++j)
+        if (j != i) {
+          c += std::fabs(at(j, i));
+          r += std::fabs(at(i, j));
+        }
+      if (c == 0.0 || r == 0.0) continue;
+      const double s0 = c + r;
+      double f = 1.0;
+      while (c < 0.5 * r) {
+        c *= 2.0;
+        r *= 0.5;
+        f *= 2.0;
+      }
+      while (c >= 2.0 * r) {
+        c *= 0.5;
+        r *= 2.0;
+        f *= 0.5;
+      }
+      if (c + r < 0.95 * s0) {
+        changed = true;
+        for (int j = 0; j < n; ++j) at(j, i) *= f;
+        for (int j = 0; j < n; ++j) at(i, j) /= f;
+      }
+    }
+  }
+  // Hessenberg: reflect x = A[k+1.., k] onto a multiple of e_1
+  double v[2 * MAXM];
+  for (int k = 0; k + 2 < n; ++k) {
+    double nx = 0.0;
+    for (int i = k + 1; i < n; ++i) nx += at(i, k) * at(i, k);
+    nx = std::sqrt(nx);
+    if (nx == 0.0) continue;
+    const double a0 = at(k + 1, k);
+    for (int i = k + 1; i < n; ++i) v[i] = at(i, k);
+    v[k + 1] = a0 + (a0 >= 0.0 ? nx : -nx);
+    double vv = 0.0;
+    for (int i = k + 1; i < n; ++i) vv += v[i] * v[i];
+    for (int j = 0; j < n; ++j) {  // A <- (I - 2 v v^T / vv) A
+      double d = 0.0;
+      for (int i = k + 1; i < n; ++i) d += v[i] * at(i, j);
+      d *= 2.0 / vv;
+      for (int i = k + 1; i < n; ++i) at(i, j) -= d * v[i];
+    }
+    for (int i = 0; i < n; ++i) {  // A <- A (I - 2 v v^T / vv)
+      double d = 0.0;
+      for (int j = k + 1; j < n; ++j) d += at(i, j) * v[j];
+      d *= 2.0 / vv;
+      for (int j = k + 1; j < n; ++j) at(i, j) -= d * v[j];
+    }
+    for (int i = k + 2; i < n; ++i) at(i, k) = 0.0;
+  }
+  cplx H[2 * MAXM][2 * MAXM];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) H[i][j] = cplx(at(i, j), 0.0);
+  const double eps = 2.220446049250313e-16;
+  for (int m = n; m > 0;) {  // H[0..m) is the active block
+    if (m == 1) {
+      ev[0] = H[0][0];
+      break;
+    }
+    int its = 0;
+    for (;;) {
+      if (std::abs(H[m - 1][m - 2]) <= eps * (std::abs(H[m - 1][m - 1]) + std::abs(H[m - 2][m - 2]))) break;
+      if (its == 60) return false;
+      // shift: the eigenvalue of the trailing 2 x 2 block nearer its last entry
+      cplx mu;
+      if (its == 10 || its == 20) {
+        mu = H[m - 1][m - 1] + cplx(0.75 * std::abs(H[m - 1][m - 2]), 0.0);
+      } else {
+        const cplx a = H[m - 2][m - 2], b = H[m - 2][m - 1], c = H[m - 1][m - 2], d = H[m - 1][m - 1];
+        const cplx hlf = 0.5 * (a - d), disc = std::sqrt(hlf * hlf + b * c);
+        const cplx l1 = d + hlf + disc, l2 = d + hlf - disc;
+        mu = std::abs(l1 - d) < std::abs(l2 - d) ? l1 : l2;
+      }
+      ++its;
+      // H - mu I = Q R by Givens rotations on rows (k, k+1); then H = R Q + mu I
+      cplx gc[2 * MAXM], gs[2 * MAXM];
+      for (int i = 0; i < m; ++i) H[i][i] -= mu;
+      for (int k = 0; k + 1 < m; ++k) {
+        const cplx x = H[k][k], y = H[k + 1][k];
+        const double r = std::sqrt(std::norm(x) + std::norm(y));
+        cplx c(1.0, 0.0), s(0.0, 0.0);
+        if (r > 0.0) {
+          c = x / r;
+          s = y / r;
+        }
+        gc[k] = c;
+        gs[k] = s;
+        for (int j = k; j < m; ++j) {  // [c* s*; -s c] applied to rows k, k+1
+          const cplx p = H[k][j], q = H[k + 1][j];
+          H[k][j] = std::conj(c) * p + std::conj(s) * q;
+          H[k + 1][j] = -s * p + c * q;
+        }
+      }
+      for (int k = 0; k + 1 < m; ++k) {  // columns k, k+1 times the adjoint rotation
+        const cplx c = gc[k], s = gs[k];
+        const int top = std::min(k + 2, m - 1);
+        for (int i = 0; i <= top; ++i) {
+          const cplx p = H[i][k], q = H[i][k + 1];
+          H[i][k] = p * c + q * s;
+          H[i][k + 1] = -p * std::conj(s) + q * std::conj(c);
+        }
+      }
+      for (int i = 0; i < m; ++i) H[i][i] += mu;
+    }
+    ev[m - 1] = H[m - 1][m - 1];
+    --m;
+  }
+  return true;
+}
+
+// Highest ringing angular frequency of a gap's circuit: the largest |Im lambda|
+// over the finite roots of det(lambda^2 L + lambda R + S') = 0, S' = S plus the
+// gap element's elastance 1 / (C_gap + c_par) in the gap mesh (the free
+// response of L q'' + R q' + S' q = 0).  L, R and S' may all be singular, so
+// the roots come from a shifted and inverted pencil: with a real shift s that
+// is not a root, P(s + 1/mu) = 0 exactly when mu is an eigenvalue of the
+// companion matrix [[0, I], [-P(s)^-1 L, -P(s)^-1 (2 s L + R)]]; mu = 0
+// belongs to infinite roots (so do roots more than 1e6 times farther from s
+// than the nearest one).  0 when no root oscillates.
+static gs_status circuit_resonance(const gs_gap_params &p, double *omega) {
+  const int M = p.n_mesh, n = 2 * M;
+  const double cgap = p.eps0 * p.area / p.d;
+  double S[MAXM][MAXM], Ln = 0.0, Rn = 0.0, Sn = 0.0;
+  for (int i = 0; i < M; ++i)
+    for (int j = 0; j < M; ++j) {
+      S[i][j] = p.S[i][j];
+      if (i == p.gap_mesh && j == p.gap_mesh) S[i][j] += 1.0 / (cgap + p.c_par);
+      Ln = std::max(Ln, std::fabs(p.L[i][j]));
+      Rn = std::max(Rn, std::fabs(p.R[i][j]));
+      Sn = std::max(Sn, std::fabs(S[i][j]));
+    }
+  *omega = 0.0;
+  // no inductance, or nothing for it to ring against: no oscillating root
+  if (Ln == 0.0 || (Sn == 0.0 && Rn == 0.0)) return GS_OK;
+  // shift of the size of the roots: the LC (else RL) rate of the largest entries
+  const double s0 = Sn > 0.0 ? -std::sqrt(Sn / Ln) : -Rn / Ln;
+  static const double tries[] = {1.0, 1.37, 0.61, 2.9, 0.23};
+  for (double f : tries) {
+    const double s = s0 * f;
+    // P(s) and its LU factors with partial pivoting
+    double P[MAXM][MAXM], Rs[MAXM][MAXM];
+    int piv[MAXM];
+    double pmax = 0.0;
+    for (int i = 0; i < M; ++i)
+      for (int j = 0; j < M; ++j) {
+        P[i][j] = s * s * p.L[i][j] + s * p.R[i][j] + S[i][j];
+        Rs[i][j] = 2.0 * s * p.L[i][j] + p.R[i][j];
+        pmax = std::max(pmax, std::fabs(P[i][j]));
+      }
+    bool singular = false;
+    for (int k = 0; k < M && !singular; ++k) {
+      int r = k;
+      for (int i = k + 1; i < M; ++i)
+        if (std::fabs(P[i][k]) > std::fabs(P[r][k])) r = i;
+      if (!(std::fabs(P[r][k]) > 1e-12 * pmax)) {
+        singular = true;
+        break;
+      }
+      piv[k] = r;
+      if (r != k)
+        for (int j = 0; j < M; ++j) std::swap(P[k][j], P[r][j]);
+      for (int i = k + 1; i < M; ++i) {
+        P[i][k] /= P[k][k];
+        for (int j = k + 1; j < M; ++j) P[i][j] -= P[i][k] * P[k][j];
+      }
+    }
+    if (singular) continue;
+    auto solve = [&](double *b) {
+      // whole rows (multipliers included) were swapped: permute b first
+      for (int k = 0; k < M; ++k) std::swap(b[k], b[piv[k]]);
+      for (int k = 0; k < M; ++k)
+        for (int i = k + 1; i < M; ++i) b[i] -= P[i][k] * b[k];
+      for (int k = M - 1; k >= 0; --k) {
+        for (int j = k + 1; j < M; ++j) b[k] -= P[k][j] * b[j];
+        b[k] /= P[k][k];
+      }
+    };
+    double K[4 * MAXM * MAXM];
+    for (int i = 0; i < n * n; ++i) K[i] = 0.0;
+    for (int i = 0; i < M; ++i) K[i * n + M + i] = 1.0;
+    for (int j = 0; j < M; ++j) {
+      double a[MAXM], b[MAXM];
+      for (int i = 0; i < M; ++i) {
+        a[i] = p.L[i][j];
+        b[i] = Rs[i][j];
+      }
+      solve(a);
+      solve(b);
+      for (int i = 0; i < M; ++i) {
+        K[(M + i) * n + j] = -a[i];
+        K[(M + i) * n + M + j] = -b[i];
+      }
+    }
+    cplx mu[2 * MAXM];
+    if (!eigenvalues(n, K, mu)) continue;
+    double mmax = 0.0;
+    for (int i = 0; i < n; ++i) mmax = std::max(mmax, std::abs(mu[i]));
+    // mu = 0 (an infinite root) can sit in a Jordan block of size two (a loop
+    // of capacitors without inductance), which rounding splits by about
+    // sqrt(eps) of the spectrum: take |mu| below 1e-6 of the largest as infinite
+    double w = 0.0;
+    for (int i = 0; i < n; ++i)
+      if (std::abs(mu[i]) > 1e-6 * mmax) w = std::max(w, std::fabs((1.0 / mu[i]).imag()));
+    *omega = w;
+    return GS_OK;
+  }
+  return GS_EINVAL;
+}
+
+extern "C" gs_status gs_circuit_resonance(const gs_gap_params *p, double *omega_max) {
+  if (!p || !omega_max) return GS_EINVAL;
+  char msg[256];
+  if (gs_validate_params(p, msg, sizeof msg) != GS_OK) return GS_EINVAL;
+  return circuit_resonance(*p, omega_max);
+}
+
+extern "C" gs_status gs_dt_check(gs_ctx *ctx, int32_t gap, gs_dt_report *out) {
+  if (!ctx) return GS_ESTATE;
+  if (gap < 0 || gap >= ctx->G || !out) return fail(ctx, GS_EINVAL, "bad gap or out is NULL");
+  gs_status st = check_sticky(ctx, true);
+  if (st != GS_OK) return st;
+  const GapConst &c = ctx->hc[gap];
+  const gs_gap_params &p = ctx->params[gap];
+  const size_t bytes = 16 + (size_t)c.N * 4;
+  void *buf = nullptr;
+  if (hipMalloc(&buf, bytes) != hipSuccess) return fail(ctx, GS_ENOMEM, "time-step check: %zu bytes", bytes);
+  unsigned long long um[2] = {0ull, 0ull};
+  std::vector<unsigned int> cells((size_t)c.N);
+  GapState s;
+  hipError_t e = hipMemsetAsync(buf, 0, bytes, ctx->stream);
+  if (e == hipSuccess)
+    e = launch_dt_scan(ctx->dp, gap, c.N, ctx->fp64, (unsigned long long *)buf, (unsigned int *)((char *)buf + 16),
+                       ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(um, buf, 16, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(cells.data(), (char *)buf + 16, (size_t)c.N * 4, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&s, ctx->dp.gs + gap, sizeof s, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "time-step check: %s", hipGetErrorString(e));
+  gs_dt_report r;
+  memset(&r, 0, sizeof r);
+  r.dt = p.dt;
+  if (circuit_resonance(p, &r.omega_max) != GS_OK)
+    return fail(ctx, GS_EINVAL, "gap %d: the circuit's roots could not be found", gap);
+  r.n_omega = r.omega_max > 0.0 ? 1.0 / (r.omega_max * p.dt) : INFINITY;
+  for (int sp = 0; sp < 2; ++sp) {
+    double u;
+    if (ctx->fp64) {
+      memcpy(&u, &um[sp], 8);
+    } else {
+      const uint32_t b = (uint32_t)um[sp];
+      float f;
+      memcpy(&f, &b, 4);
+      u = (double)f;
+    }
+    r.beta[sp] = u;
+    r.v_max[sp] = u * c.dx / p.dt;
+  }
+  unsigned int cmax = 0;
+  for (unsigned int k : cells) cmax = std::max(cmax, k);
+  r.n_e_max = (double)cmax * p.weight / c.dx;
+  const double qe = p.q_unit * std::fabs((double)p.Z[0]);
+  r.omega_pe = std::sqrt(r.n_e_max * qe * qe / (p.eps0 * p.mass[0]));
+  r.alpha = r.omega_pe * p.dt;
+  const double qprev = s.qcirc_star - s.qcirc_step;
+  const double qref = std::max(std::fabs(s.qcirc_star), std::fabs(qprev));
+  r.eta = qref > 0.0 ? std::fabs(s.qcirc_step) / qref : 0.0;
+  r.flags = (r.n_omega < 20.0 ? 1 : 0) | (r.beta[0] > 0.5 || r.beta[1] > 0.5 ? 2 : 0) | (r.alpha > 0.2 ? 4 : 0) |
+            (r.eta > 0.2 ? 8 : 0);
+  *out = r;
+  return GS_OK;
+}
+
 extern "C" gs_status gs_read_diagnostics(gs_ctx *ctx, int32_t gap, gs_diag *out, double *phi, double *E,
                                          double *rho) {
   if (!ctx) return GS_ESTATE;
@@ -792,6 +1131,7 @@ extern "C" gs_status gs_read_diagnostics(gs_ctx *ctx, int32_t gap, gs_diag *out,
   out->newton_resid = s.newton_r;
   for (int j = 0; j <= c.M; ++j) out->newton_guess[j] = s.guess[j];
   for (int j = 0; j < 3; ++j) out->mlp_proposal[j] = s.mlp_prop[j];
+  out->qcirc_step = s.qcirc_step;
   return check_sticky(ctx, true);
 }
 

@@ -77,6 +77,7 @@ struct GapState {
   double uh[3][MAXM + 1];
   // diagnostics of the last solved level
   double t, phi0, sigma, qcirc, qcirc_star, qconv, e_ground;
+  double qcirc_step;    // Q_circ* of this level minus Q_circ of the one before
   double q[MAXM], I[MAXM];
   int64_t abs_last[4], emit_last[2], inj_last, pushed_last;
   int64_t abs_cum[4], emit_cum[2], inj_cum, pushed_cum;
@@ -119,6 +120,8 @@ struct DevPtrs {
   Event *ev;                       // absorbed-ion events, per-gap lists
   unsigned long long *ev_count;    // [G]
   const int64_t *sched;            // beam schedules of all gaps (GapConst::sched_base)
+  const double *ext_v;             // [G] gap voltage an external circuit engine gave for
+                                   //   the level being solved (field mode 2)
   Event *ovf;                      // push workgroup b < ovf_wgs: events past its LDS queue,
   int64_t ovf_wgs;                 //   OVQ of them from ovf + b * OVQ
   // Newton guess network: bfloat16 weights (flat layout of gs_mlp_dev.h) and
@@ -164,6 +167,10 @@ hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStrea
 hipError_t launch_inject(const DevPtrs &p, int gap, int species, long long n, const double *x_dev,
                          const double *v_dev, long long id0, int fp64, hipStream_t s);
 hipError_t launch_phi(const DevPtrs &p, int gap, hipStream_t s);
+// time-step check: largest |u| per species (bit patterns of non-negative
+// floats, max-reduced as unsigned integers) and electrons per cell of one gap
+hipError_t launch_dt_scan(const DevPtrs &p, int gap, int N, int fp64, unsigned long long *umax,
+                          unsigned int *cells, hipStream_t s);
 // guess network (gs_mlp.hip): y[n][3] = net(x[n][48]) with bfloat16 weights W
 hipError_t launch_mlp_forward(const uint16_t *W, const float *x, long long n, float *y, hipStream_t s);
 size_t push_lds_bytes(int nmax, int fp64, int G, int wide);

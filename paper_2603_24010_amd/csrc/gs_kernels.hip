@@ -459,6 +459,22 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
     }
     st.newton_r0 = r0n;
     st.newton_r = rn;
+  } else if (mode == 2) {
+    // weak with an external circuit engine: its gap voltage V* for this level
+    // gives Q_circ* = C_gap V* (Sec. 2.4.3); the library's own loops are not
+    // advanced, only the gap mesh follows the re-imposed charge
+    qstar = c.cgap * p.ext_v[g];
+    sigma = st.sigma_prev + (qconv + qstar - st.qcirc_prev) / A;
+    phi0 = (c.d / eps0) * sigma + P;
+    for (int j = 0; j < M; ++j) {
+      q[j] = st.qprev[j];
+      Dn[j] = 0.0;
+    }
+    q[gm] = (c.cgap + c.c_par) * phi0;
+    Dn[gm] = q[gm] - st.qprev[gm];
+    qcirc = c.cgap * phi0;
+    st.newton_last = -1;
+    st.newton_fb_last = 0;
   } else {
     // weak: the circuit alone with the gap as a capacitor, then the field
     for (int i = 0; i < M; ++i) {
@@ -508,6 +524,7 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
     st.hist[hh][5] = qsh_e * (double)em[0];
     st.hist_head = (hh + 1) & 7;
   }
+  st.qcirc_step = qstar - st.qcirc_prev;
   st.sigma_prev = sigma;
   st.qcirc_prev = qcirc;
   st.level = n;
@@ -1478,6 +1495,61 @@ __global__ __launch_bounds__(PBS) void k_phi(DevPtrs p, int gap) {
 }
 
 // ---------------------------------------------------------------------------
+// time-step check of one gap (App. time segment selection): largest |u| of the
+// live particles of each species and the live electrons in each cell
+// ---------------------------------------------------------------------------
+constexpr int DBS = 256;
+template <class P>
+__device__ inline unsigned long long nonneg_bits(P v);
+template <>
+__device__ inline unsigned long long nonneg_bits<float>(float v) {
+  return (unsigned long long)__float_as_uint(v);
+}
+template <>
+__device__ inline unsigned long long nonneg_bits<double>(double v) {
+  return (unsigned long long)__double_as_longlong(v);
+}
+
+template <class P>
+__global__ __launch_bounds__(DBS) void k_dt_scan(DevPtrs p, int gap, unsigned long long *umax,
+                                                 unsigned int *cells) {
+  extern __shared__ unsigned int hist[];  // [N]
+  __shared__ P red[DBS / 64][2];
+  const GapConst &c = p.gc[gap];
+  const int N = c.N;
+  const int sel = (int)(*p.epoch & 1);
+  for (int k = threadIdx.x; k < N; k += DBS) hist[k] = 0u;
+  __syncthreads();
+  const P *X = (const P *)p.X[sel], *U = (const P *)p.U[sel];
+  P m[2] = {(P)0, (P)0};
+  const long long stride = (long long)gridDim.x * DBS;
+  for (int s = 0; s < 2; ++s) {
+    const long long n = min((long long)p.next_count[gap * 2 + s], (long long)c.cap[s]);
+    const size_t b = (size_t)c.pbase[s];
+    for (long long i = (long long)blockIdx.x * DBS + threadIdx.x; i < n; i += stride) {
+      const P x = X[b + i];
+      if (!(x >= (P)0)) continue;  // absorbed slot
+      m[s] = fmax(m[s], fabs(U[b + i]));
+      if (s == 0) atomicAdd(&hist[min((int)x, N - 1)], 1u);
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int s = 0; s < 2; ++s) {
+    P v = m[s];
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if (lane == 0) red[wave][s] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    P v = red[0][threadIdx.x];
+    for (int w = 1; w < DBS / 64; ++w) v = fmax(v, red[w][threadIdx.x]);
+    atomicMax(&umax[threadIdx.x], nonneg_bits<P>(v));
+  }
+  for (int k = threadIdx.x; k < N; k += DBS)
+    if (hist[k]) atomicAdd(&cells[k], hist[k]);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 size_t push_lds_bytes(int nmax, int fp64, int G, int wide) {
@@ -1570,6 +1642,24 @@ hipError_t launch_inject(const DevPtrs &p, int gap, int species, long long n, co
     hipLaunchKernelGGL(k_inject<double>, dim3(grid), dim3(bs), 0, s, p, gap, species, n, x, v, id0);
   else
     hipLaunchKernelGGL(k_inject<float>, dim3(grid), dim3(bs), 0, s, p, gap, species, n, x, v, id0);
+  return hipGetLastError();
+}
+
+hipError_t launch_dt_scan(const DevPtrs &p, int gap, int N, int fp64, unsigned long long *umax,
+                          unsigned int *cells, hipStream_t s) {
+  const size_t lds = (size_t)N * 4;
+  static bool attr[2] = {false, false};
+  const void *k = fp64 ? (const void *)k_dt_scan<double> : (const void *)k_dt_scan<float>;
+  if (!attr[fp64]) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    if (e != hipSuccess) return e;
+    attr[fp64] = true;
+  }
+  if (lds > 65536) return hipErrorInvalidValue;
+  if (fp64)
+    hipLaunchKernelGGL(k_dt_scan<double>, dim3(512), dim3(DBS), lds, s, p, gap, umax, cells);
+  else
+    hipLaunchKernelGGL(k_dt_scan<float>, dim3(512), dim3(DBS), lds, s, p, gap, umax, cells);
   return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libgapsim.so")
 MAX_MESH = 8
 
 GS_OK, GS_EINVAL, GS_ENOMEM, GS_ECAPACITY, GS_EDEVICE, GS_ENOCONV, GS_ESTATE = 0, -1, -2, -3, -4, -5, -6
+GS_ECALLBACK = -7
 GUESS_DIRECT, GUESS_EXTRAP, GUESS_MLP = 0, 1, 2
 OPT_BLOCK, OPT_TILE, OPT_GRID, OPT_COMPACT_EVERY, OPT_GRAPH, OPT_TIMING = 1, 2, 3, 4, 5, 6
 OPT_NEWTON_TOL, OPT_NEWTON_MAXIT, OPT_DEPOSIT, OPT_COMPACT_GRID, OPT_PPT = 7, 8, 9, 10, 11
@@ -28,7 +29,7 @@ EXPORTED = [
     "gs_init", "gs_destroy", "gs_inject", "gs_step_strict", "gs_step_weak", "gs_read_diagnostics",
     "gs_read_particles", "gs_set_option", "gs_get_timing", "gs_validate_params", "gs_last_error",
     "gs_version", "gs_mlp_set_weights", "gs_mlp_forward", "gs_mlp_record", "gs_mlp_train_workspace",
-    "gs_mlp_train", "gs_autotune",
+    "gs_mlp_train", "gs_autotune", "gs_step_weak_external", "gs_circuit_resonance", "gs_dt_check",
 ]
 MLP_IN, MLP_OUT, MLP_NPARAM, MLP_NORM = 48, 3, 39683, 102
 
@@ -81,6 +82,7 @@ class GsDiag(C.Structure):
         ("newton_resid0", C.c_double), ("newton_resid", C.c_double),
         ("newton_guess", C.c_double * (MAX_MESH + 1)),
         ("mlp_proposal", C.c_double * 3),
+        ("qcirc_step", C.c_double),
     ]
 
 
@@ -98,6 +100,18 @@ class GsTuning(C.Structure):
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+# gs_circuit_fn: (user, gap, level, dt, phi0_prev, v_gap out) -> status
+CIRCUIT_FN = C.CFUNCTYPE(C.c_int32, C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_double,
+                         C.POINTER(C.c_double))
+
+
+class GsDtReport(C.Structure):
+    _fields_ = [("dt", C.c_double), ("omega_max", C.c_double), ("n_omega", C.c_double),
+                ("v_max", C.c_double * 2), ("beta", C.c_double * 2), ("n_e_max", C.c_double),
+                ("omega_pe", C.c_double), ("alpha", C.c_double), ("eta", C.c_double),
+                ("flags", C.c_int32)]
 
 
 class GsAllocator(C.Structure):
@@ -152,6 +166,12 @@ def lib():
         L.gs_mlp_train.restype = C.c_int
         L.gs_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_char_p, C.POINTER(GsTuning)]
         L.gs_autotune.restype = C.c_int
+        L.gs_step_weak_external.argtypes = [vp, C.c_int32, CIRCUIT_FN, vp]
+        L.gs_step_weak_external.restype = C.c_int
+        L.gs_circuit_resonance.argtypes = [C.POINTER(GsGapParams), P]
+        L.gs_circuit_resonance.restype = C.c_int
+        L.gs_dt_check.argtypes = [vp, C.c_int32, C.POINTER(GsDtReport)]
+        L.gs_dt_check.restype = C.c_int
         _lib = L
     return _lib
 
@@ -205,6 +225,16 @@ def validate(cfg, particle_fp: int = 32, capacity=(1 << 20, 1 << 20)) -> Optiona
     buf = C.create_string_buffer(256)
     rc = lib().gs_validate_params(C.byref(p), buf, 256)
     return None if rc == GS_OK else buf.value.decode()
+
+
+def circuit_resonance(cfg) -> float:
+    """Highest ringing angular frequency of the gap's circuit [rad/s] (host only)."""
+    p = params_from(cfg, 32, (1, 1))
+    w = C.c_double()
+    rc = lib().gs_circuit_resonance(C.byref(p), C.byref(w))
+    if rc != GS_OK:
+        raise GapsimError(rc, "gs_circuit_resonance failed")
+    return w.value
 
 
 _live = weakref.WeakSet()
@@ -312,6 +342,34 @@ class GapSim:
     def step_weak(self, n: int = 1):
         self._chk(lib().gs_step_weak(self._h, n))
 
+    def step_weak_external(self, n: int, engine):
+        """Weak steps with an external circuit engine: engine(gap, level, dt, phi0_prev)
+        returns the gap voltage its circuit reaches at that level.  An exception in the
+        engine stops the call before that step's device work and is raised again here."""
+        caught = []
+
+        def _fn(user, gap, level, dt, phi0_prev, v_out):
+            try:
+                v_out[0] = float(engine(int(gap), int(level), float(dt), float(phi0_prev)))
+                return 0
+            except BaseException as e:  # noqa: BLE001 - handed back after the C call
+                caught.append(e)
+                return 1
+
+        cb = CIRCUIT_FN(_fn)
+        rc = lib().gs_step_weak_external(self._h, n, cb, None)
+        if caught:
+            raise caught[0]
+        self._chk(rc)
+
+    def dt_check(self, gap: int = 0) -> dict:
+        """The time-step constraints of App. D at the last completed step."""
+        R = GsDtReport()
+        self._chk(lib().gs_dt_check(self._h, gap, C.byref(R)))
+        return dict(dt=R.dt, omega_max=R.omega_max, n_omega=R.n_omega, v_max=np.array(R.v_max[:]),
+                    beta=np.array(R.beta[:]), n_e_max=R.n_e_max, omega_pe=R.omega_pe, alpha=R.alpha,
+                    eta=R.eta, flags=R.flags)
+
     def step(self, mode: int, n: int = 1, guess: int = GUESS_DIRECT):
         """mode 0 = strict, 1 = weak (the oracle's numbering)."""
         if mode == 0:
@@ -344,7 +402,7 @@ class GapSim:
                     newton_max=D.newton_max, newton_levels=D.newton_levels,
                     newton_resid0=D.newton_resid0, newton_resid=D.newton_resid,
                     newton_guess=np.array(D.newton_guess[:M + 1]),
-                    mlp_proposal=np.array(D.mlp_proposal[:]))
+                    mlp_proposal=np.array(D.mlp_proposal[:]), qcirc_step=D.qcirc_step)
 
     def autotune(self, mode: int, guess: int = GUESS_DIRECT, trial_steps: int = 8,
                  cache_path: Optional[str] = None) -> dict:

@@ -99,3 +99,17 @@ def test_null_context_is_a_state_error():
     assert lib.gs_step_weak(None, 1) == gapsim.GS_ESTATE
     assert lib.gs_step_strict(None, 1, 0) == gapsim.GS_ESTATE
     assert lib.gs_set_option(None, 1, 256) == gapsim.GS_ESTATE
+
+
+def test_external_engine_and_dt_check_argument_errors_without_a_device():
+    lib = gapsim.lib()
+    fn = gapsim.CIRCUIT_FN(lambda *a: 0)
+    assert lib.gs_step_weak_external(None, 1, fn, None) == gapsim.GS_ESTATE
+    assert lib.gs_dt_check(None, 0, C.byref(gapsim.GsDtReport())) == gapsim.GS_ESTATE
+    w = C.c_double(-1.0)
+    assert lib.gs_circuit_resonance(None, C.byref(w)) == gapsim.GS_EINVAL
+    bad = gapsim.params_from(W.config1(n_cells=1), 64, (10, 10))
+    assert lib.gs_circuit_resonance(C.byref(bad), C.byref(w)) == gapsim.GS_EINVAL
+    good = gapsim.params_from(W.config1(), 64, (10, 10))
+    assert lib.gs_circuit_resonance(C.byref(good), None) == gapsim.GS_EINVAL
+    assert lib.gs_circuit_resonance(C.byref(good), C.byref(w)) == gapsim.GS_OK and w.value == 0.0

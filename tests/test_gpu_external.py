@@ -1,0 +1,181 @@
+"""GPU: weak coupling with an external circuit engine (gs_step_weak_external)
+and the time-step check (gs_dt_check), through the C ABI, against the oracle.
+
+Bars as in the other parity tests: counts bit-exact; binary64 particles within
+1e-12 norm-wise, binary32 particles (against the oracle's binary32 mode) within
+1e-5; the time-step figures of one state: the largest |u| equal (binary32) or
+within 1e-12 (binary64), the per-cell electron maximum equal, the rest within
+rounding.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from circuit_engines import IdealSource, SeriesRCBDF2
+from paper_2603_24010_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _gapsim():
+    from paper_2603_24010_amd import gapsim
+    return gapsim
+
+
+def plasma_cfg():
+    return W.config1(n_cells=128).replace(c_par=20e-12, beam_per_step=40, beam_Emin_eV=1e3,
+                                          beam_Emax_eV=20e3)
+
+
+def plasma_loads():
+    loads = W.load_config1(n_per_species=4000, seed=3)
+    return {s: (x, v * 30.0) for s, (x, v) in loads.items()}
+
+
+def _series_rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    s = np.abs(b).max()
+    return float(np.abs(a - b).max() / s) if s > 0 else float(np.abs(a - b).max())
+
+
+def run_external(fp32, nsteps=60):
+    gs = _gapsim()
+    cfg = plasma_cfg()
+    sim = gs.GapSim(cfg, particle_fp=32 if fp32 else 64, capacity=(200000, 200000))
+    orc = oracle.OracleSim(cfg, fp32=fp32)
+    for s, (x, v) in plasma_loads().items():
+        sim.inject(0, s, x, v)
+        orc.inject(s, x, v)
+    eg, eo = SeriesRCBDF2(cfg), SeriesRCBDF2(cfg)
+    recs = []
+    for _ in range(nsteps):
+        sim.step_weak_external(1, eg)
+        orc.step_external(eo)
+        recs.append((sim.diag(0), orc.diag()))
+    return cfg, sim, orc, recs
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_external_engine_parity(fp32):
+    cfg, sim, orc, recs = run_external(fp32)
+    tol = 1e-5 if fp32 else 1e-12
+    for dg, do in recs:
+        assert dg["step"] == do["step"]
+        np.testing.assert_array_equal(dg["abs_cum"], do["abs_cum"])
+        np.testing.assert_array_equal(dg["emit_cum"], do["emit_cum"])
+        assert dg["inj_cum"] == do["inj_cum"]
+        np.testing.assert_array_equal(dg["n_live"], do["n_live"])
+    for key in ("phi0", "sigma", "qcirc", "qcirc_star", "qcirc_step"):
+        r = _series_rel([d[key] for d, _ in recs], [o[key] for _, o in recs])
+        assert r <= tol, (key, r)
+    g = np.array([d["q"][0] for d, _ in recs])
+    o = np.array([od["q"][0] for _, od in recs])
+    assert _series_rel(g, o) <= tol
+    pg, Eg, rg = sim.fields(0)
+    po, Eo, ro = orc.fields()
+    for a, b, name in ((rg, ro, "rho"), (Eg, Eo, "E"), (pg, po, "phi")):
+        assert _series_rel(a, b) <= tol, name
+    d = recs[-1][0]
+    assert d["abs_cum"].sum() > 50 and d["emit_cum"].sum() > 0
+    # the time-step check of that state
+    rg_ = sim.dt_check(0)
+    ro_ = orc.dt_report()
+    assert rg_["omega_max"] == pytest.approx(ro_["omega_max"], rel=1e-10, abs=1e-6)
+    if fp32:
+        np.testing.assert_array_equal(rg_["beta"], ro_["beta"])
+    else:
+        np.testing.assert_allclose(rg_["beta"], ro_["beta"], rtol=1e-12)
+    assert rg_["n_e_max"] == ro_["n_e_max"]
+    assert rg_["omega_pe"] == pytest.approx(ro_["omega_pe"], rel=1e-14)
+    assert rg_["eta"] == pytest.approx(ro_["eta"], rel=1e-6, abs=1e-14)
+    assert rg_["flags"] == ro_["flags"]
+    sim.close()
+
+
+def test_external_engine_equals_internal_weak_on_gpu():
+    """The engine that steps the library's own one-mesh circuit in BDF2 gives the
+    library's internal weak mode back (binary64 particles)."""
+    gs = _gapsim()
+    cfg = plasma_cfg()
+    a = gs.GapSim(cfg, particle_fp=64, capacity=(200000, 200000))
+    b = gs.GapSim(cfg, particle_fp=64, capacity=(200000, 200000))
+    for s, (x, v) in plasma_loads().items():
+        a.inject(0, s, x, v)
+        b.inject(0, s, x, v)
+    a.step_weak(40)
+    b.step_weak_external(40, SeriesRCBDF2(cfg))
+    da, db = a.diag(0), b.diag(0)
+    np.testing.assert_array_equal(da["abs_cum"], db["abs_cum"])
+    np.testing.assert_array_equal(da["emit_cum"], db["emit_cum"])
+    for key in ("phi0", "sigma", "qcirc_star"):
+        assert abs(da[key] - db[key]) <= 1e-10 * abs(da[key]), key
+    a.close()
+    b.close()
+
+
+def test_external_ideal_source_vacuum_batched():
+    """Three vacuum gaps, each driven by its own ideal source through one callback:
+    phi0 equals the source voltage at every level, and the callback sees the gaps
+    in order with the level and the previous potential."""
+    gs = _gapsim()
+    cfgs = [W.config1(n_cells=64 + 32 * g).replace(see_amp=0.0) for g in range(3)]
+    sim = gs.GapSim(cfgs, particle_fp=64, capacity=(64, 64))
+    srcs = [IdealSource(1e3 * (g + 1), 2 * math.pi * 1e9 * (g + 1), dc=10.0 * g) for g in range(3)]
+    calls = []
+
+    def engine(gap, level, dt, phi0_prev):
+        calls.append((gap, level, phi0_prev))
+        return srcs[gap](gap, level, dt, phi0_prev)
+    sim.step_weak_external(12, engine)
+    assert [c[:2] for c in calls] == [(g, n) for n in range(12) for g in range(3)]
+    for g in range(3):
+        d = sim.diag(g)
+        assert d["step"] == 11
+        assert abs(d["phi0"] - srcs[g](g, 11, cfgs[g].dt, 0.0)) <= 1e-12 * 1e3 * (g + 1)
+        prev = [c[2] for c in calls if c[0] == g]
+        expect = [0.0] + [srcs[g](g, n, cfgs[g].dt, 0.0) for n in range(11)]
+        np.testing.assert_allclose(prev, expect, rtol=1e-12, atol=1e-9)
+    sim.close()
+
+
+def test_external_engine_failure_stops_before_the_step():
+    gs = _gapsim()
+    cfg = plasma_cfg()
+    sim = gs.GapSim(cfg, particle_fp=32, capacity=(200000, 200000))
+    for s, (x, v) in plasma_loads().items():
+        sim.inject(0, s, x, v)
+    good = SeriesRCBDF2(cfg)
+
+    def failing(gap, level, dt, phi0_prev):
+        if level == 3:
+            raise ValueError("engine stopped")
+        return good(gap, level, dt, phi0_prev)
+    with pytest.raises(ValueError, match="engine stopped"):
+        sim.step_weak_external(10, failing)
+    assert sim.diag(0)["step"] == 2
+    with pytest.raises(gs.GapsimError) as e:
+        sim.step_weak_external(1, lambda *a: float("nan"))
+    assert e.value.status == gs.GS_EINVAL
+    assert sim.diag(0)["step"] == 2
+    # the run goes on from level 3
+    sim.step_weak_external(2, good)
+    assert sim.diag(0)["step"] == 4
+    sim.close()
+
+
+def test_dt_check_flags_fast_particles_and_tesla_resonance():
+    gs = _gapsim()
+    cfg = W.config_tesla(n_steps=8)
+    sim = gs.GapSim(cfg, particle_fp=32, capacity=(1 << 16, 1 << 16))
+    dx = cfg.d / cfg.n_cells
+    sim.inject(0, 0, np.array([10.5 * dx, 11.5 * dx]), np.array([0.1 * dx / cfg.dt, -0.3 * dx / cfg.dt]))
+    r = sim.dt_check(0)  # before the first step
+    assert 1.2e6 < r["omega_max"] < 1.3e6 and r["n_omega"] > 50
+    assert r["flags"] == 0 and r["beta"][0] == pytest.approx(0.3, rel=1e-6) and r["eta"] == 0.0
+    assert r["n_e_max"] == pytest.approx(cfg.weight / dx, rel=1e-15)
+    sim.inject(0, 0, np.array([100.5 * dx]), np.array([0.7 * dx / cfg.dt]))
+    r = sim.dt_check(0)
+    assert r["flags"] & 2 and r["beta"][0] == pytest.approx(0.7, rel=1e-6)
+    sim.close()
