@@ -560,6 +560,103 @@ def run_tesla(args, copy_gbs):
     print(json.dumps(out), flush=True)
 
 
+EXTERNAL_WORKLOAD = "beam_gap_4096c_2e7p_external_engine"
+
+
+def run_external(args, copy_gbs):
+    """The default beam gap (4096 cells, 2e7 H+, coupled LC) in weak coupling with
+    the circuit stepped by an external engine (the package's exact linear engine,
+    in Python) through gs_step_weak_external, against the same run with the
+    library's own weak circuit.  Both read the diagnostics every 25 steps; the
+    external path also waits for the device once per step to exchange voltages."""
+    import torch
+    from paper_2603_24010_amd import gapsim
+    from paper_2603_24010_amd.engines import LinearCircuitEngine
+    spec = WORKLOADS["beam_gap_4096c_2e7p_weak"]
+    K, Wm = args.steps, args.warmup
+    res, series = {}, {}
+    for case in ("internal", "external"):
+        sim, cfg, _ = make_sim(case, spec, Wm + K)
+        sim.set_option(gapsim.OPT_COMPACT_EVERY, args.compact_every)
+        eng = LinearCircuitEngine(cfg)
+        in_engine = [0.0]
+
+        def timed_engine(g, n, dt, p):
+            t = time.perf_counter()
+            v = eng(g, n, dt, p)
+            in_engine[0] += time.perf_counter() - t
+            return v
+
+        def advance(k):
+            if case == "internal":
+                sim.step_weak(k)
+            else:
+                sim.step_weak_external(k, timed_engine)
+        advance(Wm)
+        d0 = sim.diag(0)
+        sim.set_option(gapsim.OPT_TIMING, 1)
+        sim.timing(reset=True)
+        in_engine[0] = 0.0
+        V = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < K:
+            k = min(25, K - done)
+            advance(k)
+            done += k
+            V.append(sim.diag(0)["phi0"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        d1 = sim.diag(0)
+        tm = sim.timing(reset=True)
+        pushed = d1["pushed_cum"] - d0["pushed_cum"]
+        res[case] = {"particle_steps_per_s": pushed / el, "ms_per_step": el * 1e3 / K,
+                     "push_us": tm["push_ms"] * 1e3 / max(1, tm["push_launches"]),
+                     "field_us": tm["field_ms"] * 1e3 / max(1, tm["field_launches"]),
+                     "engine_us_per_step": in_engine[0] * 1e6 / K, "pushed": int(pushed),
+                     "push_GBps": BYTES_PER_PUSH_F32 * pushed / (tm["push_ms"] * 1e-3) / 1e9}
+        series[case] = np.array(V)
+        log(f"[bench] {case}: {res[case]}")
+        sim.close()
+    ex, it = res["external"], res["internal"]
+    dv = float(np.abs(series["external"] - series["internal"]).max() / np.abs(series["internal"]).max())
+    out = {
+        "metric": "particle-steps/s, weak coupling with an external circuit engine",
+        "value": ex["particle_steps_per_s"], "unit": "particle-steps/s", "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": ex["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": EXTERNAL_WORKLOAD, "cells": 4096, "initial_particles": spec["n0"],
+                   "beam_per_step": spec["beam"], "engine": "exact linear (expm) coupled-LC engine in Python",
+                   "coupling": "weak, external circuit engine"},
+        "cases": res,
+        "overhead_us_per_step": (ex["ms_per_step"] - it["ms_per_step"]) * 1e3,
+        "gap_voltage_max_rel_diff_vs_internal_weak": dv,
+        "roofline": {"bound": "hbm", "kernel": "k_push", "achieved": ex["push_GBps"], "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": ex["push_GBps"] / PEAK_HBM_GBS, "traffic": None,
+                     "avg_launch_ms": ex["push_us"] * 1e-3, "copy_GBps": copy_gbs,
+                     "bytes_per_particle_step": BYTES_PER_PUSH_F32},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from paper_2603_24010_amd import workloads as W
+        cfg = W.config2(n_cells=4096, beam_per_step=spec["beam"])
+        n = spec["n0"]
+        o = oracle.OracleSim(cfg, fp32=True)
+        for sp, (x, v) in W.load_config2(n=n, seed=2, d=cfg.d).items():
+            o.inject(sp, x, v)
+        eng = LinearCircuitEngine(cfg)
+        steps = max(4, args.cpu_steps // 2)
+        t0 = time.perf_counter()
+        o.step_external(eng, steps)
+        elc = time.perf_counter() - t0
+        pc = o.diag()["pushed_cum"]
+        out["cpu_baseline"] = {"value": pc / elc, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{n} initial H+ of the same workload, {steps} external-engine steps, "
+                                         f"binary32 oracle mode, {pc} particle-steps in {elc:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline_batched(spec, steps):
     import oracle
     from paper_2603_24010_amd import workloads as W
@@ -608,7 +705,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="beam_gap_4096c_2e7p_weak",
                     choices=sorted(WORKLOADS) + sorted(BATCHED) + [MLP_WORKLOAD, DIVERGENCE, FP64_WORKLOAD,
-                                                                   TESLA_WORKLOAD])
+                                                                   TESLA_WORKLOAD, EXTERNAL_WORKLOAD])
     ap.add_argument("--div-particles", type=int, default=200_000_000)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -679,6 +776,8 @@ def main():
         return run_fp64(args, copy_gbs)
     if args.workload == TESLA_WORKLOAD:
         return run_tesla(args, copy_gbs)
+    if args.workload == EXTERNAL_WORKLOAD:
+        return run_external(args, copy_gbs)
     spec = WORKLOADS[args.workload]
     log(f"[bench] building workload {args.workload}")
     sim, cfg, _ = make_sim(args.workload, spec, args.warmup + args.steps)

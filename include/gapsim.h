@@ -261,9 +261,14 @@ gs_status gs_step_weak(gs_ctx *ctx, int32_t n_steps);
  * loop currents in gs_diag are not the engine's).  Any non-zero return from fn,
  * or a non-finite v_gap, stops the call before that step's device work:
  * GS_ECALLBACK (GS_EINVAL for a non-finite v_gap), with every earlier step
- * done.  Synchronises the stream once per step; never uses a captured graph.
- * Errors: GS_EINVAL (fn NULL, n_steps < 0), GS_ECALLBACK and those of
- * gs_step_weak. */
+ * done.  Timing: the first step of a call waits for the stream; each later
+ * step waits only for the previous field solve, whose potentials the field
+ * kernel writes to a small pinned host buffer the library owns (16 bytes per
+ * gap, also where the engine's voltages go), so the engine runs while that
+ * step's push is still on the device.  Otherwise asynchronous like
+ * gs_step_weak (device errors surface at the next synchronising call); never
+ * uses a captured graph.  Errors: GS_EINVAL (fn NULL, n_steps < 0),
+ * GS_ECALLBACK and those of gs_step_weak. */
 typedef int32_t (*gs_circuit_fn)(void *user, int32_t gap, int64_t level, double dt, double phi0_prev,
                                  double *v_gap);
 gs_status gs_step_weak_external(gs_ctx *ctx, int32_t n_steps, gs_circuit_fn fn, void *user);

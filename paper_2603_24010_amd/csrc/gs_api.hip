@@ -46,7 +46,8 @@ struct gs_ctx {
   std::vector<int64_t> next_id;
   std::vector<std::vector<int64_t>> sched;  // per gap: copy of the beam schedule (empty: none)
   std::vector<int> sched_on;                // per gap: the schedule is in force
-  std::vector<double> ext_phi, ext_v;       // host staging of the external circuit engine's exchange
+  double *ext_host = nullptr;               // pinned, mapped: [G] engine voltages, [G] field potentials
+  hipEvent_t ext_ev = nullptr;              // recorded after each external-mode field solve
   std::string err;
   int sticky = 0;  // gs_status of a device error already seen
   // timing
@@ -402,9 +403,19 @@ static gs_status setup(gs_ctx *ctx) {
   int64_t *sched_d = nullptr;
   ALLOC(sched_d, int64_t *, std::max<size_t>(nsched, 1) * 8);
   d.sched = sched_d;
-  double *ext_d = nullptr;
-  ALLOC(ext_d, double *, (size_t)G * 8);
-  d.ext_v = ext_d;
+  // exchange buffer of the external circuit engine: coherent pinned host memory
+  // the field kernel reads and writes directly (16 bytes per gap)
+  {
+    void *h = nullptr, *dptr = nullptr;
+    if (hipHostMalloc(&h, (size_t)G * 16, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess || !h)
+      return fail(ctx, GS_ENOMEM, "pinned host allocation of %zu bytes failed", (size_t)G * 16);
+    ctx->ext_host = (double *)h;
+    memset(h, 0, (size_t)G * 16);
+    HIPCHK(ctx, hipHostGetDevicePointer(&dptr, h, 0));
+    d.ext_v = (const double *)dptr;
+    d.ext_phi = (double *)dptr + G;
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ext_ev, hipEventDisableTiming));
+  }
   // overflow event regions for up to eight 256-thread push workgroups per CU
   // (the largest grid the autotuner tries), when any gap emits
   bool emits = false;
@@ -434,7 +445,6 @@ static gs_status setup(gs_ctx *ctx) {
   HIPCHK(ctx, hipMemsetAsync(d.cursor, 0, (size_t)G * 2 * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.tally, 0, (size_t)G * T_N * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.ev_count, 0, (size_t)G * 8, s));
-  HIPCHK(ctx, hipMemsetAsync(ext_d, 0, (size_t)G * 8, s));
   for (int g = 0; g < G; ++g)
     if (!ctx->sched[g].empty())
       HIPCHK(ctx, hipMemcpyAsync(sched_d + ctx->hc[g].sched_base, ctx->sched[g].data(), ctx->sched[g].size() * 8,
@@ -528,6 +538,8 @@ extern "C" gs_status gs_init(gs_ctx **out, int32_t n_gaps, const gs_gap_params *
   gs_status st = setup(ctx);
   if (st != GS_OK) {
     g_init_error = ctx->err;
+    if (ctx->ext_ev) (void)hipEventDestroy(ctx->ext_ev);
+    if (ctx->ext_host) (void)hipHostFree(ctx->ext_host);
     dev_free_all(ctx);
     delete ctx;
     return st;
@@ -548,6 +560,8 @@ extern "C" void gs_destroy(gs_ctx *ctx) {
     for (int k = 0; k < 3; ++k)
       if (ctx->gexec[m][k]) (void)hipGraphExecDestroy(ctx->gexec[m][k]);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->ext_ev) (void)hipEventDestroy(ctx->ext_ev);
+  if (ctx->ext_host) (void)hipHostFree(ctx->ext_host);
   dev_free_all(ctx);
   delete ctx;
 }
@@ -640,12 +654,15 @@ static int64_t beam_at(const gs_ctx *ctx, int g, int64_t n) {
   return n >= 0 && n < (int64_t)s.size() ? s[(size_t)n] : 0;
 }
 
-static gs_status one_step(gs_ctx *ctx, int mode, int guess) {
+// after_field: an event to record between the field solve and the push
+static gs_status one_step(gs_ctx *ctx, int mode, int guess, hipEvent_t after_field = nullptr) {
   hipError_t e = timed(ctx, 1, [&](KTime t) {
     return launch_field(ctx->dp, ctx->G, mode, guess, ctx->newton_tol, ctx->newton_maxit, ctx->fp64,
                         ctx->nmax, ctx->stream, t);
   });
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "field launch: %s", hipGetErrorString(e));
+  if (after_field && (e = hipEventRecord(after_field, ctx->stream)) != hipSuccess)
+    return fail(ctx, GS_EDEVICE, "event record: %s", hipGetErrorString(e));
   e = timed(ctx, 0, [&](KTime t) { return launch_push(ctx->dp, ctx->G, ctx->lc, ctx->stream, t); });
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "push launch: %s", hipGetErrorString(e));
   ctx->since_compact += 1;
@@ -740,39 +757,43 @@ extern "C" gs_status gs_step_weak_external(gs_ctx *ctx, int32_t n_steps, gs_circ
   gs_status st = check_sticky(ctx, false);
   if (st != GS_OK) return st;
   const int G = ctx->G;
-  ctx->ext_phi.resize(G);
-  ctx->ext_v.resize(G);
+  double *vh = ctx->ext_host, *ph = ctx->ext_host + G;
+  std::vector<double> phi((size_t)G);
   for (int k = 0; k < n_steps; ++k) {
     const int64_t n = ctx->steps_done;  // the level this step solves
     if (n == 0) {
       // before the first level the electrode holds the gap mesh's initial charge
       for (int g = 0; g < G; ++g) {
         const GapConst &c = ctx->hc[g];
-        ctx->ext_phi[g] = ctx->params[g].q0[c.g] / (c.cgap + c.c_par);
+        phi[g] = ctx->params[g].q0[c.g] / (c.cgap + c.c_par);
       }
-    } else {
-      HIPCHK(ctx, hipMemcpy2DAsync(ctx->ext_phi.data(), 8, &ctx->dp.gs[0].phi0, sizeof(GapState), 8, (size_t)G,
+      if ((st = check_sticky(ctx, true)) != GS_OK) return st;
+    } else if (k == 0) {
+      // the last level may come from any kind of step: read the gap states
+      HIPCHK(ctx, hipMemcpy2DAsync(phi.data(), 8, &ctx->dp.gs[0].phi0, sizeof(GapState), 8, (size_t)G,
                                    hipMemcpyDeviceToHost, ctx->stream));
+      if ((st = check_sticky(ctx, true)) != GS_OK) return st;
+    } else {
+      // the previous field solve wrote its potentials to the exchange buffer;
+      // its push may still run while the engine works
+      HIPCHK(ctx, hipEventSynchronize(ctx->ext_ev));
+      for (int g = 0; g < G; ++g) phi[g] = ph[g];
     }
-    // also waits for the previous step (and the last upload from ext_v)
-    if ((st = check_sticky(ctx, true)) != GS_OK) return st;
+    // the field kernel that read vh last has finished (stream or event wait above)
     for (int g = 0; g < G; ++g) {
       double v = 0.0;
-      const int32_t rc = fn(user, g, n, ctx->hc[g].dt, ctx->ext_phi[g], &v);
+      const int32_t rc = fn(user, g, n, ctx->hc[g].dt, phi[g], &v);
       if (rc != 0)
         return fail(ctx, GS_ECALLBACK, "circuit engine returned %d for gap %d at level %lld; step not taken", rc, g,
                     (long long)n);
       if (!std::isfinite(v))
         return fail(ctx, GS_EINVAL, "circuit engine gave a non-finite gap voltage for gap %d at level %lld", g,
                     (long long)n);
-      ctx->ext_v[g] = v;
+      vh[g] = v;
     }
-    HIPCHK(ctx, hipMemcpyAsync((void *)ctx->dp.ext_v, ctx->ext_v.data(), (size_t)G * 8, hipMemcpyHostToDevice,
-                               ctx->stream));
-    if ((st = one_step(ctx, 2, GS_GUESS_DIRECT)) != GS_OK) return st;
+    if ((st = one_step(ctx, 2, GS_GUESS_DIRECT, ctx->ext_ev)) != GS_OK) return st;
   }
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  return check_sticky(ctx, false);
+  return GS_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -120,8 +120,11 @@ struct DevPtrs {
   Event *ev;                       // absorbed-ion events, per-gap lists
   unsigned long long *ev_count;    // [G]
   const int64_t *sched;            // beam schedules of all gaps (GapConst::sched_base)
-  const double *ext_v;             // [G] gap voltage an external circuit engine gave for
-                                   //   the level being solved (field mode 2)
+  // exchange with an external circuit engine (field mode 2), in pinned host
+  // memory the device maps: ext_v[g] the engine's gap voltage for the level
+  // being solved (read), ext_phi[g] the electrode potential it gave (written)
+  const double *ext_v;
+  double *ext_phi;
   Event *ovf;                      // push workgroup b < ovf_wgs: events past its LDS queue,
   int64_t ovf_wgs;                 //   OVQ of them from ovf + b * OVQ
   // Newton guess network: bfloat16 weights (flat layout of gs_mlp_dev.h) and

@@ -473,6 +473,7 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
     q[gm] = (c.cgap + c.c_par) * phi0;
     Dn[gm] = q[gm] - st.qprev[gm];
     qcirc = c.cgap * phi0;
+    p.ext_phi[g] = phi0;  // for the engine's next call, read once this kernel is done
     st.newton_last = -1;
     st.newton_fb_last = 0;
   } else {

@@ -217,3 +217,63 @@ def test_dt_report_particles_brute_force(fp32):
     assert r["flags"] == 0
     o.inject(0, np.array([3.5 * dx]), np.array([0.6 * dx / cfg.dt]))
     assert o.dt_report()["flags"] & 2
+
+
+# ---------------------------------------------------------------------------
+# the package's exact linear engine
+# ---------------------------------------------------------------------------
+def test_linear_engine_lossless_energy_and_oracle_agreement():
+    """Coupled LC without resistance, vacuum gap: the engine's propagation is exact,
+    so the circuit energy (1/2) i^T L i + (1/2) q^T S' q stays constant; in
+    vacuum the field solve returns the engine's voltage; and the oracle's own
+    BDF2 weak mode follows the same curve up to its start-up lag (the secondary
+    charge grows as t^2 from rest: a lag of at most one step is a relative
+    difference of at most 2 / (n + 1) at level n)."""
+    from paper_2603_24010_amd.engines import LinearCircuitEngine
+    cfg = W.config2(n_cells=64).replace(beam_per_step=0, see_amp=0.0)
+    eng = LinearCircuitEngine(cfg)
+    o, ref = oracle.OracleSim(cfg), oracle.OracleSim(cfg)
+    S = cfg.S.copy()
+    S[1, 1] += 1.0 / (cfg.eps0 * cfg.area / cfg.d + cfg.c_par)
+    energy = lambda q, i: 0.5 * i @ cfg.L @ i + 0.5 * q @ S @ q
+    q, i = cfg.q0.copy(), np.zeros(2)
+    e0 = energy(q, i)
+    V, Vr = [], []
+    seen = []
+    wrapped = lambda g, n, dt, p: seen.append(eng(g, n, dt, p)) or seen[-1]
+    for n in range(300):
+        o.step_external(wrapped)
+        ref.step(oracle.WEAK)
+        q, i = eng.state()
+        assert energy(q, i) == pytest.approx(e0, rel=1e-9)
+        V.append(o.diag()["phi0"])
+        Vr.append(ref.diag()["phi0"])
+        assert V[-1] == pytest.approx(seen[-1], rel=1e-12)
+    V, Vr = np.array(V), np.array(Vr)
+    n = np.arange(300)
+    assert np.all(np.abs(V - Vr) <= 2.0 * np.abs(V) / (n + 1))
+
+
+def test_linear_engine_sinusoidal_source_matches_closed_form():
+    """Series L-C-gap loop driven by a sine: the steady state plus the free
+    transient of an undamped loop, evaluated in closed form."""
+    from paper_2603_24010_amd.engines import LinearCircuitEngine
+    L, C, amp, f = 1e-6, 1e-10, 1e3, 2e8
+    cfg = W.config1(n_cells=64).replace(L=np.array([[L]]), R=np.array([[0.0]]), S=np.array([[1.0 / C]]),
+                                        src=np.array([1.0]), src_amp=amp, src_freq=f, see_amp=0.0)
+    cg = cfg.eps0 * cfg.area / cfg.d
+    st = 1.0 / C + 1.0 / cg
+    w0, w = math.sqrt(st / L), 2 * math.pi * f
+    eng = LinearCircuitEngine(cfg)
+    dt = cfg.dt
+    for n in range(200):
+        v = eng(0, n, dt, eng.state()[0][0] / cg if n else 0.0)
+        # L q'' + st q = amp sin(w t), q(-dt) = 0, q'(-dt) = 0
+        tau = (n + 1) * dt
+        s0, c0 = math.sin(-w * dt), math.cos(-w * dt)
+        # particular: qp(t) = K sin(w t), K = amp / (L (w0^2 - w^2)); free part fixes the start
+        K = amp / (L * (w0 * w0 - w * w))
+        a = -K * s0
+        b = -K * w * c0 / w0
+        q = K * math.sin(w * (n * dt)) + a * math.cos(w0 * tau) + b * math.sin(w0 * tau)
+        assert v == pytest.approx(q / cg, rel=1e-7, abs=1e-9 * abs(K) / cg)
