@@ -500,20 +500,29 @@ def run_tesla(args, copy_gbs):
     import torch
     import oracle
     from paper_2603_24010_amd import gapsim, workloads as W
+    from paper_2603_24010_amd.engines import RadauCircuitEngine
+    ENGINE = -1
     cfg0 = W.config_tesla()
     steps = len(cfg0.beam_schedule)
     cases = [("strict_see", oracle.STRICT, cfg0), ("weak_see", oracle.WEAK, cfg0),
              ("strict_no_see", oracle.STRICT, cfg0.replace(see_amp=0.0)),
              ("weak_no_see", oracle.WEAK, cfg0.replace(see_amp=0.0))]
+    # weak coupling with the circuit in an external stiff engine (Radau IIA), the
+    # way the paper's weak mode hands the circuit to a SPICE engine
+    cases.append(("weak_engine_see", ENGINE, cfg0))
     res, curves, el_all, pushed_all = {}, {}, 0.0, 0
     for name, mode, cfg in cases:
         s = gapsim.GapSim(cfg, particle_fp=32, capacity=(3_000_000, 4_000_000))
+        eng = RadauCircuitEngine(cfg) if mode == ENGINE else None
         V = np.zeros(steps)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         el = 0.0
         for n in range(steps):
-            s.step(mode, 1)
+            if eng is not None:
+                s.step_weak_external(1, eng)
+            else:
+                s.step(mode, 1)
             torch.cuda.synchronize()
             el += time.perf_counter() - t0
             V[n] = s.diag(0)["phi0"]
@@ -528,6 +537,25 @@ def run_tesla(args, copy_gbs):
                          absorbed=[int(x) for x in d["abs_cum"].ravel()])
         log(f"[bench] {name}: {res[name]}")
     rmse = lambda a, b: float(np.sqrt(np.mean((curves[a] - curves[b]) ** 2)) / 1e3)
+    # the circuit alone (no gap charge): the library's BDF2 level sequence and a
+    # Radau IIA step at the same dt, each against Radau on a 16 times finer grid
+    vac_cfg = cfg0.replace(see_amp=0.0, beam_schedule=None)
+    _, v_bdf2 = oracle.circuit_run(vac_cfg, steps)
+    fine = RadauCircuitEngine(vac_cfg.replace(dt=vac_cfg.dt / 16))
+    p, ref = 0.0, []
+    for k in range(16 * steps):
+        p = fine(0, k, vac_cfg.dt / 16, p)
+        if k % 16 == 15:
+            ref.append(p)
+    coarse = RadauCircuitEngine(vac_cfg)
+    p, v_rad = 0.0, []
+    for k in range(steps):
+        p = coarse(0, k, vac_cfg.dt, p)
+        v_rad.append(p)
+    ref = np.array(ref)
+    vac = {"bdf2": float(np.sqrt(np.mean((v_bdf2 - ref) ** 2)) / 1e3),
+           "radau": float(np.sqrt(np.mean((np.array(v_rad) - ref) ** 2)) / 1e3),
+           "note": "BDF2's constant-history start puts its waveform half a step behind"}
     out = {
         "metric": "Tesla-run waveform (collapse with vs without SEE, strict vs weak RMSE); particle-steps/s",
         "value": pushed_all / el_all, "unit": "particle-steps/s", "n_gpus": 1, "steps": steps, "warmup": 0,
@@ -539,7 +567,10 @@ def run_tesla(args, copy_gbs):
                    "injected": int(cfg0.beam_schedule.sum())},
         "cases": res,
         "strict_weak_rmse_kV": {"see": rmse("strict_see", "weak_see"), "no_see": rmse("strict_no_see", "weak_no_see"),
+                                "strict_vs_weak_external_engine_see": rmse("strict_see", "weak_engine_see"),
+                                "weak_vs_weak_external_engine_see": rmse("weak_see", "weak_engine_see"),
                                 "paper_context_kV": 0.228},
+        "vacuum_circuit_rmse_vs_converged_kV": vac,
         "curve_kV": [[round(n * cfg0.dt * 1e6, 3)] + [round(float(curves[c][n]) / 1e3, 3) for c, _, _ in cases]
                      for n in range(0, steps, 5)],
         "roofline": {"bound": "latency", "kernel": "k_push", "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -551,11 +582,14 @@ def run_tesla(args, copy_gbs):
         for name, mode, cfg in cases:
             o = oracle.OracleSim(cfg, fp32=True)
             t0 = time.perf_counter()
-            o.step(mode, steps)
+            if mode == ENGINE:
+                o.step_external(RadauCircuitEngine(cfg), steps)
+            else:
+                o.step(mode, steps)
             elc += time.perf_counter() - t0
             pc += o.diag()["pushed_cum"]
         out["cpu_baseline"] = {"value": pc / elc, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-                               "sample": f"the same four runs, {steps} steps each, binary32 oracle mode, "
+                               "sample": f"the same {len(cases)} runs, {steps} steps each, binary32 oracle mode, "
                                          f"{pc} particle-steps in {elc:.1f} s"}
     print(json.dumps(out), flush=True)
 
