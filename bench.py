@@ -16,6 +16,7 @@ import argparse
 import csv
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -45,6 +46,11 @@ WORKLOADS = {
     "beam_gap_16384c_2e8p_weak": dict(n_cells=16384, n0=200_000_000, beam=20_000, mode=1,
                                       load="gauss"),
 }
+
+
+def _finite(d):
+    """JSON has no infinity: a non-finite float (no circuit resonance) becomes null."""
+    return {k: (None if isinstance(v, float) and not math.isfinite(v) else v) for k, v in d.items()}
 
 
 def log(*a):
@@ -515,6 +521,9 @@ def run_tesla(args, copy_gbs):
         s = gapsim.GapSim(cfg, particle_fp=32, capacity=(3_000_000, 4_000_000))
         eng = RadauCircuitEngine(cfg) if mode == ENGINE else None
         V = np.zeros(steps)
+        # App. D's a posteriori check, outside the timed part of each step
+        chk = {"omega_pe_max": 0.0, "alpha_max": 0.0, "v_e_max": 0.0, "beta_max": [0.0, 0.0], "eta_max": 0.0,
+               "n_e_max": 0.0, "flagged_steps": 0}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         el = 0.0
@@ -526,6 +535,15 @@ def run_tesla(args, copy_gbs):
             torch.cuda.synchronize()
             el += time.perf_counter() - t0
             V[n] = s.diag(0)["phi0"]
+            r = s.dt_check(0)
+            chk["omega_pe_max"] = max(chk["omega_pe_max"], r["omega_pe"])
+            chk["alpha_max"] = max(chk["alpha_max"], r["alpha"])
+            chk["n_e_max"] = max(chk["n_e_max"], r["n_e_max"])
+            chk["v_e_max"] = max(chk["v_e_max"], float(r["v_max"][0]))
+            chk["beta_max"] = [max(a, float(b)) for a, b in zip(chk["beta_max"], r["beta"])]
+            chk["eta_max"] = max(chk["eta_max"], r["eta"])
+            chk["flagged_steps"] += int(r["flags"] != 0)
+            chk["omega_max"], chk["n_omega"] = r["omega_max"], r["n_omega"]
             t0 = time.perf_counter()
         d = s.diag(0)
         s.close()
@@ -534,7 +552,7 @@ def run_tesla(args, copy_gbs):
         curves[name] = V
         res[name] = dict(_collapse_metrics(V, cfg.dt), particle_steps=int(d["pushed_cum"]),
                          wall_s=el, injected=int(d["inj_cum"]), emitted=int(d["emit_cum"].sum()),
-                         absorbed=[int(x) for x in d["abs_cum"].ravel()])
+                         absorbed=[int(x) for x in d["abs_cum"].ravel()], time_step_check=_finite(chk))
         log(f"[bench] {name}: {res[name]}")
     rmse = lambda a, b: float(np.sqrt(np.mean((curves[a] - curves[b]) ** 2)) / 1e3)
     # the circuit alone (no gap charge): the library's BDF2 level sequence and a
@@ -849,6 +867,7 @@ def main():
     el = time.perf_counter() - t0
     d1 = sim.diag(0)
     tm = sim.timing(reset=True)
+    dtc = sim.dt_check(0)  # App. D's constraints at the last step (after the timed region)
     pushed = d1["pushed_cum"] - d0["pushed_cum"]
     value = pushed / el
     push_s = tm["push_ms"] * 1e-3
@@ -882,6 +901,7 @@ def main():
         "timed_with": "hip graphs" if args.graph else "eager launches, HIP events recorded by each kernel's dispatch",
         "kernel_ms_per_step": {"push": tm["push_ms"] / args.steps, "field": tm["field_ms"] / args.steps,
                                "compact": tm["compact_ms"] / args.steps},
+        "time_step_check": _finite({k: (v.tolist() if hasattr(v, "tolist") else v) for k, v in dtc.items()}),
     }
     sim.close()
     if not args.no_cpu_baseline:

@@ -209,3 +209,37 @@ def test_tesla_pulse_with_radau_engine_parity():
     po, Eo, ro = orc.fields()
     assert _series_rel(Eg, Eo) <= 1e-5 and _series_rel(rg, ro) <= 1e-5
     sim.close()
+
+
+@pytest.mark.parametrize("fp32", [True, False])
+def test_dt_check_batched_gaps_match_oracle(fp32):
+    """Three gaps of one context, each with its own load: the check of every gap
+    sees only that gap's particles (region offsets) and matches the oracle run of
+    that gap alone, after a few steps."""
+    gs = _gapsim()
+    cfgs = [W.config1(n_cells=64 + 64 * g).replace(beam_per_step=10 * g, beam_Emin_eV=1e3, beam_Emax_eV=5e3,
+                                                    seed=g) for g in range(3)]
+    sim = gs.GapSim(cfgs, particle_fp=32 if fp32 else 64, capacity=(50_000, 50_000))
+    orcs = []
+    for g, cfg in enumerate(cfgs):
+        loads = W.load_config1(n_per_species=2000 * (g + 1), seed=20 + g)
+        loads = {s: (x, v * (10.0 + 10 * g)) for s, (x, v) in loads.items()}
+        o = oracle.OracleSim(cfg, fp32=fp32)
+        for s, (x, v) in loads.items():
+            sim.inject(g, s, x, v)
+            o.inject(s, x, v)
+        orcs.append(o)
+    sim.step_strict(6)
+    for o in orcs:
+        o.step(oracle.STRICT, 6)
+    for g, o in enumerate(orcs):
+        rg, ro = sim.dt_check(g), o.dt_report()
+        assert rg["n_e_max"] == ro["n_e_max"], g
+        if fp32:
+            np.testing.assert_array_equal(rg["beta"], ro["beta"])
+        else:
+            np.testing.assert_allclose(rg["beta"], ro["beta"], rtol=1e-12)
+        assert rg["omega_max"] == pytest.approx(ro["omega_max"], rel=1e-10, abs=1e-6)
+        assert rg["eta"] == pytest.approx(ro["eta"], rel=1e-6, abs=1e-14)
+        assert rg["flags"] == ro["flags"]
+    sim.close()
