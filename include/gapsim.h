@@ -171,6 +171,10 @@ typedef struct {
   double mlp_proposal[3]; /* the guess network's u at the last GS_GUESS_MLP solve, used or not */
   double qcirc_step;      /* qcirc_star minus the previous level's qcirc: the charge the
                              circuit moved onto the gap over the last step [C] */
+  double q_space;         /* space charge in the gap at the last level: area times the
+                             integral of rho (electrode nodes at half weight) [C]; with
+                             sigma * area it is the charge that the grounded electrode
+                             mirrors (Gauss' law) */
 } gs_diag;
 
 /* Accumulated device time of the library's kernels, measured with HIP events

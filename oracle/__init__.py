@@ -71,7 +71,7 @@ class OrDiag(C.Structure):
         ("n_live", C.c_int64 * 2),
         ("abs_step", (C.c_int64 * 2) * 2), ("emit_step", C.c_int64 * 2), ("inj_step", C.c_int64),
         ("abs_cum", (C.c_int64 * 2) * 2), ("emit_cum", C.c_int64 * 2), ("inj_cum", C.c_int64),
-        ("pushed_cum", C.c_int64), ("qcirc_step", C.c_double),
+        ("pushed_cum", C.c_int64), ("qcirc_step", C.c_double), ("q_space", C.c_double),
     ]
 
 
@@ -341,7 +341,7 @@ class OracleSim:
                     emit_step=np.array(D.emit_step[:]), inj_step=D.inj_step,
                     abs_cum=np.array([[D.abs_cum[a][b] for b in range(2)] for a in range(2)]),
                     emit_cum=np.array(D.emit_cum[:]), inj_cum=D.inj_cum,
-                    pushed_cum=D.pushed_cum, qcirc_step=D.qcirc_step)
+                    pushed_cum=D.pushed_cum, qcirc_step=D.qcirc_step, q_space=D.q_space)
 
     def phi0_prev(self) -> float:
         return float(lib().or_phi0_prev(self._h))

@@ -540,6 +540,11 @@ static int solve_level(or_sim *s, int mode) {
   }
   D->qcirc_star = qstar;
   D->qcirc_step = qstar - s->qcirc_prev;
+  {
+    double sp = 0.5 * (s->rho[0] + s->rho[N]);
+    for (int k = 1; k < N; ++k) sp += s->rho[k];
+    D->q_space = A * dx * sp;
+  }
   for (int j = 0; j < M; ++j) {
     D->q[j] = q[j];
     D->I[j] = (3.0 * Dn[j] - s->dq[0][j]) / (2.0 * p->dt);

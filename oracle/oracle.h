@@ -106,6 +106,7 @@ typedef struct {
   int64_t inj_cum;
   int64_t pushed_cum;     /* particle pushes so far (particle-steps) */
   double qcirc_step;      /* qcirc_star - Q_circ^{n-1} */
+  double q_space;         /* A * integral of rho^n over the gap (trapezoid on the nodes) */
 } or_diag;
 
 typedef struct or_sim or_sim;

@@ -1153,6 +1153,7 @@ extern "C" gs_status gs_read_diagnostics(gs_ctx *ctx, int32_t gap, gs_diag *out,
   for (int j = 0; j <= c.M; ++j) out->newton_guess[j] = s.guess[j];
   for (int j = 0; j < 3; ++j) out->mlp_proposal[j] = s.mlp_prop[j];
   out->qcirc_step = s.qcirc_step;
+  out->q_space = s.q_space;
   return check_sticky(ctx, true);
 }
 

@@ -78,6 +78,7 @@ struct GapState {
   // diagnostics of the last solved level
   double t, phi0, sigma, qcirc, qcirc_star, qconv, e_ground;
   double qcirc_step;    // Q_circ* of this level minus Q_circ of the one before
+  double q_space;       // A times the integral of rho over the gap at this level
   double q[MAXM], I[MAXM];
   int64_t abs_last[4], emit_last[2], inj_last, pushed_last;
   int64_t abs_cum[4], emit_cum[2], inj_cum, pushed_cum;

@@ -676,6 +676,8 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   // 2. circuit and surface charge
   if (tid == 0) {
     double sg;
+    // space charge: the cell terms (rho_0 at half weight) plus the half cell at node N
+    ss.q_space = sc.A * (tot + 0.5 * dx * s_rhoN);
     solve_level(p, g, sc, ss, P, mode, guess, tol, maxit, &sg, s_work, s_tally, want_mlp ? s_mu : nullptr);
     s_sigma = sg;
     if (rec_here)

@@ -83,6 +83,7 @@ class GsDiag(C.Structure):
         ("newton_guess", C.c_double * (MAX_MESH + 1)),
         ("mlp_proposal", C.c_double * 3),
         ("qcirc_step", C.c_double),
+        ("q_space", C.c_double),
     ]
 
 
@@ -402,7 +403,7 @@ class GapSim:
                     newton_max=D.newton_max, newton_levels=D.newton_levels,
                     newton_resid0=D.newton_resid0, newton_resid=D.newton_resid,
                     newton_guess=np.array(D.newton_guess[:M + 1]),
-                    mlp_proposal=np.array(D.mlp_proposal[:]), qcirc_step=D.qcirc_step)
+                    mlp_proposal=np.array(D.mlp_proposal[:]), qcirc_step=D.qcirc_step, q_space=D.q_space)
 
     def autotune(self, mode: int, guess: int = GUESS_DIRECT, trial_steps: int = 8,
                  cache_path: Optional[str] = None) -> dict:

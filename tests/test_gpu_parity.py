@@ -66,7 +66,7 @@ def check_run(recs, tol, M):
     for dg, do in recs:
         assert dg["step"] == do["step"]
         assert_counts_equal(dg, do)
-    for key in ("phi0", "sigma", "qcirc", "qcirc_star"):
+    for key in ("phi0", "sigma", "qcirc", "qcirc_star", "q_space"):
         r = _series_rel([d[key] for d, _ in recs], [o[key] for _, o in recs])
         assert r <= tol, (key, r)
     # loop currents and charges norm-wise: the largest deviation over all loops

@@ -475,6 +475,8 @@ def test_charge_conservation_and_gauss(fp32, mode):
         # deposit conserves charge: sum of nodal charge = sum of particle sheets
         sheets = cfg.weight * cfg.q_unit * float(live_at_solve @ Z)
         assert abs(space - sheets) <= 1e-12 * max(abs(sheets), cfg.weight * cfg.q_unit)
+        # the reported space charge is that sum times the area, i.e. the live sheets
+        assert abs(d["q_space"] - A * sheets) <= 1e-12 * A * max(abs(sheets), cfg.weight * cfg.q_unit)
         # Gauss: surface charge + space charge + grounded-electrode charge = 0
         sigma_minus = -cfg.eps0 * d["e_ground"]
         assert abs(d["sigma"] + space + sigma_minus) <= 1e-11 * (abs(d["sigma"]) + abs(space))
