@@ -113,6 +113,12 @@ def lib():
         L.or_gather64.restype = C.c_double
         L.or_gather32.argtypes = [C.c_int32, C.POINTER(C.c_float), C.c_float]
         L.or_gather32.restype = C.c_float
+        L.or_push32.argtypes = [C.c_int32, C.POINTER(C.c_float), C.c_float, C.c_float, C.c_float,
+                                C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.or_push32.restype = C.c_int32
+        L.or_alpha32.argtypes = [C.c_void_p, C.c_int32]
+        L.or_alpha32.restype = C.c_float
+        L.or_beam_ion32.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)]
         L.or_circuit_run.argtypes = [C.POINTER(OrParams), C.c_int64, P, P]
         L.or_circuit_run.restype = C.c_int32
         L.or_gelu.argtypes = [C.c_double]
@@ -202,6 +208,16 @@ def gather32(ehat, xi) -> np.ndarray:
     F = C.POINTER(C.c_float)
     return np.array([lib().or_gather32(N, ehat.ctypes.data_as(F), float(v)) for v in xi],
                     dtype=np.float32)
+
+
+def push32(ehat, alpha: float, xi: float, u: float):
+    """One binary32 push in grid units: (xi', u', wall) with wall 0 inside, 1 at the
+    circuit electrode, 2 at the ground."""
+    ehat = np.ascontiguousarray(ehat, dtype=np.float32)
+    xo, uo = C.c_float(), C.c_float()
+    w = lib().or_push32(ehat.size - 2, ehat.ctypes.data_as(C.POINTER(C.c_float)), float(alpha), float(xi),
+                        float(u), C.byref(xo), C.byref(uo))
+    return np.float32(xo.value), np.float32(uo.value), int(w)
 
 
 def circuit_run(cfg, nsteps: int):
@@ -342,6 +358,15 @@ class OracleSim:
                     abs_cum=np.array([[D.abs_cum[a][b] for b in range(2)] for a in range(2)]),
                     emit_cum=np.array(D.emit_cum[:]), inj_cum=D.inj_cum,
                     pushed_cum=D.pushed_cum, qcirc_step=D.qcirc_step, q_space=D.q_space)
+
+    def alpha32(self, species: int) -> np.float32:
+        return np.float32(lib().or_alpha32(self._h, species))
+
+    def beam_ion32(self, step: int, k: int):
+        """Beam ion k of the step that solves level `step`, in grid units."""
+        xi, u = C.c_float(), C.c_float()
+        lib().or_beam_ion32(self._h, step, k, C.byref(xi), C.byref(u))
+        return np.float32(xi.value), np.float32(u.value)
 
     def phi0_prev(self) -> float:
         return float(lib().or_phi0_prev(self._h))

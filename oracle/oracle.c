@@ -609,7 +609,21 @@ float or_gather32(int32_t N, const float *ehat, float xi) {
   return a + m;
 }
 
-static float gather32(const or_sim *s, float xi) { return or_gather32(s->N, s->ehat, xi); }
+/* eq. vel_update_main and eq. pos_update_main for one binary32 particle in grid
+ * units; the wall it reaches, if any (App. E: x <= 0 circuit, x >= N ground) */
+int32_t or_push32(int32_t N, const float *ehat, float alpha, float xi, float u, float *xi_out, float *u_out) {
+  const float Ep = or_gather32(N, ehat, xi);
+  const float du = alpha * Ep;
+  const float u1 = u + du;
+  const float x1 = xi + u1;
+  *xi_out = x1;
+  *u_out = u1;
+  if (x1 <= 0.0f) return 1;
+  if (x1 >= (float)N) return 2;
+  return 0;
+}
+
+float or_alpha32(const or_sim *s, int32_t species) { return s->alpha32[species & 1]; }
 
 /* ------------------------------------------------------------------------ */
 /* secondary emission for one absorbed ion (Alg. 2)                          */
@@ -668,6 +682,30 @@ static void emit_electrons(or_sim *s, uint32_t ion_id, double v_ion, int wall,
 /* ------------------------------------------------------------------------ */
 /* one time step                                                             */
 /* ------------------------------------------------------------------------ */
+/* beam ion k of the step that solves level `step` (Sec. 4.2 and the beam of
+ * the workloads): energy uniform in [Emin, Emax] and depth below its entry
+ * electrode from its own random block */
+static void beam_ion(const or_params *p, double dx, int64_t step, int64_t k, double *x_out, double *v_out,
+                     float *xi_out, float *u_out) {
+  const double dt = p->dt;
+  uint64_t blk[4];
+  draw_block(p->seed, (uint64_t)step, (uint64_t)k, 2, 0, blk);
+  double E = p->beam_Emin_eV + (p->beam_Emax_eV - p->beam_Emin_eV) * unit_open(blk[0]);
+  double v = sqrt(2.0 * E * p->ev / p->mass[1]);
+  double depth = unit_open(blk[1]) * (p->beam_layer > 0.0 ? p->beam_layer : v * dt);
+  double x = (p->beam_side == 1) ? p->d - depth : depth;
+  double uv = (v * dt) / dx;
+  *x_out = x;
+  *v_out = (p->beam_side == 1) ? -v : v;
+  *xi_out = (float)(x / dx);
+  *u_out = (float)((p->beam_side == 1) ? -uv : uv);
+}
+
+void or_beam_ion32(const or_sim *s, int64_t step, int64_t k, float *xi, float *u) {
+  double x, v;
+  beam_ion(&s->p, s->dx, step, k, &x, &v, xi, u);
+}
+
 int32_t or_step(or_sim *s, int32_t mode) {
   const or_params *p = &s->p;
   const int N = s->N;
@@ -707,12 +745,8 @@ int32_t or_step(or_sim *s, int32_t mode) {
       s->v[k] = v1;
       v_new_si = v1;
     } else {
-      float Ep = gather32(s, s->xf[k]);
-      float du = s->alpha32[sp] * Ep;
-      float u1 = s->uf[k] + du;
-      float x1 = s->xf[k] + u1;
-      if (x1 <= 0.0f) wall = 0;
-      else if (x1 >= (float)N) wall = 1;
+      float x1, u1;
+      wall = or_push32(N, s->ehat, s->alpha32[sp], s->xf[k], s->uf[k], &x1, &u1) - 1;
       s->xf[k] = x1;
       s->uf[k] = u1;
       v_new_si = (double)u1 * dx / dt;
@@ -759,16 +793,9 @@ int32_t or_step(or_sim *s, int32_t mode) {
   if (n_inj > 0) {
     if (grow(s, s->n + n_inj)) return -2;
     for (int64_t k = 0; k < n_inj; ++k) {
-      uint64_t blk[4];
-      draw_block(p->seed, (uint64_t)s->step, (uint64_t)k, 2, 0, blk);
-      double E = p->beam_Emin_eV + (p->beam_Emax_eV - p->beam_Emin_eV) * unit_open(blk[0]);
-      double v = sqrt(2.0 * E * p->ev / p->mass[1]);
-      double depth = unit_open(blk[1]) * (p->beam_layer > 0.0 ? p->beam_layer : v * dt);
-      double x = (p->beam_side == 1) ? p->d - depth : depth;
-      float xi = (float)(x / dx);
-      double uv = (v * dt) / dx;
-      float u = (float)((p->beam_side == 1) ? -uv : uv);
-      double vs = (p->beam_side == 1) ? -v : v;
+      double x, vs;
+      float xi, u;
+      beam_ion(p, dx, s->step, k, &x, &vs, &xi, &u);
       append(s, 1, x, vs, xi, u, s->next_id);
       s->next_id += 1;
     }

@@ -151,6 +151,14 @@ double or_gather64(int32_t n_cells, double dx, const double *E, double e0_surf, 
 /* the same in binary32, grid units: ehat[0] = surface field at node 0,
  * ehat[k] = E_{k-1/2} (k = 1..N), ehat[N+1] = field at node N */
 float or_gather32(int32_t n_cells, const float *ehat, float xi);
+/* one binary32 push in grid units with that gather and charge-to-mass factor
+ * alpha = Z q dt^2 / (m dx): writes the new position and velocity; returns 0
+ * inside the gap, 1 at the circuit electrode (x <= 0), 2 at the ground (x >= N) */
+int32_t or_push32(int32_t n_cells, const float *ehat, float alpha, float xi, float u, float *xi_out, float *u_out);
+/* the binary32 alpha of a species as the oracle's push uses it */
+float or_alpha32(const or_sim *s, int32_t species);
+/* beam ion k of the step that solves level `step`, in grid units (binary32) */
+void or_beam_ion32(const or_sim *s, int64_t step, int64_t k, float *xi, float *u);
 /* Circuit alone, the gap as a capacitor eps0*A/d (plus c_par): q_out[n*M+j],
  * v_out[n] = gap voltage, for levels 0..nsteps-1 */
 int32_t or_circuit_run(const or_params *p, int64_t nsteps, double *q_out, double *v_out);
