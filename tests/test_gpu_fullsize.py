@@ -111,3 +111,77 @@ def test_full_size_sampled_push_and_invariants(name):
         bx, bu = orc.beam_ion32(warm, int(q))
         assert xb[k] == bx and ub[k] == bu, q
     sim.close()
+
+
+def test_batched_512_gaps_full_size_autotuned():
+    """The batched ensemble at full size (512 gaps of 512 cells, 5e4..5e5 H+ each,
+    1.4e8 in all, strict coupling), with the launch shape the autotuner picks and
+    graph replay, as the benchmark runs it.  One more step is then checked: the
+    space charge and the counts of every gap, and in four gaps sampled pushes and
+    beam ions against the oracle."""
+    from paper_2603_24010_amd import gapsim as gs
+    G, cells = 512, 512
+    cfgs, nps, ebs, caps = [], [], [], []
+    for g in range(G):
+        cfg, n_p, e_b = W.config4_gap(g, n_cells=cells)
+        cfgs.append(cfg)
+        nps.append(n_p)
+        ebs.append(e_b)
+        caps.append((n_p // 2 + 65536, int(1.3 * n_p) + 64 * cfg.beam_per_step + 4096))
+    sim = gs.GapSim(cfgs, particle_fp=32, capacity=caps)
+    for g in range(G):
+        for sp, (x, v) in W.load_config4_gap(nps[g], ebs[g], g).items():
+            sim.inject(g, sp, x, v)
+    print(f"batched: {sum(nps)} H+ in {G} gaps", flush=True)
+    sim.step_strict(10)
+    tuning = sim.autotune(0, gs.GUESS_DIRECT, trial_steps=8)
+    print(f"batched: autotuned {tuning}", flush=True)
+    sim.set_option(gs.OPT_GRAPH, 1)
+    sim.step_strict(30)
+    level = 40
+    da = [sim.diag(g) for g in range(G)]
+    picks = [0, 137, 300, 511]
+    snap = {g: sim.particles(g, 1) for g in picks}
+    sim.step_strict(1)
+    db = [sim.diag(g) for g in range(G)]
+    print("batched: states read", flush=True)
+    for g in range(G):
+        a, b, cfg = da[g], db[g], cfgs[g]
+        assert b["step"] == level
+        em_total = int((b["emit_cum"] - a["emit_cum"]).sum())
+        deferred = em_total - int(b["emit_step"].sum())
+        assert b["inj_step"] == cfg.beam_per_step and deferred >= 0
+        assert b["n_live"][1] == a["n_live"][1] + b["inj_step"] - b["abs_step"][1].sum()
+        assert b["n_live"][0] == a["n_live"][0] + em_total - b["abs_step"][0].sum()
+        s0 = cfg.weight * cfg.q_unit
+        expect = cfg.area * s0 * (cfg.Z[1] * int(a["n_live"][1]) + cfg.Z[0] * (int(a["n_live"][0]) + deferred))
+        assert abs(b["q_space"] - expect) <= 1e-12 * abs(expect), g
+    rng = np.random.default_rng(7)
+    for g in picks:
+        cfg = cfgs[g]
+        xa, ua, ida = snap[g]
+        _, E, _ = sim.fields(g)
+        xb, ub, idb = sim.particles(g, 1)
+        ehat = np.concatenate([[db[g]["sigma"] / cfg.eps0], E, [db[g]["e_ground"]]]).astype(np.float32)
+        orc = oracle.OracleSim(cfg, fp32=True)
+        alpha = orc.alpha32(1)
+        ob = np.argsort(idb)
+        ids_b = idb[ob]
+
+        def find(i):
+            k = np.searchsorted(ids_b, np.uint32(i))
+            return ob[k] if k < len(ids_b) and ids_b[k] == i else -1
+        for j in rng.integers(0, len(xa), size=5000):
+            x1, u1, wall = oracle.push32(ehat, alpha, xa[j], ua[j])
+            k = find(ida[j])
+            if wall == 0:
+                assert k >= 0 and xb[k] == x1 and ub[k] == u1, (g, ida[j])
+            else:
+                assert k < 0, (g, ida[j])
+        id0 = nps[g] + level * cfg.beam_per_step
+        for q in rng.integers(0, cfg.beam_per_step, size=min(2000, cfg.beam_per_step)):
+            k = find(id0 + int(q))
+            bx, bu = orc.beam_ion32(level, int(q))
+            assert k >= 0 and xb[k] == bx and ub[k] == bu, (g, q)
+    print("batched: sampled pushes and beam ions equal", flush=True)
+    sim.close()
