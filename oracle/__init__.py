@@ -119,6 +119,9 @@ def lib():
         L.or_alpha32.argtypes = [C.c_void_p, C.c_int32]
         L.or_alpha32.restype = C.c_float
         L.or_beam_ion32.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.or_emit_sample.argtypes = [C.c_void_p, C.c_int64, C.c_uint32, C.c_double, C.c_int32,
+                                     C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int32]
+        L.or_emit_sample.restype = C.c_int32
         L.or_circuit_run.argtypes = [C.POINTER(OrParams), C.c_int64, P, P]
         L.or_circuit_run.restype = C.c_int32
         L.or_gelu.argtypes = [C.c_double]
@@ -367,6 +370,15 @@ class OracleSim:
         xi, u = C.c_float(), C.c_float()
         lib().or_beam_ion32(self._h, step, k, C.byref(xi), C.byref(u))
         return np.float32(xi.value), np.float32(u.value)
+
+    def emit_sample(self, step: int, ion_id: int, v_ion: float, wall: int):
+        """The secondary electrons of one absorbed ion (wall 0 circuit, 1 ground) in the
+        push after level `step`: (xi, u) arrays in grid units."""
+        xi, u = np.zeros(1024, dtype=np.float32), np.zeros(1024, dtype=np.float32)
+        F = C.POINTER(C.c_float)
+        k = lib().or_emit_sample(self._h, step, int(ion_id), float(v_ion), wall, xi.ctypes.data_as(F),
+                                 u.ctypes.data_as(F), 1024)
+        return xi[:min(k, 1024)], u[:min(k, 1024)]
 
     def phi0_prev(self) -> float:
         return float(lib().or_phi0_prev(self._h))

@@ -628,10 +628,14 @@ float or_alpha32(const or_sim *s, int32_t species) { return s->alpha32[species &
 /* ------------------------------------------------------------------------ */
 /* secondary emission for one absorbed ion (Alg. 2)                          */
 /* ------------------------------------------------------------------------ */
-static void emit_electrons(or_sim *s, uint32_t ion_id, double v_ion, int wall,
-                           int64_t *n_emitted) {
+/* The secondary electrons of one ion absorbed at `wall` (0 circuit, 1 ground)
+ * in the push after level `step`, impact velocity v_ion [m/s] (Alg. 2): returns
+ * their count and writes the first max_out of them (start and velocity, SI and
+ * grid units). */
+static int32_t see_draw(const or_sim *s, int64_t step, uint32_t ion_id, double v_ion, int wall, double *x_si,
+                        double *v_si, float *xi, float *u, int32_t max_out) {
   const or_params *p = &s->p;
-  if (p->see_amp <= 0.0) return;
+  if (p->see_amp <= 0.0) return 0;
   /* Alg. 2: the incident energy, the mean yield (clipped at zero), the count */
   double e_ion = 0.5 * p->mass[1] * v_ion * v_ion / p->ev; /* eV */
   double lam;
@@ -646,36 +650,50 @@ static void emit_electrons(or_sim *s, uint32_t ion_id, double v_ion, int wall,
   }
   if (lam < 0.0) lam = 0.0;
   uint64_t blk[4];
-  draw_block(p->seed, (uint64_t)s->step, (uint64_t)ion_id, 1, 0, blk);
+  draw_block(p->seed, (uint64_t)step, (uint64_t)ion_id, 1, 0, blk);
   int32_t k = or_poisson_draw(lam, unit_open(blk[0]), p->see_max);
   /* the electrons' energies take the ion's stream words from 1 on, in order:
    * one per electron (fixed, exponential) or two (lognormal) */
   int32_t w = 1;
-  for (int32_t e = 0; e < k; ++e) {
+  for (int32_t e = 0; e < k && e < max_out; ++e) {
     double E_se;
     if (p->see_law == OR_SEE_LOGNORMAL) {
-      if (w % 4 == 0) draw_block(p->seed, (uint64_t)s->step, (uint64_t)ion_id, 1, (uint64_t)(w / 4), blk);
+      if (w % 4 == 0) draw_block(p->seed, (uint64_t)step, (uint64_t)ion_id, 1, (uint64_t)(w / 4), blk);
       double u1 = unit_open(blk[w % 4]);
       w += 1;
-      if (w % 4 == 0) draw_block(p->seed, (uint64_t)s->step, (uint64_t)ion_id, 1, (uint64_t)(w / 4), blk);
+      if (w % 4 == 0) draw_block(p->seed, (uint64_t)step, (uint64_t)ion_id, 1, (uint64_t)(w / 4), blk);
       double u2 = unit_open(blk[w % 4]);
       w += 1;
       double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
       E_se = exp(p->see_ln_mu + p->see_ln_sigma * z);
     } else {
-      if (w % 4 == 0) draw_block(p->seed, (uint64_t)s->step, (uint64_t)ion_id, 1, (uint64_t)(w / 4), blk);
-      double u = unit_open(blk[w % 4]);
+      if (w % 4 == 0) draw_block(p->seed, (uint64_t)step, (uint64_t)ion_id, 1, (uint64_t)(w / 4), blk);
+      double uu = unit_open(blk[w % 4]);
       w += 1;
-      E_se = (p->see_law == OR_SEE_EXP) ? -p->see_E_eV * log(u) : p->see_E_eV;
+      E_se = (p->see_law == OR_SEE_EXP) ? -p->see_E_eV * log(uu) : p->see_E_eV;
     }
     double v_se = sqrt(2.0 * E_se * p->ev / p->mass[0]);
     /* normal emission into the gap, starting on the surface */
-    double x_si = wall == 0 ? 0.0 : p->d;
-    double v_si = wall == 0 ? v_se : -v_se;
-    float xi = wall == 0 ? 0.0f : (float)s->N;
-    float uu = (float)((v_si * p->dt) / s->dx);
-    append(s, 0, x_si, v_si, xi, uu, NO_ID);
+    x_si[e] = wall == 0 ? 0.0 : p->d;
+    v_si[e] = wall == 0 ? v_se : -v_se;
+    xi[e] = wall == 0 ? 0.0f : (float)s->N;
+    u[e] = (float)((v_si[e] * p->dt) / s->dx);
   }
+  return k;
+}
+
+int32_t or_emit_sample(const or_sim *s, int64_t step, uint32_t ion_id, double v_ion, int32_t wall, float *xi,
+                       float *u, int32_t max_out) {
+  double xs[1024], vs[1024];
+  if (max_out > 1024) max_out = 1024;
+  return see_draw(s, step, ion_id, v_ion, wall, xs, vs, xi, u, max_out);
+}
+
+static void emit_electrons(or_sim *s, uint32_t ion_id, double v_ion, int wall, int64_t *n_emitted) {
+  double xs[1024], vs[1024];
+  float xi[1024], u[1024];
+  const int32_t k = see_draw(s, s->step, ion_id, v_ion, wall, xs, vs, xi, u, 1024);
+  for (int32_t e = 0; e < k && e < 1024; ++e) append(s, 0, xs[e], vs[e], xi[e], u[e], NO_ID);
   *n_emitted += k;
 }
 

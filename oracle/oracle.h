@@ -159,6 +159,12 @@ int32_t or_push32(int32_t n_cells, const float *ehat, float alpha, float xi, flo
 float or_alpha32(const or_sim *s, int32_t species);
 /* beam ion k of the step that solves level `step`, in grid units (binary32) */
 void or_beam_ion32(const or_sim *s, int64_t step, int64_t k, float *xi, float *u);
+/* the secondary electrons of one ion absorbed at wall 0 (circuit) or 1 (ground)
+ * in the push after level `step`, impact velocity v_ion [m/s] (Alg. 2): their
+ * count; the first max_out (at most 1024) written as start and velocity in
+ * grid units.  Or_step emits through the same routine. */
+int32_t or_emit_sample(const or_sim *s, int64_t step, uint32_t ion_id, double v_ion, int32_t wall, float *xi,
+                       float *u, int32_t max_out);
 /* Circuit alone, the gap as a capacitor eps0*A/d (plus c_par): q_out[n*M+j],
  * v_out[n] = gap voltage, for levels 0..nsteps-1 */
 int32_t or_circuit_run(const or_params *p, int64_t nsteps, double *q_out, double *v_out);

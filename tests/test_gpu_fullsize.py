@@ -12,6 +12,9 @@ steps (one compaction on the way), one more step is checked:
     eq. vel_update_main and eq. pos_update_main); an ion the oracle's push puts
     on a wall is gone;
   - a sample of the step's beam ions equals the oracle's draws for their indices;
+  - the step's secondary electrons (still on their wall node) number as the
+    push's tally, and at 2e7 they equal, as a multiset, the oracle's emission
+    (Alg. 2) for every ion that left, at the impact velocity of its push;
   - the level's space charge equals the charge of the particles it was deposited
     from, exactly (fixed-point weights sum to whole macroparticles);
   - live count after = live before + injected + emitted - absorbed.
@@ -110,6 +113,32 @@ def test_full_size_sampled_push_and_invariants(name):
         assert k >= 0
         bx, bu = orc.beam_ion32(warm, int(q))
         assert xb[k] == bx and ub[k] == bu, q
+
+    # the step's secondary electrons sit on their wall node until their first push
+    # (a live electron is never exactly on a wall: it would have been absorbed)
+    xe, ue, _ = sim.particles(0, 0)
+    at_wall = (xe == 0.0) | (xe == np.float32(cfg.n_cells))
+    assert at_wall.sum() == db["emit_step"].sum()
+    if spec["n0"] <= 20_000_000:
+        # every ion that left, through the oracle's push and emission: the same
+        # electrons, compared as a multiset (their slots are unspecified)
+        gone = ~np.isin(ida, ids_b, assume_unique=True)
+        assert gone.sum() == absorbed[1].sum()
+        dx = cfg.d / cfg.n_cells
+        ox, ou = [], []
+        for j in np.nonzero(gone)[0]:
+            x1, u1, wall = oracle.push32(ehat, alpha, xa[j], ua[j])
+            assert wall != 0, ida[j]
+            ex, eu = orc.emit_sample(warm, int(ida[j]), float(u1) * dx / cfg.dt, wall - 1)
+            ox.append(ex)
+            ou.append(eu)
+        ox, ou = np.concatenate(ox), np.concatenate(ou)
+        assert len(ox) == at_wall.sum() > 100
+        gx, gu = xe[at_wall], ue[at_wall]
+        og, oo = np.lexsort((gu, gx)), np.lexsort((ou, ox))
+        np.testing.assert_array_equal(gx[og], ox[oo])
+        np.testing.assert_array_equal(gu[og], ou[oo])
+        print(f"{name}: {len(ox)} secondary electrons of {gone.sum()} absorbed ions equal", flush=True)
     sim.close()
 
 
