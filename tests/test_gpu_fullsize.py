@@ -16,7 +16,8 @@ steps (one compaction on the way), one more step is checked:
     push's tally, and at 2e7 they equal, as a multiset, the oracle's emission
     (Alg. 2) for every ion that left, at the impact velocity of its push;
   - the level's space charge equals the charge of the particles it was deposited
-    from, exactly (fixed-point weights sum to whole macroparticles);
+    from, exactly (fixed-point weights sum to whole macroparticles), and its
+    potential is the oracle's Poisson solve of its density and surface charge;
   - live count after = live before + injected + emitted - absorbed.
 """
 import numpy as np
@@ -61,8 +62,15 @@ def test_full_size_sampled_push_and_invariants(name):
     sim.step(spec["mode"], 1)  # solves level `warm` from these particles, then pushes them
     db = sim.diag(0)
     assert db["step"] == warm
-    _, E, _ = sim.fields(0)
+    phi, E, rho = sim.fields(0)
     xb, ub, idb = sim.particles(0, 1)
+
+    # the level's field from its density and surface charge: the oracle's Poisson
+    # with the Gauss row at the circuit electrode (the strict closure only decides
+    # sigma, which the diagnostics give)
+    phi_o = oracle.poisson_gauss(rho, cfg.d / cfg.n_cells, cfg.eps0, db["sigma"])
+    assert np.abs(phi - phi_o).max() <= 1e-11 * np.abs(phi_o).max()
+    assert abs(db["phi0"] - phi_o[0]) <= 1e-11 * np.abs(phi_o).max()
     print(f"{name}: states read ({len(xa)} / {len(xb)} ions)", flush=True)
 
     # bookkeeping of the step; electrons past a full event queue of the previous
