@@ -709,6 +709,108 @@ def run_external(args, copy_gbs):
     print(json.dumps(out), flush=True)
 
 
+TESLA_FINE_WORKLOAD = "tesla_600c_ground_pulse_dt15ps"
+
+
+def run_tesla_fine(args, copy_gbs):
+    """The Tesla run at the time step App. D verifies (1.5e-11 s, 575000 steps for
+    the same 8.62 us and the same physical pulse), where the stand-in run keeps
+    the particle constraints: strict and weak with and without emission, and weak
+    with the circuit in an external Radau engine; graphs replay the steps, the
+    gap voltage is read every 100 steps and the time-step check every 1000."""
+    import torch
+    import oracle
+    from paper_2603_24010_amd import gapsim, workloads as W
+    from paper_2603_24010_amd.engines import RadauCircuitEngine
+    ENGINE = -1
+    cfg0 = W.config_tesla(dt=1.5e-11)
+    steps, every, chk_every = len(cfg0.beam_schedule), 100, 1000
+    cases = [("strict_see", oracle.STRICT, cfg0), ("weak_see", oracle.WEAK, cfg0),
+             ("strict_no_see", oracle.STRICT, cfg0.replace(see_amp=0.0)),
+             ("weak_no_see", oracle.WEAK, cfg0.replace(see_amp=0.0)), ("weak_engine_see", ENGINE, cfg0)]
+    res, curves, el_all, pushed_all = {}, {}, 0.0, 0
+    for name, mode, cfg in cases:
+        s = gapsim.GapSim(cfg, particle_fp=32, capacity=(3_000_000, 4_000_000))
+        s.set_option(gapsim.OPT_COMPACT_EVERY, 50)
+        eng = RadauCircuitEngine(cfg) if mode == ENGINE else None
+        if eng is None:
+            s.set_option(gapsim.OPT_GRAPH, 1)
+        V = []
+        chk = {"omega_pe_max": 0.0, "alpha_max": 0.0, "v_e_max": 0.0, "beta_max": [0.0, 0.0], "eta_max": 0.0,
+               "n_e_max": 0.0, "flagged_checks": 0, "checks": 0}
+        el = 0.0
+        for n0 in range(0, steps, every):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if eng is not None:
+                s.step_weak_external(every, eng)
+            else:
+                s.step(mode, every)
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t0
+            V.append(s.diag(0)["phi0"])
+            if (n0 + every) % chk_every == 0:
+                r = s.dt_check(0)
+                chk["omega_pe_max"] = max(chk["omega_pe_max"], r["omega_pe"])
+                chk["alpha_max"] = max(chk["alpha_max"], r["alpha"])
+                chk["n_e_max"] = max(chk["n_e_max"], r["n_e_max"])
+                chk["v_e_max"] = max(chk["v_e_max"], float(r["v_max"][0]))
+                chk["beta_max"] = [max(a, float(b)) for a, b in zip(chk["beta_max"], r["beta"])]
+                chk["eta_max"] = max(chk["eta_max"], r["eta"])
+                chk["flagged_checks"] += int(r["flags"] != 0)
+                chk["checks"] += 1
+                chk["n_omega"] = r["n_omega"]
+        d = s.diag(0)
+        s.close()
+        V = np.array(V)
+        el_all += el
+        pushed_all += d["pushed_cum"]
+        curves[name] = V
+        dts = cfg.dt * every
+        lo = int(np.argmin(V[int(4.0e-6 / dts):int(6.0e-6 / dts)])) + int(4.0e-6 / dts)
+        up = lo + int(np.argmax(V[lo:] > -3e3))
+        res[name] = {"swing_bottom_kV": float(V[lo] / 1e3), "swing_bottom_us": (lo + 1) * dts * 1e6,
+                     "above_minus3kV_us": (up + 1) * dts * 1e6, "next_peak_kV": float(V[lo:].max() / 1e3),
+                     "particle_steps": int(d["pushed_cum"]), "wall_s": el, "injected": int(d["inj_cum"]),
+                     "emitted": int(d["emit_cum"].sum()), "absorbed": [int(x) for x in d["abs_cum"].ravel()],
+                     "time_step_check": _finite(chk)}
+        log(f"[bench] {name}: {res[name]}")
+    rmse = lambda a, b: float(np.sqrt(np.mean((curves[a] - curves[b]) ** 2)) / 1e3)
+    out = {
+        "metric": "Tesla-run waveform at dt = 1.5e-11 s (collapse with vs without SEE, strict vs weak RMSE); "
+                  "particle-steps/s",
+        "value": pushed_all / el_all, "unit": "particle-steps/s", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": el_all * 1e3 / (len(cases) * steps), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": TESLA_FINE_WORKLOAD, "cells": cfg0.n_cells, "dt_s": cfg0.dt,
+                   "beam": "the 15 ns run's stand-in pulse in physical time: 40 ions per 15 ps step at 4.5 us, "
+                           "0.75 us width, 2 mm layer, 10-50 eV; yield 3 E/(E + 20 keV)",
+                   "injected": int(cfg0.beam_schedule.sum()), "timed_with": "hip graphs (engine case eager)"},
+        "cases": res,
+        "strict_weak_rmse_kV": {"see": rmse("strict_see", "weak_see"), "no_see": rmse("strict_no_see", "weak_no_see"),
+                                "strict_vs_weak_external_engine_see": rmse("strict_see", "weak_engine_see"),
+                                "paper_context_kV": 0.228},
+        "curve_kV_every_5ns": [[round((k + 1) * cfg0.dt * every * 1e6, 4)] +
+                               [round(float(curves[c][k]) / 1e3, 3) for c, _, _ in cases]
+                               for k in range(0, len(curves["strict_see"]), 50)],
+        "roofline": {"bound": "latency", "kernel": "k_push", "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "achieved": None, "frac": None, "traffic": None, "copy_GBps": copy_gbs,
+                     "note": "at most ~1.3e6 live particles: each step is a few short launches"},
+    }
+    if not args.no_cpu_baseline:
+        # the oracle from level 0 into the rise of the pulse (about 20 s on one core)
+        o = oracle.OracleSim(cfg0, fp32=True)
+        n = 250_000
+        t0 = time.perf_counter()
+        o.step(oracle.STRICT, n)
+        elc = time.perf_counter() - t0
+        pc = o.diag()["pushed_cum"]
+        out["cpu_baseline"] = {"value": pc / elc, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"strict with SEE, levels 0..{n - 1} (the pulse's rise), binary32 "
+                                         f"oracle mode, {pc} particle-steps in {elc:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline_batched(spec, steps):
     import oracle
     from paper_2603_24010_amd import workloads as W
@@ -757,7 +859,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="beam_gap_4096c_2e7p_weak",
                     choices=sorted(WORKLOADS) + sorted(BATCHED) + [MLP_WORKLOAD, DIVERGENCE, FP64_WORKLOAD,
-                                                                   TESLA_WORKLOAD, EXTERNAL_WORKLOAD])
+                                                                   TESLA_WORKLOAD, EXTERNAL_WORKLOAD,
+                                                                   TESLA_FINE_WORKLOAD])
     ap.add_argument("--div-particles", type=int, default=200_000_000)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -830,6 +933,8 @@ def main():
         return run_tesla(args, copy_gbs)
     if args.workload == EXTERNAL_WORKLOAD:
         return run_external(args, copy_gbs)
+    if args.workload == TESLA_FINE_WORKLOAD:
+        return run_tesla_fine(args, copy_gbs)
     spec = WORKLOADS[args.workload]
     log(f"[bench] building workload {args.workload}")
     sim, cfg, _ = make_sim(args.workload, spec, args.warmup + args.steps)

@@ -194,7 +194,7 @@ def gaussian_schedule(n_steps: int, peak: float, center: float, width: float) ->
 
 def config_tesla(n_cells: int = 600, n_steps: int = 575, peak: float = 40000.0, center: float = 300.0,
                  width: float = 50.0, layer: float = 2e-3, see_amp: float = 3.0, see_E0_eV: float = 2e4,
-                 E_lo: float = 10.0, E_hi: float = 50.0, seed: int = 5) -> GapConfig:
+                 E_lo: float = 10.0, E_hi: float = 50.0, seed: int = 5, dt: float = 15e-9) -> GapConfig:
     """The paper's integrated Tesla run (Sec. 4.2, tab:space_time_variable,
     tab:circuit_parameters): 80 mm gap of 2.53e-2 m^2 on 600 cells, dt 15 ns, 575
     steps (8.62 us), Ti+ ions and electrons of 1000 times their mass, superparticle
@@ -204,8 +204,15 @@ def config_tesla(n_cells: int = 600, n_steps: int = 575, peak: float = 40000.0, 
     as figures; peak / center / width (ions per step, steps), layer [m], energies
     [eV] and the yield law's a and E0 here are stand-ins.  The pulse is centred on
     the first swing that drives the circuit electrode negative (it attracts the
-    ions), at 4.5 us."""
-    return GapConfig(n_cells=n_cells, d=0.08, area=2.53e-2, eps0=EPS0, dt=15e-9,
+    ions), at 4.5 us.  n_steps, peak (ions per step), center and width are given
+    for 15 ns steps; another dt keeps the same physical pulse and run length
+    (dt = 1.5e-11 s, the step the paper's App. D checks, gives 574667 steps of
+    40 ions at the peak)."""
+    f = 15e-9 / dt
+    if f != 1.0:
+        n_steps = int(round(n_steps * f))
+        peak, center, width = peak / f, center * f, width * f
+    return GapConfig(n_cells=n_cells, d=0.08, area=2.53e-2, eps0=EPS0, dt=dt,
                      mass=(M_ELECTRON_X1000, M_TI), weight=2.5e7,
                      see_amp=see_amp, see_E0_eV=see_E0_eV, see_law=SEE_EXP, see_E_eV=3.0,
                      beam_side=BEAM_GROUND, beam_layer=layer,
