@@ -1336,9 +1336,8 @@ __global__ __launch_bounds__(BS) void k_compact(DevPtrs p, int G, int tile) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   int *prefix = (int *)lds_raw;  // [2G + 1]
   __shared__ int scan_sh[BS];
-  __shared__ unsigned int wave_cnt[BS / 64];
   __shared__ unsigned long long seg_base;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x;
   const int src = (int)(*p.epoch & 1), dst = src ^ 1;
   const int R = 2 * G;
   {
@@ -1373,11 +1372,32 @@ __global__ __launch_bounds__(BS) void k_compact(DevPtrs p, int G, int tile) {
     const long long i_beg = (long long)(t - prefix[r]) * tile;
     const long long i_end = min(n, (long long)(tend - prefix[r]) * tile);
     const P *Xs = (const P *)p.X[src] + c.pbase[s];
+    // the run starts on a tile boundary (a multiple of 8 x the block size) and
+    // regions on 64-slot boundaries: each thread takes VN consecutive slots as
+    // 16-byte vectors, the last partial vector slot by slot
+    constexpr int VN = Vec<P>::n;
+    constexpr int NV = 1;  // vectors per thread per round (two measured slower)
+    constexpr int SPT = VN * NV;
+    typedef typename Vec<P>::type PV;
+    typedef unsigned int IDV __attribute__((ext_vector_type(VN)));
+    const long long step = (long long)BS * SPT;
     // pass 1: live slots of this region in the run
     int cnt = 0;
-    for (long long i = i_beg + tid; i < i_end; i += BS) cnt += Xs[i] >= (P)0;
+    for (long long i = i_beg + (long long)tid * SPT; i < i_end; i += step) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const long long j = i + v * VN;
+        if (j + VN <= i_end) {
+          PV xv = *(const PV *)(Xs + j);
+#pragma unroll
+          for (int k = 0; k < VN; ++k) cnt += Vec<P>::at(xv, k) >= (P)0;
+        } else {
+          for (int k = 0; k < VN; ++k) cnt += (j + k < i_end) && Xs[j + k] >= (P)0;
+        }
+      }
+    }
     int tot_live;
-    (void)block_exclusive_scan<int>(cnt, scan_sh, &tot_live);
+    (void)block_exclusive_scan_i(cnt, scan_sh, &tot_live);
     if (tid == 0)
       seg_base = tot_live ? atomicAdd(&p.cursor[r], (unsigned long long)tot_live) : 0ull;
     __syncthreads();
@@ -1389,27 +1409,46 @@ __global__ __launch_bounds__(BS) void k_compact(DevPtrs p, int G, int tile) {
     P *Ud = (P *)p.U[dst] + c.pbase[s];
     uint32_t *Id = p.ID[dst] + c.pbase[s];
     unsigned long long written = 0;
-    for (long long i0 = i_beg; i0 < i_end; i0 += BS) {
-      const long long i = i0 + tid;
-      const P x = i < i_end ? Xs[i] : (P)-1;
-      const bool live = x >= (P)0;
-      const unsigned long long mask = __ballot(live);
-      if (lane == 0) wave_cnt[w] = (unsigned int)__popcll(mask);
-      __syncthreads();
-      unsigned int before = 0, all = 0;
-      for (int q = 0; q < BS / 64; ++q) {
-        if (q < w) before += wave_cnt[q];
-        all += wave_cnt[q];
+    for (long long i0 = i_beg; i0 < i_end; i0 += step) {
+      const long long i = i0 + (long long)tid * SPT;
+      PV xv[NV], uv[NV];
+      IDV iv[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const long long j = i + v * VN;
+        if (j + VN <= i_end) {
+          xv[v] = *(const PV *)(Xs + j);
+          uv[v] = *(const PV *)(Us + j);
+          iv[v] = *(const IDV *)(Is + j);
+        } else {
+#pragma unroll
+          for (int k = 0; k < VN; ++k) {
+            const bool in = j + k < i_end;
+            Vec<P>::at(xv[v], k) = in ? Xs[j + k] : (P)-1;
+            Vec<P>::at(uv[v], k) = in ? Us[j + k] : (P)0;
+            iv[v][k] = in ? Is[j + k] : 0u;
+          }
+        }
       }
-      if (live) {
-        const unsigned long long o =
-            base + written + before + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
-        Xd[o] = x;
-        Ud[o] = Us[i];
-        Id[o] = Is[i];
-      }
-      written += all;
-      __syncthreads();
+      int c = 0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int k = 0; k < VN; ++k) c += Vec<P>::at(xv[v], k) >= (P)0;
+      int all;
+      const int before = block_exclusive_scan_i(c, scan_sh, &all);
+      unsigned long long o = base + written + (unsigned long long)before;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int k = 0; k < VN; ++k)
+          if (Vec<P>::at(xv[v], k) >= (P)0) {
+            Xd[o] = Vec<P>::at(xv[v], k);
+            Ud[o] = Vec<P>::at(uv[v], k);
+            Id[o] = iv[v][k];
+            ++o;
+          }
+      written += (unsigned long long)all;
     }
     t = tend;
   }
