@@ -351,7 +351,8 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
   st.live[0] += em[0] + em[1] - ab[0] - ab[1];
   st.live[1] += inj - ab[2] - ab[3];
 
-  const double Vs = c.src_dc + c.src_amp * sin(c.src_w * t + c.src_phase);
+  // (no sine on this serial path when there is no AC source: dc + 0 sin = dc)
+  const double Vs = c.src_amp != 0.0 ? c.src_dc + c.src_amp * sin(c.src_w * t + c.src_phase) : c.src_dc;
   // small work vectors live in LDS: indexed by the run-time mesh count they would
   // otherwise go to scratch memory
   double *h = wk, *q = wk + MAXM, *Dn = wk + 2 * MAXM, *y = wk + 3 * MAXM;
@@ -648,14 +649,27 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
 
   // 1. nodal density of level n (to global rho and, as the cell terms of the
   //    prefix sums, to LDS); the accumulator is cleared for the next push
-  for (int k = tid; k <= N; k += FBS) {
-    const double r = node_rho(s0, dx, acc[k] + (k == 0 ? ex0 : 0ull) + (k == N ? exN : 0ull), k, N, fp64);
-    rho[k] = r;
-    acc[k] = 0ull;
-    if (k < N)
-      Sk[k] = (k == 0) ? dx * r / 2.0 : dx * r;
-    else
-      s_rhoN = r;
+  // (four loads in flight per thread before any of the clearing stores, which
+  // the compiler may not move the later loads past)
+  for (int k0 = tid; k0 <= N; k0 += 4 * FBS) {
+    unsigned long long av[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + q * FBS;
+      av[q] = k <= N ? acc[k] : 0ull;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + q * FBS;
+      if (k > N) break;
+      const double r = node_rho(s0, dx, av[q] + (k == 0 ? ex0 : 0ull) + (k == N ? exN : 0ull), k, N, fp64);
+      rho[k] = r;
+      acc[k] = 0ull;
+      if (k < N)
+        Sk[k] = (k == 0) ? dx * r / 2.0 : dx * r;
+      else
+        s_rhoN = r;
+    }
   }
   __syncthreads();
   // prefix sums S_k = dx rho_0/2 + dx sum_{1..k} rho_j over contiguous chunks
