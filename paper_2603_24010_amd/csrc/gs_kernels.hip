@@ -567,6 +567,18 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   __shared__ int s_wsum_i[FBS / 64];
   __shared__ unsigned long long s_ebase;
   __shared__ unsigned int s_emit[2];
+  // the first FBS x 4 nodes of the push's charge accumulator, loaded before
+  // anything else (nothing in this kernel writes them before the density pass)
+  unsigned long long av0[4];
+  {
+    const int n0 = p.gc[g].N;
+    const unsigned long long *a0 = p.acc + p.gc[g].nbase;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = tid + q * FBS;
+      av0[q] = k <= n0 ? a0[k] : 0ull;
+    }
+  }
   // stage the gap's constants, state and last push's tallies in LDS
   if (tid < T_N) {
     unsigned long long *tl = p.tally + (size_t)g * T_N;
@@ -656,7 +668,7 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int k = k0 + q * FBS;
-      av[q] = k <= N ? acc[k] : 0ull;
+      av[q] = k0 == tid ? av0[q] : k <= N ? acc[k] : 0ull;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
