@@ -893,7 +893,7 @@ def main():
         print(json.dumps(rec))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this method has no multi-GPU path in this build "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(independent gaps would shard across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
