@@ -27,7 +27,8 @@ class LinearCircuitEngine:
     electrode potential the field solve gave (q_gap = (C_gap + c_par) phi0_prev);
     the other loop charges and every current carry over, as when a circuit
     simulator restarts from given capacitor voltages and inductor currents.
-    The state before level 0 is q0 with no current, at t = -dt.
+    The state before level 0 is q0 with no current, at t = -dt, so an engine
+    drives a context from its first level (a call for another level raises).
     """
 
     def __init__(self, cfgs):
@@ -90,7 +91,7 @@ class RadauCircuitEngine:
     the method puts their currents back on the constraint after each restart of
     the gap capacitor, where the trapezoidal rule would ring.  The gap capacitor
     restarts from phi0_prev at each call; the state before level 0 is q0 with no
-    current, at t = -dt."""
+    current, at t = -dt, so an engine drives a context from its first level."""
 
     C = (1.0 / 3.0, 1.0)
     A = ((5.0 / 12.0, -1.0 / 12.0), (3.0 / 4.0, 1.0 / 4.0))
