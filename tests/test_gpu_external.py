@@ -162,6 +162,34 @@ def test_external_engine_failure_stops_before_the_step():
     # the run goes on from level 3
     sim.step_weak_external(2, good)
     assert sim.diag(0)["step"] == 4
+    # no steps: nothing happens, the engine is not called
+    sim.step_weak_external(0, lambda *a: 1 / 0)
+    assert sim.diag(0)["step"] == 4
+    # a plain non-zero status through the C ABI, with the message naming it
+    import ctypes as C
+    cb = gs.CIRCUIT_FN(lambda user, gap, level, dt, phi, v: 5)
+    assert gs.lib().gs_step_weak_external(sim._h, 3, cb, None) == gs.GS_ECALLBACK
+    assert b"returned 5" in gs.lib().gs_last_error(sim._h)
+    assert sim.diag(0)["step"] == 4
+    sim.close()
+
+
+def test_external_engine_failure_in_a_later_gap():
+    """Three gaps: the engine fails for gap 2 at level 1; level 0 is complete for
+    every gap and level 1 was not started for any."""
+    gs = _gapsim()
+    cfgs = [W.config1(n_cells=64).replace(see_amp=0.0) for _ in range(3)]
+    sim = gs.GapSim(cfgs, particle_fp=64, capacity=(64, 64))
+
+    def engine(gap, level, dt, phi0_prev):
+        if gap == 2 and level == 1:
+            raise RuntimeError("gap 2 failed")
+        return 100.0 * (gap + 1)
+    with pytest.raises(RuntimeError, match="gap 2 failed"):
+        sim.step_weak_external(3, engine)
+    for g in range(3):
+        d = sim.diag(g)
+        assert d["step"] == 0 and d["phi0"] == pytest.approx(100.0 * (g + 1), rel=1e-12)
     sim.close()
 
 
