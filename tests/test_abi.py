@@ -113,3 +113,12 @@ def test_external_engine_and_dt_check_argument_errors_without_a_device():
     good = gapsim.params_from(W.config1(), 64, (10, 10))
     assert lib.gs_circuit_resonance(C.byref(good), None) == gapsim.GS_EINVAL
     assert lib.gs_circuit_resonance(C.byref(good), C.byref(w)) == gapsim.GS_OK and w.value == 0.0
+
+
+def test_c_program_compiles_and_links_against_the_library(tmp_path):
+    """The boundary is usable from plain C: tests/c/abi_run.c builds with gcc
+    against include/gapsim.h and links libgapsim.so (run on the GPU by
+    tests/test_gpu_c_abi.py)."""
+    import c_abi
+    exe = c_abi.build(str(tmp_path))
+    assert os.path.exists(exe)
