@@ -714,7 +714,7 @@ def run_external(args, copy_gbs):
         for sp, (x, v) in W.load_config2(n=n, seed=2, d=cfg.d).items():
             o.inject(sp, x, v)
         eng = LinearCircuitEngine(cfg)
-        steps = max(4, args.cpu_steps // 2)
+        steps = max(4, args.cpu_steps)
         t0 = time.perf_counter()
         o.step_external(eng, steps)
         elc = time.perf_counter() - t0
@@ -814,9 +814,9 @@ def run_tesla_fine(args, copy_gbs):
                      "note": "at most ~1.3e6 live particles: each step is a few short launches"},
     }
     if not args.no_cpu_baseline:
-        # the oracle from level 0 into the rise of the pulse (about 20 s on one core)
+        # the oracle from level 0 into the rise of the pulse (about 25 s on one core)
         o = oracle.OracleSim(cfg0, fp32=True)
-        n = 250_000
+        n = 245_000
         t0 = time.perf_counter()
         o.step(oracle.STRICT, n)
         elc = time.perf_counter() - t0
