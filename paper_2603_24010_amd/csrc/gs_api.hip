@@ -1,5 +1,7 @@
 // Host side of the C ABI (include/gapsim.h): parameter checks, the constant
-// circuit matrices of each gap, device memory, launch orchestration, readback.
+// circuit matrices of each gap, device memory, launch orchestration, readback,
+// the external circuit engine's step loop, the circuit's resonance (damped
+// roots of the loop equations) and the time-step check, the autotuner.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

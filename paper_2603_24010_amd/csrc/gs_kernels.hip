@@ -4,12 +4,15 @@
 //   k_field   one workgroup per gap: charge accumulator -> rho, prefix scans for
 //             the half-grid field, the circuit/surface-charge update (strict or
 //             weak), the binary32/64 field table the push gathers from.
+//             With an external circuit engine (field mode 2) the engine's gap
+//             voltage comes from, and the potential goes to, pinned host memory.
 //   k_push    persistent workgroups over tiles of every gap's particles: gather,
 //             leapfrog, wall test and the charge deposit, privatised in LDS per
-//             workgroup; at the end of each of its ion segments a workgroup
-//             emits the secondary electrons of the ions it absorbed and injects
-//             its share of the beam.
-// Every few steps k_compact reclaims the slots of absorbed particles.
+//             workgroup; at the start of each of its ion segments a workgroup
+//             injects its share of the beam, at the end it emits the secondary
+//             electrons of the ions it absorbed.
+// Every few steps k_compact reclaims the slots of absorbed particles.  On
+// request k_dt_scan reads one gap's particles for the time-step check.
 //
 // Compiled with -ffp-contract=off: the binary32 particle arithmetic is a fixed
 // sequence of IEEE operations (no fused multiply-adds).
