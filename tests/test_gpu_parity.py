@@ -414,3 +414,29 @@ def test_tesla_scenario_waveform_matches_oracle():
     assert dev < 1e-2
     assert sim.diag(0)["inj_cum"] == orc.diag()["inj_cum"] == int(cfg.beam_schedule.sum())
     sim.close()
+
+
+@pytest.mark.parametrize("mode", [oracle.STRICT, oracle.WEAK])
+def test_fp64_largest_grid_parity(mode):
+    """The largest binary64 grid (8192 cells: the 64-bit accumulator and the
+    binary64 table take 128 KiB of LDS), with a beam and emission."""
+    cfg = W.config2(n_cells=8192, beam_per_step=300, seed=9)
+    loads = W.load_config2(n=60_000, seed=13)
+    opts = {_gapsim().OPT_COMPACT_EVERY: 6}
+    sim, orc, recs = run_pair(cfg, loads, mode, 25, False, (200_000, 200_000), opts=opts)
+    for dg, do in recs:
+        assert dg["step"] == do["step"]
+        assert_counts_equal(dg, do)
+    for key in ("phi0", "qcirc", "qcirc_star", "q_space"):
+        assert _series_rel([d[key] for d, _ in recs], [o[key] for _, o in recs]) <= 1e-12, key
+    # sigma is a sum whose terms can be five orders above it: in weak mode the
+    # circuit's gap charge and the re-imposed C_gap phi0 nearly cancel (here
+    # ~1e-9 against ~1e-14 C/m^2), so rounding is bounded relative to the terms
+    A = cfg.area
+    terms = max(max(abs(o["sigma"]), abs(o["qcirc_star"]) / A, abs(o["qcirc"]) / A) for _, o in recs)
+    dsig = max(abs(d["sigma"] - o["sigma"]) for d, o in recs)
+    assert dsig <= 1e-12 * terms, (dsig, terms)
+    check_fields(sim, orc, 1e-12)
+    d = recs[-1][0]
+    assert d["inj_cum"] == 25 * 300 and d["abs_cum"][1].sum() > 10, d["abs_cum"]
+    sim.close()
