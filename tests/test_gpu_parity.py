@@ -440,3 +440,51 @@ def test_fp64_largest_grid_parity(mode):
     d = recs[-1][0]
     assert d["inj_cum"] == 25 * 300 and d["abs_cum"][1].sum() > 10, d["abs_cum"]
     sim.close()
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_two_cell_gap_parity(fp32):
+    """The smallest grid: two cells, three nodes (both electrode half cells meet
+    in the middle), with particles crossing it every few steps, emission and a
+    beam."""
+    d_gap = 2e-4  # 200 um, so that the hot load reaches both walls within the run
+    cfg = W.config1(n_cells=2).replace(d=d_gap, beam_per_step=3, beam_Emin_eV=100.0, beam_Emax_eV=500.0,
+                                       see_amp=3.0)
+    loads = W.load_config1(n_per_species=500, seed=17, d=d_gap)
+    loads = {s: (x, v * 30.0) for s, (x, v) in loads.items()}
+    sim, orc, recs = run_pair(cfg, loads, oracle.STRICT, 30, fp32, (20_000, 20_000))
+    check_run(recs, 1e-5 if fp32 else 1e-12, cfg.n_mesh)
+    check_fields(sim, orc, 1e-5 if fp32 else 1e-12)
+    d = recs[-1][0]
+    assert d["abs_cum"][0].sum() > 100 and d["abs_cum"][1].sum() > 10 and d["inj_cum"] == 90, d["abs_cum"]
+    sim.close()
+
+
+def test_many_gaps_batched():
+    """3000 gaps of 16 cells in one context (the push's per-workgroup prefix over
+    gaps and its LDS): every gap's counts against its own oracle run, and the
+    voltages within 1e-12 (binary64)."""
+    gs = _gapsim()
+    G = 3000
+    cfgs = [W.config1(n_cells=16).replace(seed=g, beam_per_step=g % 3, beam_Emin_eV=1e3, beam_Emax_eV=5e3)
+            for g in range(G)]
+    rng = np.random.default_rng(3)
+    sim = gs.GapSim(cfgs, particle_fp=64, capacity=(256, 256))
+    orcs = []
+    for g in range(G):
+        n = int(rng.integers(0, 40))
+        x = rng.uniform(0.0, cfgs[g].d, size=n)
+        v = rng.normal(0.0, 3e5, size=n)
+        o = oracle.OracleSim(cfgs[g])
+        if n:
+            sim.inject(g, 1, x, v)
+            o.inject(1, x, v)
+        orcs.append(o)
+    sim.step_strict(8)
+    for g in range(G):
+        orcs[g].step(oracle.STRICT, 8)
+        dg, do = sim.diag(g), orcs[g].diag()
+        assert dg["step"] == do["step"] == 7
+        assert_counts_equal(dg, do)
+        assert abs(dg["phi0"] - do["phi0"]) <= 1e-12 * max(abs(do["phi0"]), 1.0), g
+    sim.close()
