@@ -725,3 +725,111 @@ def test_tesla_pulse_collapse_needs_see():
     up_no = lo + int(np.argmax(V_no[lo:] > -3e3))
     assert up_no - up_see >= 15, (up_see, up_no)
     assert V_see[lo:].max() < 0.8 * V_no[lo:].max()
+
+
+# ---------------------------------------------------------------------------
+# the deposit's in-cell split (App. C: the gather's linear weights), off-node
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("frac", [0.3, 0.75])
+def test_off_node_sheet_split_and_potential(fp32, frac):
+    """A sheet between two nodes: the linear split puts (1 - f) s / dx on the node
+    below it and f s / dx on the node above (App. C), and with that split the
+    discrete potential at the nodes is the continuous two-region solution for a
+    sheet at x0, eq. potential_left_right_2, exactly (the second difference of the
+    kinked line at the two nodes beside the kink is what the split deposits).  In
+    weak mode the circuit does not see the sheet at its own step (Q_circ = 0)."""
+    g = golden()
+    cfg = W.config_paper_validation()
+    dx = cfg.d / cfg.n_cells
+    x0 = g["x0_m"] + frac * dx
+    s = oracle.OracleSim(cfg, fp32=fp32)
+    s.step(oracle.WEAK, int(g["appear_step"]))
+    s.inject(1, np.array([x0]), np.array([0.0]))
+    s.step(oracle.WEAK, 1)
+    d = s.diag()
+    phi, _, rho = s.fields()
+    assert d["qcirc_star"] == 0.0
+    sheet = cfg.weight * cfg.q_unit
+    j = int(round(g["x0_m"] / dx))
+    if fp32:
+        # the position in cells is held in binary32, the weights in units of 2^-24
+        xi = float(np.float32(x0 / dx))
+        f = round((xi - j) * 2**24) / 2**24
+        x_eff = (j + f) * dx
+        tol_rho, tol_phi = 1e-12, 1e-12
+    else:
+        f = x0 / dx - j
+        x_eff = x0
+        tol_rho, tol_phi = 1e-9, 1e-12
+    assert abs(f - frac) < 1e-5
+    want = np.zeros(cfg.n_cells + 1)
+    want[j] = sheet * (1.0 - f) / dx
+    want[j + 1] = sheet * f / dx
+    assert np.abs(rho - want).max() <= tol_rho * sheet / dx
+    L, eps0 = cfg.d, cfg.eps0
+    x = np.arange(cfg.n_cells + 1) * dx
+    ana = np.where(x < x_eff, sheet / eps0 * (L - x_eff), sheet / eps0 * (L - x))
+    assert np.abs(phi - ana).max() <= tol_phi * np.abs(ana).max()
+
+
+# ---------------------------------------------------------------------------
+# emission at the grounded electrode (Alg. 2: electrons leave the struck
+# surface along its normal, into the gap)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("fp32", [False, True])
+def test_see_at_the_grounded_electrode(fp32):
+    """Ions of one energy hitting the grounded electrode (node N): the electrons
+    start on that surface, x = d, move back into the gap (v < 0), and number
+    gamma(E) per impact on average; none appear at the circuit electrode."""
+    cfg = W.config1(n_cells=64).replace(see_amp=0.8, weight=0.0, see_law=W.SEE_EXP, see_E_eV=3.0)
+    E_eV = 20e3
+    v = math.sqrt(2 * E_eV * cfg.ev / cfg.mass[1])
+    n = 20000
+    s = oracle.OracleSim(cfg, fp32=fp32)
+    s.inject(1, np.full(n, cfg.d - 1e-9), np.full(n, v))
+    s.step(oracle.STRICT, 1)
+    d = s.diag()
+    assert d["abs_step"][1][1] == n and d["abs_step"][1][0] == 0
+    assert d["emit_step"][0] == 0
+    gamma = 0.8 * (E_eV / 1e3) / (1 + E_eV / 1e3)
+    mean = d["emit_step"][1] / n
+    assert abs(mean - gamma) < 5 * math.sqrt(gamma / n)
+    xe, ve, _ = s.particles(0)
+    assert xe.size == d["emit_step"][1]
+    assert np.all(xe == cfg.d) and np.all(ve < 0)
+    e = 0.5 * cfg.mass[0] * ve**2 / cfg.ev
+    assert abs(e.mean() - 3.0) < 5 * 3.0 / math.sqrt(e.size)
+
+
+# ---------------------------------------------------------------------------
+# the beam's energy and depth laws: E ~ U(Emin, Emax); depth ~ U(0, layer), or
+# U(0, v dt) (one step's flight) without a layer
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("side,layer", [("circuit", 0.0), ("circuit", 2e-4), ("ground", 0.0), ("ground", 1e-3)])
+def test_beam_energy_and_depth_laws(side, layer):
+    """One step's beam of 20000 ions: a KS test of the entry energies against the
+    uniform law on [Emin, Emax], and of the depths below the entry electrode
+    against the uniform law on [0, layer] (or, per ion, [0, v dt])."""
+    from scipy import stats
+    cfg = W.config2(n_cells=64, beam_per_step=20000).replace(see_amp=0.0, weight=0.0, beam_layer=layer,
+                                                             beam_side=W.BEAM_GROUND if side == "ground"
+                                                             else W.BEAM_CIRCUIT)
+    s = oracle.OracleSim(cfg)
+    s.step(oracle.WEAK, 1)
+    x, v, _ = s.particles(1)
+    assert x.size == 20000
+    E = 0.5 * cfg.mass[1] * v**2 / cfg.ev
+    lo, hi = cfg.beam_Emin_eV, cfg.beam_Emax_eV
+    assert np.all(E >= lo * (1 - 1e-12)) and np.all(E <= hi * (1 + 1e-12))
+    assert stats.kstest(E, stats.uniform(loc=lo, scale=hi - lo).cdf).pvalue > 0.01
+    if side == "ground":
+        assert np.all(v < 0)
+        depth = cfg.d - x
+    else:
+        assert np.all(v > 0)
+        depth = x
+    scale = layer if layer > 0 else np.abs(v) * cfg.dt
+    r = depth / scale
+    assert np.all(r > 0) and np.all(r < 1)
+    assert stats.kstest(r, stats.uniform().cdf).pvalue > 0.01
