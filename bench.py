@@ -1,10 +1,14 @@
 """Throughput of the circuit-coupled ES-PIC step on one MI355X.
 
-Default workload: the weak-coupling beam gap (4096 cells, 2e7 H+ macroparticles in
-binary32, 2e4 beam ions per step, coupled-LC circuit, SEE with exponential 3 eV
-electrons), inputs resident in HBM before the timed region.  One step = circuit +
-field solve, gather/push/walls/SEE/beam/deposit, and the periodic slot
-compaction, for every particle.
+Default workload: the largest single-gap configuration, strict coupling on a
+16384-cell gap holding 2e8 H+ macroparticles in binary32 (a Gaussian load at
+0.9 d), 2e4 beam ions per step, coupled-LC circuit, SEE with exponential 3 eV
+electrons; inputs resident in HBM before the timed region.  One step = circuit
++ field solve, gather/push/walls/SEE/beam/deposit for every particle, and the
+periodic slot compaction (or cell sort): the timed window always ends with one,
+so at least its amortised share is inside the measurement.  The launch shape
+and the compaction interval come from the library's autotuner, run before the
+timed region.
 
 Prints one JSON line: particle-steps/s, the push kernel against the HBM
 roofline (HIP events on the library's stream over the timed region), and the
@@ -33,7 +37,11 @@ BYTES_PER_PUSH_F32 = 16  # read x, v and write x, v (binary32)
 # HBM traffic of the push kernel, taken with rocprofv3 FETCH_SIZE / WRITE_SIZE
 # runs of this script; it is reported only while the sources it was measured
 # on are unchanged and the run is the one that was measured.
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_push_traffic_beam_gap_4096c_2e7p_weak.json")
+def traffic_record_path(workload):
+    return os.path.join(ROOT, "profiles", f"k_push_traffic_{workload}.json")
+
+
+DEFAULT_WORKLOAD = "beam_gap_16384c_2e8p_strict"
 KERNEL_SOURCES = ["paper_2603_24010_amd/csrc/gs_kernels.hip", "paper_2603_24010_amd/csrc/gs_api.hip",
                   "paper_2603_24010_amd/csrc/gs_internal.h"]
 
@@ -99,18 +107,35 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic(workload, steps, warmup, compact_every, tuned):
-    """Bytes per push launch from the committed counter record, or None."""
+def run_key(workload, steps, warmup, launch):
+    return {"workload": workload, "steps": steps, "warmup": warmup, "launch": launch}
+
+
+def recorded_traffic(key):
+    """Bytes per push launch from the committed counter record of this exact run
+    (workload, steps, warmup and launch shape) on the current kernel sources, or None."""
     try:
-        with open(TRAFFIC_RECORD) as f:
+        with open(traffic_record_path(key["workload"])) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    run = rec.get("run", {})
-    if (rec.get("source_sha256") != kernel_source_hash() or tuned
-            or run != {"workload": workload, "steps": steps, "warmup": warmup, "compact_every": compact_every}):
+    if rec.get("source_sha256") != kernel_source_hash() or rec.get("run") != key:
         return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def host_cpu():
+    """Model name of the host CPU and the threads the process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
 
 
 def _counter_rows(path, counter):
@@ -419,7 +444,7 @@ def run_fp64(args, copy_gbs):
         s.step(oracle.STRICT, args.steps)
         elc = time.perf_counter() - t0
         pc = s.diag()["pushed_cum"]
-        out["cpu_baseline"] = {"value": pc / elc, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+        out["cpu_baseline"] = {"value": pc / elc, "unit": "particle-steps/s", "cores": 1, "cpu_model": host_cpu()[0], "kind": "oracle",
                                "sample": f"the whole run: {args.steps} strict steps, binary64, {pc} particle-steps "
                                          f"in {elc:.1f} s"}
     print(json.dumps(out), flush=True)
@@ -622,7 +647,7 @@ def run_tesla(args, copy_gbs):
                 o.step(mode, steps)
             elc += time.perf_counter() - t0
             pc += o.diag()["pushed_cum"]
-        out["cpu_baseline"] = {"value": pc / elc, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+        out["cpu_baseline"] = {"value": pc / elc, "unit": "particle-steps/s", "cores": 1, "cpu_model": host_cpu()[0], "kind": "oracle",
                                "sample": f"the same {len(cases)} runs, {steps} steps each, binary32 oracle mode, "
                                          f"{pc} particle-steps in {elc:.1f} s"}
     print(json.dumps(out), flush=True)
@@ -719,7 +744,7 @@ def run_external(args, copy_gbs):
         o.step_external(eng, steps)
         elc = time.perf_counter() - t0
         pc = o.diag()["pushed_cum"]
-        out["cpu_baseline"] = {"value": pc / elc, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+        out["cpu_baseline"] = {"value": pc / elc, "unit": "particle-steps/s", "cores": 1, "cpu_model": host_cpu()[0], "kind": "oracle",
                                "sample": f"{n} initial H+ of the same workload, {steps} external-engine steps, "
                                          f"binary32 oracle mode, {pc} particle-steps in {elc:.1f} s"}
     print(json.dumps(out), flush=True)
@@ -821,7 +846,7 @@ def run_tesla_fine(args, copy_gbs):
         o.step(oracle.STRICT, n)
         elc = time.perf_counter() - t0
         pc = o.diag()["pushed_cum"]
-        out["cpu_baseline"] = {"value": pc / elc, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+        out["cpu_baseline"] = {"value": pc / elc, "unit": "particle-steps/s", "cores": 1, "cpu_model": host_cpu()[0], "kind": "oracle",
                                "sample": f"strict with SEE, levels 0..{n - 1} (the pulse's rise), binary32 "
                                          f"oracle mode, {pc} particle-steps in {elc:.1f} s"}
     print(json.dumps(out), flush=True)
@@ -841,7 +866,7 @@ def cpu_baseline_batched(spec, steps):
         s.step(oracle.STRICT, steps)
         el += time.perf_counter() - t0
         pushed += s.diag()["pushed_cum"]
-    return {"value": pushed / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+    return {"value": pushed / el, "unit": "particle-steps/s", "cores": 1, "cpu_model": host_cpu()[0], "kind": "oracle",
             "sample": f"the first {gaps} gaps of the ensemble, {steps} strict steps each, binary32 oracle mode, "
                       f"{pushed} particle-steps in {el:.1f} s"}
 
@@ -863,7 +888,7 @@ def cpu_baseline(spec, steps: int):
     s.step(spec["mode"], steps)
     el = time.perf_counter() - t0
     d = s.diag()
-    return {"value": d["pushed_cum"] / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+    return {"value": d["pushed_cum"] / el, "unit": "particle-steps/s", "cores": 1, "cpu_model": host_cpu()[0], "kind": "oracle",
             "sample": f"{n} initial H+ of the same workload, {steps} steps, binary32 oracle mode, "
                       f"{d['pushed_cum']} particle-steps in {el:.1f} s"}
 
@@ -873,20 +898,27 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="beam_gap_4096c_2e7p_weak",
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
                     choices=sorted(WORKLOADS) + sorted(BATCHED) + [MLP_WORKLOAD, DIVERGENCE, FP64_WORKLOAD,
                                                                    TESLA_WORKLOAD, EXTERNAL_WORKLOAD,
                                                                    TESLA_FINE_WORKLOAD])
     ap.add_argument("--div-particles", type=int, default=200_000_000)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--compact-every", type=int, default=32)
+    ap.add_argument("--compact-every", type=int, default=0,
+                    help="steps between compactions (or cell sorts); 0: the autotuner's choice (32 without it)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="single-gap workloads: keep the default launch shape instead of the autotuner's")
+    ap.add_argument("--tuning-cache", default=os.path.join(ROOT, "paper_2603_24010_amd", "tuning_cache.txt"),
+                    help="the autotuner's cache of choices per workload shape and device ('' for none)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--deposit", type=int, default=0, help="0 auto, 1 64-bit LDS cells, 2 32-bit")
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--ppt", type=int, default=0, help="16-byte particle vectors per thread (1, 2)")
+    ap.add_argument("--sort-bin", type=int, default=-1,
+                    help="cells per bin of the periodic cell sort (0: plain compaction; -1: the autotuner's or 0)")
     ap.add_argument("--mlp-gaps", type=int, default=512)
     ap.add_argument("--mlp-train-steps", type=int, default=2000)
     ap.add_argument("--mlp-eval-steps", type=int, default=500)
@@ -894,17 +926,20 @@ def main():
     ap.add_argument("--copy-reference-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times): the "
                          "reference that scales rocprof's FETCH_SIZE / WRITE_SIZE to bytes")
-    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
-                    help="no GPU work: reduce rocprofv3 counter CSVs of a bench run (same --steps) and of a "
-                         "--copy-reference-mb 1024 run to the push kernel's bytes per launch, and write the record "
-                         "that later bench runs report as roofline.traffic")
+    ap.add_argument("--pmc-summary", nargs=5,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "BENCH_JSON"),
+                    help="no GPU work: reduce rocprofv3 counter CSVs of a bench run (its JSON line in BENCH_JSON) "
+                         "and of a --copy-reference-mb 1024 run to the push kernel's bytes per launch, and write "
+                         "the record that later runs of the same command report as roofline.traffic")
     args = ap.parse_args()
     if args.pmc_summary:
-        rec = pmc_summary(*args.pmc_summary, copy_mb=1024, kernel="k_push", last_n=args.steps)
+        with open(args.pmc_summary[4]) as f:
+            run = json.loads([ln for ln in f if ln.startswith("{")][-1])
+        rec = pmc_summary(*args.pmc_summary[:4], copy_mb=1024, kernel="k_push", last_n=run["roofline"]["launches"])
         rec["source_sha256"] = kernel_source_hash()
-        rec["run"] = {"workload": args.workload, "steps": args.steps, "warmup": args.warmup,
-                      "compact_every": args.compact_every}
-        with open(TRAFFIC_RECORD, "w") as f:
+        rec["run"] = run["roofline"]["run_key"]
+        rec["algorithmic_bytes_per_launch"] = run["roofline"]["algorithmic_bytes_per_launch"]
+        with open(traffic_record_path(rec["run"]["workload"]), "w") as f:
             json.dump(rec, f, indent=1)
         print(json.dumps(rec))
         return
@@ -953,8 +988,10 @@ def main():
         return run_tesla_fine(args, copy_gbs)
     spec = WORKLOADS[args.workload]
     log(f"[bench] building workload {args.workload}")
-    sim, cfg, _ = make_sim(args.workload, spec, args.warmup + args.steps)
-    sim.set_option(gapsim.OPT_COMPACT_EVERY, args.compact_every)
+    sim, cfg, _ = make_sim(args.workload, spec, args.warmup + args.steps + 128)
+    manual = bool(args.block or args.tile or args.grid or args.deposit or args.ppt or args.sort_bin >= 0)
+    if args.sort_bin >= 0:
+        sim.set_option(gapsim.OPT_SORT_BIN, args.sort_bin)
     if args.block:
         sim.set_option(gapsim.OPT_BLOCK, args.block)
     if args.tile:
@@ -965,10 +1002,32 @@ def main():
         sim.set_option(gapsim.OPT_DEPOSIT, args.deposit)
     if args.ppt:
         sim.set_option(gapsim.OPT_PPT, args.ppt)
-    tuned = bool(args.block or args.tile or args.grid or args.deposit or args.ppt or args.graph)
     mode = spec["mode"]
+    tuning = None
+    if not (manual or args.no_autotune):
+        # the autotuner times candidate launch shapes and compaction intervals on
+        # this state (which it restores); a cached choice for this shape is reused
+        log("[bench] autotuning")
+        tuning = sim.autotune(mode, gapsim.GUESS_DIRECT, trial_steps=8, cache_path=args.tuning_cache or None)
+        log(f"[bench] tuning: {tuning}")
+    if args.compact_every:
+        sim.set_option(gapsim.OPT_COMPACT_EVERY, args.compact_every)
+    elif tuning is None:
+        sim.set_option(gapsim.OPT_COMPACT_EVERY, 32)
+    interval = args.compact_every or (tuning["compact_every"] if tuning else 32)
+    launch = sim.launch()
     log(f"[bench] warmup {args.warmup} steps")
     sim.step(mode, args.warmup)
+    # the timed window ends with a compaction: at least its amortised share is
+    # inside the measurement (one per window when the window is shorter than the
+    # interval)
+    # (and at least one before it, so that the timed steps see the particle order
+    # the chosen compaction or sort keeps)
+    align = (-(args.warmup + args.steps)) % interval
+    if args.warmup + align < interval:
+        align += interval
+    if align:
+        sim.step(mode, align)
     d0 = sim.diag(0)
     if args.graph:
         sim.set_option(gapsim.OPT_GRAPH, 1)
@@ -993,7 +1052,8 @@ def main():
     value = pushed / el
     push_s = tm["push_ms"] * 1e-3
     achieved = BYTES_PER_PUSH_F32 * pushed / push_s / 1e9 if push_s > 0 else None
-    traffic = recorded_traffic(args.workload, args.steps, args.warmup, args.compact_every, tuned)
+    key = run_key(args.workload, args.steps, args.warmup, launch)
+    traffic = None if args.graph else recorded_traffic(key)
     out = {
         "metric": "particle-steps/s",
         "value": value,
@@ -1014,7 +1074,10 @@ def main():
                    "see": ("paper laws: fifth-order yield (stand-in coefficients), lognormal energies "
                            "(mu ln 8 eV, sigma 0.7)") if spec.get("see") == "paper"
                    else "saturating yield 0.5 E/(E + 1 keV), Exp(3 eV)",
-                   "emitted_in_timed_steps": int((d1["emit_cum"] - d0["emit_cum"]).sum())},
+                   "emitted_in_timed_steps": int((d1["emit_cum"] - d0["emit_cum"]).sum()),
+                   "launch": launch, "autotuned": tuning is not None,
+                   "untimed_steps_before": args.warmup + align,
+                   "compactions_in_timed_steps": tm["compact_launches"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
@@ -1022,10 +1085,10 @@ def main():
                      "algorithmic_bytes_per_launch": BYTES_PER_PUSH_F32 * pushed / max(1, tm["push_launches"]),
                      "avg_launch_ms": tm["push_ms"] / max(1, tm["push_launches"]),
                      "copy_GBps": copy_gbs,
-                     "launches": tm["push_launches"]},
+                     "launches": tm["push_launches"], "run_key": key},
         "timed_with": "hip graphs" if args.graph else "eager launches, HIP events recorded by each kernel's dispatch",
         "kernel_ms_per_step": {"push": tm["push_ms"] / args.steps, "field": tm["field_ms"] / args.steps,
-                               "compact": tm["compact_ms"] / args.steps},
+                               "compact": tm["compact_ms"] / args.steps, "emit": tm["emit_ms"] / args.steps},
         "time_step_check": _finite({k: (v.tolist() if hasattr(v, "tolist") else v) for k, v in dtc.items()}),
     }
     sim.close()

@@ -21,7 +21,7 @@
  *
  * Conventions of every entry point:
  *   - Return a gs_status; nothing throws or aborts across this boundary.
- *   - Work is queued on the HIP stream given to gs_init and is asynchronous,
+ *   - Work is queued on the HIP stream given to gs_init_gap and is asynchronous,
  *     except gs_read_diagnostics / gs_read_particles / gs_get_timing, which
  *     synchronise that stream.
  *   - The library owns all device state; caller buffers are read or written
@@ -100,7 +100,7 @@ typedef struct {
  *   (Sec. 4.2); a pulse is given as a schedule: with beam_schedule non-NULL the
  *   step that solves level n injects beam_schedule[n] ions (n <
  *   beam_schedule_len, none after), else beam_per_step every step.  The
- *   schedule is copied by gs_init; the caller keeps its array.
+ *   schedule is copied by gs_init_gap; the caller keeps its array.
  *   particle_fp: 32 (binary32 particles, 2^-24 fixed-point deposit weights) or
  *   64 (binary64 particles, 2^-44 weights); the same for every gap of a context.
  *   capacity[s]: particle slots of species s (live plus not-yet-reclaimed). */
@@ -137,7 +137,15 @@ typedef struct {
   double v_ref; /* voltage scale of the Newton residual norm (> 0) */
 } gs_gap_params;
 
-/* State of one gap after the last completed step (level n = step). */
+/* State of one gap after the last completed step (level n = step).  The
+ * quantities are the coupling variables of the paper's variables table
+ * (tab:variables, Sec. 2.4): the electrode potential phi0 = V_gap, the surface
+ * charge sigma_+ of the circuit electrode, the circuit charge on the gap Q_circ
+ * (weak mode: Q_circ* before the reset), the convection charge Q_conv that the
+ * push delivered, and the loop charges and currents; the counts are the
+ * electrode impact statistics of Sec. 2.3 and Sec. 4.2 (absorbed, emitted,
+ * injected), and the Newton fields describe the strict step's Newton form (not
+ * in the paper). */
 typedef struct {
   int64_t step;           /* level of the last field solve (-1 before the first step) */
   double t;               /* step * dt */
@@ -182,6 +190,9 @@ typedef struct {
 typedef struct {
   double push_ms, field_ms, compact_ms;
   int64_t push_launches, field_launches, compact_launches;
+  double emit_ms;          /* the emission kernel that runs after each push while the
+                              cell sort is on */
+  int64_t emit_launches;
 } gs_timing;
 
 /* Options for gs_set_option. */
@@ -197,7 +208,13 @@ enum {
   GS_OPT_NEWTON_MAXIT = 8, /* Newton corrections allowed per level, 0..64 (default 8) */
   GS_OPT_DEPOSIT = 9,      /* binary32 deposit cells: 0 auto, 1 64-bit, 2 32-bit with carries */
   GS_OPT_COMPACT_GRID = 10,/* workgroups of the compaction kernel (>= 1) */
-  GS_OPT_PPT = 11          /* 16-byte particle vectors per thread per chunk: 1 (default) or 2 */
+  GS_OPT_PPT = 11,         /* 16-byte particle vectors per thread per chunk: 1 (default) or 2 */
+  GS_OPT_SORT_BIN = 12     /* 0 (default): every GS_OPT_COMPACT_EVERY steps absorbed slots are
+                              reclaimed in place of order; >= 4: instead the live particles
+                              are counting-sorted by bins of this many cells, so that each
+                              push workgroup deposits onto, and flushes, a narrow band of
+                              nodes; the secondary emission of a push then runs in its own
+                              kernel right after it.  Results do not depend on it. */
 };
 
 typedef struct gs_ctx gs_ctx;
@@ -208,7 +225,7 @@ typedef struct gs_ctx gs_ctx;
  * of the gap-mesh charge; the first step solves level 0.  alloc may be NULL.
  * hip_stream is a hipStream_t (NULL = the default stream).  Errors: GS_EINVAL
  * (message from gs_last_error(NULL)), GS_ENOMEM, GS_EDEVICE; *out is NULL then. */
-gs_status gs_init(gs_ctx **out, int32_t n_gaps, const gs_gap_params *params,
+gs_status gs_init_gap(gs_ctx **out, int32_t n_gaps, const gs_gap_params *params,
                   const gs_allocator *alloc, void *hip_stream);
 
 /* Destroy a context and free its device memory (NULL is ignored). */
@@ -316,7 +333,8 @@ typedef struct {
 } gs_dt_report;
 gs_status gs_dt_check(gs_ctx *ctx, int32_t gap, gs_dt_report *out);
 
-/* Read one gap's state (synchronises the stream).  phi (n_cells + 1 values),
+/* Read one gap's state (synchronises the stream): the coupling variables of
+ * tab:variables and the impact counts (gs_diag).  phi (n_cells + 1 values),
  * E (n_cells half-grid values E_{k+1/2}) and rho (n_cells + 1 nodal densities,
  * electrode nodes already doubled) of the last solved level are written to the
  * caller's host arrays when not NULL.  Errors: GS_EINVAL, GS_EDEVICE; the sticky
@@ -402,19 +420,27 @@ gs_status gs_mlp_train(const float *x, const float *t, int64_t n, const int32_t 
                        double beta1, double beta2, double eps, float *loss, float *grad_last, void *work,
                        size_t work_bytes, void *hip_stream);
 
-/* A launch configuration chosen by gs_autotune. */
+/* A launch configuration chosen by gs_autotune (or in effect, gs_get_launch). */
 typedef struct {
   int32_t block;          /* push threads per workgroup */
   int32_t tile;           /* particles per work tile */
   int32_t grid;           /* push workgroups */
   int32_t ppt;            /* 16-byte particle vectors per thread per chunk (1 or 2) */
   int32_t deposit;        /* GS_OPT_DEPOSIT value */
-  int32_t compact_every;  /* steps between compactions */
-  double ms_per_step;     /* measured time per step of the chosen configuration */
+  int32_t compact_every;  /* steps between compactions (or cell sorts) */
+  int32_t sort_bin;       /* GS_OPT_SORT_BIN value (0: compaction without sorting) */
+  int32_t pad;
+  double ms_per_step;     /* measured time per step of the chosen configuration
+                             (gs_get_launch: 0) */
 } gs_tuning;
 
-/* Choose the push launch shape (block, vectors per thread, tile, grid) and then
- * the compaction interval for this context's gaps by timing candidates on its
+/* The launch configuration in effect (push shape, deposit cells, compaction
+ * interval, cell-sort bin), as gs_autotune reports its choice.  Host only. */
+gs_status gs_get_launch(const gs_ctx *ctx, gs_tuning *out);
+
+/* Choose the push launch shape (block, vectors per thread, tile, grid), then
+ * the compaction interval and whether to cell-sort (and by which bin) instead
+ * of compacting, for this context's gaps by timing candidates on its
  * own current state: every device buffer and host counter is saved first and
  * put back afterwards, so the state after the call is the state before it.
  * mode 0 strict (with guess) or 1 weak; trial_steps timed steps per shape
@@ -440,7 +466,7 @@ gs_status gs_get_timing(gs_ctx *ctx, gs_timing *out, int32_t reset);
 gs_status gs_validate_params(const gs_gap_params *p, char *msg, size_t cap);
 
 /* Message of the last failed call on ctx ("" if none); with ctx NULL the last
- * failed gs_init. */
+ * failed gs_init_gap. */
 const char *gs_last_error(const gs_ctx *ctx);
 
 /* Library version string. */

@@ -116,6 +116,7 @@ def lib():
         L.or_push32.argtypes = [C.c_int32, C.POINTER(C.c_float), C.c_float, C.c_float, C.c_float,
                                 C.POINTER(C.c_float), C.POINTER(C.c_float)]
         L.or_push32.restype = C.c_int32
+        L.or_deposit32.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_int64)]
         L.or_alpha32.argtypes = [C.c_void_p, C.c_int32]
         L.or_alpha32.restype = C.c_float
         L.or_beam_ion32.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)]
@@ -221,6 +222,18 @@ def push32(ehat, alpha: float, xi: float, u: float):
     w = lib().or_push32(ehat.size - 2, ehat.ctypes.data_as(C.POINTER(C.c_float)), float(alpha), float(xi),
                         float(u), C.byref(xo), C.byref(uo))
     return np.float32(xo.value), np.float32(uo.value), int(w)
+
+
+def deposit32(n_cells: int, Z: int, xi, acc=None) -> np.ndarray:
+    """The binary32 deposit of positions xi (cells) with charge number Z, added to
+    the int64 node accumulator acc (units of 2^-24 of a macroparticle); returns it."""
+    xi = np.ascontiguousarray(xi, dtype=np.float32)
+    if acc is None:
+        acc = np.zeros(n_cells + 1, dtype=np.int64)
+    assert acc.dtype == np.int64 and acc.size == n_cells + 1 and acc.flags["C_CONTIGUOUS"]
+    lib().or_deposit32(n_cells, Z, xi.ctypes.data_as(C.POINTER(C.c_float)), xi.size,
+                       acc.ctypes.data_as(C.POINTER(C.c_int64)))
+    return acc
 
 
 def circuit_run(cfg, nsteps: int):

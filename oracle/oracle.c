@@ -270,6 +270,23 @@ static double sheet_of(const or_sim *s, int sp) {
   return s->p.weight * s->p.q_unit * (double)s->p.Z[sp];
 }
 
+/* binary32 positions in cells: weights rounded to multiples of 2^-24 of a
+ * macroparticle, so that the two node shares of one particle add up to exactly
+ * one macroparticle; Z times them added to acc[0..N] */
+void or_deposit32(int32_t N, int32_t Z, const float *xi, int64_t n, int64_t *acc) {
+  for (int64_t k = 0; k < n; ++k) {
+    float x = xi[k];
+    int j = (int)x;
+    if (j > N - 1) j = N - 1;
+    float f = x - (float)j;
+    float w1f = f * 16777216.0f;
+    int64_t w1 = (int64_t)rintf(w1f);
+    int64_t w0 = 16777216 - w1;
+    acc[j] += (int64_t)Z * w0;
+    acc[j + 1] += (int64_t)Z * w1;
+  }
+}
+
 static void deposit(or_sim *s) {
   const int N = s->N;
   const double dx = s->dx;
@@ -285,21 +302,8 @@ static void deposit(or_sim *s) {
       s->rho[j + 1] += q * f / dx;
     }
   } else {
-    /* weights rounded to multiples of 2^-24 of a macroparticle; the two node
-     * shares of one particle add up to exactly one macroparticle */
     int64_t *acc = (int64_t *)calloc((size_t)N + 1, sizeof(int64_t));
-    for (int64_t k = 0; k < s->n; ++k) {
-      float xi = s->xf[k];
-      int j = (int)xi;
-      if (j > N - 1) j = N - 1;
-      float f = xi - (float)j;
-      float w1f = f * 16777216.0f;
-      int64_t w1 = (int64_t)rintf(w1f);
-      int64_t w0 = 16777216 - w1;
-      int64_t Z = s->p.Z[s->sp[k]];
-      acc[j] += Z * w0;
-      acc[j + 1] += Z * w1;
-    }
+    for (int64_t k = 0; k < s->n; ++k) or_deposit32(N, s->p.Z[s->sp[k]], &s->xf[k], 1, acc);
     const double s0 = s->p.weight * s->p.q_unit;
     for (int i = 0; i <= N; ++i) s->rho[i] = s0 * ((double)acc[i] / QSCALE24) / dx;
     free(acc);

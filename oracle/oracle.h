@@ -150,6 +150,10 @@ double or_gather64(int32_t n_cells, double dx, const double *E, double e0_surf, 
                    double x);
 /* the same in binary32, grid units: ehat[0] = surface field at node 0,
  * ehat[k] = E_{k-1/2} (k = 1..N), ehat[N+1] = field at node N */
+/* Binary32 deposit (App. C weights, in units of 2^-24 of a macroparticle):
+ * adds Z times the two node shares of each of the n positions xi (cells) to
+ * acc[0..n_cells]; the step's own deposit calls it. */
+void or_deposit32(int32_t n_cells, int32_t Z, const float *xi, int64_t n, int64_t *acc);
 float or_gather32(int32_t n_cells, const float *ehat, float xi);
 /* one binary32 push in grid units with that gather and charge-to-mass factor
  * alpha = Z q dt^2 / (m dx): writes the new position and velocity; returns 0

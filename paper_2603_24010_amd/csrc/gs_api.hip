@@ -36,6 +36,7 @@ struct gs_ctx {
   LaunchCfg lc{};
   int compact_every = 32;
   int since_compact = 0;
+  int emits = 0;  // some gap has secondary emission
   int use_graph = 0;
   int timing = 0;
   double newton_tol = 1e-10;
@@ -351,7 +352,7 @@ static void choose_launch(gs_ctx *ctx);
 static gs_status setup(gs_ctx *ctx) {
   const int G = ctx->G;
   ctx->hc.resize(G);
-  size_t slots = 0, nodes = 0, etab = 0, events = 0, nsched = 0;
+  size_t slots = 0, nodes = 0, etab = 0, events = 0, nsched = 0, bins = 0;
   ctx->nmax = 0;
   for (int g = 0; g < G; ++g) {
     gs_status st = build_const(ctx, g, ctx->params[g], ctx->hc[g]);
@@ -377,6 +378,11 @@ static gs_status setup(gs_ctx *ctx) {
     c.sched_base = (int64_t)nsched;
     c.sched_len = (int64_t)ctx->sched[g].size();
     nsched += ctx->sched[g].size();
+    // cell-sort bin counters: room for the finest bin the option allows
+    const size_t nbin = ((size_t)c.N + SORT_BIN_MIN - 1) / SORT_BIN_MIN;
+    c.hbase[0] = (int64_t)bins;
+    c.hbase[1] = (int64_t)(bins + nbin);
+    bins += 2 * nbin;
     ctx->nmax = std::max(ctx->nmax, c.N);
   }
   const size_t ps = ctx->fp64 ? 8 : 4;
@@ -402,6 +408,9 @@ static gs_status setup(gs_ctx *ctx) {
   ALLOC(d.ehat, void *, etab * ps);
   ALLOC(d.ev, Event *, events * sizeof(Event));
   ALLOC(d.ev_count, unsigned long long *, (size_t)G * 8);
+  ALLOC(d.ev_done, unsigned long long *, (size_t)G * 8);
+  ALLOC(d.hist, unsigned long long *, bins * 8);
+  ALLOC(d.bcur, unsigned long long *, bins * 8);
   int64_t *sched_d = nullptr;
   ALLOC(sched_d, int64_t *, std::max<size_t>(nsched, 1) * 8);
   d.sched = sched_d;
@@ -428,6 +437,7 @@ static gs_status setup(gs_ctx *ctx) {
     HIPCHK(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     d.ovf_wgs = emits ? (int64_t)8 * std::max(ncu, 1) : 0;
   }
+  ctx->emits = emits ? 1 : 0;
   ALLOC(d.ovf, Event *, (size_t)std::max<int64_t>(d.ovf_wgs, 1) * OVQ * sizeof(Event));
   ALLOC(d.epoch, int64_t *, 8);
   ALLOC(d.err, unsigned int *, 8);
@@ -447,6 +457,9 @@ static gs_status setup(gs_ctx *ctx) {
   HIPCHK(ctx, hipMemsetAsync(d.cursor, 0, (size_t)G * 2 * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.tally, 0, (size_t)G * T_N * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.ev_count, 0, (size_t)G * 8, s));
+  HIPCHK(ctx, hipMemsetAsync(d.ev_done, 0, (size_t)G * 8, s));
+  HIPCHK(ctx, hipMemsetAsync(d.hist, 0, bins * 8, s));
+  HIPCHK(ctx, hipMemsetAsync(d.bcur, 0, bins * 8, s));
   for (int g = 0; g < G; ++g)
     if (!ctx->sched[g].empty())
       HIPCHK(ctx, hipMemcpyAsync(sched_d + ctx->hc[g].sched_base, ctx->sched[g].data(), ctx->sched[g].size() * 8,
@@ -469,6 +482,7 @@ static gs_status setup(gs_ctx *ctx) {
   ctx->lc.wide = 1;
   ctx->lc.compact_grid = 4 * ctx->ncu;
   ctx->lc.ppt = ctx->fp64 ? 2 : 4;
+  ctx->lc.sort_bin = 0;
   choose_launch(ctx);
   return GS_OK;
 }
@@ -498,7 +512,7 @@ static bool launch_fits(const gs_ctx *ctx) {
   return push_lds_total(ctx, ctx->lc.wide, ctx->lc.block) <= 163840;
 }
 
-extern "C" gs_status gs_init(gs_ctx **out, int32_t n_gaps, const gs_gap_params *params,
+extern "C" gs_status gs_init_gap(gs_ctx **out, int32_t n_gaps, const gs_gap_params *params,
                              const gs_allocator *alloc, void *hip_stream) {
   if (!out) return fail(nullptr, GS_EINVAL, "out is NULL");
   *out = nullptr;
@@ -656,6 +670,27 @@ static int64_t beam_at(const gs_ctx *ctx, int g, int64_t n) {
   return n >= 0 && n < (int64_t)s.size() ? s[(size_t)n] : 0;
 }
 
+// The push, and with the cell sort on the emission kernel after it: sorted
+// particles put a wall's impacts into few workgroups, so the push queues
+// nothing past its LDS queue (no per-workgroup overflow regions) and the gap
+// lists are emitted by many workgroups.
+static hipError_t launch_push_emit(gs_ctx *ctx, hipStream_t s, bool timing) {
+  DevPtrs dp = ctx->dp;
+  const bool sep = ctx->lc.sort_bin > 0 && ctx->emits;
+  if (sep) dp.ovf_wgs = 0;
+  auto push = [&](KTime t) { return launch_push(dp, ctx->G, ctx->lc, s, t); };
+  hipError_t e = timing ? timed(ctx, 0, push) : push(KTime{});
+  if (e != hipSuccess || !sep) return e;
+  auto emit = [&](KTime t) { return launch_emit(ctx->dp, ctx->G, ctx->fp64, std::max(ctx->ncu, 1), s, t); };
+  return timing ? timed(ctx, 3, emit) : emit(KTime{});
+}
+
+// the compaction, or the cell sort in its place
+static hipError_t launch_reclaim(gs_ctx *ctx, hipStream_t s, KTime t) {
+  return ctx->lc.sort_bin > 0 ? launch_sort(ctx->dp, ctx->G, ctx->lc, s, t)
+                              : launch_compact(ctx->dp, ctx->G, ctx->lc, s, t);
+}
+
 // after_field: an event to record between the field solve and the push
 static gs_status one_step(gs_ctx *ctx, int mode, int guess, hipEvent_t after_field = nullptr) {
   hipError_t e = timed(ctx, 1, [&](KTime t) {
@@ -665,11 +700,11 @@ static gs_status one_step(gs_ctx *ctx, int mode, int guess, hipEvent_t after_fie
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "field launch: %s", hipGetErrorString(e));
   if (after_field && (e = hipEventRecord(after_field, ctx->stream)) != hipSuccess)
     return fail(ctx, GS_EDEVICE, "event record: %s", hipGetErrorString(e));
-  e = timed(ctx, 0, [&](KTime t) { return launch_push(ctx->dp, ctx->G, ctx->lc, ctx->stream, t); });
+  e = launch_push_emit(ctx, ctx->stream, true);
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "push launch: %s", hipGetErrorString(e));
   ctx->since_compact += 1;
   if (ctx->since_compact >= ctx->compact_every) {
-    e = timed(ctx, 2, [&](KTime t) { return launch_compact(ctx->dp, ctx->G, ctx->lc, ctx->stream, t); });
+    e = timed(ctx, 2, [&](KTime t) { return launch_reclaim(ctx, ctx->stream, t); });
     if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "compact launch: %s", hipGetErrorString(e));
     ctx->since_compact = 0;
     ctx->epoch += 1;
@@ -707,9 +742,9 @@ static gs_status run_steps(gs_ctx *ctx, int n_steps, int mode, int guess) {
         for (int k = 0; k < L && e1 == hipSuccess && e2 == hipSuccess; ++k) {
           e1 = launch_field(ctx->dp, ctx->G, mode, guess, ctx->newton_tol, ctx->newton_maxit, ctx->fp64,
                             ctx->nmax, cs);
-          if (e1 == hipSuccess) e2 = launch_push(ctx->dp, ctx->G, ctx->lc, cs);
+          if (e1 == hipSuccess) e2 = launch_push_emit(ctx, cs, false);
         }
-        if (e1 == hipSuccess && e2 == hipSuccess) e3 = launch_compact(ctx->dp, ctx->G, ctx->lc, cs);
+        if (e1 == hipSuccess && e2 == hipSuccess) e3 = launch_reclaim(ctx, cs, KTime{});
         hipError_t ec = hipStreamEndCapture(cs, &graph);
         if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || ec != hipSuccess || !graph) {
           if (graph) (void)hipGraphDestroy(graph);
@@ -1300,9 +1335,28 @@ static void apply_tuning(gs_ctx *ctx, const gs_tuning &t) {
   ctx->grid_opt = 1;
   ctx->lc.grid = t.grid;
   ctx->compact_every = t.compact_every;
+  ctx->lc.sort_bin = t.sort_bin;
   choose_launch(ctx);
   ctx->lc.grid = t.grid;
   drop_graphs(ctx);
+}
+
+static gs_tuning current_tuning(const gs_ctx *ctx) {
+  gs_tuning t{};
+  t.block = ctx->lc.block;
+  t.tile = ctx->lc.tile;
+  t.grid = ctx->lc.grid;
+  t.ppt = ctx->lc.ppt / (ctx->fp64 ? 2 : 4);
+  t.deposit = ctx->deposit_opt;
+  t.compact_every = ctx->compact_every;
+  t.sort_bin = ctx->lc.sort_bin;
+  return t;
+}
+
+extern "C" gs_status gs_get_launch(const gs_ctx *ctx, gs_tuning *out) {
+  if (!ctx || !out) return GS_ESTATE;
+  *out = current_tuning(ctx);
+  return GS_OK;
 }
 
 extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32_t trial_steps,
@@ -1331,7 +1385,7 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
       if (bar == std::string::npos || line.substr(0, bar) != key) continue;
       gs_tuning t{};
       std::istringstream v(line.substr(bar + 1));
-      if (v >> t.block >> t.tile >> t.grid >> t.ppt >> t.deposit >> t.compact_every >> t.ms_per_step) {
+      if (v >> t.block >> t.tile >> t.grid >> t.ppt >> t.deposit >> t.compact_every >> t.sort_bin >> t.ms_per_step) {
         const LaunchCfg keep = ctx->lc;
         apply_tuning(ctx, t);
         if (!launch_fits(ctx)) {
@@ -1365,6 +1419,7 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
   const HostCounters hc0{ctx->epoch, ctx->steps_done, ctx->since_compact, ctx->next_id};
   const LaunchCfg lc0 = ctx->lc;
   const int dep0 = ctx->deposit_opt, grid_opt0 = ctx->grid_opt, ce0 = ctx->compact_every;
+  const int sb0 = ctx->lc.sort_bin;
   const int graph0 = ctx->use_graph, timing0 = ctx->timing;
   float *rx = ctx->dp.rec_x, *ry = ctx->dp.rec_y;
   ctx->dp.rec_x = ctx->dp.rec_y = nullptr;  // trials record nothing
@@ -1385,7 +1440,9 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   // time one candidate: warm-up steps, then `steps` timed steps, from the snapshot
-  auto trial = [&](const gs_tuning &t, int steps, double *ms) -> gs_status {
+  // (reclaim_first: the first warm-up step ends with a compaction or sort, so
+  // that the timed steps see particles in the order that choice keeps)
+  auto trial = [&](const gs_tuning &t, int steps, double *ms, bool reclaim_first) -> gs_status {
     gs_status r = restore();
     if (r != GS_OK) return r;
     apply_tuning(ctx, t);
@@ -1393,6 +1450,7 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
       *ms = 1e300;
       return GS_OK;
     }
+    if (reclaim_first) ctx->since_compact = t.compact_every - 1;
     for (int k = 0; k < 2; ++k)
       if ((r = one_step(ctx, mode, guess)) != GS_OK) return r;
     HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
@@ -1409,37 +1467,47 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
   best.ms_per_step = 1e300;
   const int vper = ctx->fp64 ? 2 : 4;
   gs_status r = GS_OK;
-  // launch shape first, at the current compaction interval
-  for (int block : {256, 512, 768})
+  // launch shape first, at the current compaction interval and sort setting
+  for (int block : {256, 512, 768, 1024})
     for (int ppt : {1, 2})
       for (int tmul : {8, 32})
         for (int per_cu : {1, 2, 3, 4, 8}) {  // 256-thread workgroups per CU
+          if (r != GS_OK) break;
           gs_tuning t{};
           t.block = block;
           t.ppt = ppt;
           t.tile = block * tmul;
           if (t.tile % (block * ppt * vper)) continue;
-          t.deposit = dep0;
           // the same threads per CU at other block sizes
+          if (per_cu * 256 < block) continue;
+          t.deposit = dep0;
           t.grid = std::max(1, ctx->ncu * per_cu * 256 / block);
           t.compact_every = ce0;
+          t.sort_bin = sb0;
           double ms = 0;
-          if ((r = trial(t, trial_steps, &ms)) != GS_OK) break;
+          if ((r = trial(t, trial_steps, &ms, false)) != GS_OK) break;
           t.ms_per_step = ms;
           if (ms < best.ms_per_step) best = t;
         }
-  // then the compaction interval, over a span that includes compactions
+  // then the compaction interval and the cell sort (off, or bins of 16, 64 or
+  // 256 cells), over a span that holds several compactions or sorts: the
+  // sort's cost is amortised over the interval and its gain shows in the
+  // pushes that follow it
   if (r == GS_OK) {
     const gs_tuning base = best;
     best.ms_per_step = 1e300;
-    for (int ce : {16, 32, 64}) {
-      gs_tuning t = base;
-      t.compact_every = ce;
-      double ms = 0;
-      if ((r = trial(t, std::max(trial_steps, 64), &ms)) != GS_OK) break;
-      t.ms_per_step = ms;
-      if (ms < best.ms_per_step) best = t;
-    }
+    for (int sb : {0, 16, 64, 256})
+      for (int ce : {16, 32, 64}) {
+        if (sb && sort_lds_bytes(ctx->G, ctx->nmax, sb) > 163840) continue;
+        if (sb && (ctx->nmax + sb - 1) / sb < 2) continue;  // one bin: nothing to sort
+        gs_tuning t = base;
+        t.compact_every = ce;
+        t.sort_bin = sb;
+        double ms = 0;
+        if ((r = trial(t, std::max(trial_steps, 2 * ce), &ms, true)) != GS_OK) break;
+        t.ms_per_step = ms;
+        if (ms < best.ms_per_step) best = t;
+      }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1454,6 +1522,7 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
     ctx->deposit_opt = dep0;
     ctx->grid_opt = grid_opt0;
     ctx->compact_every = ce0;
+    ctx->lc.sort_bin = sb0;
     drop_graphs(ctx);
     if (r != GS_OK) return r;
     if (rr != GS_OK) return rr;
@@ -1463,7 +1532,7 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
   if (cache_path && *cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     f << key << "|" << best.block << " " << best.tile << " " << best.grid << " " << best.ppt << " " << best.deposit
-      << " " << best.compact_every << " " << best.ms_per_step << "\n";
+      << " " << best.compact_every << " " << best.sort_bin << " " << best.ms_per_step << "\n";
   }
   if (out) *out = best;
   return GS_OK;
@@ -1498,6 +1567,14 @@ extern "C" gs_status gs_set_option(gs_ctx *ctx, int32_t option, int64_t value) {
       if (value != 1 && value != 2) return fail(ctx, GS_EINVAL, "vectors per thread must be 1 or 2");
       ctx->lc.ppt = (int)value * (ctx->fp64 ? 2 : 4);
       if (ctx->lc.tile % (ctx->lc.block * ctx->lc.ppt)) ctx->lc.tile = ctx->lc.block * ctx->lc.ppt * 4;
+      break;
+    case GS_OPT_SORT_BIN:
+      if (value != 0 && (value < SORT_BIN_MIN || value > 1 << 20))
+        return fail(ctx, GS_EINVAL, "sort bin must be 0 or at least %d cells", SORT_BIN_MIN);
+      if (value != 0 && sort_lds_bytes(ctx->G, ctx->nmax, (int)value) > 163840)
+        return fail(ctx, GS_EINVAL, "a sort bin of %lld cells needs more than 160 KiB of LDS for %d gaps",
+                    (long long)value, ctx->G);
+      ctx->lc.sort_bin = (int)value;
       break;
     case GS_OPT_COMPACT_GRID:
       if (value < 1 || value > 1 << 20) return fail(ctx, GS_EINVAL, "compact grid out of range");
@@ -1553,6 +1630,9 @@ extern "C" gs_status gs_get_timing(gs_ctx *ctx, gs_timing *out, int32_t reset) {
     } else if (pe.kind == 1) {
       ctx->tm.field_ms += ms;
       ctx->tm.field_launches += 1;
+    } else if (pe.kind == 3) {
+      ctx->tm.emit_ms += ms;
+      ctx->tm.emit_launches += 1;
     } else {
       ctx->tm.compact_ms += ms;
       ctx->tm.compact_launches += 1;

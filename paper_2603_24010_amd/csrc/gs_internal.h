@@ -38,6 +38,8 @@ struct GapConst {
   int64_t evbase;     // first slot of the gap's absorbed-ion event list
   int64_t evcap;      // its capacity
   int64_t ebase;      // offset of the binary32/64 field table (N + 2 entries)
+  int64_t hbase[2];   // first counter of species s in the cell-sort bin arrays
+                      // (room for ceil(N / SORT_BIN_MIN) bins per species)
   uint64_t seed;
   double d, dx, A, eps0, dt, cgap, c_par;
   double s0;           // sheet charge per unit of Z: weight * q_unit [C/m^2]
@@ -120,6 +122,9 @@ struct DevPtrs {
   unsigned int *err;               // [0] flags, [1] gap of first error
   Event *ev;                       // absorbed-ion events, per-gap lists
   unsigned long long *ev_count;    // [G]
+  unsigned long long *ev_done;     // [G] events of the list already emitted by k_emit
+  // periodic cell sort: live particles per bin, then per-bin write cursors
+  unsigned long long *hist, *bcur;
   const int64_t *sched;            // beam schedules of all gaps (GapConst::sched_base)
   // exchange with an external circuit engine (field mode 2), in pinned host
   // memory the device maps: ext_v[g] the engine's gap voltage for the level
@@ -141,6 +146,10 @@ struct DevPtrs {
 
 enum { ERR_CAPACITY = 1u, ERR_BADINJECT = 2u, ERR_NOCONV = 4u };
 
+// Smallest cell-sort bin (cells per bin): bounds the bin arrays and the LDS of
+// the sort kernels (16384 cells -> 4096 bins per species).
+constexpr int SORT_BIN_MIN = 4;
+
 // Absorbed-ion events a push workgroup keeps in its global overflow region
 // (past these they go to the gap's list, emitted by the next field solve).
 constexpr int OVQ = 1024;
@@ -154,6 +163,9 @@ struct LaunchCfg {
   int wide;          // binary32: 64-bit LDS deposit cells (else 32-bit cells with carries)
   int compact_grid;  // compaction blocks
   int ppt;           // particles per thread per chunk (one or two 16-byte vectors)
+  int sort_bin;      // cells per bin of the periodic counting sort that replaces the
+                     // compaction (0: plain compaction); with it the push queues no
+                     // events past its LDS queue and k_emit emits them after the push
 };
 
 // launchers (gs_kernels.hip)
@@ -168,6 +180,10 @@ hipError_t launch_field(const DevPtrs &p, int G, int mode, int guess, double new
                         int newton_maxit, int fp64, int nmax, hipStream_t s, KTime t = {});
 hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t = {});
 hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t = {});
+// the cell sort (count, scan, scatter, commit), in place of launch_compact
+hipError_t launch_sort(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t = {});
+// secondary emission of every gap's queued events, many workgroups (after a push)
+hipError_t launch_emit(const DevPtrs &p, int G, int fp64, int grid, hipStream_t s, KTime t = {});
 hipError_t launch_inject(const DevPtrs &p, int gap, int species, long long n, const double *x_dev,
                          const double *v_dev, long long id0, int fp64, hipStream_t s);
 hipError_t launch_phi(const DevPtrs &p, int gap, hipStream_t s);
@@ -178,5 +194,6 @@ hipError_t launch_dt_scan(const DevPtrs &p, int gap, int N, int fp64, unsigned l
 // guess network (gs_mlp.hip): y[n][3] = net(x[n][48]) with bfloat16 weights W
 hipError_t launch_mlp_forward(const uint16_t *W, const float *x, long long n, float *y, hipStream_t s);
 size_t push_lds_bytes(int nmax, int fp64, int G, int wide);
+size_t sort_lds_bytes(int G, int nmax, int bin);
 
 }  // namespace gs

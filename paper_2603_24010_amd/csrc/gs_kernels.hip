@@ -550,6 +550,7 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
   st.beam_now = nb;
   p.next_count[g * 2 + 1] = (unsigned long long)(st.count[1] + nb);
   p.ev_count[g] = 0ull;
+  p.ev_done[g] = 0ull;
   st.beam_id0 = st.next_id;
   st.next_id += nb;
   *sigma_out = sigma;
@@ -603,14 +604,15 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   // secondary electrons are emitted here, keyed by the push's level
   unsigned long long ex0 = 0ull, exN = 0ull;
   {
-    const long long nov = min((long long)p.ev_count[g], sc.evcap);
+    const long long nall = min((long long)p.ev_count[g], sc.evcap);
+    const long long ndone = min((long long)p.ev_done[g], nall);
+    const long long nov = nall - ndone;
     if (nov > 0) {
+      const Event *evs = p.ev + sc.evbase + ndone;
       if (fp64)
-        see_emit<double>(p, sc, ss.level, g, (int)(*p.epoch & 1), p.ev + sc.evbase, (int)nov, s_wsum_i, &s_ebase,
-                         s_emit);
+        see_emit<double>(p, sc, ss.level, g, (int)(*p.epoch & 1), evs, (int)nov, s_wsum_i, &s_ebase, s_emit);
       else
-        see_emit<float>(p, sc, ss.level, g, (int)(*p.epoch & 1), p.ev + sc.evbase, (int)nov, s_wsum_i, &s_ebase,
-                        s_emit);
+        see_emit<float>(p, sc, ss.level, g, (int)(*p.epoch & 1), evs, (int)nov, s_wsum_i, &s_ebase, s_emit);
       __syncthreads();
       const long long ze = (long long)sc.Z[0] * (fp64 ? (1ll << F64_BITS) : (1ll << F32_BITS));
       ex0 = (unsigned long long)(ze * (long long)s_emit[0]);
@@ -1157,35 +1159,55 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
     acc_add<AC>(sh.acc, c.gacc, jj[k] + 1, (unsigned long long)w1[k], zhi);
   }
   // absorbed ions are queued for secondary emission: in LDS (emitted at the
-  // segment's flush), or straight to the gap's list (emitted by the next field
-  // solve) when the workgroup's queue is full
-  if (see && (hit & 0xFFFFu) != 0u) {
-    unsigned int rest = hit & 0xFFFFu;
-    while (rest) {
-      const int k = __ffs(rest) - 1;
-      rest &= rest - 1u;
-      Event ev;
-      P uk = u_hit[0];
+  // segment's flush), then in the workgroup's overflow region, then in the
+  // gap's list (emitted after the push, or by the next field solve).  The wave
+  // takes its queue positions, and its share of the gap's list, with one atomic
+  // each: a workgroup whose particles sit at a wall (sorted particles) absorbs
+  // thousands of ions in one push, and an atomic per ion on the gap's counter
+  // would serialise them.
+  if (see) {
+    const int nh = __popc(hit & 0xFFFFu);
+    if (__ballot(nh != 0) != 0ull) {
+      const int lane = tid & 63;
+      const int incl = wave_incl_scan(nh);
+      const unsigned int tot = (unsigned int)__shfl(incl, 63, 64);
+      unsigned int q0 = 0;
+      if (lane == 0) q0 = atomicAdd(sh.evq_n, tot);
+      q0 = (unsigned int)__shfl((int)q0, 0, 64);
+      const unsigned int lim = (unsigned int)EVQ + ((long long)blockIdx.x < p.ovf_wgs ? (unsigned int)OVQ : 0u);
+      const unsigned int over0 = q0 > lim ? q0 : lim;
+      const unsigned int n_over = q0 + tot > lim ? q0 + tot - over0 : 0u;
+      unsigned long long gb = 0;
+      if (n_over && lane == 0) gb = atomicAdd(&p.ev_count[g], (unsigned long long)n_over);
+      gb = __shfl(gb, 0, 64);
+      unsigned int q = q0 + (unsigned int)(incl - nh);
+      unsigned int rest = hit & 0xFFFFu;
+      while (rest) {
+        const int k = __ffs(rest) - 1;
+        rest &= rest - 1u;
+        Event ev;
+        P uk = u_hit[0];
 #pragma unroll
-      for (int q = 1; q < PPT; ++q)
-        if (q == k) uk = u_hit[q];
-      ev.u = (double)uk;
-      ev.ref = (uint32_t)(r0 + (long long)((k / VN) * BS + tid) * VN + k % VN);
-      ev.wall = (hit >> (k + 16)) & 1u;
-      const unsigned int q = atomicAdd(sh.evq_n, 1u);
-      if (q < (unsigned int)EVQ) {
-        sh.evq[q] = ev;
-      } else if (q < (unsigned int)(EVQ + OVQ) && (long long)blockIdx.x < p.ovf_wgs) {
-        p.ovf[(size_t)blockIdx.x * OVQ + (q - EVQ)] = ev;
-      } else {
-        const unsigned long long e = atomicAdd(&p.ev_count[g], 1ull);
-        if (e < (unsigned long long)c.evcap) {
-          ev.ref = c.ids[ev.ref];
-          p.ev[c.evbase + e] = ev;
+        for (int j = 1; j < PPT; ++j)
+          if (j == k) uk = u_hit[j];
+        ev.u = (double)uk;
+        ev.ref = (uint32_t)(r0 + (long long)((k / VN) * BS + tid) * VN + k % VN);
+        ev.wall = (hit >> (k + 16)) & 1u;
+        if (q < (unsigned int)EVQ) {
+          sh.evq[q] = ev;
+        } else if (q < lim) {
+          p.ovf[(size_t)blockIdx.x * OVQ + (q - EVQ)] = ev;
         } else {
-          atomicOr(&p.err[0], ERR_CAPACITY);
-          atomicCAS(&p.err[1], 0xFFFFFFFFu, (unsigned int)g);
+          const unsigned long long e = gb + (unsigned long long)(q - over0);
+          if (e < (unsigned long long)c.evcap) {
+            ev.ref = c.ids[ev.ref];
+            p.ev[c.evbase + e] = ev;
+          } else {
+            atomicOr(&p.err[0], ERR_CAPACITY);
+            atomicCAS(&p.err[1], 0xFFFFFFFFu, (unsigned int)g);
+          }
         }
+        q += 1u;
       }
     }
   }
@@ -1493,6 +1515,302 @@ __global__ void k_commit(DevPtrs p, int G) {
 }
 
 // ---------------------------------------------------------------------------
+// Periodic cell sort: a counting sort of every (gap, species) region by bins of
+// `bin` cells, in place of the compaction.  The live particles are written to
+// the other buffer grouped by bin in increasing x, absorbed slots dropped; the
+// order inside a bin is unspecified (no result depends on particle order).
+// With sorted particles each push workgroup's run of tiles covers a narrow band
+// of cells, so its deposit touches, and its flush adds, only that band.
+//   k_sort_count    live particles per bin (hist)
+//   k_sort_scan     bin offsets (bcur) and the region's live count (cursor)
+//   k_sort_scatter  every particle to its bin's next slot
+// then k_commit switches buffers as after a compaction.
+// ---------------------------------------------------------------------------
+
+// Adds one to cnt[bin] for every valid lane and returns each lane's rank among
+// all additions to its bin so far.  Lanes of one bin share one LDS atomic (a
+// sorted stream puts most of a wave in one or two bins, and separate atomics to
+// one address would serialise); once the wave's leading bin holds fewer than 4
+// lanes the remaining lanes add one by one.  Every lane of the wave calls it.
+__device__ inline unsigned int wave_bin_rank(unsigned int *cnt, int bin, bool valid) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long act = __ballot(valid);
+  unsigned int rank = 0;
+  while (act) {
+    const int leader = __ffsll((long long)act) - 1;
+    const int b0 = __shfl(bin, leader, 64);
+    const unsigned long long m = __ballot(valid && bin == b0) & act;
+    const int n = __popcll(m);
+    if (n < 4) {
+      if ((act >> lane) & 1ull) rank = atomicAdd(&cnt[bin], 1u);
+      break;
+    }
+    unsigned int base = 0;
+    if (lane == leader) base = atomicAdd(&cnt[b0], (unsigned int)n);
+    base = __shfl(base, leader, 64);
+    if ((m >> lane) & 1ull) rank = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
+    act &= ~m;
+  }
+  return rank;
+}
+
+template <class P>
+__device__ inline int bin_of(P x, int bin, int nb) {
+  const int b = (int)x / bin;
+  return b < nb - 1 ? b : nb - 1;
+}
+
+// The tile partition of k_compact over the regions' current slot counts:
+// prefix[r] = first tile of region r (LDS, 2G + 1 entries).
+template <int BS>
+__device__ inline void region_tile_prefix(const DevPtrs &p, int G, int tile, int *prefix, int *scan_sh) {
+  const int tid = threadIdx.x;
+  const int R = 2 * G;
+  const int per = (R + BS - 1) / BS;
+  int mine = 0;
+  for (int q = 0; q < per; ++q) {
+    const int r = tid * per + q;
+    if (r < R) mine += (int)((min((long long)p.next_count[r], p.gc[r >> 1].cap[r & 1]) + tile - 1) / tile);
+  }
+  int total_t;
+  int run = block_exclusive_scan<int>(mine, scan_sh, &total_t);
+  for (int q = 0; q < per; ++q) {
+    const int r = tid * per + q;
+    if (r < R) {
+      prefix[r] = run;
+      run += (int)((min((long long)p.next_count[r], p.gc[r >> 1].cap[r & 1]) + tile - 1) / tile);
+    }
+  }
+  if (tid == 0) prefix[R] = total_t;
+  __syncthreads();
+}
+
+// One vector of VN slots starting at slot j (below i_end, or masked past it):
+// positions, velocities, ids; slots past i_end read as absorbed.
+template <class P>
+__device__ inline void load_vec(const P *X, const P *U, const uint32_t *I, long long j, long long i_end,
+                                typename Vec<P>::type &xv, typename Vec<P>::type &uv, uint32_t *iv) {
+  typedef typename Vec<P>::type PV;
+  constexpr int VN = Vec<P>::n;
+  typedef unsigned int IDV __attribute__((ext_vector_type(VN)));
+  if (j + VN <= i_end) {
+    xv = *(const PV *)(X + j);
+    uv = *(const PV *)(U + j);
+    const IDV t = *(const IDV *)(I + j);
+#pragma unroll
+    for (int k = 0; k < VN; ++k) iv[k] = t[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < VN; ++k) {
+      const bool in = j + k < i_end;
+      Vec<P>::at(xv, k) = in ? X[j + k] : (P)-1;
+      Vec<P>::at(uv, k) = in ? U[j + k] : (P)0;
+      iv[k] = in ? I[j + k] : 0u;
+    }
+  }
+}
+
+template <class P, int BS>
+__global__ __launch_bounds__(BS) void k_sort_count(DevPtrs p, int G, int tile, int bin, int nbmax) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  int *prefix = (int *)lds_raw;  // [2G + 1]
+  unsigned int *cnt = (unsigned int *)(lds_raw + ((size_t)(2 * G + 1) * 4 + 15) / 16 * 16);  // [nbmax]
+  __shared__ int scan_sh[BS];
+  const int tid = threadIdx.x;
+  const int src = (int)(*p.epoch & 1);
+  region_tile_prefix<BS>(p, G, tile, prefix, scan_sh);
+  const int total = prefix[2 * G];
+  const int t0 = (int)(((long long)blockIdx.x * total) / gridDim.x);
+  const int t1 = (int)(((long long)(blockIdx.x + 1) * total) / gridDim.x);
+  constexpr int VN = Vec<P>::n;
+  int r = 0;
+  for (int t = t0; t < t1;) {
+    while (prefix[r + 1] <= t) ++r;
+    const int tend = min(t1, prefix[r + 1]);
+    const int g = r >> 1, s = r & 1;
+    const GapConst &c = p.gc[g];
+    const int nb = (c.N + bin - 1) / bin;
+    const long long n = min((long long)p.next_count[r], c.cap[s]);
+    const long long i_beg = (long long)(t - prefix[r]) * tile;
+    const long long i_end = min(n, (long long)(tend - prefix[r]) * tile);
+    const P *X = (const P *)p.X[src] + c.pbase[s];
+    for (int b = tid; b < nb; b += BS) cnt[b] = 0u;
+    __syncthreads();
+    for (long long i0 = i_beg; i0 < i_end; i0 += (long long)BS * VN) {
+      const long long j = i0 + (long long)tid * VN;
+      typename Vec<P>::type xv;
+      if (j + VN <= i_end) {
+        xv = *(const typename Vec<P>::type *)(X + j);
+      } else {
+#pragma unroll
+        for (int k = 0; k < VN; ++k) Vec<P>::at(xv, k) = j + k < i_end ? X[j + k] : (P)-1;
+      }
+#pragma unroll
+      for (int k = 0; k < VN; ++k) {
+        const P x = Vec<P>::at(xv, k);
+        const bool live = x >= (P)0;
+        (void)wave_bin_rank(cnt, live ? bin_of<P>(x, bin, nb) : 0, live);
+      }
+    }
+    __syncthreads();
+    unsigned long long *h = p.hist + c.hbase[s];
+    for (int b = tid; b < nb; b += BS)
+      if (cnt[b]) atomicAdd(&h[b], (unsigned long long)cnt[b]);
+    __syncthreads();
+    t = tend;
+  }
+}
+
+// one workgroup per region: exclusive scan of the bin counts into the bins'
+// first slots, the region's live count for k_commit, counts cleared
+constexpr int SSB = 256;
+__global__ __launch_bounds__(SSB) void k_sort_scan(DevPtrs p, int bin) {
+  __shared__ unsigned long long sh[SSB];
+  const int r = blockIdx.x, g = r >> 1, s = r & 1;
+  const GapConst &c = p.gc[g];
+  const int nb = (c.N + bin - 1) / bin;
+  unsigned long long *h = p.hist + c.hbase[s];
+  unsigned long long *bc = p.bcur + c.hbase[s];
+  unsigned long long run = 0;
+  for (int b0 = 0; b0 < nb; b0 += SSB) {
+    const int b = b0 + (int)threadIdx.x;
+    const unsigned long long v = b < nb ? h[b] : 0ull;
+    unsigned long long tot;
+    const unsigned long long ex = block_exclusive_scan<unsigned long long>(v, sh, &tot);
+    if (b < nb) {
+      bc[b] = run + ex;
+      h[b] = 0ull;
+    }
+    run += tot;
+  }
+  if (threadIdx.x == 0) p.cursor[r] = run;
+}
+
+template <class P, int BS>
+__global__ __launch_bounds__(BS) void k_sort_scatter(DevPtrs p, int G, int tile, int bin, int nbmax) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  int *prefix = (int *)lds_raw;  // [2G + 1]
+  const size_t o1 = ((size_t)(2 * G + 1) * 4 + 15) / 16 * 16;
+  unsigned long long *base = (unsigned long long *)(lds_raw + o1);          // [nbmax]
+  unsigned int *cnt = (unsigned int *)(lds_raw + o1 + (size_t)nbmax * 8);   // [nbmax]
+  int *touched = (int *)(lds_raw + o1 + (size_t)nbmax * 12);                // [nbmax]
+  __shared__ int scan_sh[BS];
+  __shared__ int ntouched;
+  const int tid = threadIdx.x;
+  const int src = (int)(*p.epoch & 1), dst = src ^ 1;
+  region_tile_prefix<BS>(p, G, tile, prefix, scan_sh);
+  const int total = prefix[2 * G];
+  const int t0 = (int)(((long long)blockIdx.x * total) / gridDim.x);
+  const int t1 = (int)(((long long)(blockIdx.x + 1) * total) / gridDim.x);
+  constexpr int VN = Vec<P>::n;
+  int r = 0;
+  for (int t = t0; t < t1;) {
+    while (prefix[r + 1] <= t) ++r;
+    const int tend = min(t1, prefix[r + 1]);
+    const int g = r >> 1, s = r & 1;
+    const GapConst &c = p.gc[g];
+    const int nb = (c.N + bin - 1) / bin;
+    const long long n = min((long long)p.next_count[r], c.cap[s]);
+    const long long i_beg = (long long)(t - prefix[r]) * tile;
+    const long long i_end = min(n, (long long)(tend - prefix[r]) * tile);
+    const P *Xs = (const P *)p.X[src] + c.pbase[s];
+    const P *Us = (const P *)p.U[src] + c.pbase[s];
+    const uint32_t *Is = p.ID[src] + c.pbase[s];
+    P *Xd = (P *)p.X[dst] + c.pbase[s];
+    P *Ud = (P *)p.U[dst] + c.pbase[s];
+    uint32_t *Id = p.ID[dst] + c.pbase[s];
+    unsigned long long *bc = p.bcur + c.hbase[s];
+    for (int b = tid; b < nb; b += BS) cnt[b] = 0u;
+    if (tid == 0) ntouched = 0;
+    __syncthreads();
+    for (long long i0 = i_beg; i0 < i_end; i0 += (long long)BS * VN) {
+      const long long j = i0 + (long long)tid * VN;
+      typename Vec<P>::type xv, uv;
+      uint32_t iv[VN];
+      load_vec<P>(Xs, Us, Is, j, i_end, xv, uv, iv);
+      int bk[VN];
+      unsigned int rk[VN];
+#pragma unroll
+      for (int k = 0; k < VN; ++k) {
+        const P x = Vec<P>::at(xv, k);
+        const bool live = x >= (P)0;
+        bk[k] = live ? bin_of<P>(x, bin, nb) : -1;
+        rk[k] = wave_bin_rank(cnt, live ? bk[k] : 0, live);
+        // the first particle of a bin in this chunk lists the bin
+        if (live && rk[k] == 0u) touched[atomicAdd(&ntouched, 1)] = bk[k];
+      }
+      __syncthreads();
+      // one slot reservation per bin the chunk touched
+      const int nt = ntouched;
+      for (int q = tid; q < nt; q += BS) {
+        const int b = touched[q];
+        base[b] = atomicAdd(&bc[b], (unsigned long long)cnt[b]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < VN; ++k)
+        if (bk[k] >= 0) {
+          const unsigned long long o = base[bk[k]] + rk[k];
+          Xd[o] = Vec<P>::at(xv, k);
+          Ud[o] = Vec<P>::at(uv, k);
+          Id[o] = iv[k];
+        }
+      for (int q = tid; q < nt; q += BS) cnt[touched[q]] = 0u;
+      __syncthreads();
+      if (tid == 0) ntouched = 0;
+      __syncthreads();
+    }
+    t = tend;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_emit: secondary emission (Alg. 2) of the absorbed ions a push queued in the
+// gaps' event lists, spread over many workgroups: chunks of EBS events, each
+// with one slot reservation.  Keyed by the push's level, as in the push, so
+// the electrons and their draws are the same; their wall charge goes to the
+// node accumulator and their counts to the tallies the next field solve reads.
+// Every event handled is counted in ev_done, so that the field solve emits
+// only what is left.
+// ---------------------------------------------------------------------------
+constexpr int EBS = 256;
+template <class P>
+__global__ __launch_bounds__(EBS) void k_emit(DevPtrs p, int G) {
+  __shared__ int wsum[EBS / 64];
+  __shared__ unsigned long long s_base;
+  __shared__ unsigned int s_emit[2];
+  const int sel = (int)(*p.epoch & 1);
+  for (int g = 0; g < G; ++g) {
+    const GapConst &c = p.gc[g];
+    const long long ne = min((long long)p.ev_count[g], c.evcap);
+    if (ne <= (long long)blockIdx.x * EBS) continue;
+    const long long level = p.gs[g].level;
+    for (long long r0 = (long long)blockIdx.x * EBS; r0 < ne; r0 += (long long)gridDim.x * EBS) {
+      if (threadIdx.x < 2) s_emit[threadIdx.x] = 0u;
+      __syncthreads();
+      const int nr = (int)min((long long)EBS, ne - r0);
+      see_emit<P>(p, c, level, g, sel, p.ev + c.evbase + r0, nr, wsum, &s_base, s_emit);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const unsigned int e0 = s_emit[0], e1 = s_emit[1];
+        const long long ze = (long long)c.Z[0] * Prec<P>::W;
+        unsigned long long *gacc = p.acc + c.nbase;
+        if (e0) {
+          atomicAdd(&gacc[0], (unsigned long long)(ze * (long long)e0));
+          atomicAdd(&p.tally[(size_t)g * T_N + T_EMIT], (unsigned long long)e0);
+        }
+        if (e1) {
+          atomicAdd(&gacc[c.N], (unsigned long long)(ze * (long long)e1));
+          atomicAdd(&p.tally[(size_t)g * T_N + T_EMIT + 1], (unsigned long long)e1);
+        }
+        atomicAdd(&p.ev_done[g], (unsigned long long)nr);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // injection of caller particles (SI) into one gap
 // ---------------------------------------------------------------------------
 template <class P>
@@ -1702,6 +2020,48 @@ hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStrea
                                     lc.tile);
   if (e != hipSuccess) return e;
   return launch_k(k_commit, dim3((2 * G + 255) / 256), dim3(256), 0, s, nullptr, t.b, p, G);
+}
+
+size_t sort_lds_bytes(int G, int nmax, int bin) {
+  const int nbmax = (nmax + bin - 1) / bin;
+  return ((size_t)(2 * G + 1) * 4 + 15) / 16 * 16 + (size_t)nbmax * 16;
+}
+
+template <class P>
+static hipError_t sort_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+  const int bin = lc.sort_bin;
+  const int nbmax = (lc.nmax + bin - 1) / bin;
+  const size_t lds = sort_lds_bytes(G, lc.nmax, bin);
+  static size_t attr_set = 65536;
+  if (lds > attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_sort_count<P, 256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void *)k_sort_scatter<P, 256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = lds;
+  }
+  const int grid = lc.compact_grid > 0 ? lc.compact_grid : 1024;
+  // the start event goes with the count pass, the end event with the commit
+  hipError_t e = launch_k(k_sort_count<P, 256>, dim3(grid), dim3(256), lds, s, t.a, nullptr, p, G, lc.tile, bin,
+                          nbmax);
+  if (e != hipSuccess) return e;
+  e = launch_k(k_sort_scan, dim3(2 * G), dim3(SSB), 0, s, nullptr, nullptr, p, bin);
+  if (e != hipSuccess) return e;
+  e = launch_k(k_sort_scatter<P, 256>, dim3(grid), dim3(256), lds, s, nullptr, nullptr, p, G, lc.tile, bin, nbmax);
+  if (e != hipSuccess) return e;
+  return launch_k(k_commit, dim3((2 * G + 255) / 256), dim3(256), 0, s, nullptr, t.b, p, G);
+}
+
+hipError_t launch_sort(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+  if (lc.sort_bin < SORT_BIN_MIN) return hipErrorInvalidValue;
+  return lc.fp64 ? sort_t<double>(p, G, lc, s, t) : sort_t<float>(p, G, lc, s, t);
+}
+
+hipError_t launch_emit(const DevPtrs &p, int G, int fp64, int grid, hipStream_t s, KTime t) {
+  return fp64 ? launch_k(k_emit<double>, dim3(grid), dim3(EBS), 0, s, t.a, t.b, p, G)
+              : launch_k(k_emit<float>, dim3(grid), dim3(EBS), 0, s, t.a, t.b, p, G);
 }
 
 hipError_t launch_inject(const DevPtrs &p, int gap, int species, long long n, const double *x,

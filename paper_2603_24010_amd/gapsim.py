@@ -24,12 +24,14 @@ GS_ECALLBACK = -7
 GUESS_DIRECT, GUESS_EXTRAP, GUESS_MLP = 0, 1, 2
 OPT_BLOCK, OPT_TILE, OPT_GRID, OPT_COMPACT_EVERY, OPT_GRAPH, OPT_TIMING = 1, 2, 3, 4, 5, 6
 OPT_NEWTON_TOL, OPT_NEWTON_MAXIT, OPT_DEPOSIT, OPT_COMPACT_GRID, OPT_PPT = 7, 8, 9, 10, 11
+OPT_SORT_BIN = 12
 
 EXPORTED = [
-    "gs_init", "gs_destroy", "gs_inject", "gs_step_strict", "gs_step_weak", "gs_read_diagnostics",
+    "gs_init_gap", "gs_destroy", "gs_inject", "gs_step_strict", "gs_step_weak", "gs_read_diagnostics",
     "gs_read_particles", "gs_set_option", "gs_get_timing", "gs_validate_params", "gs_last_error",
     "gs_version", "gs_mlp_set_weights", "gs_mlp_forward", "gs_mlp_record", "gs_mlp_train_workspace",
     "gs_mlp_train", "gs_autotune", "gs_step_weak_external", "gs_circuit_resonance", "gs_dt_check",
+    "gs_get_launch",
 ]
 MLP_IN, MLP_OUT, MLP_NPARAM, MLP_NORM = 48, 3, 39683, 102
 
@@ -91,12 +93,14 @@ class GsTiming(C.Structure):
     _fields_ = [
         ("push_ms", C.c_double), ("field_ms", C.c_double), ("compact_ms", C.c_double),
         ("push_launches", C.c_int64), ("field_launches", C.c_int64), ("compact_launches", C.c_int64),
+        ("emit_ms", C.c_double), ("emit_launches", C.c_int64),
     ]
 
 
 class GsTuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("tile", C.c_int32), ("grid", C.c_int32), ("ppt", C.c_int32),
-                ("deposit", C.c_int32), ("compact_every", C.c_int32), ("ms_per_step", C.c_double)]
+                ("deposit", C.c_int32), ("compact_every", C.c_int32), ("sort_bin", C.c_int32),
+                ("pad", C.c_int32), ("ms_per_step", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -130,8 +134,8 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2603_24010_amd/build.py")
         L = C.CDLL(LIB_PATH)
         vp, P = C.c_void_p, C.POINTER(C.c_double)
-        L.gs_init.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(GsGapParams), C.POINTER(GsAllocator), vp]
-        L.gs_init.restype = C.c_int
+        L.gs_init_gap.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(GsGapParams), C.POINTER(GsAllocator), vp]
+        L.gs_init_gap.restype = C.c_int
         L.gs_destroy.argtypes = [vp]
         L.gs_inject.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, vp, vp, C.c_int32]
         L.gs_inject.restype = C.c_int
@@ -167,6 +171,8 @@ def lib():
         L.gs_mlp_train.restype = C.c_int
         L.gs_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_char_p, C.POINTER(GsTuning)]
         L.gs_autotune.restype = C.c_int
+        L.gs_get_launch.argtypes = [vp, C.POINTER(GsTuning)]
+        L.gs_get_launch.restype = C.c_int
         L.gs_step_weak_external.argtypes = [vp, C.c_int32, CIRCUIT_FN, vp]
         L.gs_step_weak_external.restype = C.c_int
         L.gs_circuit_resonance.argtypes = [C.POINTER(GsGapParams), P]
@@ -175,6 +181,11 @@ def lib():
         L.gs_dt_check.restype = C.c_int
         _lib = L
     return _lib
+
+
+def _tuning_dict(t) -> dict:
+    return dict(block=t.block, tile=t.tile, grid=t.grid, ppt=t.ppt, deposit=t.deposit,
+                compact_every=t.compact_every, sort_bin=t.sort_bin, ms_per_step=t.ms_per_step)
 
 
 class GapsimError(RuntimeError):
@@ -295,7 +306,7 @@ class GapSim:
             self._alloc = GsAllocator(ALLOC_FN(_a), RELEASE_FN(_r), None)
             alloc_p = C.byref(self._alloc)
         h = C.c_void_p()
-        rc = lib().gs_init(C.byref(h), self.G, arr, alloc_p, C.c_void_p(self.stream.cuda_stream))
+        rc = lib().gs_init_gap(C.byref(h), self.G, arr, alloc_p, C.c_void_p(self.stream.cuda_stream))
         if rc != GS_OK:
             raise GapsimError(rc, lib().gs_last_error(None).decode())
         self._h = h
@@ -412,8 +423,15 @@ class GapSim:
         t = GsTuning()
         self._chk(lib().gs_autotune(self._h, mode, guess, trial_steps,
                                     cache_path.encode() if cache_path else None, C.byref(t)))
-        return dict(block=t.block, tile=t.tile, grid=t.grid, ppt=t.ppt, deposit=t.deposit,
-                    compact_every=t.compact_every, ms_per_step=t.ms_per_step)
+        return _tuning_dict(t)
+
+    def launch(self) -> dict:
+        """gs_get_launch: the launch configuration in effect."""
+        t = GsTuning()
+        self._chk(lib().gs_get_launch(self._h, C.byref(t)))
+        d = _tuning_dict(t)
+        del d["ms_per_step"]
+        return d
 
     # -- Newton guess network -------------------------------------------------
     def mlp_set_weights(self, theta, norm):
@@ -475,7 +493,7 @@ class GapSim:
         self._chk(lib().gs_get_timing(self._h, C.byref(T), 1 if reset else 0))
         return dict(push_ms=T.push_ms, field_ms=T.field_ms, compact_ms=T.compact_ms,
                     push_launches=T.push_launches, field_launches=T.field_launches,
-                    compact_launches=T.compact_launches)
+                    compact_launches=T.compact_launches, emit_ms=T.emit_ms, emit_launches=T.emit_launches)
 
 
 def mlp_train(x, t, order, batch: int, theta, adam_m, adam_v, step0: int = 0, lr: float = 1e-3,

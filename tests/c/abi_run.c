@@ -45,9 +45,9 @@ int main(int argc, char **argv) {
     return 2;
   }
   gs_ctx *ctx = NULL;
-  gs_status st = gs_init(&ctx, 1, &p, NULL, NULL);
+  gs_status st = gs_init_gap(&ctx, 1, &p, NULL, NULL);
   if (st != GS_OK) {
-    fprintf(stderr, "gs_init: %d %s\n", (int)st, gs_last_error(NULL));
+    fprintf(stderr, "gs_init_gap: %d %s\n", (int)st, gs_last_error(NULL));
     return 1;
   }
   /* particle file: for species 0 then 1, an int64 count n and n x then n v (binary64) */

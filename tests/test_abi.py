@@ -82,15 +82,15 @@ def test_init_rejects_bad_arguments_without_touching_a_device():
     h = C.c_void_p()
     arr = (gapsim.GsGapParams * 1)()
     arr[0] = gapsim.params_from(W.config1(n_cells=1), 64, (10, 10))
-    rc = lib.gs_init(C.byref(h), 1, arr, None, None)
+    rc = lib.gs_init_gap(C.byref(h), 1, arr, None, None)
     assert rc == gapsim.GS_EINVAL and not h.value
     assert b"n_cells" in lib.gs_last_error(None)
-    rc = lib.gs_init(C.byref(h), 0, arr, None, None)
+    rc = lib.gs_init_gap(C.byref(h), 0, arr, None, None)
     assert rc == gapsim.GS_EINVAL
     mixed = (gapsim.GsGapParams * 2)()
     mixed[0] = gapsim.params_from(W.config1(), 64, (10, 10))
     mixed[1] = gapsim.params_from(W.config1(), 32, (10, 10))
-    assert lib.gs_init(C.byref(h), 2, mixed, None, None) == gapsim.GS_EINVAL
+    assert lib.gs_init_gap(C.byref(h), 2, mixed, None, None) == gapsim.GS_EINVAL
     assert b"particle_fp" in lib.gs_last_error(None)
 
 

@@ -56,8 +56,9 @@ def test_full_size_sampled_push_and_invariants(name):
     sim.step(spec["mode"], warm)
     da = sim.diag(0)
     xa, ua, ida = sim.particles(0, 1)
+    xea, _, _ = sim.particles(0, 0)
     n_el_a = int(da["n_live"][0])
-    assert da["n_live"][1] == len(xa)
+    assert da["n_live"][1] == len(xa) and n_el_a == len(xea)
 
     sim.step(spec["mode"], 1)  # solves level `warm` from these particles, then pushes them
     db = sim.diag(0)
@@ -87,6 +88,21 @@ def test_full_size_sampled_push_and_invariants(name):
     s0 = cfg.weight * cfg.q_unit
     expect = cfg.area * s0 * (cfg.Z[1] * len(xa) + cfg.Z[0] * (n_el_a + deferred))
     assert abs(db["q_space"] - expect) <= 1e-12 * abs(expect)
+    # and node by node: the oracle's binary32 deposit (App. C weights, doubled
+    # electrode nodes) of those particles, plus any electrons emitted on the wall
+    # nodes before the density was formed
+    N, dx = cfg.n_cells, cfg.d / cfg.n_cells
+    acc = oracle.deposit32(N, cfg.Z[1], xa)
+    oracle.deposit32(N, cfg.Z[0], xea, acc)
+    late = (db["emit_cum"] - da["emit_cum"]) - db["emit_step"]
+    acc[0] += cfg.Z[0] * (1 << 24) * int(late[0])
+    acc[N] += cfg.Z[0] * (1 << 24) * int(late[1])
+    rho_o = s0 * (acc.astype(np.float64) * 2.0**-24) / dx
+    rho_o[0] *= 2.0
+    rho_o[N] *= 2.0
+    np.testing.assert_array_equal(rho, rho_o)
+    del acc, xea
+    print(f"{name}: density equal to the oracle's deposit at all {N + 1} nodes", flush=True)
 
     # the field table the push gathered from: surface field, E_{k+1/2}, ground field
     ehat = np.concatenate([[db["sigma"] / cfg.eps0], E, [db["e_ground"]]]).astype(np.float32)
@@ -147,6 +163,70 @@ def test_full_size_sampled_push_and_invariants(name):
         np.testing.assert_array_equal(gx[og], ox[oo])
         np.testing.assert_array_equal(gu[og], ou[oo])
         print(f"{name}: {len(ox)} secondary electrons of {gone.sum()} absorbed ions equal", flush=True)
+    sim.close()
+
+
+def test_full_size_beam_gap_end_to_end():
+    """The 4096-cell beam gap at full size (2e7 H+, 2e4 beam ions per step, weak
+    coupling, compaction every 32 steps, the benchmark's launch shape) stepped 50
+    times beside the oracle's binary32 mode on the same inputs: at every level the
+    absorbed, emitted and injected counts are equal and V, sigma, Q_circ and every
+    loop's current and charge agree within 1e-5 of their own scale; at the end phi,
+    E and rho agree within 1e-5 element-wise and both particle populations are the
+    same multisets."""
+    from paper_2603_24010_amd import gapsim as gs
+    beam, n0, steps = 20_000, 20_000_000, 50
+    cfg = W.config2(n_cells=4096, beam_per_step=beam)
+    loads = W.load_config2(n=n0, seed=2, d=cfg.d)
+    grow = (steps + 8) * beam
+    sim = gs.GapSim(cfg, particle_fp=32, capacity=((1 << 22) + grow, n0 + grow + (1 << 20)))
+    sim.set_option(gs.OPT_COMPACT_EVERY, 32)
+    orc = oracle.OracleSim(cfg, fp32=True)
+    for sp, (x, v) in loads.items():
+        sim.inject(0, sp, x, v)
+        orc.inject(sp, x, v)
+    del loads
+    print(f"end to end: {n0} H+ injected on both sides", flush=True)
+    recs = []
+    for n in range(steps):
+        sim.step_weak(1)
+        orc.step(oracle.WEAK, 1)
+        recs.append((sim.diag(0), orc.diag()))
+        if n % 10 == 9:
+            print(f"end to end: {n + 1} steps", flush=True)
+    for dg, do in recs:
+        assert dg["step"] == do["step"]
+        np.testing.assert_array_equal(dg["abs_cum"], do["abs_cum"])
+        np.testing.assert_array_equal(dg["emit_cum"], do["emit_cum"])
+        assert dg["inj_cum"] == do["inj_cum"]
+        np.testing.assert_array_equal(dg["n_live"], do["n_live"])
+    for key in ("phi0", "sigma", "qcirc", "qcirc_star", "q_space"):
+        g = np.array([d[key] for d, _ in recs])
+        o = np.array([od[key] for _, od in recs])
+        assert np.abs(g - o).max() <= 1e-5 * np.abs(o).max(), key
+    for key in ("I", "q"):
+        for j in range(cfg.n_mesh):
+            g = np.array([d[key][j] for d, _ in recs])
+            o = np.array([od[key][j] for _, od in recs])
+            assert np.abs(g - o).max() <= 1e-5 * np.abs(o).max(), (key, j)
+    pg, Eg, rg = sim.fields(0)
+    po, Eo, ro = orc.fields()
+    # element-wise, with the binary64 rounding floor of the two solves (prefix
+    # sums against Thomas, ~N eps of the largest value) where a value crosses zero
+    for name, a, b in (("phi", pg, po), ("E", Eg, Eo), ("rho", rg, ro)):
+        err = np.abs(a - b)
+        bound = 1e-5 * np.abs(b) + 4096 * 2.0**-52 * np.abs(b).max()
+        assert np.all(err <= bound), (name, float((err / bound).max()))
+    d = recs[-1][0]
+    assert d["abs_cum"][1].sum() > 10_000 and d["emit_cum"].sum() > 1000 and d["inj_cum"] == steps * beam
+    for sp in (0, 1):
+        xg, ug, _ = sim.particles(0, sp)
+        xo, uo, _ = orc.particles_f32(sp)
+        assert len(xg) == len(xo)
+        og, oo = np.lexsort((ug, xg)), np.lexsort((uo, xo))
+        np.testing.assert_array_equal(xg[og], xo[oo])
+        np.testing.assert_array_equal(ug[og], uo[oo])
+    print(f"end to end: 50 levels, fields and {int(d['n_live'].sum())} particles equal", flush=True)
     sim.close()
 
 

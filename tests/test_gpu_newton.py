@@ -69,7 +69,7 @@ def test_newton_one_correction_reaches_the_direct_solve(which, floor):
     orc, ods = _oracle_strict(cfg, loads, n)
     sim, nds = _run(cfg, loads, n, gs.GUESS_EXTRAP, fp32=False,
                     opts={gs.OPT_NEWTON_TOL: 1, gs.OPT_NEWTON_MAXIT: 1})
-    check_run(list(zip(nds, ods)), 1e-12, cfg.n_mesh)
+    check_run(list(zip(nds, ods)), 1e-12, cfg.n_mesh, cfg, oracle.STRICT)
     check_fields(sim, orc, 1e-12)
     its = np.array([d["newton_last"] for d in nds])
     res = np.array([d["newton_resid"] for d in nds])

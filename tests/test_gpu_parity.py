@@ -62,21 +62,87 @@ def assert_counts_equal(dg, do):
     assert dg["pushed_cum"] == do["pushed_cum"]
 
 
-def check_run(recs, tol, M):
+EPS64 = 2.0 ** -52
+
+
+def loop_rounding_floor(cfg, recs, mode):
+    """Per level and loop, a bound on how far two correct binary64 evaluations of
+    the loop increments D^n = q^n - q^{n-1} can differ.
+
+    The library forms D_j as a sum of products, T^-1 times the BDF2 right-hand
+    side (L h / (4 dt^2) + R D^{n-1} / (2 dt) - S q^{n-1} + b V_s, with
+    h = 15 D^{n-1} - 7 D^{n-2} + D^{n-3}), minus z_j phi0 in strict mode, where
+    T = 9 L / (4 dt^2) + 3 R / (2 dt) + S (in weak mode with the gap capacitor on
+    the gap loop's diagonal) and z = T^-1 e_gap.  Its rounding is at most a few
+    ulps of the sum of the terms' magnitudes, (3M + 4) eps times
+    |T^-1| (|L| |h| / (4 dt^2) + |R| |D^{n-1}| / (2 dt) + |S| |q^{n-1}|) + |T^-1 b| |V_s|
+    + |z| |phi0|, and in strict mode the two sides' electrode potentials differ by
+    the measured |dphi0|, which moves D by |z| |dphi0|.  A loop whose increment is
+    a near-cancellation of much larger terms (a loop closed by a large resistor)
+    can only be held to this floor; for the others it is far below tol.
+    Returns (floor of I, floor of q) as arrays [level, loop]."""
+    M, g, dt = cfg.n_mesh, cfg.gap_mesh, cfg.dt
+    L, R, S = (np.abs(np.asarray(a, dtype=np.float64)).reshape(M, M) for a in (cfg.L, cfg.R, cfg.S))
+    T = 9 * np.asarray(cfg.L, dtype=np.float64).reshape(M, M) / (4 * dt * dt) \
+        + 3 * np.asarray(cfg.R, dtype=np.float64).reshape(M, M) / (2 * dt) + np.asarray(cfg.S, dtype=np.float64).reshape(M, M)
+    if mode == oracle.WEAK:
+        cg = cfg.eps0 * cfg.area / cfg.d + cfg.c_par
+        T[g, g] += 1.0 / cg
+        S = S.copy()
+        S[g, g] += 1.0 / cg
+    Ti = np.linalg.inv(T)
+    Tia = np.abs(Ti)
+    bz = np.abs(Ti @ np.asarray(cfg.src, dtype=np.float64).reshape(M))
+    z = np.abs(Ti[:, g])
+    q_prev = np.asarray(cfg.q0, dtype=np.float64).reshape(M).copy()
+    Dh = [np.zeros(M), np.zeros(M), np.zeros(M)]  # D^{n-1}, D^{n-2}, D^{n-3}
+    c = (3 * M + 4) * EPS64
+    fD_prev = np.zeros(M)
+    fq = np.zeros(M)
+    fI_all, fq_all = [], []
+    for dg, do in recs:
+        t = do["t"]
+        Vs = cfg.src_dc + cfg.src_amp * math.sin(2 * math.pi * cfg.src_freq * t + cfg.src_phase)
+        h = 15 * Dh[0] - 7 * Dh[1] + Dh[2]
+        mag = Tia @ (L @ np.abs(h) / (4 * dt * dt) + R @ np.abs(Dh[0]) / (2 * dt) + S @ np.abs(q_prev)) \
+            + bz * abs(Vs) + z * abs(do["phi0"])
+        fD = c * mag
+        if mode == oracle.STRICT:
+            fD = fD + z * abs(dg["phi0"] - do["phi0"])
+        q = np.array([do["q"][j] for j in range(M)])
+        I = np.array([do["I"][j] for j in range(M)])
+        fI_all.append((3 * fD + fD_prev) / (2 * dt) + 4 * EPS64 * np.abs(I))
+        fq = fq + fD + 2 * EPS64 * np.abs(q)
+        fq_all.append(fq.copy())
+        fD_prev = fD
+        Dh = [q - q_prev, Dh[0], Dh[1]]
+        q_prev = q
+    return np.array(fI_all), np.array(fq_all)
+
+
+def check_run(recs, tol, M, cfg=None, mode=None):
     for dg, do in recs:
         assert dg["step"] == do["step"]
         assert_counts_equal(dg, do)
     for key in ("phi0", "sigma", "qcirc", "qcirc_star", "q_space"):
         r = _series_rel([d[key] for d, _ in recs], [o[key] for _, o in recs])
         assert r <= tol, (key, r)
-    # loop currents and charges norm-wise: the largest deviation over all loops
-    # against the largest value over all loops (a loop closed by a large
-    # resistor carries currents many orders below the others)
-    for key in ("I", "q"):
+    # loop currents and charges, each loop against its own scale; a loop may
+    # fall back on its derived binary64 rounding floor (consecutive levels only)
+    floors = loop_rounding_floor(cfg, recs, mode) if cfg is not None else (None, None)
+    for key, fl in (("I", floors[0]), ("q", floors[1])):
         g = np.array([[d[key][j] for j in range(M)] for d, _ in recs])
         o = np.array([[od[key][j] for j in range(M)] for _, od in recs])
-        r = _series_rel(g, o)
-        assert r <= tol, (key, r)
+        for j in range(M):
+            err = np.abs(g[:, j] - o[:, j])
+            scale = np.abs(o[:, j]).max()
+            if err.max() <= tol * scale:
+                continue
+            assert fl is not None, (key, j, float(err.max()), float(scale))
+            assert np.all(err <= tol * scale + fl[:, j]), \
+                (key, j, float(err.max()), float(scale), float((err / (tol * scale + fl[:, j])).max()))
+            print(f"loop {j} {key}: error {err.max():.3e} of scale {scale:.3e}, within the rounding floor "
+                  f"(max floor {fl[:, j].max():.3e})")
 
 
 def check_fields(sim, orc, tol):
@@ -102,7 +168,7 @@ def test_config1_fp64_parity(mode):
     # hotter load so that walls and emission are exercised within 50 steps
     loads = {s: (x, v * 30.0) for s, (x, v) in loads.items()}
     sim, orc, recs = run_pair(cfg, loads, mode, 50, False, (150000, 150000))
-    check_run(recs, 1e-12, cfg.n_mesh)
+    check_run(recs, 1e-12, cfg.n_mesh, cfg, mode)
     check_fields(sim, orc, 1e-12)
     d = recs[-1][0]
     assert d["abs_cum"].sum() > 100 and d["emit_cum"].sum() > 0
@@ -144,8 +210,8 @@ def test_paper_worked_value_on_gpu():
 @pytest.mark.parametrize("mode", [oracle.STRICT, oracle.WEAK])
 def test_vacuum_circuit_parity(make, mode):
     cfg = make()
-    sim, orc, recs = run_pair(cfg, {}, mode, 300, False, (16, 16), check_every=10)
-    check_run(recs, 1e-12, cfg.n_mesh)
+    sim, orc, recs = run_pair(cfg, {}, mode, 300, False, (16, 16))
+    check_run(recs, 1e-12, cfg.n_mesh, cfg, mode)
 
 
 # ---------------------------------------------------------------------------
@@ -155,14 +221,18 @@ def cfg2_small(n_cells=4096, beam=2000):
     return W.config2(n_cells=n_cells, beam_per_step=beam)
 
 
+@pytest.mark.parametrize("sort_bin", [0, 64])
 @pytest.mark.parametrize("mode", [oracle.WEAK, oracle.STRICT])
 @pytest.mark.parametrize("n_cells", [4096, 16384])
-def test_fp32_beam_gap_parity(mode, n_cells):
+def test_fp32_beam_gap_parity(mode, n_cells, sort_bin):
+    """With and without the periodic cell sort (bins of 64 cells): the sort only
+    reorders particles, so the bars are the same."""
     cfg = cfg2_small(n_cells=n_cells)
     loads = W.load_config2(n=200_000, seed=11)
-    opts = {_gapsim().OPT_COMPACT_EVERY: 7}
+    gs = _gapsim()
+    opts = {gs.OPT_COMPACT_EVERY: 7, gs.OPT_SORT_BIN: sort_bin}
     sim, orc, recs = run_pair(cfg, loads, mode, 50, True, (400_000, 600_000), opts=opts)
-    check_run(recs, 1e-5, cfg.n_mesh)
+    check_run(recs, 1e-5, cfg.n_mesh, cfg, mode)
     check_fields(sim, orc, 1e-5)
     d = recs[-1][0]
     assert d["abs_cum"][1].sum() > 100 and d["emit_cum"].sum() > 10 and d["inj_cum"] == 100_000
@@ -175,9 +245,10 @@ def test_fp32_beam_gap_parity(mode, n_cells):
         np.testing.assert_array_equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("sort_bin", [0, 16])
 @pytest.mark.parametrize("mode", [oracle.STRICT, oracle.WEAK])
 @pytest.mark.parametrize("layer", [2e-3, 0.0])
-def test_fp32_tesla_ground_pulse_parity(mode, layer):
+def test_fp32_tesla_ground_pulse_parity(mode, layer, sort_bin):
     """The paper's integrated-run shape (Sec. 4.2): five-loop Tesla circuit, ions
     entering next to the grounded electrode by a Gaussian schedule (here early and
     short, so that 80 steps see it rise and fall), emission on."""
@@ -186,9 +257,10 @@ def test_fp32_tesla_ground_pulse_parity(mode, layer):
     # them within the 1152 events a workgroup emits in the same step
     sched = W.gaussian_schedule(80, 3000.0 if layer > 0 else 500.0, 35.0, 10.0)
     cfg = W.config_tesla(layer=layer).replace(beam_schedule=sched, see_amp=30.0)
-    opts = {_gapsim().OPT_COMPACT_EVERY: 9}
+    gs = _gapsim()
+    opts = {gs.OPT_COMPACT_EVERY: 9, gs.OPT_SORT_BIN: sort_bin}
     sim, orc, recs = run_pair(cfg, {}, mode, 80, True, (200_000, 200_000), opts=opts)
-    check_run(recs, 1e-5, cfg.n_mesh)
+    check_run(recs, 1e-5, cfg.n_mesh, cfg, mode)
     check_fields(sim, orc, 1e-5)
     d = recs[-1][0]
     assert d["inj_cum"] == int(sched.sum())
@@ -214,7 +286,7 @@ def test_fp32_paper_see_laws_parity(mode):
     loads = W.load_config2(n=200_000, seed=12)
     opts = {_gapsim().OPT_COMPACT_EVERY: 7}
     sim, orc, recs = run_pair(cfg, loads, mode, 50, True, (400_000, 600_000), opts=opts)
-    check_run(recs, 1e-5, cfg.n_mesh)
+    check_run(recs, 1e-5, cfg.n_mesh, cfg, mode)
     check_fields(sim, orc, 1e-5)
     d = recs[-1][0]
     assert d["abs_cum"][1].sum() > 100 and d["emit_cum"].sum() > 100, (d["abs_cum"], d["emit_cum"])
@@ -228,32 +300,58 @@ def test_fp32_paper_see_laws_parity(mode):
     sim.close()
 
 
-def test_fp32_error_against_fp64_oracle():
-    """What binary32 particles cost, stated against the binary64 oracle (no bar
-    beyond staying small over 50 steps)."""
-    cfg = cfg2_small(n_cells=4096, beam=2000)
-    loads = W.load_config2(n=200_000, seed=12)
+@pytest.mark.parametrize("mode", [oracle.WEAK, oracle.STRICT])
+@pytest.mark.parametrize("n_cells", [4096, 16384])
+def test_fp32_error_against_fp64_oracle(mode, n_cells):
+    """What binary32 particles cost against the binary64 oracle over the 50-step
+    horizon: phi and E at the end, and V, sigma, Q_circ and every loop's current
+    and charge at every level, within 1e-5 relative (each against its own scale);
+    absorbed counts equal.  The nodal density is the deposit of positions held in
+    binary32 (a position one ulp away moves weight between two nodes), so it is
+    stated, not held to the bar: the bar is on what the field and the circuit see.
+    2e6 ions: the field's rounding noise is an average over them.  Absorbed
+    counts may differ by an ion grazing a wall (a few at most)."""
+    cfg = cfg2_small(n_cells=n_cells, beam=2000)
+    loads = W.load_config2(n=2_000_000, seed=12)
     gs = _gapsim()
-    sim = gs.GapSim(cfg, particle_fp=32, capacity=(400_000, 600_000))
+    sim = gs.GapSim(cfg, particle_fp=32, capacity=(600_000, 2_400_000))
+    sim.set_option(gs.OPT_COMPACT_EVERY, 16)
     orc = oracle.OracleSim(cfg, fp32=False)
     for sp, (x, v) in loads.items():
         sim.inject(0, sp, x, v)
         orc.inject(sp, x, v)
-    sim.step_weak(50)
-    orc.step(oracle.WEAK, 50)
-    _, Eg, _ = sim.fields(0)
-    _, Eo, _ = orc.fields()
-    err = rel(Eg, Eo)
-    dg, do = sim.diag(0), orc.diag()
-    print(f"binary32 vs binary64 after 50 steps: E {err:.2e}, phi0 "
-          f"{abs(dg['phi0'] - do['phi0']) / abs(do['phi0']):.2e}")
-    assert err < 1e-3
+    recs = []
+    for _ in range(50):
+        sim.step(mode, 1)
+        orc.step(mode, 1)
+        recs.append((sim.diag(0), orc.diag()))
+    pg, Eg, rg = sim.fields(0)
+    po, Eo, ro = orc.fields()
+    errs = {"phi": rel(pg, po), "E": rel(Eg, Eo)}
+    for key in ("phi0", "sigma", "qcirc", "qcirc_star"):
+        errs[key] = _series_rel([d[key] for d, _ in recs], [o[key] for _, o in recs])
+    for key in ("I", "q"):
+        for j in range(cfg.n_mesh):
+            errs[f"{key}{j}"] = _series_rel([d[key][j] for d, _ in recs], [o[key][j] for _, o in recs])
+    print(f"binary32 vs binary64, {n_cells} cells, {'weak' if mode else 'strict'}, 50 steps: "
+          + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()) + f"; nodal rho {rel(rg, ro):.2e}")
+    for k, v in errs.items():
+        assert v <= 1e-5, (k, v)
+    # absorbed counts: an ion that grazes a wall can be absorbed one step apart
+    # in the two precisions (counts are bit-exact against the oracle's binary32
+    # mode, the other parity tests); here they may differ by a few
+    dmax = max(int(np.abs(dg["abs_cum"] - do["abs_cum"]).max()) for dg, do in recs)
+    print(f"largest absorbed-count difference at one level: {dmax}")
+    assert dmax <= 3
+    assert recs[-1][0]["abs_cum"][1].sum() > 1000
+    sim.close()
 
 
 # ---------------------------------------------------------------------------
 # several gaps in one context
 # ---------------------------------------------------------------------------
-def test_batched_gaps_parity():
+@pytest.mark.parametrize("sort_bin", [0, 8])
+def test_batched_gaps_parity(sort_bin):
     gs = _gapsim()
     G = 6
     cfgs, loads = [], []
@@ -263,6 +361,7 @@ def test_batched_gaps_parity():
         loads.append(W.load_config4_gap(n_p, e_b, g))
     sim = gs.GapSim(cfgs, particle_fp=32, capacity=(200_000, 200_000))
     sim.set_option(gs.OPT_COMPACT_EVERY, 5)
+    sim.set_option(gs.OPT_SORT_BIN, sort_bin)
     orcs = []
     for g in range(G):
         o = oracle.OracleSim(cfgs[g], fp32=True)
@@ -277,7 +376,7 @@ def test_batched_gaps_parity():
             orcs[g].step(oracle.STRICT, 1)
             recs[g].append((sim.diag(g), orcs[g].diag()))
     for g in range(G):
-        check_run(recs[g], 1e-5, cfgs[g].n_mesh)
+        check_run(recs[g], 1e-5, cfgs[g].n_mesh, cfgs[g], oracle.STRICT)
 
 
 # ---------------------------------------------------------------------------
@@ -315,6 +414,10 @@ def test_launch_shapes_and_graph_agree():
         {gs.OPT_COMPACT_EVERY: 2, gs.OPT_BLOCK: 256, gs.OPT_TILE: 256 * 24, gs.OPT_DEPOSIT: 2,
          gs.OPT_COMPACT_GRID: 3},
         {gs.OPT_COMPACT_EVERY: 4, gs.OPT_GRAPH: 1, gs.OPT_DEPOSIT: 2, gs.OPT_GRID: 33},
+        {gs.OPT_COMPACT_EVERY: 8, gs.OPT_SORT_BIN: 16},
+        {gs.OPT_COMPACT_EVERY: 3, gs.OPT_SORT_BIN: 4, gs.OPT_BLOCK: 512, gs.OPT_COMPACT_GRID: 5},
+        {gs.OPT_COMPACT_EVERY: 5, gs.OPT_SORT_BIN: 1024, gs.OPT_GRAPH: 1, gs.OPT_DEPOSIT: 2},
+        {gs.OPT_COMPACT_EVERY: 1, gs.OPT_SORT_BIN: 64, gs.OPT_PPT: 2, gs.OPT_GRID: 13},
     ]
     for opts in variants:
         d, E, ions, els = _cfg2_state(opts)
@@ -331,6 +434,53 @@ def test_run_to_run_bitwise_identical():
     b = _cfg2_state({gs.OPT_COMPACT_EVERY: 4}, seed=5)
     np.testing.assert_array_equal(a[1], b[1])
     np.testing.assert_array_equal(a[2][0], b[2][0])
+
+
+@pytest.mark.parametrize("fp32", [True, False])
+@pytest.mark.parametrize("sort_bin", [4, 16, 100])
+def test_cell_sort_orders_by_bin(sort_bin, fp32):
+    """Right after a sort every region holds its live particles in increasing
+    bin (cells // sort_bin, the last bin taking the electrode node), none lost:
+    the ids of the live set are those before the sort."""
+    gs = _gapsim()
+    cfg = cfg2_small(n_cells=1000, beam=700)
+    loads = W.load_config2(n=60_000, seed=4)
+    sim = gs.GapSim(cfg, particle_fp=32 if fp32 else 64, capacity=(100_000, 100_000))
+    sim.set_option(gs.OPT_COMPACT_EVERY, 6)
+    sim.set_option(gs.OPT_SORT_BIN, sort_bin)
+    for sp, (x, v) in loads.items():
+        sim.inject(0, sp, x, v)
+    sim.step_weak(6)  # the sixth step ends with the sort
+    nb = -(-cfg.n_cells // sort_bin)
+    for sp in (0, 1):
+        x, u, ids = sim.particles(0, sp)
+        assert len(x) == sim.diag(0)["n_live"][sp]
+        b = np.minimum(np.floor(x).astype(np.int64) // sort_bin, nb - 1)
+        assert np.all(np.diff(b) >= 0), sp
+        if sp == 1:
+            assert len(np.unique(ids)) == len(ids) > 50_000
+    sim.close()
+
+
+def test_emission_kernel_emits_within_the_step():
+    """With the cell sort on, the ions a push absorbs past its LDS queue are
+    emitted by the emission kernel in the same step: the emitted counts equal
+    the oracle's at every level (no lag), as do voltages and fields."""
+    gs = _gapsim()
+    sched = W.gaussian_schedule(60, 3000.0, 30.0, 8.0)
+    cfg = W.config_tesla(layer=0.0).replace(beam_schedule=sched, see_amp=30.0)
+    sim, orc, recs = run_pair(cfg, {}, oracle.STRICT, 60, True, (200_000, 200_000),
+                              opts={gs.OPT_SORT_BIN: 8, gs.OPT_COMPACT_EVERY: 4})
+    check_run(recs, 1e-5, cfg.n_mesh, cfg, oracle.STRICT)
+    check_fields(sim, orc, 1e-5)
+    assert recs[-1][0]["emit_cum"].sum() > 1000
+    sim.close()
+    # the same run without the sort: the push's own queues overflow and part of
+    # the emission lags into the next step, so the events did pass the queue
+    sim, _, recs = run_pair(cfg, {}, oracle.STRICT, 60, True, (200_000, 200_000),
+                            opts={gs.OPT_COMPACT_EVERY: 4})
+    assert any(dg["emit_cum"].sum() < do["emit_cum"].sum() for dg, do in recs)
+    sim.close()
 
 
 def test_empty_and_edge_particles():
@@ -453,7 +603,7 @@ def test_two_cell_gap_parity(fp32):
     loads = W.load_config1(n_per_species=500, seed=17, d=d_gap)
     loads = {s: (x, v * 30.0) for s, (x, v) in loads.items()}
     sim, orc, recs = run_pair(cfg, loads, oracle.STRICT, 30, fp32, (20_000, 20_000))
-    check_run(recs, 1e-5 if fp32 else 1e-12, cfg.n_mesh)
+    check_run(recs, 1e-5 if fp32 else 1e-12, cfg.n_mesh, cfg, oracle.STRICT)
     check_fields(sim, orc, 1e-5 if fp32 else 1e-12)
     d = recs[-1][0]
     assert d["abs_cum"][0].sum() > 100 and d["abs_cum"][1].sum() > 10 and d["inj_cum"] == 90, d["abs_cum"]
