@@ -418,8 +418,10 @@ static gs_status setup(gs_ctx *ctx) {
   // the field kernel reads and writes directly (16 bytes per gap)
   {
     void *h = nullptr, *dptr = nullptr;
-    if (hipHostMalloc(&h, (size_t)G * 16, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess || !h)
-      return fail(ctx, GS_ENOMEM, "pinned host allocation of %zu bytes failed", (size_t)G * 16);
+    const hipError_t eh = hipHostMalloc(&h, (size_t)G * 16, hipHostMallocMapped | hipHostMallocCoherent);
+    if (eh != hipSuccess || !h)
+      return fail(ctx, GS_ENOMEM, "pinned host allocation of %zu bytes failed: %s", (size_t)G * 16,
+                  hipGetErrorString(eh));
     ctx->ext_host = (double *)h;
     memset(h, 0, (size_t)G * 16);
     HIPCHK(ctx, hipHostGetDevicePointer(&dptr, h, 0));

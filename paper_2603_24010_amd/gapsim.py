@@ -132,6 +132,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2603_24010_amd/build.py")
+        # torch carries its own HIP runtime beside the system one the library
+        # links: torch's must have found the GPU before the library is loaded,
+        # or the library's runtime finds none (no effect on a machine without one)
+        import torch
+        torch.cuda.is_available()
         L = C.CDLL(LIB_PATH)
         vp, P = C.c_void_p, C.POINTER(C.c_double)
         L.gs_init_gap.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(GsGapParams), C.POINTER(GsAllocator), vp]
