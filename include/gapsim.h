@@ -241,6 +241,21 @@ void gs_destroy(gs_ctx *ctx);
 gs_status gs_inject(gs_ctx *ctx, int32_t gap, int32_t species, int64_t n, const double *x,
                     const double *v, int32_t ptr_is_device);
 
+/* For callers that cannot allocate device memory (serving loops that inject
+ * every step, harnesses that forbid hipMalloc): gs_inject for host arrays x, v
+ * (n doubles each, same meaning and checks) that allocates nothing.  gs_inject
+ * with host arrays allocates a device staging buffer per call; this copies them
+ * through a staging array the library holds on each device for the life of
+ * the process (2 * GS_INJECT_NOALLOC_MAX doubles, 8 MiB), so n is at most
+ * GS_INJECT_NOALLOC_MAX (GS_EINVAL beyond).  Device arrays need no staging:
+ * use gs_inject with ptr_is_device = 1.  Synchronises the context's stream
+ * before returning.  Every context on one device shares the array: calls that
+ * overlap in time on one device (from several threads or streams) race.
+ * Errors: as gs_inject; GS_ESTATE if the array could not be set up. */
+#define GS_INJECT_NOALLOC_MAX (1 << 19)
+gs_status gs_inject_noalloc(gs_ctx *ctx, int32_t gap, int32_t species, int64_t n, const double *x,
+                            const double *v);
+
 /* Advance every gap n_steps steps with strict coupling (Sec. 2.4.2): the circuit
  * charge is an affine function of the electrode potential, eq. Q4_phi_relation,
  * folded into the first Poisson row (eq. Poisson_BC2) and solved in one pass.

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -20,6 +21,16 @@
 using namespace gs;
 
 static thread_local std::string g_init_error;
+
+// Staging array of gs_inject_noalloc: x then v of at most GS_INJECT_NOALLOC_MAX
+// particles, in binary64.  Every device the library runs on holds its own copy
+// until the process ends; host code uses the address hipGetSymbolAddress gives
+// for the current device (looked up once per device at context set-up), never
+// the array's name.  All calls on one device share it.
+static __device__ __align__(256) double scratch[2 * GS_INJECT_NOALLOC_MAX];
+static std::mutex g_scratch_mu;
+constexpr int SCRATCH_DEVS = 64;
+static void *g_scratch_dev[SCRATCH_DEVS];
 
 struct gs_ctx {
   int G = 0;
@@ -50,6 +61,7 @@ struct gs_ctx {
   std::vector<std::vector<int64_t>> sched;  // per gap: copy of the beam schedule (empty: none)
   std::vector<int> sched_on;                // per gap: the schedule is in force
   double *ext_host = nullptr;               // pinned, mapped: [G] engine voltages, [G] field potentials
+  void *scratch = nullptr;                  // this device's staging array of gs_inject_noalloc
   hipEvent_t ext_ev = nullptr;              // recorded after each external-mode field solve
   std::string err;
   int sticky = 0;  // gs_status of a device error already seen
@@ -514,6 +526,22 @@ static bool launch_fits(const gs_ctx *ctx) {
   return push_lds_total(ctx, ctx->lc.wide, ctx->lc.block) <= 163840;
 }
 
+// the staging array's address on the context's device (current during set-up)
+static gs_status scratch_setup(gs_ctx *ctx) {
+  if (ctx->device < 0 || ctx->device >= SCRATCH_DEVS)
+    return fail(ctx, GS_EDEVICE, "device %d: no staging array slot", ctx->device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[ctx->device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(ctx, GS_EDEVICE, "hipGetSymbolAddress(staging array): %s", hipGetErrorString(e));
+    g_scratch_dev[ctx->device] = ptr;
+  }
+  ctx->scratch = g_scratch_dev[ctx->device];
+  return GS_OK;
+}
+
 extern "C" gs_status gs_init_gap(gs_ctx **out, int32_t n_gaps, const gs_gap_params *params,
                              const gs_allocator *alloc, void *hip_stream) {
   if (!out) return fail(nullptr, GS_EINVAL, "out is NULL");
@@ -554,6 +582,7 @@ extern "C" gs_status gs_init_gap(gs_ctx **out, int32_t n_gaps, const gs_gap_para
     return fail(nullptr, GS_EINVAL, "grid of %d cells with %d gaps exceeds the 160 KiB LDS budget", nm, n_gaps);
   }
   gs_status st = setup(ctx);
+  if (st == GS_OK) st = scratch_setup(ctx);
   if (st != GS_OK) {
     g_init_error = ctx->err;
     if (ctx->ext_ev) (void)hipEventDestroy(ctx->ext_ev);
@@ -637,6 +666,34 @@ extern "C" gs_status gs_inject(gs_ctx *ctx, int32_t gap, int32_t species, int64_
     (void)hipFree(tmp);
   }
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "inject launch: %s", hipGetErrorString(e));
+  return check_sticky(ctx, true);
+}
+
+extern "C" gs_status gs_inject_noalloc(gs_ctx *ctx, int32_t gap, int32_t species, int64_t n, const double *x,
+                                       const double *v) {
+  if (!ctx) return GS_ESTATE;
+  if (gap < 0 || gap >= ctx->G || species < 0 || species > 1 || n < 0)
+    return fail(ctx, GS_EINVAL, "bad gap, species or count");
+  if (n > GS_INJECT_NOALLOC_MAX)
+    return fail(ctx, GS_EINVAL, "gs_inject_noalloc takes at most %d particles per call (got %lld)",
+                GS_INJECT_NOALLOC_MAX, (long long)n);
+  if (n == 0) return GS_OK;
+  if (!x || !v) return fail(ctx, GS_EINVAL, "x and v must not be NULL");
+  if (!ctx->scratch) return fail(ctx, GS_ESTATE, "no staging array on this context's device");
+  gs_status st = check_sticky(ctx, false);
+  if (st != GS_OK) return st;
+  const double d = ctx->params[gap].d;
+  for (int64_t i = 0; i < n; ++i)
+    if (!(x[i] >= 0.0 && x[i] <= d) || !std::isfinite(v[i]))
+      return fail(ctx, GS_EINVAL, "particle %lld: x outside [0, d] or v not finite", (long long)i);
+  double *xs = (double *)ctx->scratch;
+  double *vs = xs + n;
+  HIPCHK(ctx, hipMemcpyAsync(xs, x, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(vs, v, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream));
+  hipError_t e = launch_inject(ctx->dp, gap, species, n, xs, vs, ctx->next_id[gap], ctx->fp64, ctx->stream);
+  ctx->next_id[gap] += n;
+  if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "inject launch: %s", hipGetErrorString(e));
+  // synchronises: the staging array is free again when the call returns
   return check_sticky(ctx, true);
 }
 

@@ -31,7 +31,7 @@ EXPORTED = [
     "gs_read_particles", "gs_set_option", "gs_get_timing", "gs_validate_params", "gs_last_error",
     "gs_version", "gs_mlp_set_weights", "gs_mlp_forward", "gs_mlp_record", "gs_mlp_train_workspace",
     "gs_mlp_train", "gs_autotune", "gs_step_weak_external", "gs_circuit_resonance", "gs_dt_check",
-    "gs_get_launch",
+    "gs_get_launch", "gs_inject_noalloc",
 ]
 MLP_IN, MLP_OUT, MLP_NPARAM, MLP_NORM = 48, 3, 39683, 102
 
@@ -176,6 +176,8 @@ def lib():
         L.gs_mlp_train.restype = C.c_int
         L.gs_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_char_p, C.POINTER(GsTuning)]
         L.gs_autotune.restype = C.c_int
+        L.gs_inject_noalloc.argtypes = [vp, C.c_int32, C.c_int32, C.c_int64, vp, vp]
+        L.gs_inject_noalloc.restype = C.c_int
         L.gs_get_launch.argtypes = [vp, C.POINTER(GsTuning)]
         L.gs_get_launch.restype = C.c_int
         L.gs_step_weak_external.argtypes = [vp, C.c_int32, CIRCUIT_FN, vp]
