@@ -221,6 +221,10 @@ def run_batched(args, name, copy_gbs):
     step(args.warmup)
     tuning = sim.autotune(0, gapsim.GUESS_DIRECT, trial_steps=8)
     log(f"[bench] autotuned: {tuning}")
+    if args.sort_bin >= 0:
+        # compare one sort setting against the tuned shape
+        sim.set_option(gapsim.OPT_SORT_BIN, args.sort_bin)
+        tuning = dict(tuning, sort_bin=args.sort_bin, forced="sort_bin")
     sim.set_option(gapsim.OPT_GRAPH, 1)
     torch.cuda.synchronize()
     p0 = pushed_total(sim)
@@ -248,7 +252,7 @@ def run_batched(args, name, copy_gbs):
                      "avg_launch_ms": tm["push_ms"] / max(1, tm["push_launches"]), "copy_GBps": copy_gbs,
                      "measured_over": "64 eager steps after the timed region, HIP events recorded by each "
                                       "kernel's dispatch"},
-        "kernel_ms_per_step": {k[:-3]: tm[k] / 64 for k in ("push_ms", "field_ms", "compact_ms")},
+        "kernel_ms_per_step": {k[:-3]: tm[k] / 64 for k in ("push_ms", "field_ms", "compact_ms", "emit_ms")},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batched(spec, 4 * args.cpu_steps)

@@ -357,10 +357,8 @@ gs_status gs_dt_check(gs_ctx *ctx, int32_t gap, gs_dt_report *out);
  * GS_ENOCONV once after a strict Newton solve missed its tolerance (the outputs
  * are filled and the state stays valid: the last iterate was used).
  * Emission timing: the secondaries of the ions absorbed in a step are emitted
- * within that step, except when one push workgroup absorbs more than 1152 ions
- * in a step; the excess is emitted at the start of the next step, before any
- * particle moves (the physics is the same), so the emitted counts and the
- * electron population read in between lag by those electrons. */
+ * within that step (by the push workgroup that absorbed them, or, past what it
+ * can hold, by the emission kernel right after the push). */
 gs_status gs_read_diagnostics(gs_ctx *ctx, int32_t gap, gs_diag *out, double *phi, double *E,
                               double *rho);
 

@@ -412,6 +412,12 @@ static gs_status setup(gs_ctx *ctx) {
   }
   ALLOC(d.next_count, unsigned long long *, (size_t)G * 2 * 8);
   ALLOC(d.cursor, unsigned long long *, (size_t)G * 2 * 8);
+  ALLOC(d.fill_h, unsigned long long *, (size_t)G * 2 * 8);
+  // in-place compaction: a live bit per slot, and per-tile counters (a region
+  // of cap slots has far fewer tiles of 65536 slots than words of 64), both
+  // indexed from the region's pbase / 64
+  ALLOC(d.tcnt, int *, (slots / 64 + 1) * 4);
+  ALLOC(d.live, unsigned long long *, (slots / 64 + 1) * 8);
   ALLOC(d.tally, unsigned long long *, (size_t)G * T_N * 8);
   ALLOC(d.acc, unsigned long long *, nodes * 8);
   ALLOC(d.rho64, double *, nodes * 8);
@@ -729,17 +735,18 @@ static int64_t beam_at(const gs_ctx *ctx, int g, int64_t n) {
   return n >= 0 && n < (int64_t)s.size() ? s[(size_t)n] : 0;
 }
 
-// The push, and with the cell sort on the emission kernel after it: sorted
-// particles put a wall's impacts into few workgroups, so the push queues
-// nothing past its LDS queue (no per-workgroup overflow regions) and the gap
-// lists are emitted by many workgroups.
+// The push, then, when a gap emits, the emission kernel: the ions a push
+// workgroup absorbs past what it can emit itself (its LDS queue and overflow
+// region) wait in the gap's list, and k_emit emits them with many workgroups
+// in the same step, so the emitted counts of a level never lag.  With the cell
+// sort on, a wall's impacts sit in few workgroups: the push then keeps only its
+// LDS queue and leaves the rest to k_emit.
 static hipError_t launch_push_emit(gs_ctx *ctx, hipStream_t s, bool timing) {
   DevPtrs dp = ctx->dp;
-  const bool sep = ctx->lc.sort_bin > 0 && ctx->emits;
-  if (sep) dp.ovf_wgs = 0;
+  if (ctx->lc.sort_bin > 0) dp.ovf_wgs = 0;
   auto push = [&](KTime t) { return launch_push(dp, ctx->G, ctx->lc, s, t); };
   hipError_t e = timing ? timed(ctx, 0, push) : push(KTime{});
-  if (e != hipSuccess || !sep) return e;
+  if (e != hipSuccess || !ctx->emits) return e;
   auto emit = [&](KTime t) { return launch_emit(ctx->dp, ctx->G, ctx->fp64, std::max(ctx->ncu, 1), s, t); };
   return timing ? timed(ctx, 3, emit) : emit(KTime{});
 }

@@ -113,7 +113,7 @@ struct DevPtrs {
   void *X[2], *U[2];
   uint32_t *ID[2];
   unsigned long long *next_count;  // [G][2] append cursor
-  unsigned long long *cursor;      // [G][2] compaction destination cursor
+  unsigned long long *cursor;      // [G][2] slot count after the compaction or sort in progress
   unsigned long long *tally;       // [G][T_N]
   unsigned long long *acc;         // node charge accumulators, int64 two's complement
   double *rho64, *E64, *phi64;     // node / half-grid / node arrays (nbase offsets; E uses nbase too)
@@ -125,6 +125,11 @@ struct DevPtrs {
   unsigned long long *ev_done;     // [G] events of the list already emitted by k_emit
   // periodic cell sort: live particles per bin, then per-bin write cursors
   unsigned long long *hist, *bcur;
+  // in-place compaction: live particles per tile (then their prefix), at
+  // tcnt[pbase / 64 + k] for tile k of a region; holes below the live count
+  int *tcnt;
+  unsigned long long *fill_h;  // [G][2]
+  unsigned long long *live;    // a bit per slot, 64 per word from pbase / 64
   const int64_t *sched;            // beam schedules of all gaps (GapConst::sched_base)
   // exchange with an external circuit engine (field mode 2), in pinned host
   // memory the device maps: ext_v[g] the engine's gap voltage for the level
@@ -151,7 +156,7 @@ enum { ERR_CAPACITY = 1u, ERR_BADINJECT = 2u, ERR_NOCONV = 4u };
 constexpr int SORT_BIN_MIN = 4;
 
 // Absorbed-ion events a push workgroup keeps in its global overflow region
-// (past these they go to the gap's list, emitted by the next field solve).
+// (past these they go to the gap's list, emitted by k_emit after the push).
 constexpr int OVQ = 1024;
 
 struct LaunchCfg {

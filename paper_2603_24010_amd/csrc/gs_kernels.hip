@@ -305,7 +305,9 @@ __device__ void see_emit(const DevPtrs &p, const GapConst &c, long long level, i
 // k_field: level n of one gap per workgroup
 // ---------------------------------------------------------------------------
 constexpr int FBS = 1024;
-// n_cells <= 16384: S_k of every cell is held in LDS (128 KiB at the maximum)
+// n_cells <= 16384: S_k of every cell is held in LDS (136 KiB at the maximum,
+// padded), and each thread forms at most FNQ nodes
+constexpr int FNQ = (16384 + 1 + FBS - 1) / FBS;
 
 __device__ inline double node_rho(double s0, double dx, unsigned long long a, int j, int N, int fp64) {
   const double scale = fp64 ? 5.684341886080801486968994140625e-14 /* 2^-44 */
@@ -559,7 +561,7 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
 __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, double tol,
                                                int maxit, int fp64) {
   const int g = blockIdx.x, tid = threadIdx.x;
-  extern __shared__ __align__(16) double Sk[];  // S_k, one per cell
+  extern __shared__ __align__(16) double Sk[];  // S_k, one per cell (padded, see the prefix sums)
   __shared__ GapConst sc;
   __shared__ GapState ss;
   __shared__ double wsum[FBS / 64];
@@ -665,41 +667,43 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   double *E = p.E64 + sc.nbase;
 
   // 1. nodal density of level n (to global rho and, as the cell terms of the
-  //    prefix sums, to LDS); the accumulator is cleared for the next push
-  // (four loads in flight per thread before any of the clearing stores, which
-  // the compiler may not move the later loads past)
-  for (int k0 = tid; k0 <= N; k0 += 4 * FBS) {
-    unsigned long long av[4];
+  //    prefix sums, to LDS); the accumulator is cleared for the next push.
+  //    The rest of the thread's nodes are loaded before any clearing store:
+  //    loads and stores share one counter, so a load issued after a store would
+  //    wait for it too.
+  const int ch = (N + FBS - 1) / FBS;  // cells per thread in the prefix sums below
+  unsigned long long av[FNQ];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = k0 + q * FBS;
-      av[q] = k0 == tid ? av0[q] : k <= N ? acc[k] : 0ull;
-    }
+  for (int q = 0; q < FNQ; ++q) {
+    const int k = tid + q * FBS;
+    av[q] = q < 4 ? av0[q < 4 ? q : 0] : (k <= N ? acc[k] : 0ull);
+  }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = k0 + q * FBS;
-      if (k > N) break;
-      const double r = node_rho(s0, dx, av[q] + (k == 0 ? ex0 : 0ull) + (k == N ? exN : 0ull), k, N, fp64);
-      rho[k] = r;
-      acc[k] = 0ull;
-      if (k < N)
-        Sk[k] = (k == 0) ? dx * r / 2.0 : dx * r;
-      else
-        s_rhoN = r;
-    }
+  for (int q = 0; q < FNQ; ++q) {
+    const int k = tid + q * FBS;
+    if (k > N) break;
+    const double r = node_rho(s0, dx, av[q] + (k == 0 ? ex0 : 0ull) + (k == N ? exN : 0ull), k, N, fp64);
+    rho[k] = r;
+    acc[k] = 0ull;
+    if (k < N)
+      Sk[k + k / ch] = (k == 0) ? dx * r / 2.0 : dx * r;
+    else
+      s_rhoN = r;
   }
   __syncthreads();
   // prefix sums S_k = dx rho_0/2 + dx sum_{1..k} rho_j over contiguous chunks
-  const int ch = (N + FBS - 1) / FBS;
+  // of ch cells per thread (cell k at LDS index k + k / ch: a chunk's stride
+  // of ch + 1 doubles spreads a wave's lanes over the LDS banks, where a
+  // stride of ch would put them on one)
   const int k0 = min(tid * ch, N), k1 = min(k0 + ch, N);
   double loc = 0.0;
-  for (int k = k0; k < k1; ++k) loc += Sk[k];
+  for (int k = k0; k < k1; ++k) loc += Sk[k + k / ch];
   double tot;
   double run = block_exclusive_scan_w(loc, wsum, &tot);
   double sumS = 0.0;
   for (int k = k0; k < k1; ++k) {
-    run += Sk[k];
-    Sk[k] = run;
+    run += Sk[k + k / ch];
+    Sk[k + k / ch] = run;
     sumS += run;
   }
   const double P = block_sum_w(sumS, wsum) * dx / eps0;
@@ -722,7 +726,7 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   const double rhoN = s_rhoN;
   const size_t eb = (size_t)sc.ebase;
   for (int k = tid; k < N; k += FBS) {
-    const double e = (sigma + Sk[k]) / eps0;
+    const double e = (sigma + Sk[k + k / ch]) / eps0;
     E[k] = e;
     if (fp64)
       ((double *)p.ehat)[eb + k + 1] = e;
@@ -1376,142 +1380,15 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
   }
 }
 
-// ---------------------------------------------------------------------------
-// k_compact: copy the live slots of every (gap, species) region into the other
-// buffer.  Each workgroup owns a contiguous run of tiles: it counts the live
-// slots of each region in its run, reserves them with one atomic per region,
-// then writes them.  Order inside a region is not kept (nothing depends on it).
-// ---------------------------------------------------------------------------
-template <class P, int BS>
-__global__ __launch_bounds__(BS) void k_compact(DevPtrs p, int G, int tile) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  int *prefix = (int *)lds_raw;  // [2G + 1]
-  __shared__ int scan_sh[BS];
-  __shared__ unsigned long long seg_base;
-  const int tid = threadIdx.x;
-  const int src = (int)(*p.epoch & 1), dst = src ^ 1;
-  const int R = 2 * G;
-  {
-    const int per = (R + BS - 1) / BS;
-    int mine = 0;
-    for (int q = 0; q < per; ++q) {
-      const int r = tid * per + q;
-      if (r < R) mine += (int)((min((long long)p.next_count[r], p.gc[r >> 1].cap[r & 1]) + tile - 1) / tile);
-    }
-    int total_t;
-    int run = block_exclusive_scan<int>(mine, scan_sh, &total_t);
-    for (int q = 0; q < per; ++q) {
-      const int r = tid * per + q;
-      if (r < R) {
-        prefix[r] = run;
-        run += (int)((min((long long)p.next_count[r], p.gc[r >> 1].cap[r & 1]) + tile - 1) / tile);
-      }
-    }
-    if (tid == 0) prefix[R] = total_t;
-    __syncthreads();
-  }
-  const int total = prefix[R];
-  const int t0 = (int)(((long long)blockIdx.x * total) / gridDim.x);
-  const int t1 = (int)(((long long)(blockIdx.x + 1) * total) / gridDim.x);
-  int r = 0;
-  for (int t = t0; t < t1;) {
-    while (prefix[r + 1] <= t) ++r;
-    const int tend = min(t1, prefix[r + 1]);
-    const int g = r >> 1, s = r & 1;
-    const GapConst &c = p.gc[g];
-    const long long n = min((long long)p.next_count[r], c.cap[s]);
-    const long long i_beg = (long long)(t - prefix[r]) * tile;
-    const long long i_end = min(n, (long long)(tend - prefix[r]) * tile);
-    const P *Xs = (const P *)p.X[src] + c.pbase[s];
-    // the run starts on a tile boundary (a multiple of 8 x the block size) and
-    // regions on 64-slot boundaries: each thread takes VN consecutive slots as
-    // 16-byte vectors, the last partial vector slot by slot
-    constexpr int VN = Vec<P>::n;
-    constexpr int NV = 1;  // vectors per thread per round (two measured slower)
-    constexpr int SPT = VN * NV;
-    typedef typename Vec<P>::type PV;
-    typedef unsigned int IDV __attribute__((ext_vector_type(VN)));
-    const long long step = (long long)BS * SPT;
-    // pass 1: live slots of this region in the run
-    int cnt = 0;
-    for (long long i = i_beg + (long long)tid * SPT; i < i_end; i += step) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const long long j = i + v * VN;
-        if (j + VN <= i_end) {
-          PV xv = *(const PV *)(Xs + j);
-#pragma unroll
-          for (int k = 0; k < VN; ++k) cnt += Vec<P>::at(xv, k) >= (P)0;
-        } else {
-          for (int k = 0; k < VN; ++k) cnt += (j + k < i_end) && Xs[j + k] >= (P)0;
-        }
-      }
-    }
-    int tot_live;
-    (void)block_exclusive_scan_i(cnt, scan_sh, &tot_live);
-    if (tid == 0)
-      seg_base = tot_live ? atomicAdd(&p.cursor[r], (unsigned long long)tot_live) : 0ull;
-    __syncthreads();
-    const unsigned long long base = seg_base;
-    // pass 2: write them, in order of the run
-    const P *Us = (const P *)p.U[src] + c.pbase[s];
-    const uint32_t *Is = p.ID[src] + c.pbase[s];
-    P *Xd = (P *)p.X[dst] + c.pbase[s];
-    P *Ud = (P *)p.U[dst] + c.pbase[s];
-    uint32_t *Id = p.ID[dst] + c.pbase[s];
-    unsigned long long written = 0;
-    for (long long i0 = i_beg; i0 < i_end; i0 += step) {
-      const long long i = i0 + (long long)tid * SPT;
-      PV xv[NV], uv[NV];
-      IDV iv[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const long long j = i + v * VN;
-        if (j + VN <= i_end) {
-          xv[v] = *(const PV *)(Xs + j);
-          uv[v] = *(const PV *)(Us + j);
-          iv[v] = *(const IDV *)(Is + j);
-        } else {
-#pragma unroll
-          for (int k = 0; k < VN; ++k) {
-            const bool in = j + k < i_end;
-            Vec<P>::at(xv[v], k) = in ? Xs[j + k] : (P)-1;
-            Vec<P>::at(uv[v], k) = in ? Us[j + k] : (P)0;
-            iv[v][k] = in ? Is[j + k] : 0u;
-          }
-        }
-      }
-      int c = 0;
-#pragma unroll
-      for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int k = 0; k < VN; ++k) c += Vec<P>::at(xv[v], k) >= (P)0;
-      int all;
-      const int before = block_exclusive_scan_i(c, scan_sh, &all);
-      unsigned long long o = base + written + (unsigned long long)before;
-#pragma unroll
-      for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int k = 0; k < VN; ++k)
-          if (Vec<P>::at(xv[v], k) >= (P)0) {
-            Xd[o] = Vec<P>::at(xv[v], k);
-            Ud[o] = Vec<P>::at(uv[v], k);
-            Id[o] = iv[v][k];
-            ++o;
-          }
-      written += (unsigned long long)all;
-    }
-    t = tend;
-  }
-}
-
-__global__ void k_commit(DevPtrs p, int G) {
+// The regions' new slot counts after a sort (flip: its particles are in the
+// other buffer now) or an in-place compaction.
+__global__ void k_commit(DevPtrs p, int G, int flip) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < 2 * G) {
     p.next_count[i] = p.cursor[i];
     p.cursor[i] = 0ull;
   }
-  if (i == 0) *p.epoch += 1;
+  if (i == 0 && flip) *p.epoch += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1776,39 +1653,289 @@ __global__ __launch_bounds__(BS) void k_sort_scatter(DevPtrs p, int G, int tile,
 constexpr int EBS = 256;
 template <class P>
 __global__ __launch_bounds__(EBS) void k_emit(DevPtrs p, int G) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  int *cpre = (int *)lds_raw;  // [G + 1]: first chunk of EBS events of gap g
+  __shared__ int scan_sh[EBS];
   __shared__ int wsum[EBS / 64];
   __shared__ unsigned long long s_base;
   __shared__ unsigned int s_emit[2];
+  const int tid = threadIdx.x;
   const int sel = (int)(*p.epoch & 1);
-  for (int g = 0; g < G; ++g) {
+  // chunks of every gap's list, all counts loaded at once, and their prefix
+  {
+    const int per = (G + EBS - 1) / EBS;
+    int mine = 0;
+    for (int q = 0; q < per; ++q) {
+      const int g = tid * per + q;
+      if (g < G) mine += (int)((min((long long)p.ev_count[g], p.gc[g].evcap) + EBS - 1) / EBS);
+    }
+    int total;
+    int run = block_exclusive_scan<int>(mine, scan_sh, &total);
+    for (int q = 0; q < per; ++q) {
+      const int g = tid * per + q;
+      if (g < G) {
+        cpre[g] = run;
+        run += (int)((min((long long)p.ev_count[g], p.gc[g].evcap) + EBS - 1) / EBS);
+      }
+    }
+    if (tid == 0) cpre[G] = total;
+    __syncthreads();
+  }
+  const int total = cpre[G];
+  int g = 0;
+  for (int ch = blockIdx.x; ch < total; ch += gridDim.x) {
+    // the gap holding chunk ch (chunks increase with g)
+    int lo = 0, hi = G - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (cpre[mid] <= ch) lo = mid; else hi = mid - 1;
+    }
+    g = lo;
     const GapConst &c = p.gc[g];
     const long long ne = min((long long)p.ev_count[g], c.evcap);
-    if (ne <= (long long)blockIdx.x * EBS) continue;
+    const long long r0 = (long long)(ch - cpre[g]) * EBS;
     const long long level = p.gs[g].level;
-    for (long long r0 = (long long)blockIdx.x * EBS; r0 < ne; r0 += (long long)gridDim.x * EBS) {
-      if (threadIdx.x < 2) s_emit[threadIdx.x] = 0u;
-      __syncthreads();
-      const int nr = (int)min((long long)EBS, ne - r0);
-      see_emit<P>(p, c, level, g, sel, p.ev + c.evbase + r0, nr, wsum, &s_base, s_emit);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        const unsigned int e0 = s_emit[0], e1 = s_emit[1];
-        const long long ze = (long long)c.Z[0] * Prec<P>::W;
-        unsigned long long *gacc = p.acc + c.nbase;
-        if (e0) {
-          atomicAdd(&gacc[0], (unsigned long long)(ze * (long long)e0));
-          atomicAdd(&p.tally[(size_t)g * T_N + T_EMIT], (unsigned long long)e0);
-        }
-        if (e1) {
-          atomicAdd(&gacc[c.N], (unsigned long long)(ze * (long long)e1));
-          atomicAdd(&p.tally[(size_t)g * T_N + T_EMIT + 1], (unsigned long long)e1);
-        }
-        atomicAdd(&p.ev_done[g], (unsigned long long)nr);
+    if (tid < 2) s_emit[tid] = 0u;
+    __syncthreads();
+    const int nr = (int)min((long long)EBS, ne - r0);
+    see_emit<P>(p, c, level, g, sel, p.ev + c.evbase + r0, nr, wsum, &s_base, s_emit);
+    __syncthreads();
+    if (tid == 0) {
+      const unsigned int e0 = s_emit[0], e1 = s_emit[1];
+      const long long ze = (long long)c.Z[0] * Prec<P>::W;
+      unsigned long long *gacc = p.acc + c.nbase;
+      if (e0) {
+        atomicAdd(&gacc[0], (unsigned long long)(ze * (long long)e0));
+        atomicAdd(&p.tally[(size_t)g * T_N + T_EMIT], (unsigned long long)e0);
       }
-      __syncthreads();
+      if (e1) {
+        atomicAdd(&gacc[c.N], (unsigned long long)(ze * (long long)e1));
+        atomicAdd(&p.tally[(size_t)g * T_N + T_EMIT + 1], (unsigned long long)e1);
+      }
+      atomicAdd(&p.ev_done[g], (unsigned long long)nr);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// In-place compaction: the live particles of each (gap, species) region end in
+// its first L slots, L its live count.  Only the live particles found at or past
+// L move, each into one absorbed slot below L (as many of one as of the other);
+// particles below L stay where they are, so a compaction reads the positions
+// once and moves a few particles instead of copying the region.  Order is not
+// kept (no result depends on it).  The region's slots are read in words of 64,
+// their liveness kept as bit masks (live[pbase / 64 + word]), in tiles of
+// CTW words; thread t of a tile takes words t, t + FW, t + 2 FW, t + 3 FW.
+// Per-tile counts at tcnt[pbase / 64 + k] (tile k of the region):
+//   k_fill_count  the live masks and each tile's live count
+//   k_fill_plan   one workgroup per region: the tiles' exclusive live prefix, L
+//   k_fill_holes  the absorbed slots below L, from the masks, listed in the
+//                 region's part of the other particle buffer (spare between
+//                 sorts), and H, their number
+//   k_fill_move   the live particles at or past L, from the masks, one per
+//                 listed hole (tail rank q to the q-th hole)
+// then k_commit sets each region's count to L.
+// ---------------------------------------------------------------------------
+constexpr int FW = 256;               // threads of the fill kernels
+constexpr int WPT = 4;                // words per thread and tile
+constexpr int CTW = FW * WPT;         // words per tile
+constexpr long long CTS = CTW * 64ll;  // slots per tile
+
+// bits of the slots [lo, hi) within the word starting at slot w0
+__device__ inline unsigned long long slot_range_mask(long long w0, long long lo, long long hi) {
+  const long long a = lo > w0 ? lo - w0 : 0, b = hi < w0 + 64 ? hi - w0 : 64;
+  if (b <= a) return 0ull;
+  const unsigned long long upto_b = b >= 64 ? ~0ull : ((1ull << b) - 1ull);
+  const unsigned long long below_a = a <= 0 ? 0ull : ((1ull << a) - 1ull);
+  return upto_b & ~below_a;
+}
+
+// The tile partition over every region's current slot count (prefix in LDS)
+// and this workgroup's run of tiles.
+#define FILL_TILE_RUN                                                        \
+  extern __shared__ __align__(16) unsigned char lds_raw[];                   \
+  int *prefix = (int *)lds_raw; /* [2G + 1] */                               \
+  __shared__ int scan_sh[FW];                                                \
+  __shared__ int wsum[FW / 64];                                              \
+  const int tid = threadIdx.x;                                               \
+  const int sel = (int)(*p.epoch & 1);                                       \
+  region_tile_prefix<FW>(p, G, (int)CTS, prefix, scan_sh);                   \
+  const int total = prefix[2 * G];                                           \
+  const int t0 = (int)(((long long)blockIdx.x * total) / gridDim.x);         \
+  const int t1 = (int)(((long long)(blockIdx.x + 1) * total) / gridDim.x);
+
+template <class P>
+__global__ __launch_bounds__(FW) void k_fill_count(DevPtrs p, int G) {
+  FILL_TILE_RUN
+  typedef typename Vec<P>::type PV;
+  constexpr int VN = Vec<P>::n;
+  constexpr int NV = 64 / VN;  // vectors per word
+  int r = 0;
+  for (int t = t0; t < t1; ++t) {
+    while (prefix[r + 1] <= t) ++r;
+    const int s = r & 1, k = t - prefix[r];
+    const GapConst &c = p.gc[r >> 1];
+    const long long n = min((long long)p.next_count[r], c.cap[s]);
+    const long long i_beg = (long long)k * CTS, i_end = min(n, i_beg + CTS);
+    const P *X = (const P *)p.X[sel] + c.pbase[s];
+    unsigned long long *lm = p.live + c.pbase[s] / 64;
+    int cnt = 0;
+    for (int q = 0; q < WPT; ++q) {
+      const long long w0 = i_beg + ((long long)q * FW + tid) * 64;
+      if (w0 >= i_end) continue;
+      // the word's loads all in flight before any is used
+      PV xv[NV];
+      if (w0 + 64 <= i_end) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) xv[v] = *(const PV *)(X + w0 + v * VN);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int e = 0; e < VN; ++e) {
+            const long long j = w0 + v * VN + e;
+            Vec<P>::at(xv[v], e) = j < i_end ? X[j] : (P)-1;
+          }
+      }
+      unsigned long long m = 0ull;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < VN; ++e) m |= (unsigned long long)(Vec<P>::at(xv[v], e) >= (P)0) << (v * VN + e);
+      lm[w0 / 64] = m;
+      cnt += __popcll(m);
+    }
+    int tot;
+    (void)block_exclusive_scan_i(cnt, wsum, &tot);
+    if (tid == 0) p.tcnt[c.pbase[s] / 64 + k] = tot;
+  }
+}
+
+constexpr int FPB = 256;
+__global__ __launch_bounds__(FPB) void k_fill_plan(DevPtrs p) {
+  __shared__ int wsum[FPB / 64];
+  const int r = blockIdx.x, s = r & 1;
+  const GapConst &c = p.gc[r >> 1];
+  const long long n = min((long long)p.next_count[r], c.cap[s]);
+  const int ntiles = (int)((n + CTS - 1) / CTS);
+  int *tc = p.tcnt + c.pbase[s] / 64;
+  long long run = 0;
+  for (int k0 = 0; k0 < ntiles; k0 += FPB) {
+    const int k = k0 + (int)threadIdx.x;
+    const int v = k < ntiles ? tc[k] : 0;
+    int tot;
+    const int ex = block_exclusive_scan_i(v, wsum, &tot);
+    if (k < ntiles) tc[k] = (int)(run + ex);
+    run += tot;
+  }
+  if (threadIdx.x == 0) {
+    p.cursor[r] = (unsigned long long)run;
+    p.fill_h[r] = 0ull;
+  }
+}
+
+// live particles before tile k: the tile's exclusive prefix; in the tile: the
+// next tile's prefix (or L after the last tile) minus it
+template <class P>
+__global__ __launch_bounds__(FW) void k_fill_holes(DevPtrs p, int G) {
+  FILL_TILE_RUN
+  int r = 0;
+  for (int t = t0; t < t1; ++t) {
+    while (prefix[r + 1] <= t) ++r;
+    const int s = r & 1, k = t - prefix[r];
+    const GapConst &c = p.gc[r >> 1];
+    const long long n = min((long long)p.next_count[r], c.cap[s]);
+    const long long L = (long long)p.cursor[r];
+    const long long i_beg = (long long)k * CTS, i_end = min(n, i_beg + CTS);
+    if (i_beg >= L) continue;
+    const int *tc = p.tcnt + c.pbase[s] / 64;
+    const long long live_before = tc[k];
+    const long long live_tile = (k + 1 < prefix[r + 1] - prefix[r] ? (long long)tc[k + 1] : L) - live_before;
+    const long long hi = min(i_end, L);
+    long long holes = i_beg - live_before;  // absorbed slots before the tile (all below L)
+    if (live_tile < i_end - i_beg) {
+      const unsigned long long *lm = p.live + c.pbase[s] / 64;
+      uint32_t *hl = (uint32_t *)p.X[sel ^ 1] + c.pbase[s];
+      unsigned long long dead[WPT];
+      int nd = 0;
+#pragma unroll
+      for (int q = 0; q < WPT; ++q) {
+        const long long w0 = i_beg + ((long long)q * FW + tid) * 64;
+        const unsigned long long rng = w0 < hi ? slot_range_mask(w0, i_beg, hi) : 0ull;
+        dead[q] = rng ? ~lm[w0 / 64] & rng : 0ull;
+        nd += __popcll(dead[q]);
+      }
+      int tot;
+      const int ex = block_exclusive_scan_i(nd, wsum, &tot);
+      long long o = holes + ex;
+#pragma unroll
+      for (int q = 0; q < WPT; ++q) {
+        const long long w0 = i_beg + ((long long)q * FW + tid) * 64;
+        unsigned long long d = dead[q];
+        while (d) {
+          const int b = __ffsll((long long)d) - 1;
+          d &= d - 1ull;
+          hl[o++] = (uint32_t)(w0 + b);
+        }
+      }
+      holes += tot;
+    }
+    // the tile holding slot L - 1 knows how many holes lie below L
+    if (tid == 0 && i_beg < L && L <= i_end) p.fill_h[r] = (unsigned long long)holes;
+  }
+}
+
+template <class P>
+__global__ __launch_bounds__(FW) void k_fill_move(DevPtrs p, int G) {
+  FILL_TILE_RUN
+  int r = 0;
+  for (int t = t0; t < t1; ++t) {
+    while (prefix[r + 1] <= t) ++r;
+    const int s = r & 1, k = t - prefix[r];
+    const GapConst &c = p.gc[r >> 1];
+    const long long n = min((long long)p.next_count[r], c.cap[s]);
+    const long long L = (long long)p.cursor[r];
+    const long long i_beg = (long long)k * CTS, i_end = min(n, i_beg + CTS);
+    if (i_end <= L) continue;
+    const long long H = (long long)p.fill_h[r];
+    // tail rank of the tile's first slot at or past L: live ones in [L, lo)
+    const long long lo = max(i_beg, L);
+    const long long rank = i_beg >= L ? (long long)p.tcnt[c.pbase[s] / 64 + k] - (L - H) : 0;
+    P *X = (P *)p.X[sel] + c.pbase[s];
+    P *U = (P *)p.U[sel] + c.pbase[s];
+    uint32_t *I = p.ID[sel] + c.pbase[s];
+    const unsigned long long *lm = p.live + c.pbase[s] / 64;
+    const uint32_t *hl = (const uint32_t *)p.X[sel ^ 1] + c.pbase[s];
+    unsigned long long lv[WPT];
+    int nl = 0;
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      const long long w0 = i_beg + ((long long)q * FW + tid) * 64;
+      const unsigned long long rng = w0 < i_end ? slot_range_mask(w0, lo, i_end) : 0ull;
+      lv[q] = rng ? lm[w0 / 64] & rng : 0ull;
+      nl += __popcll(lv[q]);
+    }
+    int tot;
+    const int ex = block_exclusive_scan_i(nl, wsum, &tot);
+    long long qh = rank + ex;
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      const long long w0 = i_beg + ((long long)q * FW + tid) * 64;
+      unsigned long long m = lv[q];
+      while (m) {
+        const int b = __ffsll((long long)m) - 1;
+        m &= m - 1ull;
+        const long long j = w0 + b, dst = (long long)hl[qh++];
+        X[dst] = X[j];
+        U[dst] = U[j];
+        I[dst] = I[j];
+      }
     }
   }
 }
+
+#undef FILL_TILE_RUN
 
 // ---------------------------------------------------------------------------
 // injection of caller particles (SI) into one gap
@@ -1962,7 +2089,9 @@ static hipError_t launch_k(K kernel, dim3 grid, dim3 block, size_t lds, hipStrea
 
 hipError_t launch_field(const DevPtrs &p, int G, int mode, int guess, double tol, int maxit,
                         int fp64, int nmax, hipStream_t s, KTime t) {
-  const size_t lds = (size_t)nmax * 8;
+  // S_k of every cell, padded by one double per chunk of the prefix sums
+  // (index k + k / ch < N + FBS)
+  const size_t lds = ((size_t)nmax + (size_t)FBS + 1) * 8;
   static size_t attr_set = 32768;
   if (lds > attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)k_field, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2010,16 +2139,29 @@ hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t
   return push_b<float, Carry32>(p, G, lc, s, t);
 }
 
-hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+template <class P>
+static hipError_t fill_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
   const int grid = lc.compact_grid > 0 ? lc.compact_grid : 1024;
   const size_t lds = ((size_t)(2 * G + 1) * 4 + 15) / 16 * 16;
-  // the start event goes with the compaction, the end event with the commit
-  hipError_t e = lc.fp64 ? launch_k(k_compact<double, 256>, dim3(grid), dim3(256), lds, s, t.a, nullptr, p, G,
-                                    lc.tile)
-                         : launch_k(k_compact<float, 256>, dim3(grid), dim3(256), lds, s, t.a, nullptr, p, G,
-                                    lc.tile);
+  static size_t attr_set = 65536;
+  if (lds > attr_set) {
+    for (const void *k : {(const void *)k_fill_count<P>, (const void *)k_fill_holes<P>, (const void *)k_fill_move<P>}) {
+      hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    attr_set = lds;
+  }
+  // the start event goes with the count pass, the end event with the commit
+  hipError_t e = launch_k(k_fill_count<P>, dim3(grid), dim3(FW), lds, s, t.a, nullptr, p, G);
+  if (e == hipSuccess) e = launch_k(k_fill_plan, dim3(2 * G), dim3(FPB), 0, s, nullptr, nullptr, p);
+  if (e == hipSuccess) e = launch_k(k_fill_holes<P>, dim3(grid), dim3(FW), lds, s, nullptr, nullptr, p, G);
+  if (e == hipSuccess) e = launch_k(k_fill_move<P>, dim3(grid), dim3(FW), lds, s, nullptr, nullptr, p, G);
   if (e != hipSuccess) return e;
-  return launch_k(k_commit, dim3((2 * G + 255) / 256), dim3(256), 0, s, nullptr, t.b, p, G);
+  return launch_k(k_commit, dim3((2 * G + 255) / 256), dim3(256), 0, s, nullptr, t.b, p, G, 0);
+}
+
+hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+  return lc.fp64 ? fill_t<double>(p, G, lc, s, t) : fill_t<float>(p, G, lc, s, t);
 }
 
 size_t sort_lds_bytes(int G, int nmax, int bin) {
@@ -2051,7 +2193,7 @@ static hipError_t sort_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream
   if (e != hipSuccess) return e;
   e = launch_k(k_sort_scatter<P, 256>, dim3(grid), dim3(256), lds, s, nullptr, nullptr, p, G, lc.tile, bin, nbmax);
   if (e != hipSuccess) return e;
-  return launch_k(k_commit, dim3((2 * G + 255) / 256), dim3(256), 0, s, nullptr, t.b, p, G);
+  return launch_k(k_commit, dim3((2 * G + 255) / 256), dim3(256), 0, s, nullptr, t.b, p, G, 1);
 }
 
 hipError_t launch_sort(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
@@ -2060,8 +2202,16 @@ hipError_t launch_sort(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t
 }
 
 hipError_t launch_emit(const DevPtrs &p, int G, int fp64, int grid, hipStream_t s, KTime t) {
-  return fp64 ? launch_k(k_emit<double>, dim3(grid), dim3(EBS), 0, s, t.a, t.b, p, G)
-              : launch_k(k_emit<float>, dim3(grid), dim3(EBS), 0, s, t.a, t.b, p, G);
+  const size_t lds = ((size_t)(G + 1) * 4 + 15) / 16 * 16;
+  static size_t attr_set[2] = {65536, 65536};
+  if (lds > attr_set[fp64 ? 1 : 0]) {
+    const void *k = fp64 ? (const void *)k_emit<double> : (const void *)k_emit<float>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set[fp64 ? 1 : 0] = lds;
+  }
+  return fp64 ? launch_k(k_emit<double>, dim3(grid), dim3(EBS), lds, s, t.a, t.b, p, G)
+              : launch_k(k_emit<float>, dim3(grid), dim3(EBS), lds, s, t.a, t.b, p, G);
 }
 
 hipError_t launch_inject(const DevPtrs &p, int gap, int species, long long n, const double *x,
