@@ -32,6 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+STRICT, WEAK = 0, 1  # coupling modes in the library's numbering (gs_autotune, GapSim.step)
 BYTES_PER_PUSH_F32 = 16  # read x, v and write x, v (binary32)
 
 # HBM traffic of the push kernel, taken with rocprofv3 FETCH_SIZE / WRITE_SIZE
@@ -409,7 +410,6 @@ FP64_WORKLOAD = "rc_gap_256c_1e5p_strict_fp64"
 
 def run_fp64(args, copy_gbs):
     import torch
-    import oracle
     from paper_2603_24010_amd import gapsim, workloads as W
     cfg = W.config1()
     loads = W.load_config1(n_per_species=50_000, seed=0)
@@ -441,6 +441,7 @@ def run_fp64(args, copy_gbs):
         "kernel_ms_per_step": {k[:-3]: tm[k] / 64 for k in ("push_ms", "field_ms", "compact_ms")},
     }
     if not args.no_cpu_baseline:
+        import oracle
         s = oracle.OracleSim(cfg, fp32=False)
         for sp, (x, v) in loads.items():
             s.inject(sp, x, v)
@@ -549,15 +550,14 @@ def run_tesla(args, copy_gbs):
     emission, the whole 575 steps each on the GPU; the oracle (binary32 mode)
     timed on the same runs."""
     import torch
-    import oracle
     from paper_2603_24010_amd import gapsim, workloads as W
     from paper_2603_24010_amd.engines import RadauCircuitEngine
     ENGINE = -1
     cfg0 = W.config_tesla()
     steps = len(cfg0.beam_schedule)
-    cases = [("strict_see", oracle.STRICT, cfg0), ("weak_see", oracle.WEAK, cfg0),
-             ("strict_no_see", oracle.STRICT, cfg0.replace(see_amp=0.0)),
-             ("weak_no_see", oracle.WEAK, cfg0.replace(see_amp=0.0))]
+    cases = [("strict_see", STRICT, cfg0), ("weak_see", WEAK, cfg0),
+             ("strict_no_see", STRICT, cfg0.replace(see_amp=0.0)),
+             ("weak_no_see", WEAK, cfg0.replace(see_amp=0.0))]
     # weak coupling with the circuit in an external stiff engine (Radau IIA), the
     # way the paper's weak mode hands the circuit to a SPICE engine
     cases.append(("weak_engine_see", ENGINE, cfg0))
@@ -600,10 +600,17 @@ def run_tesla(args, copy_gbs):
                          absorbed=[int(x) for x in d["abs_cum"].ravel()], time_step_check=_finite(chk))
         log(f"[bench] {name}: {res[name]}")
     rmse = lambda a, b: float(np.sqrt(np.mean((curves[a] - curves[b]) ** 2)) / 1e3)
-    # the circuit alone (no gap charge): the library's BDF2 level sequence and a
-    # Radau IIA step at the same dt, each against Radau on a 16 times finer grid
+    # the circuit alone (no particles): the library's BDF2 levels (strict steps
+    # of an empty gap) and a Radau IIA step at the same dt, each against Radau on
+    # a 16 times finer grid
     vac_cfg = cfg0.replace(see_amp=0.0, beam_schedule=None)
-    _, v_bdf2 = oracle.circuit_run(vac_cfg, steps)
+    vs = gapsim.GapSim(vac_cfg, particle_fp=32, capacity=(64, 64))
+    v_bdf2 = []
+    for _ in range(steps):
+        vs.step_strict(1)
+        v_bdf2.append(vs.diag(0)["phi0"])
+    vs.close()
+    v_bdf2 = np.array(v_bdf2)
     fine = RadauCircuitEngine(vac_cfg.replace(dt=vac_cfg.dt / 16))
     p, ref = 0.0, []
     for k in range(16 * steps):
@@ -641,6 +648,7 @@ def run_tesla(args, copy_gbs):
                      "note": "at most ~1.3e6 live particles: each step is a few launches of short kernels"},
     }
     if not args.no_cpu_baseline:
+        import oracle
         pc, elc = 0, 0.0
         for name, mode, cfg in cases:
             o = oracle.OracleSim(cfg, fp32=True)
@@ -764,15 +772,14 @@ def run_tesla_fine(args, copy_gbs):
     with the circuit in an external Radau engine; graphs replay the steps, the
     gap voltage is read every 100 steps and the time-step check every 1000."""
     import torch
-    import oracle
     from paper_2603_24010_amd import gapsim, workloads as W
     from paper_2603_24010_amd.engines import RadauCircuitEngine
     ENGINE = -1
     cfg0 = W.config_tesla(dt=1.5e-11)
     steps, every, chk_every = len(cfg0.beam_schedule), 100, 1000
-    cases = [("strict_see", oracle.STRICT, cfg0), ("weak_see", oracle.WEAK, cfg0),
-             ("strict_no_see", oracle.STRICT, cfg0.replace(see_amp=0.0)),
-             ("weak_no_see", oracle.WEAK, cfg0.replace(see_amp=0.0)), ("weak_engine_see", ENGINE, cfg0)]
+    cases = [("strict_see", STRICT, cfg0), ("weak_see", WEAK, cfg0),
+             ("strict_no_see", STRICT, cfg0.replace(see_amp=0.0)),
+             ("weak_no_see", WEAK, cfg0.replace(see_amp=0.0)), ("weak_engine_see", ENGINE, cfg0)]
     res, curves, el_all, pushed_all = {}, {}, 0.0, 0
     for name, mode, cfg in cases:
         s = gapsim.GapSim(cfg, particle_fp=32, capacity=(3_000_000, 4_000_000))
@@ -844,6 +851,7 @@ def run_tesla_fine(args, copy_gbs):
     }
     if not args.no_cpu_baseline:
         # the oracle from level 0 into the rise of the pulse (about 25 s on one core)
+        import oracle
         o = oracle.OracleSim(cfg0, fp32=True)
         n = 245_000
         t0 = time.perf_counter()

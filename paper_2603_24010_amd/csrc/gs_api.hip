@@ -418,6 +418,7 @@ static gs_status setup(gs_ctx *ctx) {
   // indexed from the region's pbase / 64
   ALLOC(d.tcnt, int *, (slots / 64 + 1) * 4);
   ALLOC(d.live, unsigned long long *, (slots / 64 + 1) * 8);
+  ALLOC(d.wrank, int *, (slots / 64 + 1) * 4);
   ALLOC(d.tally, unsigned long long *, (size_t)G * T_N * 8);
   ALLOC(d.acc, unsigned long long *, nodes * 8);
   ALLOC(d.rho64, double *, nodes * 8);

@@ -130,6 +130,7 @@ struct DevPtrs {
   int *tcnt;
   unsigned long long *fill_h;  // [G][2]
   unsigned long long *live;    // a bit per slot, 64 per word from pbase / 64
+  int *wrank;                  // per word past the live count: tail rank of its first live slot
   const int64_t *sched;            // beam schedules of all gaps (GapConst::sched_base)
   // exchange with an external circuit engine (field mode 2), in pinned host
   // memory the device maps: ext_v[g] the engine's gap voltage for the level

@@ -672,6 +672,9 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   //    loads and stores share one counter, so a load issued after a store would
   //    wait for it too.
   const int ch = (N + FBS - 1) / FBS;  // cells per thread in the prefix sums below
+  // floor(k / ch) = (k * ceil(2^32 / ch)) >> 32 for every k here (k <= 16384 + FBS)
+  const unsigned long long chm = (4294967296ull + (unsigned long long)ch - 1ull) / (unsigned long long)ch;
+  auto pad = [&](int k) { return k + (int)(((unsigned long long)k * chm) >> 32); };
   unsigned long long av[FNQ];
 #pragma unroll
   for (int q = 0; q < FNQ; ++q) {
@@ -686,7 +689,7 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
     rho[k] = r;
     acc[k] = 0ull;
     if (k < N)
-      Sk[k + k / ch] = (k == 0) ? dx * r / 2.0 : dx * r;
+      Sk[pad(k)] = (k == 0) ? dx * r / 2.0 : dx * r;
     else
       s_rhoN = r;
   }
@@ -695,17 +698,27 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   // of ch cells per thread (cell k at LDS index k + k / ch: a chunk's stride
   // of ch + 1 doubles spreads a wave's lanes over the LDS banks, where a
   // stride of ch would put them on one)
+  // (the chunk's cells are held in registers between the two passes; cell
+  // k0 + i of thread tid sits at LDS index k0 + i + tid)
   const int k0 = min(tid * ch, N), k1 = min(k0 + ch, N);
+  const int nk = k1 - k0;
+  double cv[FNQ];
+#pragma unroll
+  for (int i = 0; i < FNQ; ++i) cv[i] = i < nk ? Sk[k0 + i + tid] : 0.0;
   double loc = 0.0;
-  for (int k = k0; k < k1; ++k) loc += Sk[k + k / ch];
+#pragma unroll
+  for (int i = 0; i < FNQ; ++i)
+    if (i < nk) loc += cv[i];
   double tot;
   double run = block_exclusive_scan_w(loc, wsum, &tot);
   double sumS = 0.0;
-  for (int k = k0; k < k1; ++k) {
-    run += Sk[k + k / ch];
-    Sk[k + k / ch] = run;
-    sumS += run;
-  }
+#pragma unroll
+  for (int i = 0; i < FNQ; ++i)
+    if (i < nk) {
+      run += cv[i];
+      Sk[k0 + i + tid] = run;
+      sumS += run;
+    }
   const double P = block_sum_w(sumS, wsum) * dx / eps0;
 
   // 2. circuit and surface charge
@@ -726,7 +739,7 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   const double rhoN = s_rhoN;
   const size_t eb = (size_t)sc.ebase;
   for (int k = tid; k < N; k += FBS) {
-    const double e = (sigma + Sk[k + k / ch]) / eps0;
+    const double e = (sigma + Sk[pad(k)]) / eps0;
     E[k] = e;
     if (fp64)
       ((double *)p.ehat)[eb + k + 1] = e;
@@ -1733,8 +1746,9 @@ __global__ __launch_bounds__(EBS) void k_emit(DevPtrs p, int G) {
 //   k_fill_holes  the absorbed slots below L, from the masks, listed in the
 //                 region's part of the other particle buffer (spare between
 //                 sorts), and H, their number
-//   k_fill_move   the live particles at or past L, from the masks, one per
-//                 listed hole (tail rank q to the q-th hole)
+//   k_fill_rank   per word past L, the tail rank of its first live slot
+//   k_fill_move   one thread per slot past L: a live one goes to the hole of
+//                 its tail rank (the q-th listed hole for rank q)
 // then k_commit sets each region's count to L.
 // ---------------------------------------------------------------------------
 constexpr int FW = 256;               // threads of the fill kernels
@@ -1886,9 +1900,11 @@ __global__ __launch_bounds__(FW) void k_fill_holes(DevPtrs p, int G) {
   }
 }
 
+// the tail rank of each word's first live slot at or past L (tiles past L)
 template <class P>
-__global__ __launch_bounds__(FW) void k_fill_move(DevPtrs p, int G) {
+__global__ __launch_bounds__(FW) void k_fill_rank(DevPtrs p, int G) {
   FILL_TILE_RUN
+  (void)sel;
   int r = 0;
   for (int t = t0; t < t1; ++t) {
     while (prefix[r + 1] <= t) ++r;
@@ -1902,36 +1918,82 @@ __global__ __launch_bounds__(FW) void k_fill_move(DevPtrs p, int G) {
     // tail rank of the tile's first slot at or past L: live ones in [L, lo)
     const long long lo = max(i_beg, L);
     const long long rank = i_beg >= L ? (long long)p.tcnt[c.pbase[s] / 64 + k] - (L - H) : 0;
-    P *X = (P *)p.X[sel] + c.pbase[s];
-    P *U = (P *)p.U[sel] + c.pbase[s];
-    uint32_t *I = p.ID[sel] + c.pbase[s];
     const unsigned long long *lm = p.live + c.pbase[s] / 64;
-    const uint32_t *hl = (const uint32_t *)p.X[sel ^ 1] + c.pbase[s];
-    unsigned long long lv[WPT];
+    int *wr = p.wrank + c.pbase[s] / 64;
+    int cnt[WPT];
     int nl = 0;
 #pragma unroll
     for (int q = 0; q < WPT; ++q) {
       const long long w0 = i_beg + ((long long)q * FW + tid) * 64;
       const unsigned long long rng = w0 < i_end ? slot_range_mask(w0, lo, i_end) : 0ull;
-      lv[q] = rng ? lm[w0 / 64] & rng : 0ull;
-      nl += __popcll(lv[q]);
+      cnt[q] = rng ? __popcll(lm[w0 / 64] & rng) : 0;
+      nl += cnt[q];
     }
     int tot;
     const int ex = block_exclusive_scan_i(nl, wsum, &tot);
-    long long qh = rank + ex;
+    long long q0 = rank + ex;
 #pragma unroll
     for (int q = 0; q < WPT; ++q) {
       const long long w0 = i_beg + ((long long)q * FW + tid) * 64;
-      unsigned long long m = lv[q];
-      while (m) {
-        const int b = __ffsll((long long)m) - 1;
-        m &= m - 1ull;
-        const long long j = w0 + b, dst = (long long)hl[qh++];
-        X[dst] = X[j];
-        U[dst] = U[j];
-        I[dst] = I[j];
+      if (w0 < i_end && w0 + 64 > lo) wr[w0 / 64] = (int)q0;
+      q0 += cnt[q];
+    }
+  }
+}
+
+// every live slot at or past L, one thread each, to the hole of its tail rank
+// (the word's rank plus the live slots before it in the word); grid-stride over
+// the tails of all regions, whose lengths n - L are prefixed in LDS
+template <class P>
+__global__ __launch_bounds__(FW) void k_fill_move(DevPtrs p, int G) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  long long *tpre = (long long *)lds_raw;  // [2G + 1]: first flat index of region r's tail
+  __shared__ long long scan_sh[FW];
+  const int tid = threadIdx.x;
+  const int sel = (int)(*p.epoch & 1);
+  const int R = 2 * G;
+  {
+    const int per = (R + FW - 1) / FW;
+    long long mine = 0;
+    for (int q = 0; q < per; ++q) {
+      const int r = tid * per + q;
+      if (r < R) mine += min((long long)p.next_count[r], p.gc[r >> 1].cap[r & 1]) - (long long)p.cursor[r];
+    }
+    long long tot;
+    long long run = block_exclusive_scan<long long>(mine, scan_sh, &tot);
+    for (int q = 0; q < per; ++q) {
+      const int r = tid * per + q;
+      if (r < R) {
+        tpre[r] = run;
+        run += min((long long)p.next_count[r], p.gc[r >> 1].cap[r & 1]) - (long long)p.cursor[r];
       }
     }
+    if (tid == 0) tpre[R] = tot;
+    __syncthreads();
+  }
+  const long long total = tpre[R];
+  int r = 0;
+  for (long long f = (long long)blockIdx.x * FW + tid; f < total; f += (long long)gridDim.x * FW) {
+    while (tpre[r + 1] <= f) ++r;
+    const int s = r & 1;
+    const GapConst &c = p.gc[r >> 1];
+    const long long L = (long long)p.cursor[r];
+    const long long j = L + (f - tpre[r]);
+    const unsigned long long m = p.live[c.pbase[s] / 64 + j / 64];
+    const int b = (int)(j & 63);
+    if (!((m >> b) & 1ull)) continue;
+    // live slots in this word before j and at or past L
+    const long long w0 = j - b;
+    const unsigned long long before = (b ? ((1ull << b) - 1ull) : 0ull) & slot_range_mask(w0, L, j + 1);
+    const long long q = (long long)p.wrank[c.pbase[s] / 64 + j / 64] + __popcll(m & before);
+    const uint32_t *hl = (const uint32_t *)p.X[sel ^ 1] + c.pbase[s];
+    const long long dst = (long long)hl[q];
+    P *X = (P *)p.X[sel] + c.pbase[s];
+    P *U = (P *)p.U[sel] + c.pbase[s];
+    uint32_t *I = p.ID[sel] + c.pbase[s];
+    X[dst] = X[j];
+    U[dst] = U[j];
+    I[dst] = I[j];
   }
 }
 
@@ -2143,19 +2205,27 @@ template <class P>
 static hipError_t fill_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
   const int grid = lc.compact_grid > 0 ? lc.compact_grid : 1024;
   const size_t lds = ((size_t)(2 * G + 1) * 4 + 15) / 16 * 16;
-  static size_t attr_set = 65536;
+  const size_t lds2 = (size_t)(2 * G + 1) * 8;  // the move's 64-bit tail prefix
+  static size_t attr_set = 65536, attr_set2 = 65536;
   if (lds > attr_set) {
-    for (const void *k : {(const void *)k_fill_count<P>, (const void *)k_fill_holes<P>, (const void *)k_fill_move<P>}) {
+    for (const void *k : {(const void *)k_fill_count<P>, (const void *)k_fill_holes<P>, (const void *)k_fill_rank<P>}) {
       hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
     attr_set = lds;
   }
+  if (lds2 > attr_set2) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_fill_move<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds2);
+    if (e != hipSuccess) return e;
+    attr_set2 = lds2;
+  }
   // the start event goes with the count pass, the end event with the commit
   hipError_t e = launch_k(k_fill_count<P>, dim3(grid), dim3(FW), lds, s, t.a, nullptr, p, G);
   if (e == hipSuccess) e = launch_k(k_fill_plan, dim3(2 * G), dim3(FPB), 0, s, nullptr, nullptr, p);
   if (e == hipSuccess) e = launch_k(k_fill_holes<P>, dim3(grid), dim3(FW), lds, s, nullptr, nullptr, p, G);
-  if (e == hipSuccess) e = launch_k(k_fill_move<P>, dim3(grid), dim3(FW), lds, s, nullptr, nullptr, p, G);
+  if (e == hipSuccess) e = launch_k(k_fill_rank<P>, dim3(grid), dim3(FW), lds, s, nullptr, nullptr, p, G);
+  if (e == hipSuccess) e = launch_k(k_fill_move<P>, dim3(grid), dim3(FW), lds2, s, nullptr, nullptr, p, G);
   if (e != hipSuccess) return e;
   return launch_k(k_commit, dim3((2 * G + 255) / 256), dim3(256), 0, s, nullptr, t.b, p, G, 0);
 }
