@@ -91,9 +91,12 @@ def make_sim(name, spec, total_steps):
         loads = W.load_config3(n=spec["n0"], seed=3, d=cfg.d)
     n_ion = spec["n0"]
     # every beam ion may still be in flight at the end (slow ones cross in
-    # thousands of steps); emitted electrons stay well below one per beam ion
+    # thousands of steps); each absorbed ion, loaded or beam, emits at most
+    # see_amp secondary electrons, and the loaded ions are absorbed within a few
+    # hundred steps
     grow = (total_steps + 64) * spec["beam"]
-    cap = ((1 << 22) + grow, n_ion + grow + (1 << 20))
+    n_sec = int(math.ceil(cfg.see_amp * (n_ion + grow)))
+    cap = ((1 << 22) + n_sec, n_ion + grow + (1 << 20))
     sim = gapsim.GapSim(cfg, particle_fp=32, capacity=cap)
     for sp, (x, v) in loads.items():
         sim.inject(0, sp, x, v)

@@ -203,7 +203,7 @@ enum {
   GS_OPT_GRID = 3,         /* push blocks; 0 = from occupancy */
   GS_OPT_COMPACT_EVERY = 4,/* steps between reclaiming absorbed slots (>= 1) */
   GS_OPT_GRAPH = 5,        /* 1: replay steps through a captured hipGraph */
-  GS_OPT_TIMING = 6,       /* 1: time each kernel launch with HIP events */
+  GS_OPT_TIMING = 6,       /* 1: time each kernel launch with HIP events, 2: the push only */
   GS_OPT_NEWTON_TOL = 7,   /* value * 1e-12 = scaled residual tolerance (default 1e-10) */
   GS_OPT_NEWTON_MAXIT = 8, /* Newton corrections allowed per level, 0..64 (default 8) */
   GS_OPT_DEPOSIT = 9,      /* binary32 deposit cells: 0 auto, 1 64-bit, 2 32-bit with carries */

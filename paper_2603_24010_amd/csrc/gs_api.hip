@@ -449,17 +449,25 @@ static gs_status setup(gs_ctx *ctx) {
     HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ext_ev, hipEventDisableTiming));
   }
   // overflow event regions for up to eight 256-thread push workgroups per CU
-  // (the largest grid the autotuner tries), when any gap emits
+  // (the largest grid the autotuner tries), when any gap emits; each holds
+  // 1/32768 of the emitting gaps' ion slots, within [OVQ_MIN, OVQ_MAX] (a
+  // push that absorbs a few tenths of a percent of 2e8 ions stays within them)
   bool emits = false;
-  for (int g = 0; g < G; ++g) emits = emits || ctx->params[g].see_amp > 0.0;
+  int64_t ion_slots = 0;
+  for (int g = 0; g < G; ++g)
+    if (ctx->params[g].see_amp > 0.0) {
+      emits = true;
+      ion_slots += ctx->hc[g].cap[1];
+    }
   {
     int dev = 0, ncu = 0;
     HIPCHK(ctx, hipGetDevice(&dev));
     HIPCHK(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     d.ovf_wgs = emits ? (int64_t)8 * std::max(ncu, 1) : 0;
+    d.ovq = std::min<int64_t>(OVQ_MAX, std::max<int64_t>(OVQ_MIN, (ion_slots / 32768 + 255) / 256 * 256));
   }
   ctx->emits = emits ? 1 : 0;
-  ALLOC(d.ovf, Event *, (size_t)std::max<int64_t>(d.ovf_wgs, 1) * OVQ * sizeof(Event));
+  ALLOC(d.ovf, Event *, (size_t)std::max<int64_t>(d.ovf_wgs, 1) * (size_t)d.ovq * sizeof(Event));
   ALLOC(d.epoch, int64_t *, 8);
   ALLOC(d.err, unsigned int *, 8);
   ALLOC(d.gc, const GapConst *, sizeof(GapConst) * (size_t)G);
@@ -717,9 +725,12 @@ static hipEvent_t ev_get(gs_ctx *ctx) {
 
 // Runs launch(t); when timing is on, t carries two events that the kernel's
 // own dispatch packets record, so the elapsed time is the kernel's alone.
+// Timing level 2 instruments the push only: an evented launch leaves the queue
+// idle for some microseconds around it, which level 2 confines to one launch a
+// step.
 template <class F>
 static hipError_t timed(gs_ctx *ctx, int kind, F &&launch) {
-  if (!ctx->timing) return launch(KTime{});
+  if (!ctx->timing || (ctx->timing == 2 && kind != 0)) return launch(KTime{});
   KTime t;
   t.a = ev_get(ctx);
   t.b = ev_get(ctx);
@@ -1655,7 +1666,8 @@ extern "C" gs_status gs_set_option(gs_ctx *ctx, int32_t option, int64_t value) {
       ctx->use_graph = value ? 1 : 0;
       return GS_OK;
     case GS_OPT_TIMING:
-      ctx->timing = value ? 1 : 0;
+      if (value < 0 || value > 2) return fail(ctx, GS_EINVAL, "timing must be 0, 1 or 2");
+      ctx->timing = (int)value;
       return GS_OK;
     case GS_OPT_NEWTON_TOL:
       if (value <= 0) return fail(ctx, GS_EINVAL, "tolerance must be positive");

@@ -138,7 +138,8 @@ struct DevPtrs {
   const double *ext_v;
   double *ext_phi;
   Event *ovf;                      // push workgroup b < ovf_wgs: events past its LDS queue,
-  int64_t ovf_wgs;                 //   OVQ of them from ovf + b * OVQ
+  int64_t ovf_wgs;                 //   ovq of them from ovf + b * ovq
+  int64_t ovq;
   // Newton guess network: bfloat16 weights (flat layout of gs_mlp_dev.h) and
   // the normalisation block; null until weights are set
   const uint16_t *mlp_w;
@@ -157,8 +158,12 @@ enum { ERR_CAPACITY = 1u, ERR_BADINJECT = 2u, ERR_NOCONV = 4u };
 constexpr int SORT_BIN_MIN = 4;
 
 // Absorbed-ion events a push workgroup keeps in its global overflow region
-// (past these they go to the gap's list, emitted by k_emit after the push).
-constexpr int OVQ = 1024;
+// (past these they go to the gap's list, emitted by k_emit after the push):
+// from OVQ_MIN to OVQ_MAX, in proportion to the emitting gaps' ion slots.  A
+// position in the gap's list costs each wave that needs one a returning atomic
+// on the gap's counter, and at some 1e5 overflowing events a step those
+// serialise; the regions are sized so that a push rarely needs the list.
+constexpr int OVQ_MIN = 1024, OVQ_MAX = 8192;
 
 struct LaunchCfg {
   int block;         // push block size

@@ -861,7 +861,7 @@ __device__ inline void acc_add<Carry32>(unsigned int *lds, unsigned long long *g
 }
 
 constexpr int EVQ = 128;  // absorbed-ion events a push workgroup queues in LDS
-// (more go to the workgroup's OVQ-event region of a global buffer; both are
+// (more go to the workgroup's overflow region of a global buffer; both are
 // emitted at the segment's flush, so a step's emission completes in its push)
 
 template <class P, class AC>
@@ -1010,9 +1010,9 @@ __device__ void flush_seg(const DevPtrs &p, const GapConst &c, const GapState &s
                           PushShared<P, AC> &sh) {
   __shared__ unsigned long long s_base;
   __syncthreads();
-  const int ovq = (long long)blockIdx.x < p.ovf_wgs ? OVQ : 0;
+  const int ovq = (long long)blockIdx.x < p.ovf_wgs ? (int)p.ovq : 0;
   const int ne = s == 1 ? (int)min(*sh.evq_n, (unsigned int)(EVQ + ovq)) : 0;
-  const Event *ovf = p.ovf + (size_t)blockIdx.x * OVQ;
+  const Event *ovf = p.ovf + (size_t)blockIdx.x * (size_t)p.ovq;
   // one inlined copy of the round (the kernel's instruction footprint matters)
   int emitted = 0, r0 = 0;
   do {
@@ -1191,7 +1191,7 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
       unsigned int q0 = 0;
       if (lane == 0) q0 = atomicAdd(sh.evq_n, tot);
       q0 = (unsigned int)__shfl((int)q0, 0, 64);
-      const unsigned int lim = (unsigned int)EVQ + ((long long)blockIdx.x < p.ovf_wgs ? (unsigned int)OVQ : 0u);
+      const unsigned int lim = (unsigned int)EVQ + ((long long)blockIdx.x < p.ovf_wgs ? (unsigned int)p.ovq : 0u);
       const unsigned int over0 = q0 > lim ? q0 : lim;
       const unsigned int n_over = q0 + tot > lim ? q0 + tot - over0 : 0u;
       unsigned long long gb = 0;
@@ -1213,7 +1213,7 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
         if (q < (unsigned int)EVQ) {
           sh.evq[q] = ev;
         } else if (q < lim) {
-          p.ovf[(size_t)blockIdx.x * OVQ + (q - EVQ)] = ev;
+          p.ovf[(size_t)blockIdx.x * (size_t)p.ovq + (q - EVQ)] = ev;
         } else {
           const unsigned long long e = gb + (unsigned long long)(q - over0);
           if (e < (unsigned long long)c.evcap) {
