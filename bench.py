@@ -1025,11 +1025,13 @@ def main():
         log("[bench] autotuning")
         tuning = sim.autotune(mode, gapsim.GUESS_DIRECT, trial_steps=8, cache_path=args.tuning_cache or None)
         log(f"[bench] tuning: {tuning}")
-    if args.compact_every:
-        sim.set_option(gapsim.OPT_COMPACT_EVERY, args.compact_every)
-    elif tuning is None:
-        sim.set_option(gapsim.OPT_COMPACT_EVERY, 32)
     interval = args.compact_every or (tuning["compact_every"] if tuning else 32)
+    # a timed window shorter than the interval holds one compaction all the
+    # same (it ends with one), which would charge the whole interval's
+    # compaction to fewer steps: the interval is then the window's length
+    if not args.compact_every and args.steps < interval:
+        interval = args.steps
+    sim.set_option(gapsim.OPT_COMPACT_EVERY, interval)
     launch = sim.launch()
     log(f"[bench] warmup {args.warmup} steps")
     sim.step(mode, args.warmup)
@@ -1093,6 +1095,7 @@ def main():
                    else "saturating yield 0.5 E/(E + 1 keV), Exp(3 eV)",
                    "emitted_in_timed_steps": int((d1["emit_cum"] - d0["emit_cum"]).sum()),
                    "launch": launch, "autotuned": tuning is not None,
+                   "autotuned_compact_every": tuning["compact_every"] if tuning else None,
                    "untimed_steps_before": args.warmup + align,
                    "compactions_in_timed_steps": (args.warmup + align + args.steps) // interval
                    - (args.warmup + align) // interval},

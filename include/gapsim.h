@@ -209,12 +209,16 @@ enum {
   GS_OPT_DEPOSIT = 9,      /* binary32 deposit cells: 0 auto, 1 64-bit, 2 32-bit with carries */
   GS_OPT_COMPACT_GRID = 10,/* workgroups of the compaction kernel (>= 1) */
   GS_OPT_PPT = 11,         /* 16-byte particle vectors per thread per chunk: 1 (default) or 2 */
-  GS_OPT_SORT_BIN = 12     /* 0 (default): every GS_OPT_COMPACT_EVERY steps absorbed slots are
+  GS_OPT_SORT_BIN = 12,    /* 0 (default): every GS_OPT_COMPACT_EVERY steps absorbed slots are
                               reclaimed in place of order; >= 4: instead the live particles
                               are counting-sorted by bins of this many cells, so that each
                               push workgroup deposits onto, and flushes, a narrow band of
                               nodes; the secondary emission of a push then runs in its own
                               kernel right after it.  Results do not depend on it. */
+  GS_OPT_STEAL = 13        /* k in 2..64: the last 1/k of each push workgroup's run of tiles
+                              goes to a pool that workgroups done with their own runs draw
+                              from, one tile at a time; 0 (default): fixed runs.  Results do
+                              not depend on it. */
 };
 
 typedef struct gs_ctx gs_ctx;
@@ -442,7 +446,7 @@ typedef struct {
   int32_t deposit;        /* GS_OPT_DEPOSIT value */
   int32_t compact_every;  /* steps between compactions (or cell sorts) */
   int32_t sort_bin;       /* GS_OPT_SORT_BIN value (0: compaction without sorting) */
-  int32_t pad;
+  int32_t steal;          /* GS_OPT_STEAL value */
   double ms_per_step;     /* measured time per step of the chosen configuration
                              (gs_get_launch: 0) */
 } gs_tuning;

@@ -470,6 +470,7 @@ static gs_status setup(gs_ctx *ctx) {
   ALLOC(d.ovf, Event *, (size_t)std::max<int64_t>(d.ovf_wgs, 1) * (size_t)d.ovq * sizeof(Event));
   ALLOC(d.epoch, int64_t *, 8);
   ALLOC(d.err, unsigned int *, 8);
+  ALLOC(d.steal, unsigned int *, 256);
   ALLOC(d.gc, const GapConst *, sizeof(GapConst) * (size_t)G);
   ALLOC(d.gs, GapState *, sizeof(GapState) * (size_t)G);
 #undef ALLOC
@@ -487,6 +488,7 @@ static gs_status setup(gs_ctx *ctx) {
   HIPCHK(ctx, hipMemsetAsync(d.tally, 0, (size_t)G * T_N * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.ev_count, 0, (size_t)G * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.ev_done, 0, (size_t)G * 8, s));
+  HIPCHK(ctx, hipMemsetAsync(d.steal, 0, 256, s));
   HIPCHK(ctx, hipMemsetAsync(d.hist, 0, bins * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.bcur, 0, bins * 8, s));
   for (int g = 0; g < G; ++g)
@@ -512,6 +514,7 @@ static gs_status setup(gs_ctx *ctx) {
   ctx->lc.compact_grid = 4 * ctx->ncu;
   ctx->lc.ppt = ctx->fp64 ? 2 : 4;
   ctx->lc.sort_bin = 0;
+  ctx->lc.steal = 0;
   choose_launch(ctx);
   return GS_OK;
 }
@@ -1399,7 +1402,8 @@ std::string tune_key(const gs_ctx *ctx, int mode, int guess, long long live) {
   int lg = 0;
   while ((1ll << (lg + 1)) <= live) ++lg;
   std::ostringstream k;
-  k << "G=" << ctx->G << ",nmax=" << ctx->nmax << ",fp=" << (ctx->fp64 ? 64 : 32) << ",mode=" << mode
+  // (v2: lines carry the pool share after the sort bin)
+  k << "v2,G=" << ctx->G << ",nmax=" << ctx->nmax << ",fp=" << (ctx->fp64 ? 64 : 32) << ",mode=" << mode
     << ",guess=" << guess << ",log2live=" << lg << ",cu=" << ctx->ncu;
   return k.str();
 }
@@ -1414,6 +1418,7 @@ static void apply_tuning(gs_ctx *ctx, const gs_tuning &t) {
   ctx->lc.grid = t.grid;
   ctx->compact_every = t.compact_every;
   ctx->lc.sort_bin = t.sort_bin;
+  ctx->lc.steal = t.steal;
   choose_launch(ctx);
   ctx->lc.grid = t.grid;
   drop_graphs(ctx);
@@ -1428,6 +1433,7 @@ static gs_tuning current_tuning(const gs_ctx *ctx) {
   t.deposit = ctx->deposit_opt;
   t.compact_every = ctx->compact_every;
   t.sort_bin = ctx->lc.sort_bin;
+  t.steal = ctx->lc.steal;
   return t;
 }
 
@@ -1463,7 +1469,8 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
       if (bar == std::string::npos || line.substr(0, bar) != key) continue;
       gs_tuning t{};
       std::istringstream v(line.substr(bar + 1));
-      if (v >> t.block >> t.tile >> t.grid >> t.ppt >> t.deposit >> t.compact_every >> t.sort_bin >> t.ms_per_step) {
+      if (v >> t.block >> t.tile >> t.grid >> t.ppt >> t.deposit >> t.compact_every >> t.sort_bin >> t.steal >>
+          t.ms_per_step) {
         const LaunchCfg keep = ctx->lc;
         apply_tuning(ctx, t);
         if (!launch_fits(ctx)) {
@@ -1587,6 +1594,20 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
         if (ms < best.ms_per_step) best = t;
       }
   }
+  // then the share of tiles that go to the push's pool (off, a quarter, an
+  // eighth), over the same span
+  if (r == GS_OK) {
+    const gs_tuning base = best;
+    best.ms_per_step = 1e300;
+    for (int k : {0, 4, 8}) {
+      gs_tuning t = base;
+      t.steal = k;
+      double ms = 0;
+      if ((r = trial(t, std::max(trial_steps, 2 * t.compact_every), &ms, true)) != GS_OK) break;
+      t.ms_per_step = ms;
+      if (ms < best.ms_per_step) best = t;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   gs_status rr = restore();
@@ -1610,7 +1631,7 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
   if (cache_path && *cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     f << key << "|" << best.block << " " << best.tile << " " << best.grid << " " << best.ppt << " " << best.deposit
-      << " " << best.compact_every << " " << best.sort_bin << " " << best.ms_per_step << "\n";
+      << " " << best.compact_every << " " << best.sort_bin << " " << best.steal << " " << best.ms_per_step << "\n";
   }
   if (out) *out = best;
   return GS_OK;
@@ -1653,6 +1674,10 @@ extern "C" gs_status gs_set_option(gs_ctx *ctx, int32_t option, int64_t value) {
         return fail(ctx, GS_EINVAL, "a sort bin of %lld cells needs more than 160 KiB of LDS for %d gaps",
                     (long long)value, ctx->G);
       ctx->lc.sort_bin = (int)value;
+      break;
+    case GS_OPT_STEAL:
+      if (value != 0 && (value < 2 || value > 64)) return fail(ctx, GS_EINVAL, "steal must be 0 or 2..64");
+      ctx->lc.steal = (int)value;
       break;
     case GS_OPT_COMPACT_GRID:
       if (value < 1 || value > 1 << 20) return fail(ctx, GS_EINVAL, "compact grid out of range");

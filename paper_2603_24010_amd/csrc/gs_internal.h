@@ -120,6 +120,7 @@ struct DevPtrs {
   void *ehat;                      // field table for the push, binary32 or binary64
   int64_t *epoch;                  // compaction epoch (device)
   unsigned int *err;               // [0] flags, [1] gap of first error
+  unsigned int *steal;             // the push's pool counter, cleared by the field solve
   Event *ev;                       // absorbed-ion events, per-gap lists
   unsigned long long *ev_count;    // [G]
   unsigned long long *ev_done;     // [G] events of the list already emitted by k_emit
@@ -177,6 +178,8 @@ struct LaunchCfg {
   int sort_bin;      // cells per bin of the periodic counting sort that replaces the
                      // compaction (0: plain compaction); with it the push queues no
                      // events past its LDS queue and k_emit emits them after the push
+  int steal;         // the last 1/steal of each push workgroup's tiles go to a pool
+                     // that workgroups done with their own draw from (0: none)
 };
 
 // launchers (gs_kernels.hip)

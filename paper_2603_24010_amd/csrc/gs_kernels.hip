@@ -585,6 +585,8 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
       av0[q] = k <= n0 ? a0[k] : 0ull;
     }
   }
+  // the coming push's tile pool starts empty
+  if (g == 0 && tid == 0) *p.steal = 0u;
   // stage the gap's constants, state and last push's tallies in LDS
   if (tid < T_N) {
     unsigned long long *tl = p.tally + (size_t)g * T_N;
@@ -950,7 +952,12 @@ __device__ inline int emit_round(const DevPtrs &p, const GapConst &c0, const Gap
                                  unsigned long long *s_base) {
   // the emission's constants are read here, not at the kernel's start (held
   // in registers across the push they would spill)
-  const GapConst *cp = &c0;
+  // (the pointer is the workgroup's: moved to scalar registers half by half,
+  // which the empty asm then pins)
+  const unsigned long long cu = (unsigned long long)&c0;
+  const GapConst *cp = (const GapConst *)(((unsigned long long)(unsigned int)__builtin_amdgcn_readfirstlane(
+                                               (int)(cu >> 32)) << 32) |
+                                          (unsigned int)__builtin_amdgcn_readfirstlane((int)cu));
   asm volatile("" : "+s"(cp));
   const GapConst &c = *cp;
   const int i = r0 + (int)threadIdx.x;
@@ -1252,7 +1259,7 @@ __device__ inline void load_chunk(const P *X, const P *U, long long r0, typename
 template <class P, class AC, int BS, int PPT>
 __device__ void push_range(const DevPtrs &p, const GapConst &gc, const GapState &st, int g, int s, int sel,
                            PushShared<P, AC> &sh, long long a, long long b, long long kb0, long long kb1,
-                           SegCount &cnt) {
+                           bool stage, SegCount &cnt) {
   typedef typename Vec<P>::type V;
   constexpr int VN = Vec<P>::n;
   constexpr int NV = PPT / VN;
@@ -1271,9 +1278,13 @@ __device__ void push_range(const DevPtrs &p, const GapConst &gc, const GapState 
   const long long zhi = (long long)gc.Z[s] * 4294967296ll;
   const long long nfull = (b - a) / CH;
   V xa[NV], ua[NV], xb[NV], ub[NV];
-  // the first chunk's loads are in flight while the segment is staged
+  // the first chunk's loads are in flight while the segment is staged (or,
+  // when the segment is already open, while this range's beam goes in)
   if (nfull > 0) load_chunk<P, BS, PPT>(X, U, a, xa, ua);
-  load_seg<P, AC>(p, gc, st, g, sel, sh, kb0, kb1);
+  if (stage)
+    load_seg<P, AC>(p, gc, st, g, sel, sh, kb0, kb1);
+  else if (kb1 > kb0)
+    beam_inject<P, AC>(p, gc, st, g, sel, kb0, kb1, sh.acc, &sh.tally[T_INJ]);
   // one copy of the chunk body (the kernel's instruction footprint is what
   // limits it): the next chunk's loads go out before this chunk is pushed,
   // and the buffers are swapped by register moves
@@ -1301,8 +1312,63 @@ __device__ void push_range(const DevPtrs &p, const GapConst &gc, const GapState 
   }
 }
 
+// A piece is a run of tiles within one (gap, species) segment.  A segment
+// stays open in LDS (table, node sums, event queue, tallies) while the
+// workgroup's pieces continue it, and is flushed when the next piece belongs to
+// another segment, or at the end.  (og, os): the open segment, og < 0 for none.
+// (Plain functions, not lambdas: a closure holding the kernel's argument block
+// by address would copy it to the stack.)
+template <class P, class AC>
+__device__ __forceinline__ void close_seg(const DevPtrs &p, PushShared<P, AC> &sh, int sel, int og, int os) {
+  // (workgroup-uniform; made scalars for the emission's scalar loads)
+  const int g = __builtin_amdgcn_readfirstlane(og), s = __builtin_amdgcn_readfirstlane(os);
+  flush_seg<P, AC>(p, p.gc[g], p.gs[g], g, s, sel, sh);
+}
+
 template <class P, class AC, int BS, int PPT>
-__global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int nmax) {
+__device__ __forceinline__ void push_piece(const DevPtrs &p, PushShared<P, AC> &sh, int tile, int sel, int g,
+                                           int s, int ls, int le, int &og, int &os) {
+  g = __builtin_amdgcn_readfirstlane(g);
+  s = __builtin_amdgcn_readfirstlane(s);
+  ls = __builtin_amdgcn_readfirstlane(ls);
+  le = __builtin_amdgcn_readfirstlane(le);
+  const GapConst &c = p.gc[g];
+  const GapState &st = p.gs[g];
+  int te, ti;
+  gap_tiles(st, st.beam_now, tile, te, ti);
+  const bool stage = !(g == og && s == os);
+  if (stage && og >= 0) close_seg<P, AC>(p, sh, sel, og, os);
+  SegCount cnt;
+  const long long a = (long long)ls * tile;
+  const long long b = min((long long)le * tile, st.count[s]);
+  // the beam is split over the gap's ion tiles, tile lt taking ions
+  // [beam lt / ti, beam (lt + 1) / ti)
+  const long long kb0 = s == 1 ? st.beam_now * ls / ti : 0, kb1 = s == 1 ? st.beam_now * le / ti : 0;
+  push_range<P, AC, BS, PPT>(p, c, st, g, s, sel, sh, a, b, kb0, kb1, stage, cnt);
+  // wave-level sums, then one LDS atomic per wave
+  const unsigned int v0 = wave_sum(cnt.pushed), v1 = wave_sum(cnt.abs0), v2 = wave_sum(cnt.abs1);
+  if ((threadIdx.x & 63) == 0) {
+    if (v0) atomicAdd(&sh.tally[T_PUSHED], v0);
+    if (v1) atomicAdd(&sh.tally[T_ABS + s * 2 + 0], v1);
+    if (v2) atomicAdd(&sh.tally[T_ABS + s * 2 + 1], v2);
+  }
+  og = g;
+  os = s;
+}
+
+// the pieces of the global tiles [ta, tb) of gap g, whose tiles start at t_g
+template <class P, class AC, int BS, int PPT>
+__device__ __forceinline__ void push_tiles(const DevPtrs &p, PushShared<P, AC> &sh, int tile, int sel, int g,
+                                           int t_g, int ta, int tb, int &og, int &os) {
+  int te, ti;
+  gap_tiles(p.gs[g], p.gs[g].beam_now, tile, te, ti);
+  const int la = ta - t_g, lb = tb - t_g;
+  if (la < te) push_piece<P, AC, BS, PPT>(p, sh, tile, sel, g, 0, la, min(lb, te), og, os);
+  if (lb > te) push_piece<P, AC, BS, PPT>(p, sh, tile, sel, g, 1, max(la, te) - te, lb - te, og, os);
+}
+
+template <class P, class AC, int BS, int PPT>
+__global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int nmax, int steal) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   typedef typename AC::cell cell;
   __shared__ int scan_sh[BS];
@@ -1358,39 +1424,60 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
 
   auto prefix = [&](int i) { return G == 1 ? (i == 0 ? 0 : total1) : sh.prefix[i]; };
 
-  // this workgroup's contiguous run of tiles, taken one (gap, species)
-  // segment at a time
+  // the workgroup's contiguous run of tiles; with stealing on, the last R of
+  // every run go to the pool instead (runs differ by at most one tile, so each
+  // holds at least 8 R)
   const int total = prefix(G);
-  const int t1 = (int)(((long long)(blockIdx.x + 1) * total) / gridDim.x);
-  int t = (int)(((long long)blockIdx.x * total) / gridDim.x);
-  int g = 0;
-  while (t < t1) {
-    while (prefix(g + 1) <= t) ++g;
-    const GapConst &c = p.gc[g];
-    const GapState &st = p.gs[g];
-    int te, ti;
-    gap_tiles(st, st.beam_now, tile, te, ti);
-    const int lt = t - prefix(g);
-    const int s = lt < te ? 0 : 1;
-    const int seg_end = min(s == 0 ? te : te + ti, t1 - prefix(g));
-    const int ls = s == 0 ? lt : lt - te;
-    const int le = s == 0 ? seg_end : seg_end - te;
-    SegCount cnt;
-    const long long a = (long long)ls * tile;
-    const long long b = min((long long)le * tile, st.count[s]);
-    // this workgroup's share of the beam: in proportion to its ion tiles
-    const long long kb0 = s == 1 ? st.beam_now * ls / ti : 0, kb1 = s == 1 ? st.beam_now * le / ti : 0;
-    push_range<P, AC, BS, PPT>(p, c, st, g, s, sel, sh, a, b, kb0, kb1, cnt);
-    // wave-level sums, then one LDS atomic per wave
-    const unsigned int v0 = wave_sum(cnt.pushed), v1 = wave_sum(cnt.abs0), v2 = wave_sum(cnt.abs1);
-    if (lane == 0) {
-      if (v0) atomicAdd(&sh.tally[T_PUSHED], v0);
-      if (v1) atomicAdd(&sh.tally[T_ABS + s * 2 + 0], v1);
-      if (v2) atomicAdd(&sh.tally[T_ABS + s * 2 + 1], v2);
+  const int nwg = (int)gridDim.x;
+  const int R = p.steal != nullptr && steal > 0 ? (total / nwg) / steal : 0;
+  const int t0 = (int)(((long long)blockIdx.x * total) / nwg);
+  const int t1 = (int)(((long long)(blockIdx.x + 1) * total) / nwg) - R;
+  int og = -1, os = 0;  // the open segment (gap, species), none yet
+  {
+    int g = 0, t = t0;
+    while (t < t1) {
+      while (prefix(g + 1) <= t) ++g;
+      const int e = min(t1, prefix(g + 1));
+      push_tiles<P, AC, BS, PPT>(p, sh, tile, sel, g, prefix(g), t, e, og, os);
+      t = e;
     }
-    flush_seg<P, AC>(p, c, st, g, s, sel, sh);
-    t += seg_end - lt;
   }
+  if (R > 0) {
+    // pool tile q is tile k = q / nwg of run w = q % nwg's reserved end: the
+    // first reserved tile of every run goes out first
+    // (the next index is taken while a tile is pushed: the counter is one
+    // address for the whole device, and its atomics return slowly)
+    __shared__ int s_q;
+    const int npool = R * nwg;
+    unsigned int qn = 0u;
+    if (tid == 0) qn = atomicAdd(p.steal, 1u);
+    for (;;) {
+      __syncthreads();
+      if (tid == 0) s_q = (int)qn;
+      __syncthreads();
+      // (the same for every thread: made a scalar, as the tile arithmetic is)
+      const int q = __builtin_amdgcn_readfirstlane(s_q);
+      if (q >= npool) break;
+      if (tid == 0) qn = atomicAdd(p.steal, 1u);
+      const int w = q % nwg, k = q / nwg;
+      const int tt = (int)(((long long)(w + 1) * total) / nwg) - R + k;
+      // the gap holding tile tt (binary search over the tile prefix)
+      int g = 0;
+      if (G > 1) {
+        int lo = 0, hi = G - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (prefix(mid) <= tt)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        g = lo;
+      }
+      push_tiles<P, AC, BS, PPT>(p, sh, tile, sel, g, prefix(g), tt, tt + 1, og, os);
+    }
+  }
+  if (og >= 0) close_seg<P, AC>(p, sh, sel, og, os);
 }
 
 // The regions' new slot counts after a sort (flip: its particles are in the
@@ -2176,7 +2263,7 @@ static hipError_t push_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream
     attr_set = lds;
   }
   return launch_k(k_push<P, AC, BS, PPT>, dim3(lc.grid), dim3(BS), lds, s, t.a, t.b, p, G, lc.tile,
-                  lc.nmax);
+                  lc.nmax, lc.steal);
 }
 
 template <class P, class AC, int PPT>

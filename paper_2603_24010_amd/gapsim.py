@@ -25,6 +25,7 @@ GUESS_DIRECT, GUESS_EXTRAP, GUESS_MLP = 0, 1, 2
 OPT_BLOCK, OPT_TILE, OPT_GRID, OPT_COMPACT_EVERY, OPT_GRAPH, OPT_TIMING = 1, 2, 3, 4, 5, 6
 OPT_NEWTON_TOL, OPT_NEWTON_MAXIT, OPT_DEPOSIT, OPT_COMPACT_GRID, OPT_PPT = 7, 8, 9, 10, 11
 OPT_SORT_BIN = 12
+OPT_STEAL = 13
 
 EXPORTED = [
     "gs_init_gap", "gs_destroy", "gs_inject", "gs_step_strict", "gs_step_weak", "gs_read_diagnostics",
@@ -100,7 +101,7 @@ class GsTiming(C.Structure):
 class GsTuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("tile", C.c_int32), ("grid", C.c_int32), ("ppt", C.c_int32),
                 ("deposit", C.c_int32), ("compact_every", C.c_int32), ("sort_bin", C.c_int32),
-                ("pad", C.c_int32), ("ms_per_step", C.c_double)]
+                ("steal", C.c_int32), ("ms_per_step", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -192,7 +193,7 @@ def lib():
 
 def _tuning_dict(t) -> dict:
     return dict(block=t.block, tile=t.tile, grid=t.grid, ppt=t.ppt, deposit=t.deposit,
-                compact_every=t.compact_every, sort_bin=t.sort_bin, ms_per_step=t.ms_per_step)
+                compact_every=t.compact_every, sort_bin=t.sort_bin, steal=t.steal, ms_per_step=t.ms_per_step)
 
 
 class GapsimError(RuntimeError):

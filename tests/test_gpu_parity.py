@@ -350,8 +350,11 @@ def test_fp32_error_against_fp64_oracle(mode, n_cells):
 # ---------------------------------------------------------------------------
 # several gaps in one context
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("sort_bin", [0, 8])
-def test_batched_gaps_parity(sort_bin):
+@pytest.mark.parametrize("sort_bin,steal", [(0, 0), (8, 0), (0, 2)])
+def test_batched_gaps_parity(sort_bin, steal):
+    """Six gaps in one context against six oracles.  With steal on and five
+    push workgroups, half of every workgroup's tiles go to the pool, so pool
+    tiles switch between gaps and species."""
     gs = _gapsim()
     G = 6
     cfgs, loads = [], []
@@ -362,6 +365,9 @@ def test_batched_gaps_parity(sort_bin):
     sim = gs.GapSim(cfgs, particle_fp=32, capacity=(200_000, 200_000))
     sim.set_option(gs.OPT_COMPACT_EVERY, 5)
     sim.set_option(gs.OPT_SORT_BIN, sort_bin)
+    sim.set_option(gs.OPT_STEAL, steal)
+    if steal:
+        sim.set_option(gs.OPT_GRID, 5)
     orcs = []
     for g in range(G):
         o = oracle.OracleSim(cfgs[g], fp32=True)
@@ -418,6 +424,12 @@ def test_launch_shapes_and_graph_agree():
         {gs.OPT_COMPACT_EVERY: 3, gs.OPT_SORT_BIN: 4, gs.OPT_BLOCK: 512, gs.OPT_COMPACT_GRID: 5},
         {gs.OPT_COMPACT_EVERY: 5, gs.OPT_SORT_BIN: 1024, gs.OPT_GRAPH: 1, gs.OPT_DEPOSIT: 2},
         {gs.OPT_COMPACT_EVERY: 1, gs.OPT_SORT_BIN: 64, gs.OPT_PPT: 2, gs.OPT_GRID: 13},
+        # the tile pool: with a handful of workgroups, a half or a quarter of every
+        # run goes to the pool (electron and ion tiles, segment switches)
+        {gs.OPT_COMPACT_EVERY: 4, gs.OPT_GRID: 3, gs.OPT_STEAL: 2},
+        {gs.OPT_COMPACT_EVERY: 6, gs.OPT_GRID: 5, gs.OPT_STEAL: 4, gs.OPT_DEPOSIT: 2, gs.OPT_SORT_BIN: 16},
+        {gs.OPT_COMPACT_EVERY: 8, gs.OPT_GRID: 2, gs.OPT_STEAL: 2, gs.OPT_GRAPH: 1},
+        {gs.OPT_COMPACT_EVERY: 8, gs.OPT_STEAL: 0},
     ]
     for opts in variants:
         d, E, ions, els = _cfg2_state(opts)
