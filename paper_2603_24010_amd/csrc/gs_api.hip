@@ -424,6 +424,10 @@ static gs_status setup(gs_ctx *ctx) {
   ALLOC(d.rho64, double *, nodes * 8);
   ALLOC(d.E64, double *, nodes * 8);
   ALLOC(d.phi64, double *, nodes * 8);
+  ALLOC(d.fsl, double *, nodes * 8);
+  ALLOC(d.fpart, double *, (size_t)G * NCHMAX * 2 * 8);
+  ALLOC(d.foff, double *, (size_t)G * NCHMAX * 8);
+  ALLOC(d.fsig, double *, (size_t)G * 8);
   ALLOC(d.ehat, void *, etab * ps);
   ALLOC(d.ev, Event *, events * sizeof(Event));
   ALLOC(d.ev_count, unsigned long long *, (size_t)G * 8);

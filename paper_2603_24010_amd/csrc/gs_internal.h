@@ -121,6 +121,10 @@ struct DevPtrs {
   int64_t *epoch;                  // compaction epoch (device)
   unsigned int *err;               // [0] flags, [1] gap of first error
   unsigned int *steal;             // the push's pool counter, cleared by the field solve
+  // the field solve's hand-offs between its kernels: the prefix sums of the
+  // cell terms within chunks of FCN nodes (per node), the chunks' totals and
+  // weighted sums [G][NCHMAX][2], their offsets [G][NCHMAX], sigma [G]
+  double *fsl, *fpart, *foff, *fsig;
   Event *ev;                       // absorbed-ion events, per-gap lists
   unsigned long long *ev_count;    // [G]
   unsigned long long *ev_done;     // [G] events of the list already emitted by k_emit
@@ -153,6 +157,11 @@ struct DevPtrs {
 };
 
 enum { ERR_CAPACITY = 1u, ERR_BADINJECT = 2u, ERR_NOCONV = 4u };
+
+// Nodes per chunk of the field solve's density and table kernels, and the
+// chunks of the largest gap (16384 cells: nodes 0..16384).
+constexpr int FCN = 1024;
+constexpr int NCHMAX = 16384 / FCN + 1;
 
 // Smallest cell-sort bin (cells per bin): bounds the bin arrays and the LDS of
 // the sort kernels (16384 cells -> 4096 bins per species).

@@ -138,6 +138,29 @@ __device__ inline double block_exclusive_scan_w(double v, double *wsum, double *
   return before + incl - v;
 }
 
+// block_exclusive_scan_w of v, and in the same two barriers the block sum of w
+__device__ inline double block_exclusive_scan_sum_w(double v, double w, double *wsum, double *wsum2, double *total,
+                                                    double *wtotal) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const double incl = wave_incl_scan_d(v);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
+  if (lane == 63) wsum[wv] = incl;
+  if (lane == 0) wsum2[wv] = w;
+  __syncthreads();
+  double before = 0.0, all = 0.0, wall = 0.0;
+  for (int q = 0; q < nw; ++q) {
+    const double a = wsum[q];
+    if (q < wv) before += a;
+    all += a;
+    wall += wsum2[q];
+  }
+  *total = all;
+  *wtotal = wall;
+  __syncthreads();
+  return before + incl - v;
+}
+
 __device__ inline double block_sum_w(double v, double *wsum) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
@@ -302,13 +325,20 @@ __device__ void see_emit(const DevPtrs &p, const GapConst &c, long long level, i
 }
 
 // ---------------------------------------------------------------------------
-// k_field: level n of one gap per workgroup
+// The field solve of level n, in three kernels: k_fdens (the nodal density and
+// the prefix sums within chunks of FCN nodes, many workgroups), k_field (the
+// chunks' offsets, the circuit and the surface charge: one workgroup per gap)
+// and k_ftable (the half-grid field and the push's gather table, many
+// workgroups).
 // ---------------------------------------------------------------------------
-constexpr int FBS = 1024;
-// n_cells <= 16384: S_k of every cell is held in LDS (136 KiB at the maximum,
-// padded), and each thread forms at most FNQ nodes
-constexpr int FNQ = (16384 + 1 + FBS - 1) / FBS;
-
+constexpr int FBS = 1024;  // k_field threads
+constexpr int FDB = 256;   // k_fdens / k_ftable threads, four nodes each
+// Up to FIELD1_NMAX cells one workgroup per gap does all of it (k_field1): a
+// kernel costs some microseconds of its own here, and at 4096 cells the one
+// workgroup's serial path is shorter than three kernels'.  Its S_k live in LDS
+// (padded), and each thread forms at most FNQ nodes.
+constexpr int FIELD1_NMAX = 8192;
+constexpr int FNQ = (FIELD1_NMAX + 1 + FBS - 1) / FBS;
 __device__ inline double node_rho(double s0, double dx, unsigned long long a, int j, int N, int fp64) {
   const double scale = fp64 ? 5.684341886080801486968994140625e-14 /* 2^-44 */
                             : 5.9604644775390625e-08 /* 2^-24 */;
@@ -322,7 +352,8 @@ __device__ inline double node_rho(double s0, double dx, unsigned long long a, in
 // potential the space charge alone gives the electrode.
 __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState &st, double P,
                             int mode, int guess, double tol, int maxit, double *sigma_out,
-                            double *wk, const unsigned long long *tl, const double *mlp_u) {
+                            double *wk, const unsigned long long *tl, const double *mlp_u,
+                            const unsigned long long *next_count, long long nb) {
   const int M = c.M, gm = c.g;
   const double A = c.A, eps0 = c.eps0;
   const long long n = st.level + 1;
@@ -545,10 +576,10 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
   // them (its ids and slots are fixed before the push)
   // (append counters can run past the capacity after an overflow, which was
   // flagged when it happened; never sweep past the region)
-  for (int s = 0; s < 2; ++s) st.count[s] = min((long long)p.next_count[g * 2 + s], c.cap[s]);
-  // the beam of the step that solves level n: its schedule entry, else the
-  // fixed count
-  const long long nb = n < c.sched_len ? (long long)p.sched[c.sched_base + n] : c.beam_n;
+  // (next_count: the append counters as the push and the emission left them;
+  // nb: the beam of the step that solves level n, its schedule entry or else
+  // the fixed count; both read at the field kernel's start)
+  for (int s = 0; s < 2; ++s) st.count[s] = min((long long)next_count[s], c.cap[s]);
   st.beam_now = nb;
   p.next_count[g * 2 + 1] = (unsigned long long)(st.count[1] + nb);
   p.ev_count[g] = 0ull;
@@ -558,73 +589,75 @@ __device__ void solve_level(const DevPtrs &p, int g, const GapConst &c, GapState
   *sigma_out = sigma;
 }
 
-__global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, double tol,
-                                               int maxit, int fp64) {
+// k_field1: level n of one gap per workgroup, for grids up to FIELD1_NMAX
+// cells: the nodal density (the accumulator cleared for the next push), the
+// prefix sums S_k, the circuit and the surface charge, the half-grid field and
+// the push's gather table.
+__global__ __launch_bounds__(FBS) void k_field1(DevPtrs p, int mode, int guess, double tol,
+                                                int maxit, int fp64) {
   const int g = blockIdx.x, tid = threadIdx.x;
   extern __shared__ __align__(16) double Sk[];  // S_k, one per cell (padded, see the prefix sums)
-  __shared__ GapConst sc;
-  __shared__ GapState ss;
-  __shared__ double wsum[FBS / 64];
+  // the gap's constants, state and last push's tallies, staged as one block
+  // and the append counters as the push and the emission left them
+  struct Staged {
+    GapConst c;
+    GapState s;
+    unsigned long long tally[T_N];
+    unsigned long long next_count[2];
+  };
+  __shared__ Staged stg;
+  GapConst &sc = stg.c;
+  GapState &ss = stg.s;
+  unsigned long long *s_tally = stg.tally;
+  __shared__ double wsum[FBS / 64], wsum2[FBS / 64];
   __shared__ double s_sigma, s_rhoN;
   __shared__ double s_work[8 * MAXM + 8];
-  __shared__ unsigned long long s_tally[T_N];
   __shared__ float s_x[MLP_IN], s_h0[MLP_H], s_h1[MLP_H], s_y[MLP_OUT];
   __shared__ double s_ue[MAXM + 1], s_mu[MAXM + 1];
-  __shared__ int s_wsum_i[FBS / 64];
-  __shared__ unsigned long long s_ebase;
-  __shared__ unsigned int s_emit[2];
-  // the first FBS x 4 nodes of the push's charge accumulator, loaded before
-  // anything else (nothing in this kernel writes them before the density pass)
-  unsigned long long av0[4];
+  // the first FBS x AV0 nodes of the push's charge accumulator, loaded before
+  // anything else (nothing in this kernel writes them before the density pass),
+  // from clamped indices and masked afterwards: a guarded load would be waited
+  // for before the next is issued
+  // (secondary emission is complete when this kernel runs: the emission kernel
+  // ran after the push)
+  constexpr int AV0 = 5;
+  unsigned long long av0[AV0];
   {
     const int n0 = p.gc[g].N;
     const unsigned long long *a0 = p.acc + p.gc[g].nbase;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = tid + q * FBS;
-      av0[q] = k <= n0 ? a0[k] : 0ull;
-    }
+    for (int q = 0; q < AV0; ++q) av0[q] = a0[min(tid + q * FBS, n0)];
+#pragma unroll
+    for (int q = 0; q < AV0; ++q)
+      if (tid + q * FBS > n0) av0[q] = 0ull;
   }
   // the coming push's tile pool starts empty
   if (g == 0 && tid == 0) *p.steal = 0u;
-  // stage the gap's constants, state and last push's tallies in LDS
-  if (tid < T_N) {
-    unsigned long long *tl = p.tally + (size_t)g * T_N;
-    s_tally[tid] = tl[tid];
-    tl[tid] = 0ull;
-  }
+  // stage the gap's constants, state and last push's tallies: word tid of
+  // their concatenation per thread, one load and one LDS store with no branch;
+  // the tallies are cleared at the kernel's end
   {
-    const unsigned long long *a = (const unsigned long long *)&p.gc[g];
-    unsigned long long *b = (unsigned long long *)&sc;
-    for (int i = tid; i < (int)(sizeof(GapConst) / 8); i += FBS) b[i] = a[i];
-    a = (const unsigned long long *)&p.gs[g];
-    b = (unsigned long long *)&ss;
-    for (int i = tid; i < (int)(sizeof(GapState) / 8); i += FBS) b[i] = a[i];
+    constexpr int NC = (int)(sizeof(GapConst) / 8), NS = (int)(sizeof(GapState) / 8);
+    constexpr int NW = (int)(sizeof(Staged) / 8);
+    static_assert(sizeof(Staged) == sizeof(GapConst) + sizeof(GapState) + 8 * (T_N + 2) && NW <= FBS,
+                  "one staged word per thread");
+    const unsigned long long *src =
+        tid < NC ? (const unsigned long long *)&p.gc[g] + tid
+        : tid < NC + NS ? (const unsigned long long *)&p.gs[g] + (tid - NC)
+        : tid < NC + NS + T_N ? p.tally + (size_t)g * T_N + (tid - NC - NS)
+                              : p.next_count + (size_t)g * 2 + min(tid - NC - NS - T_N, 1);
+    const unsigned long long v = *src;
+    if (tid < NW) ((unsigned long long *)&stg)[tid] = v;
   }
-  if (tid < 2) s_emit[tid] = 0u;
   __syncthreads();
-
-  // absorbed ions the push could not queue in LDS (a full queue): their
-  // secondary electrons are emitted here, keyed by the push's level
-  unsigned long long ex0 = 0ull, exN = 0ull;
+  long long nbeam;
   {
-    const long long nall = min((long long)p.ev_count[g], sc.evcap);
-    const long long ndone = min((long long)p.ev_done[g], nall);
-    const long long nov = nall - ndone;
-    if (nov > 0) {
-      const Event *evs = p.ev + sc.evbase + ndone;
-      if (fp64)
-        see_emit<double>(p, sc, ss.level, g, (int)(*p.epoch & 1), evs, (int)nov, s_wsum_i, &s_ebase, s_emit);
-      else
-        see_emit<float>(p, sc, ss.level, g, (int)(*p.epoch & 1), evs, (int)nov, s_wsum_i, &s_ebase, s_emit);
-      __syncthreads();
-      const long long ze = (long long)sc.Z[0] * (fp64 ? (1ll << F64_BITS) : (1ll << F32_BITS));
-      ex0 = (unsigned long long)(ze * (long long)s_emit[0]);
-      exN = (unsigned long long)(ze * (long long)s_emit[1]);
-      __syncthreads();
-      if (tid < 2) s_tally[T_EMIT + tid] += s_emit[tid];
-      __syncthreads();
-    }
+    const long long n = ss.level + 1;
+    int lane0 = 0;
+    asm volatile("" : "+v"(lane0));
+    const long long ix = sc.sched_len > 0 ? sc.sched_base + min(n, sc.sched_len - 1) : 0;
+    const long long v = (long long)p.sched[ix + lane0];
+    nbeam = n < sc.sched_len ? v : sc.beam_n;
   }
 
   // 0. strict coupling: the guess network's input (the last 8 levels from the
@@ -679,15 +712,12 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   auto pad = [&](int k) { return k + (int)(((unsigned long long)k * chm) >> 32); };
   unsigned long long av[FNQ];
 #pragma unroll
-  for (int q = 0; q < FNQ; ++q) {
-    const int k = tid + q * FBS;
-    av[q] = q < 4 ? av0[q < 4 ? q : 0] : (k <= N ? acc[k] : 0ull);
-  }
+  for (int q = 0; q < FNQ; ++q) av[q] = q < AV0 ? av0[q < AV0 ? q : 0] : acc[min(tid + q * FBS, N)];
 #pragma unroll
   for (int q = 0; q < FNQ; ++q) {
     const int k = tid + q * FBS;
     if (k > N) break;
-    const double r = node_rho(s0, dx, av[q] + (k == 0 ? ex0 : 0ull) + (k == N ? exN : 0ull), k, N, fp64);
+    const double r = node_rho(s0, dx, av[q], k, N, fp64);
     rho[k] = r;
     acc[k] = 0ull;
     if (k < N)
@@ -707,28 +737,32 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
   double cv[FNQ];
 #pragma unroll
   for (int i = 0; i < FNQ; ++i) cv[i] = i < nk ? Sk[k0 + i + tid] : 0.0;
-  double loc = 0.0;
+  // with sum_k S_k = sum_j c_j (N - j) (c_j the cell terms) taken in the same
+  // reduction as the scan's wave totals
+  double loc = 0.0, wloc = 0.0;
 #pragma unroll
   for (int i = 0; i < FNQ; ++i)
-    if (i < nk) loc += cv[i];
-  double tot;
-  double run = block_exclusive_scan_w(loc, wsum, &tot);
-  double sumS = 0.0;
+    if (i < nk) {
+      loc += cv[i];
+      wloc += cv[i] * (double)(N - (k0 + i));
+    }
+  double tot, sumS;
+  double run = block_exclusive_scan_sum_w(loc, wloc, wsum, wsum2, &tot, &sumS);
 #pragma unroll
   for (int i = 0; i < FNQ; ++i)
     if (i < nk) {
       run += cv[i];
       Sk[k0 + i + tid] = run;
-      sumS += run;
     }
-  const double P = block_sum_w(sumS, wsum) * dx / eps0;
+  const double P = sumS * dx / eps0;
 
   // 2. circuit and surface charge
   if (tid == 0) {
     double sg;
     // space charge: the cell terms (rho_0 at half weight) plus the half cell at node N
     ss.q_space = sc.A * (tot + 0.5 * dx * s_rhoN);
-    solve_level(p, g, sc, ss, P, mode, guess, tol, maxit, &sg, s_work, s_tally, want_mlp ? s_mu : nullptr);
+    solve_level(p, g, sc, ss, P, mode, guess, tol, maxit, &sg, s_work, s_tally, want_mlp ? s_mu : nullptr,
+                stg.next_count, nbeam);
     s_sigma = sg;
     if (rec_here)
       for (int i = 0; i < MLP_OUT; ++i)
@@ -768,6 +802,252 @@ __global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, d
     const unsigned long long *a = (const unsigned long long *)&ss;
     unsigned long long *b = (unsigned long long *)&p.gs[g];
     for (int i = tid; i < (int)(sizeof(GapState) / 8); i += FBS) b[i] = a[i];
+  }
+  if (tid < T_N) p.tally[(size_t)g * T_N + tid] = 0ull;
+}
+
+
+// k_fdens: chunk c (blockIdx.x) of gap g (blockIdx.y), nodes [c FCN, (c + 1)
+// FCN) up to N.  Each node's density goes to rho and its accumulator word is
+// cleared for the next push; the cell terms c_k (dx rho_0 / 2, then dx rho_k,
+// k < N) are summed within the chunk: the inclusive prefix L_k to fsl, the
+// chunk's total and sum_k c_k (N - k) to fpart.
+__global__ __launch_bounds__(FDB) void k_fdens(DevPtrs p, int fp64) {
+  const int g = blockIdx.y, c = blockIdx.x, tid = threadIdx.x;
+  __shared__ double wsum[FDB / 64], wsum2[FDB / 64];
+  const GapConst &gc = p.gc[g];
+  const int N = gc.N;
+  const int kb = c * FCN + 4 * tid;  // this thread's first node
+  if (c * FCN > N) return;           // (the whole workgroup)
+  unsigned long long *acc = p.acc + gc.nbase;
+  double *rho = p.rho64 + gc.nbase;
+  double *sl = p.fsl + gc.nbase;
+  const double dx = gc.dx, s0 = gc.s0;
+  // (loads from clamped indices, all issued before the first is used)
+  unsigned long long a[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) a[i] = acc[min(kb + i, N)];
+  double cv[4];
+  double loc = 0.0, wloc = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int k = kb + i;
+    const double r = node_rho(s0, dx, a[i], k, N, fp64);
+    cv[i] = k < N ? (k == 0 ? dx * r / 2.0 : dx * r) : 0.0;
+    loc += cv[i];
+    wloc += cv[i] * (double)(N - k);
+    if (k <= N) {
+      rho[k] = r;
+      acc[k] = 0ull;
+    }
+  }
+  double tot, wtot;
+  double run = block_exclusive_scan_sum_w(loc, wloc, wsum, wsum2, &tot, &wtot);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    run += cv[i];
+    if (kb + i < N) sl[kb + i] = run;
+  }
+  if (tid == 0) {
+    double *pt = p.fpart + ((size_t)g * NCHMAX + c) * 2;
+    pt[0] = tot;
+    pt[1] = wtot;
+  }
+}
+
+// k_field: one workgroup per gap.  The chunks' totals give S_k's offsets, the
+// potential P = (dx / eps0) sum_k S_k that the space charge alone gives the
+// electrode and the space charge; thread 0 solves the circuit and the surface
+// charge (solve_level); the offsets and sigma go to k_ftable.
+__global__ __launch_bounds__(FBS) void k_field(DevPtrs p, int mode, int guess, double tol,
+                                               int maxit, int fp64) {
+  const int g = blockIdx.x, tid = threadIdx.x;
+  // the gap's constants, state and last push's tallies, staged as one block
+  // and the append counters as the push and the emission left them
+  struct Staged {
+    GapConst c;
+    GapState s;
+    unsigned long long tally[T_N];
+    unsigned long long next_count[2];
+  };
+  __shared__ Staged stg;
+  GapConst &sc = stg.c;
+  GapState &ss = stg.s;
+  unsigned long long *s_tally = stg.tally;
+  __shared__ double s_work[8 * MAXM + 8];
+  __shared__ float s_x[MLP_IN], s_h0[MLP_H], s_h1[MLP_H], s_y[MLP_OUT];
+  __shared__ double s_ue[MAXM + 1], s_mu[MAXM + 1];
+  // (secondary emission is complete when this kernel runs: the emission kernel
+  // ran after the push)
+  // the coming push's tile pool starts empty
+  if (g == 0 && tid == 0) *p.steal = 0u;
+  // the chunks' totals (lane c of wave 0) and rho_N, loaded before anything
+  // else (they do not depend on the staged state)
+  const int N0 = p.gc[g].N;
+  const int nch = N0 / FCN + 1;
+  double ptot = 0.0, pw = 0.0, rhoN = 0.0;
+  if (tid < 64) {
+    const double *pt = p.fpart + ((size_t)g * NCHMAX + min(tid, nch - 1)) * 2;
+    ptot = pt[0];
+    pw = pt[1];
+    rhoN = p.rho64[p.gc[g].nbase + N0];
+    if (tid >= nch) ptot = pw = 0.0;
+  }
+  // stage the gap's constants, state and last push's tallies: word tid of
+  // their concatenation per thread, one load and one LDS store with no branch
+  // (a guarded load is waited for inside its branch); the tallies are cleared at
+  // the kernel's end
+  {
+    constexpr int NC = (int)(sizeof(GapConst) / 8), NS = (int)(sizeof(GapState) / 8);
+    constexpr int NW = (int)(sizeof(Staged) / 8);
+    static_assert(sizeof(Staged) == sizeof(GapConst) + sizeof(GapState) + 8 * (T_N + 2) && NW <= FBS,
+                  "one staged word per thread");
+    const unsigned long long *src =
+        tid < NC ? (const unsigned long long *)&p.gc[g] + tid
+        : tid < NC + NS ? (const unsigned long long *)&p.gs[g] + (tid - NC)
+        : tid < NC + NS + T_N ? p.tally + (size_t)g * T_N + (tid - NC - NS)
+                              : p.next_count + (size_t)g * 2 + min(tid - NC - NS - T_N, 1);
+    const unsigned long long v = *src;
+    if (tid < NW) ((unsigned long long *)&stg)[tid] = v;
+  }
+  __syncthreads();
+  // the beam of the step that solves level n = level + 1: its schedule entry,
+  // else the fixed count
+  // (read from a clamped index and chosen afterwards, through an index the
+  // compiler takes for a per-lane one: a load on each side of the choice would
+  // become one flat load, and a uniform one a scalar load, either of which every
+  // later barrier's wait on LDS would also wait for; the schedule array holds
+  // at least one entry)
+  long long nbeam;
+  {
+    const long long n = ss.level + 1;
+    int lane0 = 0;
+    asm volatile("" : "+v"(lane0));
+    const long long ix = sc.sched_len > 0 ? sc.sched_base + min(n, sc.sched_len - 1) : 0;
+    const long long v = (long long)p.sched[ix + lane0];
+    nbeam = n < sc.sched_len ? v : sc.beam_n;
+  }
+
+  // 0. strict coupling: the guess network's input (the last 8 levels from the
+  //    history ring), recorded for training and/or evaluated for the guess
+  const bool want_mlp = mode == 0 && guess == GS_GUESS_MLP && p.mlp_w != nullptr;
+  const bool want_rec = mode == 0 && p.rec_x != nullptr;
+  const long long rec_idx = (ss.level + 1 - p.rec_level0) * (long long)gridDim.x + g;
+  const bool rec_here = want_rec && rec_idx >= 0 && rec_idx < p.rec_cap;
+  if (want_mlp || rec_here) {
+    if (tid < MLP_IN) {
+      // block k = 1..8: (V, I_0, I_1, sigma) of level n-k and the absorbed /
+      // emitted charge of the push that followed it (for k = 1 the push whose
+      // tallies this solve is about to fold in)
+      const int kk = tid / 6 + 1, q = tid % 6;
+      double raw;
+      if (q < 4) {
+        raw = ss.hist[(ss.hist_head - kk) & 7][q];
+      } else if (kk > 1) {
+        raw = ss.hist[(ss.hist_head - kk + 1) & 7][q];
+      } else {
+        const double qi = sc.A * (sc.s0 * (double)sc.Z[1]), qe = sc.A * (sc.s0 * (double)sc.Z[0]);
+        raw = q == 4 ? qi * (double)(long long)s_tally[T_ABS + 2] + qe * (double)(long long)s_tally[T_ABS + 0]
+                     : qe * (double)(long long)s_tally[T_EMIT + 0];
+      }
+      if (rec_here) p.rec_x[rec_idx * MLP_IN + tid] = (float)raw;
+      if (want_mlp) s_x[tid] = (float)((raw - p.mlp_norm[tid]) / p.mlp_norm[MLP_IN + tid]);
+    }
+    if (tid == 0)
+      for (int i = 0; i <= sc.M; ++i) s_ue[i] = 3.0 * ss.uh[0][i] - 3.0 * ss.uh[1][i] + ss.uh[2][i];
+    if (want_mlp) {
+      mlp_eval_block(p.mlp_w, s_x, s_h0, s_h1, s_y);
+      if (tid == 0)
+        for (int i = 0; i < MLP_OUT; ++i)
+          s_mu[i] = s_ue[i] + p.mlp_norm[2 * MLP_IN + i] + p.mlp_norm[2 * MLP_IN + MLP_OUT + i] * (double)s_y[i];
+    }
+  }
+
+  const int N = sc.N;
+  const double dx = sc.dx, eps0 = sc.eps0, s0 = sc.s0;
+  unsigned long long *acc = p.acc + sc.nbase;
+  double *rho = p.rho64 + sc.nbase;
+  double *E = p.E64 + sc.nbase;
+
+  // 1. the chunks' offsets O_c (exclusive prefix of their totals) for
+  //    k_ftable, the total S_{N-1} and sum_k S_k = sum_k c_k (N - k)
+  if (tid < 64) {
+    double run = ptot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double t = __shfl_up(run, o, 64);
+      if (tid >= o) run += t;
+    }
+    double wsumall = pw;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wsumall += __shfl_xor(wsumall, o, 64);
+    const double tot = __shfl(run, 63, 64);
+    if (tid < nch) p.foff[(size_t)g * NCHMAX + tid] = run - ptot;
+    // 2. circuit and surface charge
+    if (tid == 0) {
+      const double dx = sc.dx, eps0 = sc.eps0;
+      const double P = wsumall * dx / eps0;
+      double sg;
+      // space charge: the cell terms (rho_0 at half weight) plus the half cell at node N
+      ss.q_space = sc.A * (tot + 0.5 * dx * rhoN);
+      solve_level(p, g, sc, ss, P, mode, guess, tol, maxit, &sg, s_work, s_tally, want_mlp ? s_mu : nullptr,
+                  stg.next_count, nbeam);
+      p.fsig[g] = sg;
+      const size_t eb = (size_t)sc.ebase;
+      if (fp64)
+        ((double *)p.ehat)[eb] = sg / eps0;
+      else
+        ((float *)p.ehat)[eb] = (float)(sg / eps0);
+      if (rec_here)
+        for (int i = 0; i < MLP_OUT; ++i)
+          p.rec_y[rec_idx * MLP_OUT + i] = i <= sc.M ? (float)(ss.uh[0][i] - s_ue[i]) : 0.0f;
+    }
+  }
+  __syncthreads();
+  {
+    const unsigned long long *a = (const unsigned long long *)&ss;
+    unsigned long long *b = (unsigned long long *)&p.gs[g];
+    for (int i = tid; i < (int)(sizeof(GapState) / 8); i += FBS) b[i] = a[i];
+  }
+  if (tid < T_N) p.tally[(size_t)g * T_N + tid] = 0ull;
+}
+
+// k_ftable: the half-grid field E_{k+1/2} = (sigma + S_k) / eps0, S_k = O_c +
+// L_k, for the cells k < N of chunk c of gap g, and the push's gather table
+// (E at the electrode, the half-grid values, and at node N the field the half
+// cell's charge adds to the last value; that one is also the gap's e_ground).
+__global__ __launch_bounds__(FDB) void k_ftable(DevPtrs p, int fp64) {
+  const int g = blockIdx.y, c = blockIdx.x, tid = threadIdx.x;
+  const GapConst &gc = p.gc[g];
+  const int N = gc.N;
+  if (c * FCN >= N) return;  // (the whole workgroup)
+  const int kb = c * FCN + 4 * tid;
+  const double *sl = p.fsl + gc.nbase;
+  double *E = p.E64 + gc.nbase;
+  const double off = p.foff[(size_t)g * NCHMAX + c], sigma = p.fsig[g];
+  const double eps0 = gc.eps0, dx = gc.dx;
+  const size_t eb = (size_t)gc.ebase;
+  double L[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) L[i] = sl[min(kb + i, N - 1)];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int k = kb + i;
+    if (k >= N) break;
+    const double e = (sigma + (off + L[i])) / eps0;
+    E[k] = e;
+    if (fp64)
+      ((double *)p.ehat)[eb + k + 1] = e;
+    else
+      ((float *)p.ehat)[eb + k + 1] = (float)e;
+    if (k == N - 1) {
+      const double ed = e + dx * p.rho64[gc.nbase + N] / (2.0 * eps0);
+      p.gs[g].e_ground = ed;
+      if (fp64)
+        ((double *)p.ehat)[eb + N + 1] = ed;
+      else
+        ((float *)p.ehat)[eb + N + 1] = (float)ed;
+    }
   }
 }
 
@@ -2238,17 +2518,26 @@ static hipError_t launch_k(K kernel, dim3 grid, dim3 block, size_t lds, hipStrea
 
 hipError_t launch_field(const DevPtrs &p, int G, int mode, int guess, double tol, int maxit,
                         int fp64, int nmax, hipStream_t s, KTime t) {
-  // S_k of every cell, padded by one double per chunk of the prefix sums
-  // (index k + k / ch < N + FBS)
-  const size_t lds = ((size_t)nmax + (size_t)FBS + 1) * 8;
-  static size_t attr_set = 32768;
-  if (lds > attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_field, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = lds;
+  if (nmax <= FIELD1_NMAX) {
+    // S_k of every cell, padded by one double per chunk of the prefix sums
+    // (index k + k / ch < N + FBS)
+    const size_t lds = ((size_t)nmax + (size_t)FBS + 1) * 8;
+    static size_t attr_set = 32768;
+    if (lds > attr_set) {
+      hipError_t e = hipFuncSetAttribute((const void *)k_field1, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds);
+      if (e != hipSuccess) return e;
+      attr_set = lds;
+    }
+    return launch_k(k_field1, dim3(G), dim3(FBS), lds, s, t.a, t.b, p, mode, guess, tol, maxit, fp64);
   }
-  return launch_k(k_field, dim3(G), dim3(FBS), lds, s, t.a, t.b, p, mode, guess, tol, maxit, fp64);
+  // events (when timing) on the first and the last of the three launches
+  const dim3 chunks((unsigned)(nmax / FCN + 1), (unsigned)G);
+  hipError_t e = launch_k(k_fdens, chunks, dim3(FDB), 0, s, t.a, nullptr, p, fp64);
+  if (e != hipSuccess) return e;
+  e = launch_k(k_field, dim3(G), dim3(FBS), 0, s, nullptr, nullptr, p, mode, guess, tol, maxit, fp64);
+  if (e != hipSuccess) return e;
+  return launch_k(k_ftable, chunks, dim3(FDB), 0, s, nullptr, t.b, p, fp64);
 }
 
 template <class P, class AC, int BS, int PPT>

@@ -385,6 +385,50 @@ def test_batched_gaps_parity(sort_bin, steal):
         check_run(recs[g], 1e-5, cfgs[g].n_mesh, cfgs[g], oracle.STRICT)
 
 
+@pytest.mark.parametrize("mode", [oracle.STRICT, oracle.WEAK])
+def test_mixed_grid_sizes_parity(mode):
+    """A 16384-cell gap and a 700-cell gap in one context: past 8192 cells the
+    field solve runs as three kernels over chunks of 1024 nodes, and the small
+    gap's chunks past its own last node have nothing to do.  Both gaps against
+    their oracles, with the binary32 particles bit-equal."""
+    gs = _gapsim()
+    cfgs = [cfg2_small(n_cells=16384, beam=1500), cfg2_small(n_cells=700, beam=800)]
+    loads = [W.load_config2(n=60_000, seed=31), W.load_config2(n=20_000, seed=32)]
+    sim = gs.GapSim(cfgs, particle_fp=32, capacity=(200_000, 200_000))
+    sim.set_option(gs.OPT_COMPACT_EVERY, 4)
+    orcs = []
+    for g in range(2):
+        o = oracle.OracleSim(cfgs[g], fp32=True)
+        for sp in sorted(loads[g]):
+            x, v = loads[g][sp]
+            sim.inject(g, sp, x, v)
+            o.inject(sp, x, v)
+        orcs.append(o)
+    recs = [[], []]
+    for n in range(20):
+        sim.step(mode, 1)
+        for g in range(2):
+            orcs[g].step(mode, 1)
+            recs[g].append((sim.diag(g), orcs[g].diag()))
+    for g in range(2):
+        check_run(recs[g], 1e-5, cfgs[g].n_mesh, cfgs[g], mode)
+        for dg, do in recs[g]:
+            assert_counts_equal(dg, do)
+        pg, Eg, rg = sim.fields(g)
+        po, Eo, ro = orcs[g].fields()
+        for name, a, b in (("rho", rg, ro), ("E", Eg, Eo), ("phi", pg, po)):
+            assert rel(a, b) <= 1e-5, (g, name, rel(a, b))
+        for sp in (0, 1):
+            xg, ug, _ = sim.particles(g, sp)
+            xo, uo, _ = orcs[g].particles_f32(sp)
+            assert len(xg) == len(xo)
+            a, b = sorted_state(xg, ug), sorted_state(xo, uo)
+            np.testing.assert_array_equal(a[0], b[0])
+            np.testing.assert_array_equal(a[1], b[1])
+    assert recs[0][-1][0]["abs_cum"][1].sum() > 0
+    sim.close()
+
+
 # ---------------------------------------------------------------------------
 # launch configurations, graphs, determinism, edge cases
 # ---------------------------------------------------------------------------
