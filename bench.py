@@ -219,7 +219,7 @@ def run_batched(args, name, copy_gbs):
     from paper_2603_24010_amd import gapsim
     spec = BATCHED[name]
     log(f"[bench] building {spec['gaps']} gaps")
-    sim, cfgs, n0 = make_batched(spec["gaps"], spec["cells"], spec["seed0"], args.warmup + args.steps)
+    sim, cfgs, n0 = make_batched(spec["gaps"], spec["cells"], spec["seed0"], args.warmup + args.steps + 128)
     log(f"[bench] {n0} initial particles; warmup {args.warmup} steps")
     step = lambda n: sim.step_strict(n, gapsim.GUESS_DIRECT)
     step(args.warmup)
@@ -230,6 +230,9 @@ def run_batched(args, name, copy_gbs):
         sim.set_option(gapsim.OPT_SORT_BIN, args.sort_bin)
         tuning = dict(tuning, sort_bin=args.sort_bin, forced="sort_bin")
     sim.set_option(gapsim.OPT_GRAPH, 1)
+    # two intervals untimed: the graph of one interval is captured and
+    # instantiated before the timed window, not inside it
+    step(2 * tuning["compact_every"])
     torch.cuda.synchronize()
     p0 = pushed_total(sim)
     t0 = time.perf_counter()
@@ -420,7 +423,12 @@ def run_fp64(args, copy_gbs):
     for sp, (x, v) in loads.items():
         sim.inject(0, sp, x, v)
     sim.set_option(gapsim.OPT_GRAPH, 1)
+    # two compaction intervals (32 steps) untimed: the graph is captured and
+    # instantiated before the timed window
+    warm = 64
+    sim.step_strict(warm)
     torch.cuda.synchronize()
+    p0 = sim.diag(0)["pushed_cum"]
     t0 = time.perf_counter()
     sim.step_strict(args.steps)
     torch.cuda.synchronize()
@@ -431,8 +439,8 @@ def run_fp64(args, copy_gbs):
     push_s = tm["push_ms"] * 1e-3
     achieved = 32 * kp / push_s / 1e9 if push_s > 0 else None
     out = {
-        "metric": "particle-steps/s", "value": d["pushed_cum"] / el, "unit": "particle-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": 0, "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True,
+        "metric": "particle-steps/s", "value": (d["pushed_cum"] - p0) / el, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": warm, "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": FP64_WORKLOAD, "cells": cfg.n_cells, "particles": 100_000, "coupling": "strict"},
         "timed_with": "hip graphs",
@@ -685,7 +693,7 @@ def run_external(args, copy_gbs):
     res, series = {}, {}
     for case in ("internal", "external"):
         sim, cfg, _ = make_sim(case, spec, Wm + K)
-        sim.set_option(gapsim.OPT_COMPACT_EVERY, args.compact_every)
+        sim.set_option(gapsim.OPT_COMPACT_EVERY, args.compact_every or 32)
         eng = LinearCircuitEngine(cfg)
         in_engine = [0.0]
 
