@@ -112,14 +112,26 @@ __device__ inline double block_sum(double v, double *sh) {
 
 // block-wide exclusive scan of doubles built from wave scans: two barriers
 // (wsum: one slot per wave)
-__device__ inline double wave_incl_scan_d(double v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    double t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
-  return v;
+// The wave scan moves values between lanes with DPP (row shifts within rows of
+// 16 lanes, then the row broadcasts of lanes 15 and 31), a double as two
+// 32-bit halves; lanes a shift or a mask leaves out add zero.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ inline double dpp_d(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, BANK_MASK, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, BANK_MASK, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double wave_incl_scan_d(double x) {
+  double y = x + dpp_d<0x111, 0xf, 0xf>(x);  // + lane - 1 (row_shr:1)
+  y += dpp_d<0x112, 0xf, 0xf>(x);            // + lane - 2
+  y += dpp_d<0x113, 0xf, 0xf>(x);            // + lane - 3: four lanes summed
+  y += dpp_d<0x114, 0xf, 0xe>(y);            // lanes 4..15 of each row: + lane - 4
+  y += dpp_d<0x118, 0xf, 0xc>(y);            // lanes 8..15: + lane - 8, each row scanned
+  y += dpp_d<0x142, 0xa, 0xf>(y);            // rows 1 and 3: + lane 15 of the row before
+  y += dpp_d<0x143, 0xc, 0xf>(y);            // rows 2 and 3: + lane 31
+  return y;
 }
 
 __device__ inline double block_exclusive_scan_w(double v, double *wsum, double *total) {
@@ -143,10 +155,11 @@ __device__ inline double block_exclusive_scan_sum_w(double v, double w, double *
                                                     double *wtotal) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const double incl = wave_incl_scan_d(v);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
-  if (lane == 63) wsum[wv] = incl;
-  if (lane == 0) wsum2[wv] = w;
+  const double wincl = wave_incl_scan_d(w);
+  if (lane == 63) {
+    wsum[wv] = incl;
+    wsum2[wv] = wincl;
+  }
   __syncthreads();
   double before = 0.0, all = 0.0, wall = 0.0;
   for (int q = 0; q < nw; ++q) {
@@ -710,9 +723,16 @@ __global__ __launch_bounds__(FBS) void k_field1(DevPtrs p, int mode, int guess, 
   // floor(k / ch) = (k * ceil(2^32 / ch)) >> 32 for every k here (k <= 16384 + FBS)
   const unsigned long long chm = (4294967296ull + (unsigned long long)ch - 1ull) / (unsigned long long)ch;
   auto pad = [&](int k) { return k + (int)(((unsigned long long)k * chm) >> 32); };
+  // (the nodes past the first FBS x AV0 only when the grid has them: the
+  // condition is the workgroup's, and a load nobody needs still costs a round
+  // trip)
   unsigned long long av[FNQ];
 #pragma unroll
-  for (int q = 0; q < FNQ; ++q) av[q] = q < AV0 ? av0[q < AV0 ? q : 0] : acc[min(tid + q * FBS, N)];
+  for (int q = 0; q < AV0; ++q) av[q] = av0[q];
+  if (N >= AV0 * FBS) {
+#pragma unroll
+    for (int q = AV0; q < FNQ; ++q) av[q] = acc[min(tid + q * FBS, N)];
+  }
 #pragma unroll
   for (int q = 0; q < FNQ; ++q) {
     const int k = tid + q * FBS;
