@@ -949,6 +949,8 @@ def main():
     ap.add_argument("--deposit", type=int, default=0, help="0 auto, 1 64-bit LDS cells, 2 32-bit")
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--ppt", type=int, default=0, help="16-byte particle vectors per thread (1, 2)")
+    ap.add_argument("--stream", type=int, default=-1,
+                    help="push particle stream bits: 1 round-robin tile order, 2 non-temporal (-1: tuned)")
     ap.add_argument("--sort-bin", type=int, default=-1,
                     help="cells per bin of the periodic cell sort (0: plain compaction; -1: the autotuner's or 0)")
     ap.add_argument("--mlp-gaps", type=int, default=512)
@@ -1021,9 +1023,12 @@ def main():
     spec = WORKLOADS[args.workload]
     log(f"[bench] building workload {args.workload}")
     sim, cfg, _ = make_sim(args.workload, spec, args.warmup + args.steps + 128)
-    manual = bool(args.block or args.tile or args.grid or args.deposit or args.ppt or args.sort_bin >= 0)
+    manual = bool(args.block or args.tile or args.grid or args.deposit or args.ppt or args.sort_bin >= 0
+                  or args.stream >= 0)
     if args.sort_bin >= 0:
         sim.set_option(gapsim.OPT_SORT_BIN, args.sort_bin)
+    if args.stream >= 0:
+        sim.set_option(gapsim.OPT_STREAM, args.stream)
     if args.block:
         sim.set_option(gapsim.OPT_BLOCK, args.block)
     if args.tile:

@@ -215,10 +215,16 @@ enum {
                               push workgroup deposits onto, and flushes, a narrow band of
                               nodes; the secondary emission of a push then runs in its own
                               kernel right after it.  Results do not depend on it. */
-  GS_OPT_STEAL = 13        /* k in 2..64: the last 1/k of each push workgroup's run of tiles
+  GS_OPT_STEAL = 13,       /* k in 2..64: the last 1/k of each push workgroup's run of tiles
                               goes to a pool that workgroups done with their own runs draw
                               from, one tile at a time; 0 (default): fixed runs.  Results do
                               not depend on it. */
+  GS_OPT_STREAM = 14       /* how the push streams the particle arrays, bits: 1 round-robin
+                              tile order (push workgroup w takes tiles w, w + grid, ...,
+                              instead of a contiguous run; the pool of GS_OPT_STEAL is then
+                              unused), 2 non-temporal loads and stores of binary32
+                              particles (for particle arrays far larger than the caches);
+                              0 (default): neither.  Results do not depend on it. */
 };
 
 typedef struct gs_ctx gs_ctx;
@@ -447,6 +453,7 @@ typedef struct {
   int32_t compact_every;  /* steps between compactions (or cell sorts) */
   int32_t sort_bin;       /* GS_OPT_SORT_BIN value (0: compaction without sorting) */
   int32_t steal;          /* GS_OPT_STEAL value */
+  int32_t stream;         /* GS_OPT_STREAM value */
   double ms_per_step;     /* measured time per step of the chosen configuration
                              (gs_get_launch: 0) */
 } gs_tuning;
@@ -457,7 +464,8 @@ gs_status gs_get_launch(const gs_ctx *ctx, gs_tuning *out);
 
 /* Choose the push launch shape (block, vectors per thread, tile, grid), then
  * the compaction interval and whether to cell-sort (and by which bin) instead
- * of compacting, for this context's gaps by timing candidates on its
+ * of compacting, then the tile pool (GS_OPT_STEAL) and the particle stream
+ * (GS_OPT_STREAM), for this context's gaps by timing candidates on its
  * own current state: every device buffer and host counter is saved first and
  * put back afterwards, so the state after the call is the state before it.
  * mode 0 strict (with guess) or 1 weak; trial_steps timed steps per shape

@@ -519,6 +519,7 @@ static gs_status setup(gs_ctx *ctx) {
   ctx->lc.ppt = ctx->fp64 ? 2 : 4;
   ctx->lc.sort_bin = 0;
   ctx->lc.steal = 0;
+  ctx->lc.stream = 0;
   choose_launch(ctx);
   return GS_OK;
 }
@@ -1407,7 +1408,7 @@ std::string tune_key(const gs_ctx *ctx, int mode, int guess, long long live) {
   while ((1ll << (lg + 1)) <= live) ++lg;
   std::ostringstream k;
   // (v2: lines carry the pool share after the sort bin)
-  k << "v2,G=" << ctx->G << ",nmax=" << ctx->nmax << ",fp=" << (ctx->fp64 ? 64 : 32) << ",mode=" << mode
+  k << "v3,G=" << ctx->G << ",nmax=" << ctx->nmax << ",fp=" << (ctx->fp64 ? 64 : 32) << ",mode=" << mode
     << ",guess=" << guess << ",log2live=" << lg << ",cu=" << ctx->ncu;
   return k.str();
 }
@@ -1423,6 +1424,7 @@ static void apply_tuning(gs_ctx *ctx, const gs_tuning &t) {
   ctx->compact_every = t.compact_every;
   ctx->lc.sort_bin = t.sort_bin;
   ctx->lc.steal = t.steal;
+  ctx->lc.stream = t.stream;
   choose_launch(ctx);
   ctx->lc.grid = t.grid;
   drop_graphs(ctx);
@@ -1438,6 +1440,7 @@ static gs_tuning current_tuning(const gs_ctx *ctx) {
   t.compact_every = ctx->compact_every;
   t.sort_bin = ctx->lc.sort_bin;
   t.steal = ctx->lc.steal;
+  t.stream = ctx->lc.stream;
   return t;
 }
 
@@ -1474,7 +1477,7 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
       gs_tuning t{};
       std::istringstream v(line.substr(bar + 1));
       if (v >> t.block >> t.tile >> t.grid >> t.ppt >> t.deposit >> t.compact_every >> t.sort_bin >> t.steal >>
-          t.ms_per_step) {
+          t.stream >> t.ms_per_step) {
         const LaunchCfg keep = ctx->lc;
         apply_tuning(ctx, t);
         if (!launch_fits(ctx)) {
@@ -1556,28 +1559,31 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
   best.ms_per_step = 1e300;
   const int vper = ctx->fp64 ? 2 : 4;
   gs_status r = GS_OK;
-  // launch shape first, at the current compaction interval and sort setting
+  // launch shape first, with each particle stream (the best shape depends on
+  // it), at the current compaction interval and sort setting
   for (int block : {256, 512, 768, 1024})
     for (int ppt : {1, 2})
       for (int tmul : {8, 32})
-        for (int per_cu : {1, 2, 3, 4, 8}) {  // 256-thread workgroups per CU
-          if (r != GS_OK) break;
-          gs_tuning t{};
-          t.block = block;
-          t.ppt = ppt;
-          t.tile = block * tmul;
-          if (t.tile % (block * ppt * vper)) continue;
-          // the same threads per CU at other block sizes
-          if (per_cu * 256 < block) continue;
-          t.deposit = dep0;
-          t.grid = std::max(1, ctx->ncu * per_cu * 256 / block);
-          t.compact_every = ce0;
-          t.sort_bin = sb0;
-          double ms = 0;
-          if ((r = trial(t, trial_steps, &ms, false)) != GS_OK) break;
-          t.ms_per_step = ms;
-          if (ms < best.ms_per_step) best = t;
-        }
+        for (int per_cu : {1, 2, 3, 4, 8})  // 256-thread workgroups per CU
+          for (int sm = 0; sm <= (ctx->fp64 ? 1 : 3); ++sm) {
+            if (r != GS_OK) break;
+            gs_tuning t{};
+            t.block = block;
+            t.ppt = ppt;
+            t.tile = block * tmul;
+            if (t.tile % (block * ppt * vper)) continue;
+            // the same threads per CU at other block sizes
+            if (per_cu * 256 < block) continue;
+            t.deposit = dep0;
+            t.grid = std::max(1, ctx->ncu * per_cu * 256 / block);
+            t.compact_every = ce0;
+            t.sort_bin = sb0;
+            t.stream = sm;
+            double ms = 0;
+            if ((r = trial(t, trial_steps, &ms, false)) != GS_OK) break;
+            t.ms_per_step = ms;
+            if (ms < best.ms_per_step) best = t;
+          }
   // then the compaction interval and the cell sort (off, or bins of 16, 64 or
   // 256 cells), over a span that holds several compactions or sorts: the
   // sort's cost is amortised over the interval and its gain shows in the
@@ -1612,6 +1618,37 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
       if (ms < best.ms_per_step) best = t;
     }
   }
+  // then the particle stream: round-robin tile order (no pool with it) and
+  // non-temporal accesses (binary32), at the two tile sizes of the shape stage.
+  // These candidates differ by a few per cent, so each is timed twice (the
+  // second pass in reverse order) and keeps its faster time
+  if (r == GS_OK) {
+    const gs_tuning base = best;
+    std::vector<gs_tuning> cand;
+    for (int sm = 0; sm <= (ctx->fp64 ? 1 : 3); ++sm)
+      for (int tmul : {8, 32}) {
+        gs_tuning t = base;
+        t.stream = sm;
+        if (sm & STREAM_RR) t.steal = 0;
+        t.tile = t.block * tmul;
+        if (t.tile % (t.block * t.ppt * vper)) continue;
+        t.ms_per_step = 1e300;
+        cand.push_back(t);
+      }
+    for (int pass = 0; pass < 2 && r == GS_OK; ++pass)
+      for (size_t k = 0; k < cand.size(); ++k) {
+        gs_tuning &t = cand[pass ? cand.size() - 1 - k : k];
+        double ms = 0;
+        if ((r = trial(t, std::max(trial_steps, 2 * t.compact_every), &ms, true)) != GS_OK) break;
+        t.ms_per_step = std::min(t.ms_per_step, ms);
+      }
+    // (the shape stage's own choice is among the candidates, re-timed)
+    if (r == GS_OK) {
+      best.ms_per_step = 1e300;
+      for (const gs_tuning &t : cand)
+        if (t.ms_per_step < best.ms_per_step) best = t;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   gs_status rr = restore();
@@ -1635,7 +1672,8 @@ extern "C" gs_status gs_autotune(gs_ctx *ctx, int32_t mode, int32_t guess, int32
   if (cache_path && *cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     f << key << "|" << best.block << " " << best.tile << " " << best.grid << " " << best.ppt << " " << best.deposit
-      << " " << best.compact_every << " " << best.sort_bin << " " << best.steal << " " << best.ms_per_step << "\n";
+      << " " << best.compact_every << " " << best.sort_bin << " " << best.steal << " " << best.stream << " "
+      << best.ms_per_step << "\n";
   }
   if (out) *out = best;
   return GS_OK;
@@ -1682,6 +1720,10 @@ extern "C" gs_status gs_set_option(gs_ctx *ctx, int32_t option, int64_t value) {
     case GS_OPT_STEAL:
       if (value != 0 && (value < 2 || value > 64)) return fail(ctx, GS_EINVAL, "steal must be 0 or 2..64");
       ctx->lc.steal = (int)value;
+      break;
+    case GS_OPT_STREAM:
+      if (value < 0 || value > 3) return fail(ctx, GS_EINVAL, "stream must be 0..3");
+      ctx->lc.stream = (int)value;
       break;
     case GS_OPT_COMPACT_GRID:
       if (value < 1 || value > 1 << 20) return fail(ctx, GS_EINVAL, "compact grid out of range");

@@ -189,7 +189,10 @@ struct LaunchCfg {
                      // events past its LDS queue and k_emit emits them after the push
   int steal;         // the last 1/steal of each push workgroup's tiles go to a pool
                      // that workgroups done with their own draw from (0: none)
+  int stream;        // push particle stream: STREAM_RR round-robin tile order,
+                     // STREAM_NT non-temporal binary32 loads and stores
 };
+constexpr int STREAM_RR = 1, STREAM_NT = 2;
 
 // launchers (gs_kernels.hip)
 // Optional timing: when `a` is set, the start and end of the launched kernel(s)
@@ -202,6 +205,12 @@ struct KTime {
 hipError_t launch_field(const DevPtrs &p, int G, int mode, int guess, double newton_tol,
                         int newton_maxit, int fp64, int nmax, hipStream_t s, KTime t = {});
 hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t = {});
+// its instantiations, compiled in units of their own
+hipError_t launch_push_f64(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t);
+hipError_t launch_push_f32w(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t);
+hipError_t launch_push_f32c(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t);
+hipError_t launch_push_f32w_nt(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t);
+hipError_t launch_push_f32c_nt(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t);
 hipError_t launch_compact(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t = {});
 // the cell sort (count, scan, scatter, commit), in place of launch_compact
 hipError_t launch_sort(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t = {});

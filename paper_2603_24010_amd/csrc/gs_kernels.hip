@@ -337,6 +337,10 @@ __device__ void see_emit(const DevPtrs &p, const GapConst &c, long long level, i
   }
 }
 
+// This file is compiled once for everything but the push kernel's
+// instantiations, and once per GS_PUSH_PART for one set of them (the units
+// build in parallel); the push units skip the other kernels and launchers.
+#ifndef GS_PUSH_PART
 // ---------------------------------------------------------------------------
 // The field solve of level n, in three kernels: k_fdens (the nodal density and
 // the prefix sums within chunks of FCN nodes, many workgroups), k_field (the
@@ -1071,6 +1075,19 @@ __global__ __launch_bounds__(FDB) void k_ftable(DevPtrs p, int fp64) {
   }
 }
 
+#endif  // GS_PUSH_PART
+
+// Launch with or without packet-recorded timing events.
+template <typename K, typename... A>
+static hipError_t launch_k(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t ea,
+                           hipEvent_t eb, A... args) {
+  if (ea || eb)
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, ea, eb, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // k_push
 // ---------------------------------------------------------------------------
@@ -1106,6 +1123,44 @@ struct Vec<double> {
   static constexpr int n = 2;
   __device__ static inline double &at(double2 &v, int k) { return k == 0 ? v.x : v.y; }
 };
+
+// Particle-stream loads and stores, with NT marked non-temporal: a stream far
+// larger than the caches then does not evict what they hold, nor wait for
+// allocations in them.  (A compile-time switch: a run-time one lets the
+// compiler merge the two loads and drop the marking.)
+template <class V>
+struct NatV;
+template <>
+struct NatV<float4> {
+  typedef float t __attribute__((ext_vector_type(4)));
+};
+template <>
+struct NatV<double2> {
+  typedef double t __attribute__((ext_vector_type(2)));
+};
+template <bool NT, class V>
+__device__ inline V ld_stream(const V *a) {
+  typedef typename NatV<V>::t N;
+  V v;
+  if (NT) {
+    const N r = __builtin_nontemporal_load((const N *)a);
+    __builtin_memcpy(&v, &r, sizeof(V));
+  } else {
+    v = *a;
+  }
+  return v;
+}
+template <bool NT, class V>
+__device__ inline void st_stream(V *a, V v) {
+  typedef typename NatV<V>::t N;
+  if (NT) {
+    N r;
+    __builtin_memcpy(&r, &v, sizeof(V));
+    __builtin_nontemporal_store(r, (N *)a);
+  } else {
+    *a = v;
+  }
+}
 
 template <class P>
 struct Prec;
@@ -1407,7 +1462,7 @@ struct SegK {
 // Push one chunk of BS * PPT slots starting at slot r0 (relative to the region
 // base): thread tid owns slots r0 + (v * BS + tid) * VN + kk.  FULL: every slot
 // lies below n_here, so vectors are stored whole; otherwise slot by slot.
-template <class P, class AC, int BS, int PPT, bool FULL>
+template <class P, class AC, int BS, int PPT, bool FULL, bool NT>
 __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P, AC> &sh, P *X, P *U,
                                   long long r0, long long n_here, typename Vec<P>::type *xv,
                                   typename Vec<P>::type *uv, P alpha, bool see, long long zhi, SegCount &cnt) {
@@ -1465,8 +1520,8 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
   for (int v = 0; v < NV; ++v) {
     const long long i = r0 + (long long)(v * BS + tid) * VN;
     if (FULL) {
-      *(V *)(X + i) = xw[v];
-      *(V *)(U + i) = uw[v];
+      st_stream<NT>((V *)(X + i), xw[v]);
+      st_stream<NT>((V *)(U + i), uw[v]);
     } else {
 #pragma unroll
       for (int k = 0; k < VN; ++k)
@@ -1537,7 +1592,7 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
   }
 }
 
-template <class P, int BS, int PPT>
+template <class P, int BS, int PPT, bool NT>
 __device__ inline void load_chunk(const P *X, const P *U, long long r0, typename Vec<P>::type *xo,
                                   typename Vec<P>::type *uo) {
   typedef typename Vec<P>::type V;
@@ -1545,21 +1600,24 @@ __device__ inline void load_chunk(const P *X, const P *U, long long r0, typename
 #pragma unroll
   for (int v = 0; v < PPT / VN; ++v) {
     const long long i = r0 + (long long)(v * BS + threadIdx.x) * VN;
-    xo[v] = *(const V *)(X + i);
-    uo[v] = *(const V *)(U + i);
+    xo[v] = ld_stream<NT>((const V *)(X + i));
+    uo[v] = ld_stream<NT>((const V *)(U + i));
   }
 }
 
-// The slots [a, b) of one (gap, species) region, as a stream of chunks.  Full
-// chunks are software-pipelined: the loads of the next chunk are in flight
-// while this one is pushed.  Every load in the loop is unconditional (past the
-// last full chunk it repeats that chunk's, whose data is dropped), so the
-// waits count exactly.  The remainder
-// goes slot by slot: slots past b may be receiving appended particles.
-template <class P, class AC, int BS, int PPT>
+// Slots of one (gap, species) region as a stream of chunks: nrun runs of
+// `run` slots (a multiple of the chunk), `step` slots apart, from slot a; the
+// last run ends at b.  (One run: a contiguous range; several: the tiles a
+// workgroup takes in round-robin order.)  Full chunks are software-pipelined,
+// across runs too: the loads of the next chunk are in flight while this one is
+// pushed.  Every load in the loop is unconditional (past the last full chunk
+// it repeats that chunk's, whose data is dropped), so the waits count exactly.
+// The remainder goes slot by slot: slots past b may be receiving appended
+// particles.
+template <class P, class AC, int BS, int PPT, bool NT>
 __device__ void push_range(const DevPtrs &p, const GapConst &gc, const GapState &st, int g, int s, int sel,
-                           PushShared<P, AC> &sh, long long a, long long b, long long kb0, long long kb1,
-                           bool stage, SegCount &cnt) {
+                           PushShared<P, AC> &sh, long long a, long long b, long long run, long long step,
+                           int nrun, long long kb0, long long kb1, bool stage, SegCount &cnt) {
   typedef typename Vec<P>::type V;
   constexpr int VN = Vec<P>::n;
   constexpr int NV = PPT / VN;
@@ -1576,11 +1634,14 @@ __device__ void push_range(const DevPtrs &p, const GapConst &gc, const GapState 
   const P alpha = (P)gc.alpha[s];
   const bool see = (s == 1) && (gc.see_amp > 0.0) && (gc.Z[1] > 0);
   const long long zhi = (long long)gc.Z[s] * 4294967296ll;
-  const long long nfull = (b - a) / CH;
+  // runs before the last are whole (a later tile of the region exists)
+  const int cpr = (int)(run / CH);
+  const long long last = a + (long long)(nrun - 1) * step;
+  const long long nfull = (long long)(nrun - 1) * cpr + (b > last ? (b - last) / CH : 0);
   V xa[NV], ua[NV], xb[NV], ub[NV];
   // the first chunk's loads are in flight while the segment is staged (or,
   // when the segment is already open, while this range's beam goes in)
-  if (nfull > 0) load_chunk<P, BS, PPT>(X, U, a, xa, ua);
+  if (nfull > 0) load_chunk<P, BS, PPT, NT>(X, U, a, xa, ua);
   if (stage)
     load_seg<P, AC>(p, gc, st, g, sel, sh, kb0, kb1);
   else if (kb1 > kb0)
@@ -1588,16 +1649,27 @@ __device__ void push_range(const DevPtrs &p, const GapConst &gc, const GapState 
   // one copy of the chunk body (the kernel's instruction footprint is what
   // limits it): the next chunk's loads go out before this chunk is pushed,
   // and the buffers are swapped by register moves
+  long long rb = a;  // the run holding the chunk being pushed, and its index there
+  int ci = 0;
   for (long long q = 0; q < nfull; ++q) {
-    load_chunk<P, BS, PPT>(X, U, a + min(q + 1, nfull - 1) * CH, xb, ub);
-    push_chunk<P, AC, BS, PPT, true>(p, c, sh, X, U, a + q * CH, b, xa, ua, alpha, see, zhi, cnt);
+    long long rbn = rb;
+    int cin = ci + 1;
+    if (cin == cpr) {
+      cin = 0;
+      rbn += step;
+    }
+    const long long cur = rb + (long long)ci * CH;
+    load_chunk<P, BS, PPT, NT>(X, U, q + 1 < nfull ? rbn + (long long)cin * CH : cur, xb, ub);
+    push_chunk<P, AC, BS, PPT, true, NT>(p, c, sh, X, U, cur, b, xa, ua, alpha, see, zhi, cnt);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       xa[v] = xb[v];
       ua[v] = ub[v];
     }
+    rb = rbn;
+    ci = cin;
   }
-  const long long r0 = a + nfull * CH;
+  const long long r0 = rb + (long long)ci * CH;
   if (r0 < b) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -1608,7 +1680,7 @@ __device__ void push_range(const DevPtrs &p, const GapConst &gc, const GapState 
         Vec<P>::at(ua[v], k) = (i + k < b) ? U[i + k] : (P)0;
       }
     }
-    push_chunk<P, AC, BS, PPT, false>(p, c, sh, X, U, r0, b, xa, ua, alpha, see, zhi, cnt);
+    push_chunk<P, AC, BS, PPT, false, NT>(p, c, sh, X, U, r0, b, xa, ua, alpha, see, zhi, cnt);
   }
 }
 
@@ -1625,13 +1697,14 @@ __device__ __forceinline__ void close_seg(const DevPtrs &p, PushShared<P, AC> &s
   flush_seg<P, AC>(p, p.gc[g], p.gs[g], g, s, sel, sh);
 }
 
-template <class P, class AC, int BS, int PPT>
+template <class P, class AC, int BS, int PPT, bool NT>
 __device__ __forceinline__ void push_piece(const DevPtrs &p, PushShared<P, AC> &sh, int tile, int sel, int g,
-                                           int s, int ls, int le, int &og, int &os) {
+                                           int s, int ls, int le, int stride, int &og, int &os) {
   g = __builtin_amdgcn_readfirstlane(g);
   s = __builtin_amdgcn_readfirstlane(s);
   ls = __builtin_amdgcn_readfirstlane(ls);
   le = __builtin_amdgcn_readfirstlane(le);
+  stride = __builtin_amdgcn_readfirstlane(stride);
   const GapConst &c = p.gc[g];
   const GapState &st = p.gs[g];
   int te, ti;
@@ -1639,12 +1712,25 @@ __device__ __forceinline__ void push_piece(const DevPtrs &p, PushShared<P, AC> &
   const bool stage = !(g == og && s == os);
   if (stage && og >= 0) close_seg<P, AC>(p, sh, sel, og, os);
   SegCount cnt;
+  // the local tiles ls, ls + stride, ... below le (stride 1: the run [ls, le))
+  const int nrun = stride == 1 ? 1 : (le - ls + stride - 1) / stride;
+  const int lt = stride == 1 ? le - 1 : ls + (nrun - 1) * stride;
   const long long a = (long long)ls * tile;
-  const long long b = min((long long)le * tile, st.count[s]);
-  // the beam is split over the gap's ion tiles, tile lt taking ions
-  // [beam lt / ti, beam (lt + 1) / ti)
-  const long long kb0 = s == 1 ? st.beam_now * ls / ti : 0, kb1 = s == 1 ? st.beam_now * le / ti : 0;
-  push_range<P, AC, BS, PPT>(p, c, st, g, s, sel, sh, a, b, kb0, kb1, stage, cnt);
+  const long long b = min((long long)(lt + 1) * tile, st.count[s]);
+  const long long run = stride == 1 ? (long long)(le - ls) * tile : (long long)tile;
+  const long long step = stride == 1 ? run : (long long)stride * tile;
+  // the beam: over a run of tiles it is split by the gap's ion tiles, tile lt
+  // taking ions [beam lt / ti, beam (lt + 1) / ti); a strided piece (the one
+  // piece of its workgroup in this region, first tile ls < stride) takes share
+  // ls of min(ti, stride) equal shares, so that each workgroup injects its
+  // ions at once rather than a few per tile
+  long long kb0 = 0, kb1 = 0;
+  if (s == 1) {
+    const int nb = stride == 1 ? ti : min(ti, stride);
+    kb0 = st.beam_now * ls / nb;
+    kb1 = st.beam_now * (stride == 1 ? le : ls + 1) / nb;
+  }
+  push_range<P, AC, BS, PPT, NT>(p, c, st, g, s, sel, sh, a, b, run, step, nrun, kb0, kb1, stage, cnt);
   // wave-level sums, then one LDS atomic per wave
   const unsigned int v0 = wave_sum(cnt.pushed), v1 = wave_sum(cnt.abs0), v2 = wave_sum(cnt.abs1);
   if ((threadIdx.x & 63) == 0) {
@@ -1657,18 +1743,18 @@ __device__ __forceinline__ void push_piece(const DevPtrs &p, PushShared<P, AC> &
 }
 
 // the pieces of the global tiles [ta, tb) of gap g, whose tiles start at t_g
-template <class P, class AC, int BS, int PPT>
+template <class P, class AC, int BS, int PPT, bool NT>
 __device__ __forceinline__ void push_tiles(const DevPtrs &p, PushShared<P, AC> &sh, int tile, int sel, int g,
                                            int t_g, int ta, int tb, int &og, int &os) {
   int te, ti;
   gap_tiles(p.gs[g], p.gs[g].beam_now, tile, te, ti);
   const int la = ta - t_g, lb = tb - t_g;
-  if (la < te) push_piece<P, AC, BS, PPT>(p, sh, tile, sel, g, 0, la, min(lb, te), og, os);
-  if (lb > te) push_piece<P, AC, BS, PPT>(p, sh, tile, sel, g, 1, max(la, te) - te, lb - te, og, os);
+  if (la < te) push_piece<P, AC, BS, PPT, NT>(p, sh, tile, sel, g, 0, la, min(lb, te), 1, og, os);
+  if (lb > te) push_piece<P, AC, BS, PPT, NT>(p, sh, tile, sel, g, 1, max(la, te) - te, lb - te, 1, og, os);
 }
 
-template <class P, class AC, int BS, int PPT>
-__global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int nmax, int steal) {
+template <class P, class AC, int BS, int PPT, bool NT>
+__global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int nmax, int steal, int rr) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   typedef typename AC::cell cell;
   __shared__ int scan_sh[BS];
@@ -1724,21 +1810,42 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
 
   auto prefix = [&](int i) { return G == 1 ? (i == 0 ? 0 : total1) : sh.prefix[i]; };
 
+  const int total = prefix(G);
+  const int nwg = (int)gridDim.x;
+  int og = -1, os = 0;  // the open segment (gap, species), none yet
+  if (rr) {
+    // round robin: workgroup w takes the tiles w, w + nwg, w + 2 nwg, ...  At
+    // any moment the workgroups then stream neighbouring tiles, one window of
+    // memory, rather than nwg regions far apart.  Its tiles in one region are
+    // one strided piece; t visits the workgroup's first tile of each region
+    // it has tiles in (that tile's local index is below nwg)
+    int g = 0;
+    int t = (int)blockIdx.x;
+    while (t < total) {
+      while (prefix(g + 1) <= t) ++g;
+      int te, ti;
+      gap_tiles(p.gs[g], p.gs[g].beam_now, tile, te, ti);
+      const int tg = prefix(g);
+      const int s = t - tg < te ? 0 : 1;
+      const int T0 = s ? tg + te : tg, T1 = s ? tg + te + ti : tg + te;
+      push_piece<P, AC, BS, PPT, NT>(p, sh, tile, sel, g, s, t - T0, T1 - T0, nwg, og, os);
+      t += ((T1 - t + nwg - 1) / nwg) * nwg;  // the first of its tiles past the region
+    }
+    if (og >= 0) close_seg<P, AC>(p, sh, sel, og, os);
+    return;
+  }
   // the workgroup's contiguous run of tiles; with stealing on, the last R of
   // every run go to the pool instead (runs differ by at most one tile, so each
   // holds at least 8 R)
-  const int total = prefix(G);
-  const int nwg = (int)gridDim.x;
   const int R = p.steal != nullptr && steal > 0 ? (total / nwg) / steal : 0;
   const int t0 = (int)(((long long)blockIdx.x * total) / nwg);
   const int t1 = (int)(((long long)(blockIdx.x + 1) * total) / nwg) - R;
-  int og = -1, os = 0;  // the open segment (gap, species), none yet
   {
     int g = 0, t = t0;
     while (t < t1) {
       while (prefix(g + 1) <= t) ++g;
       const int e = min(t1, prefix(g + 1));
-      push_tiles<P, AC, BS, PPT>(p, sh, tile, sel, g, prefix(g), t, e, og, os);
+      push_tiles<P, AC, BS, PPT, NT>(p, sh, tile, sel, g, prefix(g), t, e, og, os);
       t = e;
     }
   }
@@ -1774,11 +1881,69 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
         }
         g = lo;
       }
-      push_tiles<P, AC, BS, PPT>(p, sh, tile, sel, g, prefix(g), tt, tt + 1, og, os);
+      push_tiles<P, AC, BS, PPT, NT>(p, sh, tile, sel, g, prefix(g), tt, tt + 1, og, os);
     }
   }
   if (og >= 0) close_seg<P, AC>(p, sh, sel, og, os);
 }
+
+template <class P, class AC, int BS, int PPT, bool NT>
+static hipError_t push_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+  const size_t lds = push_lds_bytes(lc.nmax, lc.fp64, G, sizeof(typename AC::cell) == 8);
+  // opt in to more than 64 KiB of dynamic LDS (gfx950 has 160 KiB per CU)
+  static size_t attr_set = 65536;
+  if (lds > attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_push<P, AC, BS, PPT, NT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = lds;
+  }
+  return launch_k(k_push<P, AC, BS, PPT, NT>, dim3(lc.grid), dim3(BS), lds, s, t.a, t.b, p, G, lc.tile,
+                  lc.nmax, lc.steal, (lc.stream & STREAM_RR) ? 1 : 0);
+}
+
+template <class P, class AC, int PPT, bool NT>
+static hipError_t push_bs(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+  switch (lc.block) {
+    case 256: return push_t<P, AC, 256, PPT, NT>(p, G, lc, s, t);
+    case 512: return push_t<P, AC, 512, PPT, NT>(p, G, lc, s, t);
+    case 768: return push_t<P, AC, 768, PPT, NT>(p, G, lc, s, t);
+    default: return push_t<P, AC, 1024, PPT, NT>(p, G, lc, s, t);
+  }
+}
+
+template <class P, class AC, bool NT>
+static hipError_t push_b(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+  if (lc.ppt >= 2 * Vec<P>::n) return push_bs<P, AC, 2 * Vec<P>::n, NT>(p, G, lc, s, t);
+  return push_bs<P, AC, Vec<P>::n, NT>(p, G, lc, s, t);
+}
+#ifdef GS_PUSH_PART
+// one set of the push kernel's instantiations: particle precision, deposit
+// cells, stream kind
+#if GS_PUSH_PART == 0
+hipError_t launch_push_f64(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+  return push_b<double, Wide64, false>(p, G, lc, s, t);
+}
+#elif GS_PUSH_PART == 1
+hipError_t launch_push_f32w(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+  return push_b<float, Wide64, false>(p, G, lc, s, t);
+}
+#elif GS_PUSH_PART == 2
+hipError_t launch_push_f32c(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+  return push_b<float, Carry32, false>(p, G, lc, s, t);
+}
+#elif GS_PUSH_PART == 3
+hipError_t launch_push_f32w_nt(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+  return push_b<float, Wide64, true>(p, G, lc, s, t);
+}
+#elif GS_PUSH_PART == 4
+hipError_t launch_push_f32c_nt(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
+  return push_b<float, Carry32, true>(p, G, lc, s, t);
+}
+#else
+#error "GS_PUSH_PART must be 0..4"
+#endif
+#else  // the other kernels and the launchers
 
 // The regions' new slot counts after a sort (flip: its particles are in the
 // other buffer now) or an in-place compaction.
@@ -2525,17 +2690,6 @@ size_t push_lds_bytes(int nmax, int fp64, int G, int wide) {
   return off;
 }
 
-// Launch with or without packet-recorded timing events.
-template <typename K, typename... A>
-static hipError_t launch_k(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t ea,
-                           hipEvent_t eb, A... args) {
-  if (ea || eb)
-    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, ea, eb, 0u, args...);
-  else
-    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
-  return hipGetLastError();
-}
-
 hipError_t launch_field(const DevPtrs &p, int G, int mode, int guess, double tol, int maxit,
                         int fp64, int nmax, hipStream_t s, KTime t) {
   if (nmax <= FIELD1_NMAX) {
@@ -2560,41 +2714,12 @@ hipError_t launch_field(const DevPtrs &p, int G, int mode, int guess, double tol
   return launch_k(k_ftable, chunks, dim3(FDB), 0, s, nullptr, t.b, p, fp64);
 }
 
-template <class P, class AC, int BS, int PPT>
-static hipError_t push_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
-  const size_t lds = push_lds_bytes(lc.nmax, lc.fp64, G, sizeof(typename AC::cell) == 8);
-  // opt in to more than 64 KiB of dynamic LDS (gfx950 has 160 KiB per CU)
-  static size_t attr_set = 65536;
-  if (lds > attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_push<P, AC, BS, PPT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = lds;
-  }
-  return launch_k(k_push<P, AC, BS, PPT>, dim3(lc.grid), dim3(BS), lds, s, t.a, t.b, p, G, lc.tile,
-                  lc.nmax, lc.steal);
-}
-
-template <class P, class AC, int PPT>
-static hipError_t push_bp(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
-  switch (lc.block) {
-    case 256: return push_t<P, AC, 256, PPT>(p, G, lc, s, t);
-    case 512: return push_t<P, AC, 512, PPT>(p, G, lc, s, t);
-    case 768: return push_t<P, AC, 768, PPT>(p, G, lc, s, t);
-    default: return push_t<P, AC, 1024, PPT>(p, G, lc, s, t);
-  }
-}
-
-template <class P, class AC>
-static hipError_t push_b(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
-  if (lc.ppt >= 2 * Vec<P>::n) return push_bp<P, AC, 2 * Vec<P>::n>(p, G, lc, s, t);
-  return push_bp<P, AC, Vec<P>::n>(p, G, lc, s, t);
-}
-
 hipError_t launch_push(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream_t s, KTime t) {
-  if (lc.fp64) return push_b<double, Wide64>(p, G, lc, s, t);
-  if (lc.wide) return push_b<float, Wide64>(p, G, lc, s, t);
-  return push_b<float, Carry32>(p, G, lc, s, t);
+  // (the non-temporal stream is for binary32 particles)
+  const bool nt = (lc.stream & STREAM_NT) != 0;
+  if (lc.fp64) return launch_push_f64(p, G, lc, s, t);
+  if (lc.wide) return nt ? launch_push_f32w_nt(p, G, lc, s, t) : launch_push_f32w(p, G, lc, s, t);
+  return nt ? launch_push_f32c_nt(p, G, lc, s, t) : launch_push_f32c(p, G, lc, s, t);
 }
 
 template <class P>
@@ -2714,5 +2839,6 @@ hipError_t launch_phi(const DevPtrs &p, int gap, hipStream_t s) {
   hipLaunchKernelGGL(k_phi, dim3(1), dim3(PBS), 0, s, p, gap);
   return hipGetLastError();
 }
+#endif  // GS_PUSH_PART
 
 }  // namespace gs

@@ -26,6 +26,7 @@ OPT_BLOCK, OPT_TILE, OPT_GRID, OPT_COMPACT_EVERY, OPT_GRAPH, OPT_TIMING = 1, 2, 
 OPT_NEWTON_TOL, OPT_NEWTON_MAXIT, OPT_DEPOSIT, OPT_COMPACT_GRID, OPT_PPT = 7, 8, 9, 10, 11
 OPT_SORT_BIN = 12
 OPT_STEAL = 13
+OPT_STREAM = 14
 
 EXPORTED = [
     "gs_init_gap", "gs_destroy", "gs_inject", "gs_step_strict", "gs_step_weak", "gs_read_diagnostics",
@@ -101,7 +102,7 @@ class GsTiming(C.Structure):
 class GsTuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("tile", C.c_int32), ("grid", C.c_int32), ("ppt", C.c_int32),
                 ("deposit", C.c_int32), ("compact_every", C.c_int32), ("sort_bin", C.c_int32),
-                ("steal", C.c_int32), ("ms_per_step", C.c_double)]
+                ("steal", C.c_int32), ("stream", C.c_int32), ("ms_per_step", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -193,7 +194,8 @@ def lib():
 
 def _tuning_dict(t) -> dict:
     return dict(block=t.block, tile=t.tile, grid=t.grid, ppt=t.ppt, deposit=t.deposit,
-                compact_every=t.compact_every, sort_bin=t.sort_bin, steal=t.steal, ms_per_step=t.ms_per_step)
+                compact_every=t.compact_every, sort_bin=t.sort_bin, steal=t.steal, stream=t.stream,
+                ms_per_step=t.ms_per_step)
 
 
 class GapsimError(RuntimeError):

@@ -350,11 +350,12 @@ def test_fp32_error_against_fp64_oracle(mode, n_cells):
 # ---------------------------------------------------------------------------
 # several gaps in one context
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("sort_bin,steal", [(0, 0), (8, 0), (0, 2)])
-def test_batched_gaps_parity(sort_bin, steal):
+@pytest.mark.parametrize("sort_bin,steal,stream", [(0, 0, 0), (8, 0, 0), (0, 2, 0), (0, 0, 3)])
+def test_batched_gaps_parity(sort_bin, steal, stream):
     """Six gaps in one context against six oracles.  With steal on and five
     push workgroups, half of every workgroup's tiles go to the pool, so pool
-    tiles switch between gaps and species."""
+    tiles switch between gaps and species; with the round-robin stream and
+    five workgroups, consecutive tiles of a workgroup do too."""
     gs = _gapsim()
     G = 6
     cfgs, loads = [], []
@@ -366,7 +367,8 @@ def test_batched_gaps_parity(sort_bin, steal):
     sim.set_option(gs.OPT_COMPACT_EVERY, 5)
     sim.set_option(gs.OPT_SORT_BIN, sort_bin)
     sim.set_option(gs.OPT_STEAL, steal)
-    if steal:
+    sim.set_option(gs.OPT_STREAM, stream)
+    if steal or stream:
         sim.set_option(gs.OPT_GRID, 5)
     orcs = []
     for g in range(G):
@@ -390,12 +392,14 @@ def test_mixed_grid_sizes_parity(mode):
     """A 16384-cell gap and a 700-cell gap in one context: past 8192 cells the
     field solve runs as three kernels over chunks of 1024 nodes, and the small
     gap's chunks past its own last node have nothing to do.  Both gaps against
-    their oracles, with the binary32 particles bit-equal."""
+    their oracles, with the binary32 particles bit-equal.  (Weak mode runs
+    with the round-robin, non-temporal particle stream.)"""
     gs = _gapsim()
     cfgs = [cfg2_small(n_cells=16384, beam=1500), cfg2_small(n_cells=700, beam=800)]
     loads = [W.load_config2(n=60_000, seed=31), W.load_config2(n=20_000, seed=32)]
     sim = gs.GapSim(cfgs, particle_fp=32, capacity=(200_000, 200_000))
     sim.set_option(gs.OPT_COMPACT_EVERY, 4)
+    sim.set_option(gs.OPT_STREAM, 3 if mode == oracle.WEAK else 0)
     orcs = []
     for g in range(2):
         o = oracle.OracleSim(cfgs[g], fp32=True)
@@ -474,6 +478,13 @@ def test_launch_shapes_and_graph_agree():
         {gs.OPT_COMPACT_EVERY: 6, gs.OPT_GRID: 5, gs.OPT_STEAL: 4, gs.OPT_DEPOSIT: 2, gs.OPT_SORT_BIN: 16},
         {gs.OPT_COMPACT_EVERY: 8, gs.OPT_GRID: 2, gs.OPT_STEAL: 2, gs.OPT_GRAPH: 1},
         {gs.OPT_COMPACT_EVERY: 8, gs.OPT_STEAL: 0},
+        # the particle stream: round-robin tile order with a handful of
+        # workgroups (each takes tiles of both species), non-temporal accesses
+        {gs.OPT_COMPACT_EVERY: 4, gs.OPT_GRID: 3, gs.OPT_STREAM: 1},
+        {gs.OPT_COMPACT_EVERY: 5, gs.OPT_BLOCK: 512, gs.OPT_TILE: 512 * 8, gs.OPT_GRID: 7, gs.OPT_STREAM: 3},
+        {gs.OPT_COMPACT_EVERY: 6, gs.OPT_PPT: 2, gs.OPT_TILE: 512 * 24, gs.OPT_STREAM: 2},
+        {gs.OPT_COMPACT_EVERY: 3, gs.OPT_GRID: 5, gs.OPT_STREAM: 1, gs.OPT_STEAL: 4, gs.OPT_SORT_BIN: 16},
+        {gs.OPT_COMPACT_EVERY: 8, gs.OPT_STREAM: 3, gs.OPT_GRAPH: 1, gs.OPT_DEPOSIT: 2},
     ]
     for opts in variants:
         d, E, ions, els = _cfg2_state(opts)
@@ -641,10 +652,15 @@ def test_tesla_scenario_waveform_matches_oracle():
 @pytest.mark.parametrize("mode", [oracle.STRICT, oracle.WEAK])
 def test_fp64_largest_grid_parity(mode):
     """The largest binary64 grid (8192 cells: the 64-bit accumulator and the
-    binary64 table take 128 KiB of LDS), with a beam and emission."""
+    binary64 table take 128 KiB of LDS), with a beam and emission.  Weak mode
+    runs with the round-robin tile order over a few workgroups (the
+    non-temporal bit is for binary32 particles and does nothing here)."""
     cfg = W.config2(n_cells=8192, beam_per_step=300, seed=9)
     loads = W.load_config2(n=60_000, seed=13)
-    opts = {_gapsim().OPT_COMPACT_EVERY: 6}
+    gs = _gapsim()
+    opts = {gs.OPT_COMPACT_EVERY: 6}
+    if mode == oracle.WEAK:
+        opts.update({gs.OPT_STREAM: 3, gs.OPT_GRID: 6, gs.OPT_TILE: 2048})
     sim, orc, recs = run_pair(cfg, loads, mode, 25, False, (200_000, 200_000), opts=opts)
     for dg, do in recs:
         assert dg["step"] == do["step"]
