@@ -488,8 +488,11 @@ def run_divergence(args, copy_gbs):
         s = gapsim.GapSim(cfg, particle_fp=32, capacity=cap)
         for sp, (x, v) in loads.items():
             s.inject(0, sp, x, v)
+        # the launch the autotuner picks for this gap and mode (cached per shape)
+        s.autotune(mode, gapsim.GUESS_DIRECT, trial_steps=8, cache_path=args.tuning_cache or None)
         sims.append(s)
     del loads
+    launches = [s.launch() for s in sims]
     rec = {0: [], 1: []}
     el = {0: 0.0, 1: 0.0}
     pushed = {0: 0, 1: 0}
@@ -527,8 +530,8 @@ def run_divergence(args, copy_gbs):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": DIVERGENCE, "cells": cfg.n_cells, "initial_particles": n0,
                    "beam_per_step": cfg.beam_per_step, "live_particles_end": live},
-        "strict": {"particle_steps_per_s": pushed[0] / el[0], "push_ms": tm[0]},
-        "weak": {"particle_steps_per_s": pushed[1] / el[1], "push_ms": tm[1]},
+        "strict": {"particle_steps_per_s": pushed[0] / el[0], "push_ms": tm[0], "launch": launches[0]},
+        "weak": {"particle_steps_per_s": pushed[1] / el[1], "push_ms": tm[1], "launch": launches[1]},
         "divergence": {
             "sampled_every": every,
             "max_abs_dV": float(dv.max()), "max_rel_dV": float(dv.max() / vscale),

@@ -612,6 +612,25 @@ def test_inject_rejects_outside_positions():
     assert e.value.status == gs.GS_EINVAL
 
 
+def test_launch_options_reject_out_of_range_values():
+    """gs_set_option refuses values outside each option's range (EINVAL) and
+    leaves the launch in effect as it was."""
+    gs = _gapsim()
+    cfg = W.config1(n_cells=32)
+    sim = gs.GapSim(cfg, particle_fp=32, capacity=(16, 16))
+    before = sim.launch()
+    for opt, bad in ((gs.OPT_STREAM, 4), (gs.OPT_STREAM, -1), (gs.OPT_STEAL, 1), (gs.OPT_STEAL, 65),
+                     (gs.OPT_PPT, 3), (gs.OPT_TIMING, 3)):
+        with pytest.raises(gs.GapsimError) as e:
+            sim.set_option(opt, bad)
+        assert e.value.status == gs.GS_EINVAL, (opt, bad)
+    assert sim.launch() == before
+    for v in range(4):
+        sim.set_option(gs.OPT_STREAM, v)
+        assert sim.launch()["stream"] == v
+    sim.close()
+
+
 def test_event_overflow_emitted_in_the_same_step():
     """Past 1152 absorbed ions in one workgroup and step the rest wait in the
     gap's list and the emission kernel emits them right after the push: the
