@@ -520,6 +520,7 @@ static gs_status setup(gs_ctx *ctx) {
   ctx->lc.sort_bin = 0;
   ctx->lc.steal = 0;
   ctx->lc.stream = 0;
+  ctx->lc.masks = 0;
   choose_launch(ctx);
   return GS_OK;
 }
@@ -761,20 +762,25 @@ static int64_t beam_at(const gs_ctx *ctx, int g, int64_t n) {
 // in the same step, so the emitted counts of a level never lag.  With the cell
 // sort on, a wall's impacts sit in few workgroups: the push then keeps only its
 // LDS queue and leaves the rest to k_emit.
-static hipError_t launch_push_emit(gs_ctx *ctx, hipStream_t s, bool timing) {
+// masks: a compaction follows this push (the push then writes the live masks)
+static hipError_t launch_push_emit(gs_ctx *ctx, hipStream_t s, bool timing, bool masks) {
   DevPtrs dp = ctx->dp;
   if (ctx->lc.sort_bin > 0) dp.ovf_wgs = 0;
-  auto push = [&](KTime t) { return launch_push(dp, ctx->G, ctx->lc, s, t); };
+  LaunchCfg lc = ctx->lc;
+  lc.masks = masks && lc.sort_bin == 0;
+  auto push = [&](KTime t) { return launch_push(dp, ctx->G, lc, s, t); };
   hipError_t e = timing ? timed(ctx, 0, push) : push(KTime{});
   if (e != hipSuccess || !ctx->emits) return e;
   auto emit = [&](KTime t) { return launch_emit(ctx->dp, ctx->G, ctx->fp64, std::max(ctx->ncu, 1), s, t); };
   return timing ? timed(ctx, 3, emit) : emit(KTime{});
 }
 
-// the compaction, or the cell sort in its place
+// the compaction (after a push that wrote the live masks), or the cell sort in
+// its place
 static hipError_t launch_reclaim(gs_ctx *ctx, hipStream_t s, KTime t) {
-  return ctx->lc.sort_bin > 0 ? launch_sort(ctx->dp, ctx->G, ctx->lc, s, t)
-                              : launch_compact(ctx->dp, ctx->G, ctx->lc, s, t);
+  LaunchCfg lc = ctx->lc;
+  lc.masks = 1;
+  return lc.sort_bin > 0 ? launch_sort(ctx->dp, ctx->G, lc, s, t) : launch_compact(ctx->dp, ctx->G, lc, s, t);
 }
 
 // after_field: an event to record between the field solve and the push
@@ -786,7 +792,7 @@ static gs_status one_step(gs_ctx *ctx, int mode, int guess, hipEvent_t after_fie
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "field launch: %s", hipGetErrorString(e));
   if (after_field && (e = hipEventRecord(after_field, ctx->stream)) != hipSuccess)
     return fail(ctx, GS_EDEVICE, "event record: %s", hipGetErrorString(e));
-  e = launch_push_emit(ctx, ctx->stream, true);
+  e = launch_push_emit(ctx, ctx->stream, true, ctx->since_compact + 1 >= ctx->compact_every);
   if (e != hipSuccess) return fail(ctx, GS_EDEVICE, "push launch: %s", hipGetErrorString(e));
   ctx->since_compact += 1;
   if (ctx->since_compact >= ctx->compact_every) {
@@ -828,7 +834,7 @@ static gs_status run_steps(gs_ctx *ctx, int n_steps, int mode, int guess) {
         for (int k = 0; k < L && e1 == hipSuccess && e2 == hipSuccess; ++k) {
           e1 = launch_field(ctx->dp, ctx->G, mode, guess, ctx->newton_tol, ctx->newton_maxit, ctx->fp64,
                             ctx->nmax, cs);
-          if (e1 == hipSuccess) e2 = launch_push_emit(ctx, cs, false);
+          if (e1 == hipSuccess) e2 = launch_push_emit(ctx, cs, false, k == L - 1);
         }
         if (e1 == hipSuccess && e2 == hipSuccess) e3 = launch_reclaim(ctx, cs, KTime{});
         hipError_t ec = hipStreamEndCapture(cs, &graph);

@@ -191,6 +191,9 @@ struct LaunchCfg {
                      // that workgroups done with their own draw from (0: none)
   int stream;        // push particle stream: STREAM_RR round-robin tile order,
                      // STREAM_NT non-temporal binary32 loads and stores
+  int masks;         // per launch: the push writes the live masks of the words
+                     // below each region's count, and the compaction that follows
+                     // takes them instead of reading those positions
 };
 constexpr int STREAM_RR = 1, STREAM_NT = 2;
 

@@ -1230,6 +1230,7 @@ struct PushShared {
   Event *evq;           // [EVQ]
   unsigned int *evq_n;
   int *wsum;            // [BS / 64] scan scratch
+  int masks;            // the launch writes the live masks
 };
 
 // push tiles of gap g: electrons, then ions (a gap with a beam has at least
@@ -1454,9 +1455,11 @@ struct SegCount {
 struct SegK {
   int N;
   int g;
+  int masks;  // write the live masks (a compaction follows this push)
   long long evbase, evcap;
   unsigned long long *gacc;
-  const uint32_t *ids;  // the region's particle ids (overflowing events carry the id)
+  const uint32_t *ids;        // the region's particle ids (overflowing events carry the id)
+  unsigned long long *live;   // the region's live masks, one word per 64 slots
 };
 
 // Push one chunk of BS * PPT slots starting at slot r0 (relative to the region
@@ -1480,6 +1483,7 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
   int jj[PPT];
   typename Prec<P>::wt w0[PPT], w1[PPT];
   unsigned int hit = 0;  // bit k: slot k is an absorbed ion (its wall in bit k+16)
+  unsigned int alive = 0;  // bit k: slot k holds a particle after the push
   P u_hit[PPT];
   V xw[NV], uw[NV];
 #pragma unroll
@@ -1500,6 +1504,7 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
     const bool stay = live && !(a0 || a1);
     Vec<P>::at(xw[v], kk) = stay ? x1 : (P)-1;
     Vec<P>::at(uw[v], kk) = stay ? u1 : u0;
+    alive |= (unsigned int)stay << k;
     cnt.pushed += live;
     cnt.abs0 += live && a0;
     cnt.abs1 += live && a1;
@@ -1529,6 +1534,22 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
           X[i + k] = Vec<P>::at(xw[v], k);
           U[i + k] = Vec<P>::at(uw[v], k);
         }
+    }
+  }
+  if (c.masks) {
+    // a compaction follows: the slots' liveness after this push, as whole
+    // 64-slot words of the region's live masks (the lanes of a word gather
+    // their bits; the compaction reads positions only for the words left)
+    constexpr int LPW = 64 / VN;  // lanes per word
+    const int lane = tid & 63;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      unsigned long long m = (unsigned long long)((alive >> (v * VN)) & ((1u << VN) - 1u))
+                             << (VN * (lane % LPW));
+#pragma unroll
+      for (int o = 1; o < LPW; o <<= 1) m |= __shfl_xor(m, o, 64);
+      const long long i = r0 + (long long)(v * BS + tid) * VN;
+      if (lane % LPW == 0 && (FULL || i + 64 <= n_here)) c.live[i / 64] = m;
     }
   }
   // every slot adds (zero weights for slots that do not deposit): no branches
@@ -1629,6 +1650,8 @@ __device__ void push_range(const DevPtrs &p, const GapConst &gc, const GapState 
   c.evcap = gc.evcap;
   c.gacc = p.acc + gc.nbase;
   c.ids = p.ID[sel] + gc.pbase[s];
+  c.masks = sh.masks;
+  c.live = p.live + gc.pbase[s] / 64;
   P *X = (P *)p.X[sel] + gc.pbase[s];
   P *U = (P *)p.U[sel] + gc.pbase[s];
   const P alpha = (P)gc.alpha[s];
@@ -1754,7 +1777,8 @@ __device__ __forceinline__ void push_tiles(const DevPtrs &p, PushShared<P, AC> &
 }
 
 template <class P, class AC, int BS, int PPT, bool NT>
-__global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int nmax, int steal, int rr) {
+__global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int nmax, int steal, int rr,
+                                                 int masks) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   typedef typename AC::cell cell;
   __shared__ int scan_sh[BS];
@@ -1766,6 +1790,7 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
   sh.evq = evq;
   sh.evq_n = &evq_n;
   sh.wsum = wsum_sh;
+  sh.masks = masks;
   sh.tally = (unsigned int *)lds_raw;
   sh.prefix = (int *)(lds_raw + 64);
   const size_t off = 64 + (((size_t)(G + 1) * 4 + 15) / 16) * 16;
@@ -1899,7 +1924,7 @@ static hipError_t push_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream
     attr_set = lds;
   }
   return launch_k(k_push<P, AC, BS, PPT, NT>, dim3(lc.grid), dim3(BS), lds, s, t.a, t.b, p, G, lc.tile,
-                  lc.nmax, lc.steal, (lc.stream & STREAM_RR) ? 1 : 0);
+                  lc.nmax, lc.steal, (lc.stream & STREAM_RR) ? 1 : 0, lc.masks);
 }
 
 template <class P, class AC, int PPT, bool NT>
@@ -2331,8 +2356,10 @@ __device__ inline unsigned long long slot_range_mask(long long w0, long long lo,
   const int t0 = (int)(((long long)blockIdx.x * total) / gridDim.x);         \
   const int t1 = (int)(((long long)(blockIdx.x + 1) * total) / gridDim.x);
 
+// masks: the push before wrote the masks of the words below each region's
+// count (its pushed range); only the other words are read from the positions
 template <class P>
-__global__ __launch_bounds__(FW) void k_fill_count(DevPtrs p, int G) {
+__global__ __launch_bounds__(FW) void k_fill_count(DevPtrs p, int G, int masks) {
   FILL_TILE_RUN
   typedef typename Vec<P>::type PV;
   constexpr int VN = Vec<P>::n;
@@ -2343,6 +2370,7 @@ __global__ __launch_bounds__(FW) void k_fill_count(DevPtrs p, int G) {
     const int s = r & 1, k = t - prefix[r];
     const GapConst &c = p.gc[r >> 1];
     const long long n = min((long long)p.next_count[r], c.cap[s]);
+    const long long pushed = masks ? min((long long)p.gs[r >> 1].count[s], n) : 0;
     const long long i_beg = (long long)k * CTS, i_end = min(n, i_beg + CTS);
     const P *X = (const P *)p.X[sel] + c.pbase[s];
     unsigned long long *lm = p.live + c.pbase[s] / 64;
@@ -2350,6 +2378,10 @@ __global__ __launch_bounds__(FW) void k_fill_count(DevPtrs p, int G) {
     for (int q = 0; q < WPT; ++q) {
       const long long w0 = i_beg + ((long long)q * FW + tid) * 64;
       if (w0 >= i_end) continue;
+      if (w0 + 64 <= pushed) {
+        cnt += __popcll(lm[w0 / 64]);
+        continue;
+      }
       // the word's loads all in flight before any is used
       PV xv[NV];
       if (w0 + 64 <= i_end) {
@@ -2742,7 +2774,7 @@ static hipError_t fill_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream
     attr_set2 = lds2;
   }
   // the start event goes with the count pass, the end event with the commit
-  hipError_t e = launch_k(k_fill_count<P>, dim3(grid), dim3(FW), lds, s, t.a, nullptr, p, G);
+  hipError_t e = launch_k(k_fill_count<P>, dim3(grid), dim3(FW), lds, s, t.a, nullptr, p, G, lc.masks);
   if (e == hipSuccess) e = launch_k(k_fill_plan, dim3(2 * G), dim3(FPB), 0, s, nullptr, nullptr, p);
   if (e == hipSuccess) e = launch_k(k_fill_holes<P>, dim3(grid), dim3(FW), lds, s, nullptr, nullptr, p, G);
   if (e == hipSuccess) e = launch_k(k_fill_rank<P>, dim3(grid), dim3(FW), lds, s, nullptr, nullptr, p, G);
