@@ -475,6 +475,7 @@ static gs_status setup(gs_ctx *ctx) {
   ALLOC(d.epoch, int64_t *, 8);
   ALLOC(d.err, unsigned int *, 8);
   ALLOC(d.steal, unsigned int *, 256);
+  d.push_done = d.steal + 32;  // a cache line of its own in the same block
   ALLOC(d.gc, const GapConst *, sizeof(GapConst) * (size_t)G);
   ALLOC(d.gs, GapState *, sizeof(GapState) * (size_t)G);
 #undef ALLOC
@@ -521,6 +522,7 @@ static gs_status setup(gs_ctx *ctx) {
   ctx->lc.steal = 0;
   ctx->lc.stream = 0;
   ctx->lc.masks = 0;
+  ctx->lc.lists = 0;
   choose_launch(ctx);
   return GS_OK;
 }
@@ -756,21 +758,24 @@ static int64_t beam_at(const gs_ctx *ctx, int g, int64_t n) {
   return n >= 0 && n < (int64_t)s.size() ? s[(size_t)n] : 0;
 }
 
-// The push, then, when a gap emits, the emission kernel: the ions a push
-// workgroup absorbs past what it can emit itself (its LDS queue and overflow
-// region) wait in the gap's list, and k_emit emits them with many workgroups
-// in the same step, so the emitted counts of a level never lag.  With the cell
-// sort on, a wall's impacts sit in few workgroups: the push then keeps only its
-// LDS queue and leaves the rest to k_emit.
+// The push, and the emission of every absorbed ion in the same step, so the
+// emitted counts of a level never lag: the ions a push workgroup absorbs past
+// what it can emit itself (its LDS queue and overflow region) wait in the
+// gap's list.  The push's last workgroup emits the lists (they are normally
+// empty: the overflow regions are sized for the step's impacts).  With the
+// cell sort on, a wall's impacts sit in few workgroups: the push then keeps
+// only its LDS queue, and k_emit emits the long lists with many workgroups
+// after it.
 // masks: a compaction follows this push (the push then writes the live masks)
 static hipError_t launch_push_emit(gs_ctx *ctx, hipStream_t s, bool timing, bool masks) {
   DevPtrs dp = ctx->dp;
   if (ctx->lc.sort_bin > 0) dp.ovf_wgs = 0;
   LaunchCfg lc = ctx->lc;
   lc.masks = masks && lc.sort_bin == 0;
+  lc.lists = ctx->emits && lc.sort_bin == 0 && lc.grid < 65536;
   auto push = [&](KTime t) { return launch_push(dp, ctx->G, lc, s, t); };
   hipError_t e = timing ? timed(ctx, 0, push) : push(KTime{});
-  if (e != hipSuccess || !ctx->emits) return e;
+  if (e != hipSuccess || !ctx->emits || lc.lists) return e;
   auto emit = [&](KTime t) { return launch_emit(ctx->dp, ctx->G, ctx->fp64, std::max(ctx->ncu, 1), s, t); };
   return timing ? timed(ctx, 3, emit) : emit(KTime{});
 }

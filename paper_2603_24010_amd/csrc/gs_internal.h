@@ -121,6 +121,7 @@ struct DevPtrs {
   int64_t *epoch;                  // compaction epoch (device)
   unsigned int *err;               // [0] flags, [1] gap of first error
   unsigned int *steal;             // the push's pool counter, cleared by the field solve
+  unsigned int *push_done;         // push workgroups done (the last resets it to zero)
   // the field solve's hand-offs between its kernels: the prefix sums of the
   // cell terms within chunks of FCN nodes (per node), the chunks' totals and
   // weighted sums [G][NCHMAX][2], their offsets [G][NCHMAX], sigma [G]
@@ -194,6 +195,8 @@ struct LaunchCfg {
   int masks;         // per launch: the push writes the live masks of the words
                      // below each region's count, and the compaction that follows
                      // takes them instead of reading those positions
+  int lists;         // per launch: the push's last workgroup emits the gaps'
+                     // lists of absorbed ions (else k_emit does, after the push)
 };
 constexpr int STREAM_RR = 1, STREAM_NT = 2;
 

@@ -1217,6 +1217,36 @@ __device__ inline void acc_add<Carry32>(unsigned int *lds, unsigned long long *g
   if (old + uw < old) atomicAdd(&gacc[j], (unsigned long long)zhi);
 }
 
+// Emission for the events [r0, r0 + nr) of gap g's list (every thread of the
+// block): the electrons, their wall charge added to the gap's node row and
+// their counts to its tallies, keyed by the gap's level as in the push that
+// queued them.  s_base and s_emit are LDS scratch.
+template <class P>
+__device__ void emit_list(const DevPtrs &p, int g, int sel, long long r0, int nr, int *wsum,
+                          unsigned long long *s_base, unsigned int *s_emit) {
+  const GapConst &c = p.gc[g];
+  const long long level = p.gs[g].level;
+  if (threadIdx.x < 2) s_emit[threadIdx.x] = 0u;
+  __syncthreads();
+  see_emit<P>(p, c, level, g, sel, p.ev + c.evbase + r0, nr, wsum, s_base, s_emit);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int e0 = s_emit[0], e1 = s_emit[1];
+    const long long ze = (long long)c.Z[0] * Prec<P>::W;
+    unsigned long long *gacc = p.acc + c.nbase;
+    if (e0) {
+      atomicAdd(&gacc[0], (unsigned long long)(ze * (long long)e0));
+      atomicAdd(&p.tally[(size_t)g * T_N + T_EMIT], (unsigned long long)e0);
+    }
+    if (e1) {
+      atomicAdd(&gacc[c.N], (unsigned long long)(ze * (long long)e1));
+      atomicAdd(&p.tally[(size_t)g * T_N + T_EMIT + 1], (unsigned long long)e1);
+    }
+    atomicAdd(&p.ev_done[g], (unsigned long long)nr);
+  }
+  __syncthreads();
+}
+
 constexpr int EVQ = 128;  // absorbed-ion events a push workgroup queues in LDS
 // (more go to the workgroup's overflow region of a global buffer; both are
 // emitted at the segment's flush, so a step's emission completes in its push)
@@ -1230,6 +1260,9 @@ struct PushShared {
   Event *evq;           // [EVQ]
   unsigned int *evq_n;
   int *wsum;            // [BS / 64] scan scratch
+  unsigned int *listed; // the workgroup put absorbed ions in a gap's list (set
+                        // when a segment is closed: its queue count passed the
+                        // LDS queue and the overflow region)
   int masks;            // the launch writes the live masks
 };
 
@@ -1375,6 +1408,7 @@ __device__ void flush_seg(const DevPtrs &p, const GapConst &c, const GapState &s
   __syncthreads();
   const int ovq = (long long)blockIdx.x < p.ovf_wgs ? (int)p.ovq : 0;
   const int ne = s == 1 ? (int)min(*sh.evq_n, (unsigned int)(EVQ + ovq)) : 0;
+  if (s == 1 && threadIdx.x == 0 && *sh.evq_n > (unsigned int)(EVQ + ovq)) *sh.listed = 1u;
   const Event *ovf = p.ovf + (size_t)blockIdx.x * (size_t)p.ovq;
   // one inlined copy of the round (the kernel's instruction footprint matters)
   int emitted = 0, r0 = 0;
@@ -1560,7 +1594,8 @@ __device__ inline void push_chunk(const DevPtrs &p, const SegK &c, PushShared<P,
   }
   // absorbed ions are queued for secondary emission: in LDS (emitted at the
   // segment's flush), then in the workgroup's overflow region, then in the
-  // gap's list (emitted after the push, or by the next field solve).  The wave
+  // gap's list (emitted at the end of the push by its last workgroup, or by
+  // k_emit after it).  The wave
   // takes its queue positions, and its share of the gap's list, with one atomic
   // each: a workgroup whose particles sit at a wall (sorted particles) absorbs
   // thousands of ions in one push, and an atomic per ion on the gap's counter
@@ -1776,20 +1811,83 @@ __device__ __forceinline__ void push_tiles(const DevPtrs &p, PushShared<P, AC> &
   if (lb > te) push_piece<P, AC, BS, PPT, NT>(p, sh, tile, sel, g, 1, max(la, te) - te, lb - te, 1, og, os);
 }
 
+// The gaps' lists of absorbed ions (the events past the workgroups' own
+// queues) are complete once every workgroup has pushed its particles: each
+// counts itself in push_done (the high half counting those that added to a
+// list, after making their list entries visible device-wide) before its last
+// flush, which the count's return then overlaps, and the last one to count,
+// when some added, emits the lists after its flush, as k_emit would after the
+// push.  That one leaves the count at zero for the next launch.  (The grid is
+// below 2^16 workgroups.)  push_ticket returns the count after thread 0's
+// addition, in thread 0.
+template <class P, class AC>
+__device__ __forceinline__ unsigned int push_ticket(const DevPtrs &p, PushShared<P, AC> &sh, int os) {
+  __syncthreads();
+  const unsigned int lim = (unsigned int)EVQ + ((long long)blockIdx.x < p.ovf_wgs ? (unsigned int)p.ovq : 0u);
+  const bool listed = *sh.listed != 0u || (os == 1 && *sh.evq_n > lim);
+  if (listed) {
+    __threadfence();
+    __syncthreads();
+  }
+  unsigned int now = 0u;
+  if (threadIdx.x == 0) {
+    const unsigned int add = listed ? 0x10001u : 1u;
+    now = atomicAdd(p.push_done, add) + add;
+  }
+  return now;
+}
+
+constexpr int LIST_CH = 1 << 20;  // events per emission call
+template <class P, class AC>
+__device__ __forceinline__ void push_tail_emit(const DevPtrs &p, PushShared<P, AC> &sh, int G, int sel,
+                                               unsigned int now) {
+  __shared__ unsigned int s_last;
+  __shared__ unsigned long long s_mask[16];
+  __shared__ unsigned long long s_base;
+  __shared__ unsigned int s_emit[2];
+  if (threadIdx.x == 0) s_last = (now & 0xFFFFu) == gridDim.x ? 1u + (now >> 16) : 0u;
+  __syncthreads();
+  const unsigned int last = s_last;
+  if (last == 0u) return;
+  if (threadIdx.x == 0) *p.push_done = 0u;
+  if (last == 1u) return;
+  __threadfence();
+  // the gaps with a list, blockDim.x at a time, as bit masks per wave
+  for (int g0 = 0; g0 < G; g0 += (int)blockDim.x) {
+    const int g = g0 + (int)threadIdx.x;
+    const unsigned long long m = __ballot(g < G && p.ev_count[g] != 0ull);
+    if ((threadIdx.x & 63) == 0) s_mask[threadIdx.x >> 6] = m;
+    __syncthreads();
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      unsigned long long mm = s_mask[w];
+      while (mm != 0ull) {
+        const int gg = g0 + w * 64 + (__ffsll((unsigned long long)mm) - 1);
+        mm &= mm - 1ull;
+        const long long ne = min((long long)p.ev_count[gg], p.gc[gg].evcap);
+        for (long long r0 = 0; r0 < ne; r0 += LIST_CH)
+          emit_list<P>(p, gg, sel, r0, (int)min((long long)LIST_CH, ne - r0), sh.wsum, &s_base, s_emit);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <class P, class AC, int BS, int PPT, bool NT>
 __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int nmax, int steal, int rr,
-                                                 int masks) {
+                                                 int masks, int lists) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   typedef typename AC::cell cell;
   __shared__ int scan_sh[BS];
   __shared__ Event evq[EVQ];
   __shared__ unsigned int evq_n;
   __shared__ int wsum_sh[BS / 64];
+  __shared__ unsigned int listed_sh;
   // layout: tally[T_N] | prefix[G+1] | eh[nmax+2] (P) | acc[nmax+1] (cell)
   PushShared<P, AC> sh;
   sh.evq = evq;
   sh.evq_n = &evq_n;
   sh.wsum = wsum_sh;
+  sh.listed = &listed_sh;
   sh.masks = masks;
   sh.tally = (unsigned int *)lds_raw;
   sh.prefix = (int *)(lds_raw + 64);
@@ -1799,6 +1897,8 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int sel = (int)(*p.epoch & 1);
+  // (set before the first segment's staging barrier, read after the last flush)
+  if (tid == 0) listed_sh = 0u;
 
   // tiles per gap and their prefix (each workgroup builds its own copy in LDS;
   // one gap needs no scan)
@@ -1856,7 +1956,9 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
       push_piece<P, AC, BS, PPT, NT>(p, sh, tile, sel, g, s, t - T0, T1 - T0, nwg, og, os);
       t += ((T1 - t + nwg - 1) / nwg) * nwg;  // the first of its tiles past the region
     }
+    const unsigned int now = lists ? push_ticket<P, AC>(p, sh, os) : 0u;
     if (og >= 0) close_seg<P, AC>(p, sh, sel, og, os);
+    if (lists) push_tail_emit<P, AC>(p, sh, G, sel, now);
     return;
   }
   // the workgroup's contiguous run of tiles; with stealing on, the last R of
@@ -1909,7 +2011,9 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
       push_tiles<P, AC, BS, PPT, NT>(p, sh, tile, sel, g, prefix(g), tt, tt + 1, og, os);
     }
   }
+  const unsigned int now = lists ? push_ticket<P, AC>(p, sh, os) : 0u;
   if (og >= 0) close_seg<P, AC>(p, sh, sel, og, os);
+  if (lists) push_tail_emit<P, AC>(p, sh, G, sel, now);
 }
 
 template <class P, class AC, int BS, int PPT, bool NT>
@@ -1924,7 +2028,7 @@ static hipError_t push_t(const DevPtrs &p, int G, const LaunchCfg &lc, hipStream
     attr_set = lds;
   }
   return launch_k(k_push<P, AC, BS, PPT, NT>, dim3(lc.grid), dim3(BS), lds, s, t.a, t.b, p, G, lc.tile,
-                  lc.nmax, lc.steal, (lc.stream & STREAM_RR) ? 1 : 0, lc.masks);
+                  lc.nmax, lc.steal, (lc.stream & STREAM_RR) ? 1 : 0, lc.masks, lc.lists);
 }
 
 template <class P, class AC, int PPT, bool NT>
@@ -2237,8 +2341,9 @@ __global__ __launch_bounds__(BS) void k_sort_scatter(DevPtrs p, int G, int tile,
 // with one slot reservation.  Keyed by the push's level, as in the push, so
 // the electrons and their draws are the same; their wall charge goes to the
 // node accumulator and their counts to the tallies the next field solve reads.
-// Every event handled is counted in ev_done, so that the field solve emits
-// only what is left.
+// Every event handled is counted in ev_done.  It runs when the push's last
+// workgroup does not emit the lists itself (with the cell sort, whose lists
+// are long).
 // ---------------------------------------------------------------------------
 constexpr int EBS = 256;
 template <class P>
@@ -2281,30 +2386,9 @@ __global__ __launch_bounds__(EBS) void k_emit(DevPtrs p, int G) {
       if (cpre[mid] <= ch) lo = mid; else hi = mid - 1;
     }
     g = lo;
-    const GapConst &c = p.gc[g];
-    const long long ne = min((long long)p.ev_count[g], c.evcap);
+    const long long ne = min((long long)p.ev_count[g], p.gc[g].evcap);
     const long long r0 = (long long)(ch - cpre[g]) * EBS;
-    const long long level = p.gs[g].level;
-    if (tid < 2) s_emit[tid] = 0u;
-    __syncthreads();
-    const int nr = (int)min((long long)EBS, ne - r0);
-    see_emit<P>(p, c, level, g, sel, p.ev + c.evbase + r0, nr, wsum, &s_base, s_emit);
-    __syncthreads();
-    if (tid == 0) {
-      const unsigned int e0 = s_emit[0], e1 = s_emit[1];
-      const long long ze = (long long)c.Z[0] * Prec<P>::W;
-      unsigned long long *gacc = p.acc + c.nbase;
-      if (e0) {
-        atomicAdd(&gacc[0], (unsigned long long)(ze * (long long)e0));
-        atomicAdd(&p.tally[(size_t)g * T_N + T_EMIT], (unsigned long long)e0);
-      }
-      if (e1) {
-        atomicAdd(&gacc[c.N], (unsigned long long)(ze * (long long)e1));
-        atomicAdd(&p.tally[(size_t)g * T_N + T_EMIT + 1], (unsigned long long)e1);
-      }
-      atomicAdd(&p.ev_done[g], (unsigned long long)nr);
-    }
-    __syncthreads();
+    emit_list<P>(p, g, sel, r0, (int)min((long long)EBS, ne - r0), wsum, &s_base, s_emit);
   }
 }
 

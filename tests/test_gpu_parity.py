@@ -633,15 +633,56 @@ def test_launch_options_reject_out_of_range_values():
 
 def test_event_overflow_emitted_in_the_same_step():
     """Past 1152 absorbed ions in one workgroup and step the rest wait in the
-    gap's list and the emission kernel emits them right after the push: the
-    absorbed and emitted counts equal the oracle's at every level, as do the
-    voltages and fields."""
+    gap's list, and the push's last workgroup emits them before the push ends:
+    the absorbed and emitted counts equal the oracle's at every level, as do
+    the voltages and fields."""
     sched = W.gaussian_schedule(60, 3000.0, 30.0, 8.0)
     cfg = W.config_tesla(layer=0.0).replace(beam_schedule=sched, see_amp=30.0)
     sim, orc, recs = run_pair(cfg, {}, oracle.STRICT, 60, True, (200_000, 200_000))
     check_run(recs, 1e-5, cfg.n_mesh, cfg, oracle.STRICT)
     check_fields(sim, orc, 1e-5)
     assert recs[-1][0]["emit_cum"].sum() > 1000
+    sim.close()
+
+
+@pytest.mark.parametrize("stream", [0, 3])
+def test_event_overflow_in_batched_gaps(stream):
+    """Three gaps in one context: the first and last absorb thousands of beam
+    ions a step at the grounded electrode, past their workgroups' queues, so
+    those wait in the gaps' lists that the push's last workgroup emits; the
+    middle one emits within its workgroups.  Every gap's counts, electrode
+    potential, surface and circuit charges and loop currents equal its
+    oracle's at every level, and the first gap's fields at the end (contiguous
+    tile runs, and the round-robin non-temporal stream over five workgroups)."""
+    gs = _gapsim()
+    sched = W.gaussian_schedule(40, 3000.0, 20.0, 8.0)
+    hot = W.config_tesla(layer=0.0).replace(beam_schedule=sched, see_amp=30.0)
+    cfgs = [hot, cfg2_small(n_cells=700, beam=800), hot.replace(seed=6)]
+    loads = [{}, W.load_config2(n=20_000, seed=32), {}]
+    sim = gs.GapSim(cfgs, particle_fp=32, capacity=(200_000, 200_000))
+    sim.set_option(gs.OPT_COMPACT_EVERY, 7)
+    if stream:
+        sim.set_option(gs.OPT_STREAM, stream)
+        sim.set_option(gs.OPT_GRID, 5)
+    orcs = []
+    for g, cfg in enumerate(cfgs):
+        o = oracle.OracleSim(cfg, fp32=True)
+        for sp in sorted(loads[g]):
+            x, v = loads[g][sp]
+            o.inject(sp, x, v)
+            sim.inject(g, sp, x, v)
+        orcs.append(o)
+    recs = [[] for _ in cfgs]
+    for n in range(40):
+        sim.step_strict(1)
+        for g in range(len(cfgs)):
+            orcs[g].step(oracle.STRICT, 1)
+            recs[g].append((sim.diag(g), orcs[g].diag()))
+    for g, cfg in enumerate(cfgs):
+        check_run(recs[g], 1e-5, cfg.n_mesh, cfg, oracle.STRICT)
+    check_fields(sim, orcs[0], 1e-5)
+    for g in (0, 2):
+        assert recs[g][-1][0]["emit_cum"].sum() > 1000
     sim.close()
 
 
