@@ -368,7 +368,8 @@ gs_status gs_dt_check(gs_ctx *ctx, int32_t gap, gs_dt_report *out);
  * are filled and the state stays valid: the last iterate was used).
  * Emission timing: the secondaries of the ions absorbed in a step are emitted
  * within that step (by the push workgroup that absorbed them, or, past what it
- * can hold, by the emission kernel right after the push). */
+ * can hold, by the push's last workgroup to finish, or with the cell sort on by
+ * the emission kernel right after the push). */
 gs_status gs_read_diagnostics(gs_ctx *ctx, int32_t gap, gs_diag *out, double *phi, double *E,
                               double *rho);
 
