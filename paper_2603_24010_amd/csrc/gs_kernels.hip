@@ -1439,10 +1439,12 @@ __device__ void flush_seg(const DevPtrs &p, const GapConst &c, const GapState &s
 // Stage one (gap, species) segment: clear the node accumulator and the
 // tallies, inject this workgroup's share of the beam, and copy the gap's field
 // table (16-byte aligned, N + 2 entries) into LDS with 16-byte loads, the
-// first TQ per thread issued before anything else.
+// first TQ per thread issued before anything else.  The table is the gap's,
+// for either species: table is false when LDS already holds it (the previous
+// segment was the gap's other species).
 template <class P, class AC>
 __device__ void load_seg(const DevPtrs &p, const GapConst &c, const GapState &st, int g, int sel,
-                         PushShared<P, AC> &sh, long long kb0, long long kb1) {
+                         PushShared<P, AC> &sh, long long kb0, long long kb1, bool table) {
   // the table moves as 16-byte vectors of a native vector type (arrays of it
   // stay in registers)
   typedef unsigned int V __attribute__((ext_vector_type(4)));
@@ -1454,8 +1456,10 @@ __device__ void load_seg(const DevPtrs &p, const GapConst &c, const GapState &st
   const int tid = threadIdx.x;
   // loads past the table repeat its last vector
   V t[TQ];
+  if (table) {
 #pragma unroll
-  for (int q = 0; q < TQ; ++q) t[q] = geh[min(tid + q * bs, nv - 1)];
+    for (int q = 0; q < TQ; ++q) t[q] = geh[min(tid + q * bs, nv - 1)];
+  }
   for (int j = tid; j <= c.N; j += bs) sh.acc[j] = 0;
   if (tid < T_N) sh.tally[tid] = 0u;
   if (tid == 0) *sh.evq_n = 0u;
@@ -1465,16 +1469,18 @@ __device__ void load_seg(const DevPtrs &p, const GapConst &c, const GapState &st
     __syncthreads();
     beam_inject<P, AC>(p, c, st, g, sel, kb0, kb1, sh.acc, &sh.tally[T_INJ]);
   }
+  if (table) {
 #pragma unroll
-  for (int q = 0; q < TQ; ++q)
-    if (tid + q * bs < nv) leh[tid + q * bs] = t[q];
-  for (int j0 = tid + TQ * bs; j0 < nv; j0 += 4 * bs) {
-    V r[4];
+    for (int q = 0; q < TQ; ++q)
+      if (tid + q * bs < nv) leh[tid + q * bs] = t[q];
+    for (int j0 = tid + TQ * bs; j0 < nv; j0 += 4 * bs) {
+      V r[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = geh[min(j0 + q * bs, nv - 1)];
+      for (int q = 0; q < 4; ++q) r[q] = geh[min(j0 + q * bs, nv - 1)];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (j0 + q * bs < nv) leh[j0 + q * bs] = r[q];
+      for (int q = 0; q < 4; ++q)
+        if (j0 + q * bs < nv) leh[j0 + q * bs] = r[q];
+    }
   }
   __syncthreads();
 }
@@ -1673,7 +1679,7 @@ __device__ inline void load_chunk(const P *X, const P *U, long long r0, typename
 template <class P, class AC, int BS, int PPT, bool NT>
 __device__ void push_range(const DevPtrs &p, const GapConst &gc, const GapState &st, int g, int s, int sel,
                            PushShared<P, AC> &sh, long long a, long long b, long long run, long long step,
-                           int nrun, long long kb0, long long kb1, bool stage, SegCount &cnt) {
+                           int nrun, long long kb0, long long kb1, bool stage, bool table, SegCount &cnt) {
   typedef typename Vec<P>::type V;
   constexpr int VN = Vec<P>::n;
   constexpr int NV = PPT / VN;
@@ -1701,7 +1707,7 @@ __device__ void push_range(const DevPtrs &p, const GapConst &gc, const GapState 
   // when the segment is already open, while this range's beam goes in)
   if (nfull > 0) load_chunk<P, BS, PPT, NT>(X, U, a, xa, ua);
   if (stage)
-    load_seg<P, AC>(p, gc, st, g, sel, sh, kb0, kb1);
+    load_seg<P, AC>(p, gc, st, g, sel, sh, kb0, kb1, table);
   else if (kb1 > kb0)
     beam_inject<P, AC>(p, gc, st, g, sel, kb0, kb1, sh.acc, &sh.tally[T_INJ]);
   // one copy of the chunk body (the kernel's instruction footprint is what
@@ -1768,6 +1774,7 @@ __device__ __forceinline__ void push_piece(const DevPtrs &p, PushShared<P, AC> &
   int te, ti;
   gap_tiles(st, st.beam_now, tile, te, ti);
   const bool stage = !(g == og && s == os);
+  const bool table = og != g;  // (LDS holds the table of the last gap staged)
   if (stage && og >= 0) close_seg<P, AC>(p, sh, sel, og, os);
   SegCount cnt;
   // the local tiles ls, ls + stride, ... below le (stride 1: the run [ls, le))
@@ -1788,7 +1795,7 @@ __device__ __forceinline__ void push_piece(const DevPtrs &p, PushShared<P, AC> &
     kb0 = st.beam_now * ls / nb;
     kb1 = st.beam_now * (stride == 1 ? le : ls + 1) / nb;
   }
-  push_range<P, AC, BS, PPT, NT>(p, c, st, g, s, sel, sh, a, b, run, step, nrun, kb0, kb1, stage, cnt);
+  push_range<P, AC, BS, PPT, NT>(p, c, st, g, s, sel, sh, a, b, run, step, nrun, kb0, kb1, stage, table, cnt);
   // wave-level sums, then one LDS atomic per wave
   const unsigned int v0 = wave_sum(cnt.pushed), v1 = wave_sum(cnt.abs0), v2 = wave_sum(cnt.abs1);
   if ((threadIdx.x & 63) == 0) {
