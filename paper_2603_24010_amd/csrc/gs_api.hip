@@ -60,7 +60,9 @@ struct gs_ctx {
   std::vector<int64_t> next_id;
   std::vector<std::vector<int64_t>> sched;  // per gap: copy of the beam schedule (empty: none)
   std::vector<int> sched_on;                // per gap: the schedule is in force
-  double *ext_host = nullptr;               // pinned, mapped: [G] engine voltages, [G] field potentials
+  double *ext_host = nullptr;               // pinned, mapped: [G] engine voltages, [G] field potentials,
+                                            // then the lists' size the device last saw
+  volatile unsigned long long *list_hint = nullptr;
   void *scratch = nullptr;                  // this device's staging array of gs_inject_noalloc
   hipEvent_t ext_ev = nullptr;              // recorded after each external-mode field solve
   std::string err;
@@ -438,18 +440,21 @@ static gs_status setup(gs_ctx *ctx) {
   ALLOC(sched_d, int64_t *, std::max<size_t>(nsched, 1) * 8);
   d.sched = sched_d;
   // exchange buffer of the external circuit engine: coherent pinned host memory
-  // the field kernel reads and writes directly (16 bytes per gap)
+  // the field kernel reads and writes directly (16 bytes per gap), and the
+  // word the push's tail or k_emit writes the lists' size to (16 bytes)
   {
     void *h = nullptr, *dptr = nullptr;
-    const hipError_t eh = hipHostMalloc(&h, (size_t)G * 16, hipHostMallocMapped | hipHostMallocCoherent);
+    const size_t nb = (size_t)G * 16 + 16;
+    const hipError_t eh = hipHostMalloc(&h, nb, hipHostMallocMapped | hipHostMallocCoherent);
     if (eh != hipSuccess || !h)
-      return fail(ctx, GS_ENOMEM, "pinned host allocation of %zu bytes failed: %s", (size_t)G * 16,
-                  hipGetErrorString(eh));
+      return fail(ctx, GS_ENOMEM, "pinned host allocation of %zu bytes failed: %s", nb, hipGetErrorString(eh));
     ctx->ext_host = (double *)h;
-    memset(h, 0, (size_t)G * 16);
+    memset(h, 0, nb);
     HIPCHK(ctx, hipHostGetDevicePointer(&dptr, h, 0));
     d.ext_v = (const double *)dptr;
     d.ext_phi = (double *)dptr + G;
+    d.list_seen = (unsigned long long *)((char *)dptr + (size_t)G * 16);
+    ctx->list_hint = (volatile unsigned long long *)((char *)h + (size_t)G * 16);
     HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ext_ev, hipEventDisableTiming));
   }
   // overflow event regions for up to eight 256-thread push workgroups per CU
@@ -475,7 +480,7 @@ static gs_status setup(gs_ctx *ctx) {
   ALLOC(d.epoch, int64_t *, 8);
   ALLOC(d.err, unsigned int *, 8);
   ALLOC(d.steal, unsigned int *, 256);
-  d.push_done = d.steal + 32;  // a cache line of its own in the same block
+  ALLOC(d.push_done, unsigned int *, 9 * 128);
   ALLOC(d.gc, const GapConst *, sizeof(GapConst) * (size_t)G);
   ALLOC(d.gs, GapState *, sizeof(GapState) * (size_t)G);
 #undef ALLOC
@@ -494,6 +499,7 @@ static gs_status setup(gs_ctx *ctx) {
   HIPCHK(ctx, hipMemsetAsync(d.ev_count, 0, (size_t)G * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.ev_done, 0, (size_t)G * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.steal, 0, 256, s));
+  HIPCHK(ctx, hipMemsetAsync(d.push_done, 0, 9 * 128, s));
   HIPCHK(ctx, hipMemsetAsync(d.hist, 0, bins * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.bcur, 0, bins * 8, s));
   for (int g = 0; g < G; ++g)
@@ -761,18 +767,24 @@ static int64_t beam_at(const gs_ctx *ctx, int g, int64_t n) {
 // The push, and the emission of every absorbed ion in the same step, so the
 // emitted counts of a level never lag: the ions a push workgroup absorbs past
 // what it can emit itself (its LDS queue and overflow region) wait in the
-// gap's list.  The push's last workgroup emits the lists (they are normally
-// empty: the overflow regions are sized for the step's impacts).  With the
-// cell sort on, a wall's impacts sit in few workgroups: the push then keeps
-// only its LDS queue, and k_emit emits the long lists with many workgroups
-// after it.
+// gap's list.  The push's last workgroup emits the lists when the last push
+// seen left none (the usual case: the overflow regions are sized for the
+// step's impacts); when it left some (impacts concentrated in a few
+// workgroups), k_emit emits them with many workgroups after the push, which
+// costs less than the fences and the serial passes of one workgroup.  The
+// size read here is a step or two old (the device writes it to host memory):
+// either way every list is emitted within its step.  With the cell sort on, a
+// wall's impacts sit in few workgroups: the push then keeps only its LDS
+// queue, and k_emit emits the long lists.  (A captured graph keeps the choice
+// made when it was captured.)
 // masks: a compaction follows this push (the push then writes the live masks)
 static hipError_t launch_push_emit(gs_ctx *ctx, hipStream_t s, bool timing, bool masks) {
   DevPtrs dp = ctx->dp;
   if (ctx->lc.sort_bin > 0) dp.ovf_wgs = 0;
   LaunchCfg lc = ctx->lc;
   lc.masks = masks && lc.sort_bin == 0;
-  lc.lists = ctx->emits && lc.sort_bin == 0 && lc.grid < 65536;
+  const bool listed = ctx->list_hint && *ctx->list_hint != 0ull;
+  lc.lists = ctx->emits && lc.sort_bin == 0 && lc.grid < 65536 && !listed;
   auto push = [&](KTime t) { return launch_push(dp, ctx->G, lc, s, t); };
   hipError_t e = timing ? timed(ctx, 0, push) : push(KTime{});
   if (e != hipSuccess || !ctx->emits || lc.lists) return e;

@@ -121,7 +121,8 @@ struct DevPtrs {
   int64_t *epoch;                  // compaction epoch (device)
   unsigned int *err;               // [0] flags, [1] gap of first error
   unsigned int *steal;             // the push's pool counter, cleared by the field solve
-  unsigned int *push_done;         // push workgroups done (the last resets it to zero)
+  unsigned int *push_done;         // push workgroups done: a top counter and eight group
+                                   // counters, 128 bytes apart (the last resets them)
   // the field solve's hand-offs between its kernels: the prefix sums of the
   // cell terms within chunks of FCN nodes (per node), the chunks' totals and
   // weighted sums [G][NCHMAX][2], their offsets [G][NCHMAX], sigma [G]
@@ -143,6 +144,10 @@ struct DevPtrs {
   // being solved (read), ext_phi[g] the electrode potential it gave (written)
   const double *ext_v;
   double *ext_phi;
+  // mapped host word: the events the last push left in the gaps' lists (an
+  // upper bound when k_emit wrote it), which the host reads to choose who
+  // emits the next push's lists
+  unsigned long long *list_seen;
   Event *ovf;                      // push workgroup b < ovf_wgs: events past its LDS queue,
   int64_t ovf_wgs;                 //   ovq of them from ovf + b * ovq
   int64_t ovq;
@@ -175,6 +180,7 @@ constexpr int SORT_BIN_MIN = 4;
 // on the gap's counter, and at some 1e5 overflowing events a step those
 // serialise; the regions are sized so that a push rarely needs the list.
 constexpr int OVQ_MIN = 1024, OVQ_MAX = 8192;
+
 
 struct LaunchCfg {
   int block;         // push block size

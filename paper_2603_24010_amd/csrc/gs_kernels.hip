@@ -1819,14 +1819,19 @@ __device__ __forceinline__ void push_tiles(const DevPtrs &p, PushShared<P, AC> &
 }
 
 // The gaps' lists of absorbed ions (the events past the workgroups' own
-// queues) are complete once every workgroup has pushed its particles: each
-// counts itself in push_done (the high half counting those that added to a
-// list, after making their list entries visible device-wide) before its last
-// flush, which the count's return then overlaps, and the last one to count,
-// when some added, emits the lists after its flush, as k_emit would after the
-// push.  That one leaves the count at zero for the next launch.  (The grid is
-// below 2^16 workgroups.)  push_ticket returns the count after thread 0's
-// addition, in thread 0.
+// queues) are complete once every workgroup has pushed its particles.  Each
+// workgroup counts itself, before its last flush (which the count's return
+// then overlaps), in the counter of its group (blockIdx.x mod 8, a cache line
+// each, so that a large grid does not queue on one address); the high half
+// counts those that added to a list, after making their entries visible
+// device-wide.  The workgroup that completes a group adds the group to the
+// top counter, and the one that completes that is the last: when some
+// workgroup added to a list, it emits the lists after its flush, as k_emit
+// would after the push, and it leaves every counter at zero for the next
+// launch.  (The grid is below 2^16 workgroups.)  push_ticket returns, in
+// thread 0, 0 for a workgroup that is not the last, else 1 + the number of
+// workgroups that added to a list.
+constexpr int TICKET_LINE = 32;  // counter words per cache line
 template <class P, class AC>
 __device__ __forceinline__ unsigned int push_ticket(const DevPtrs &p, PushShared<P, AC> &sh, int os) {
   __syncthreads();
@@ -1836,29 +1841,41 @@ __device__ __forceinline__ unsigned int push_ticket(const DevPtrs &p, PushShared
     __threadfence();
     __syncthreads();
   }
-  unsigned int now = 0u;
+  unsigned int last = 0u;
   if (threadIdx.x == 0) {
+    const unsigned int q = blockIdx.x & 7u;
+    const unsigned int nq = (gridDim.x - q + 7u) >> 3;  // workgroups in group q
     const unsigned int add = listed ? 0x10001u : 1u;
-    now = atomicAdd(p.push_done, add) + add;
+    const unsigned int gq = atomicAdd(&p.push_done[TICKET_LINE * (1u + q)], add) + add;
+    if ((gq & 0xFFFFu) == nq) {
+      if (gq >> 16) __threadfence();  // the group's list entries, on to the last one
+      const unsigned int add2 = 1u + ((gq >> 16) << 16);
+      const unsigned int t = atomicAdd(&p.push_done[0], add2) + add2;
+      if ((t & 0xFFFFu) == min(gridDim.x, 8u)) last = 1u + (t >> 16);
+    }
   }
-  return now;
+  return last;
 }
 
 constexpr int LIST_CH = 1 << 20;  // events per emission call
 template <class P, class AC>
 __device__ __forceinline__ void push_tail_emit(const DevPtrs &p, PushShared<P, AC> &sh, int G, int sel,
-                                               unsigned int now) {
+                                               unsigned int ticket) {
   __shared__ unsigned int s_last;
   __shared__ unsigned long long s_mask[16];
   __shared__ unsigned long long s_base;
   __shared__ unsigned int s_emit[2];
-  if (threadIdx.x == 0) s_last = (now & 0xFFFFu) == gridDim.x ? 1u + (now >> 16) : 0u;
+  if (threadIdx.x == 0) s_last = ticket;
   __syncthreads();
   const unsigned int last = s_last;
   if (last == 0u) return;
-  if (threadIdx.x == 0) *p.push_done = 0u;
-  if (last == 1u) return;
+  if (threadIdx.x <= 8u) p.push_done[TICKET_LINE * threadIdx.x] = 0u;
+  if (last == 1u) {
+    if (threadIdx.x == 0) *p.list_seen = 0ull;
+    return;
+  }
   __threadfence();
+  unsigned long long seen = 0;  // (thread 0's count of the events emitted)
   // the gaps with a list, blockDim.x at a time, as bit masks per wave
   for (int g0 = 0; g0 < G; g0 += (int)blockDim.x) {
     const int g = g0 + (int)threadIdx.x;
@@ -1871,12 +1888,14 @@ __device__ __forceinline__ void push_tail_emit(const DevPtrs &p, PushShared<P, A
         const int gg = g0 + w * 64 + (__ffsll((unsigned long long)mm) - 1);
         mm &= mm - 1ull;
         const long long ne = min((long long)p.ev_count[gg], p.gc[gg].evcap);
+        seen += (unsigned long long)ne;
         for (long long r0 = 0; r0 < ne; r0 += LIST_CH)
           emit_list<P>(p, gg, sel, r0, (int)min((long long)LIST_CH, ne - r0), sh.wsum, &s_base, s_emit);
       }
     }
     __syncthreads();
   }
+  if (threadIdx.x == 0) *p.list_seen = seen;
 }
 
 template <class P, class AC, int BS, int PPT, bool NT>
@@ -1963,9 +1982,9 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
       push_piece<P, AC, BS, PPT, NT>(p, sh, tile, sel, g, s, t - T0, T1 - T0, nwg, og, os);
       t += ((T1 - t + nwg - 1) / nwg) * nwg;  // the first of its tiles past the region
     }
-    const unsigned int now = lists ? push_ticket<P, AC>(p, sh, os) : 0u;
+    const unsigned int ticket = lists ? push_ticket<P, AC>(p, sh, os) : 0u;
     if (og >= 0) close_seg<P, AC>(p, sh, sel, og, os);
-    if (lists) push_tail_emit<P, AC>(p, sh, G, sel, now);
+    if (lists) push_tail_emit<P, AC>(p, sh, G, sel, ticket);
     return;
   }
   // the workgroup's contiguous run of tiles; with stealing on, the last R of
@@ -2018,9 +2037,9 @@ __global__ __launch_bounds__(BS, 3) void k_push(DevPtrs p, int G, int tile, int 
       push_tiles<P, AC, BS, PPT, NT>(p, sh, tile, sel, g, prefix(g), tt, tt + 1, og, os);
     }
   }
-  const unsigned int now = lists ? push_ticket<P, AC>(p, sh, os) : 0u;
+  const unsigned int ticket = lists ? push_ticket<P, AC>(p, sh, os) : 0u;
   if (og >= 0) close_seg<P, AC>(p, sh, sel, og, os);
-  if (lists) push_tail_emit<P, AC>(p, sh, G, sel, now);
+  if (lists) push_tail_emit<P, AC>(p, sh, G, sel, ticket);
 }
 
 template <class P, class AC, int BS, int PPT, bool NT>
@@ -2384,6 +2403,8 @@ __global__ __launch_bounds__(EBS) void k_emit(DevPtrs p, int G) {
     __syncthreads();
   }
   const int total = cpre[G];
+  // the lists' size for the host's next choice (whole chunks: an upper bound)
+  if (blockIdx.x == 0 && tid == 0) *p.list_seen = (unsigned long long)total * EBS;
   int g = 0;
   for (int ch = blockIdx.x; ch < total; ch += gridDim.x) {
     // the gap holding chunk ch (chunks increase with g)
