@@ -1828,7 +1828,9 @@ __device__ __forceinline__ void push_tiles(const DevPtrs &p, PushShared<P, AC> &
 // top counter, and the one that completes that is the last: when some
 // workgroup added to a list, it emits the lists after its flush, as k_emit
 // would after the push, and it leaves every counter at zero for the next
-// launch.  (The grid is below 2^16 workgroups.)  push_ticket returns, in
+// launch and the number of list events it emitted in the host word from which
+// the host chooses who emits the next push's lists.  (The grid is below 2^16
+// workgroups.)  push_ticket returns, in
 // thread 0, 0 for a workgroup that is not the last, else 1 + the number of
 // workgroups that added to a list.
 constexpr int TICKET_LINE = 32;  // counter words per cache line
@@ -1875,7 +1877,7 @@ __device__ __forceinline__ void push_tail_emit(const DevPtrs &p, PushShared<P, A
     return;
   }
   __threadfence();
-  unsigned long long seen = 0;  // (thread 0's count of the events emitted)
+  unsigned long long seen = 0;  // list events emitted (the same in every thread)
   // the gaps with a list, blockDim.x at a time, as bit masks per wave
   for (int g0 = 0; g0 < G; g0 += (int)blockDim.x) {
     const int g = g0 + (int)threadIdx.x;
