@@ -480,7 +480,7 @@ static gs_status setup(gs_ctx *ctx) {
   ALLOC(d.epoch, int64_t *, 8);
   ALLOC(d.err, unsigned int *, 8);
   ALLOC(d.steal, unsigned int *, 256);
-  ALLOC(d.push_done, unsigned int *, 9 * 128);
+  ALLOC(d.push_done, unsigned int *, 33 * 128);
   ALLOC(d.gc, const GapConst *, sizeof(GapConst) * (size_t)G);
   ALLOC(d.gs, GapState *, sizeof(GapState) * (size_t)G);
 #undef ALLOC
@@ -499,7 +499,7 @@ static gs_status setup(gs_ctx *ctx) {
   HIPCHK(ctx, hipMemsetAsync(d.ev_count, 0, (size_t)G * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.ev_done, 0, (size_t)G * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.steal, 0, 256, s));
-  HIPCHK(ctx, hipMemsetAsync(d.push_done, 0, 9 * 128, s));
+  HIPCHK(ctx, hipMemsetAsync(d.push_done, 0, 33 * 128, s));
   HIPCHK(ctx, hipMemsetAsync(d.hist, 0, bins * 8, s));
   HIPCHK(ctx, hipMemsetAsync(d.bcur, 0, bins * 8, s));
   for (int g = 0; g < G; ++g)

@@ -121,7 +121,7 @@ struct DevPtrs {
   int64_t *epoch;                  // compaction epoch (device)
   unsigned int *err;               // [0] flags, [1] gap of first error
   unsigned int *steal;             // the push's pool counter, cleared by the field solve
-  unsigned int *push_done;         // push workgroups done: a top counter and eight group
+  unsigned int *push_done;         // push workgroups done: a top counter and 32 group
                                    // counters, 128 bytes apart (the last resets them)
   // the field solve's hand-offs between its kernels: the prefix sums of the
   // cell terms within chunks of FCN nodes (per node), the chunks' totals and

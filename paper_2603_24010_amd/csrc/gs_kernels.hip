@@ -1821,19 +1821,19 @@ __device__ __forceinline__ void push_tiles(const DevPtrs &p, PushShared<P, AC> &
 // The gaps' lists of absorbed ions (the events past the workgroups' own
 // queues) are complete once every workgroup has pushed its particles.  Each
 // workgroup counts itself, before its last flush (which the count's return
-// then overlaps), in the counter of its group (blockIdx.x mod 8, a cache line
-// each, so that a large grid does not queue on one address); the high half
-// counts those that added to a list, after making their entries visible
-// device-wide.  The workgroup that completes a group adds the group to the
-// top counter, and the one that completes that is the last: when some
+// then overlaps), in the counter of its group (blockIdx.x mod TICKET_GROUPS, a
+// cache line each, so that a large grid does not queue on one address); the
+// high half counts those that added to a list, after making their entries
+// visible device-wide.  The workgroup that completes a group adds the group
+// to the top counter, and the one that completes that is the last: when some
 // workgroup added to a list, it emits the lists after its flush, as k_emit
-// would after the push, and it leaves every counter at zero for the next
-// launch and the number of list events it emitted in the host word from which
-// the host chooses who emits the next push's lists.  (The grid is below 2^16
-// workgroups.)  push_ticket returns, in
-// thread 0, 0 for a workgroup that is not the last, else 1 + the number of
-// workgroups that added to a list.
-constexpr int TICKET_LINE = 32;  // counter words per cache line
+// would after the push.  It leaves every counter at zero for the next launch,
+// and the number of list events it emitted in the host word from which the
+// host chooses who emits the next push's lists.  (The grid is below 2^16
+// workgroups.)  push_ticket returns, in thread 0, 0 for a workgroup that is
+// not the last, else 1 + the number of workgroups that added to a list.
+constexpr int TICKET_LINE = 32;    // counter words per cache line
+constexpr int TICKET_GROUPS = 32;  // group counters (see the allocation of push_done)
 template <class P, class AC>
 __device__ __forceinline__ unsigned int push_ticket(const DevPtrs &p, PushShared<P, AC> &sh, int os) {
   __syncthreads();
@@ -1845,15 +1845,16 @@ __device__ __forceinline__ unsigned int push_ticket(const DevPtrs &p, PushShared
   }
   unsigned int last = 0u;
   if (threadIdx.x == 0) {
-    const unsigned int q = blockIdx.x & 7u;
-    const unsigned int nq = (gridDim.x - q + 7u) >> 3;  // workgroups in group q
+    constexpr unsigned int NG = (unsigned int)TICKET_GROUPS;
+    const unsigned int q = blockIdx.x % NG;
+    const unsigned int nq = (gridDim.x - q + NG - 1u) / NG;  // workgroups in group q
     const unsigned int add = listed ? 0x10001u : 1u;
     const unsigned int gq = atomicAdd(&p.push_done[TICKET_LINE * (1u + q)], add) + add;
     if ((gq & 0xFFFFu) == nq) {
       if (gq >> 16) __threadfence();  // the group's list entries, on to the last one
       const unsigned int add2 = 1u + ((gq >> 16) << 16);
       const unsigned int t = atomicAdd(&p.push_done[0], add2) + add2;
-      if ((t & 0xFFFFu) == min(gridDim.x, 8u)) last = 1u + (t >> 16);
+      if ((t & 0xFFFFu) == min(gridDim.x, NG)) last = 1u + (t >> 16);
     }
   }
   return last;
@@ -1871,7 +1872,7 @@ __device__ __forceinline__ void push_tail_emit(const DevPtrs &p, PushShared<P, A
   __syncthreads();
   const unsigned int last = s_last;
   if (last == 0u) return;
-  if (threadIdx.x <= 8u) p.push_done[TICKET_LINE * threadIdx.x] = 0u;
+  if (threadIdx.x <= (unsigned int)TICKET_GROUPS) p.push_done[TICKET_LINE * threadIdx.x] = 0u;
   if (last == 1u) {
     if (threadIdx.x == 0) *p.list_seen = 0ull;
     return;
